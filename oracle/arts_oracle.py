@@ -1,0 +1,211 @@
+"""Plain CPU oracle for the ARTS single-pulse search (van Leeuwen et al., "The Apertif Radio
+Transient System", arXiv:2205.12362).
+
+TEST INFRASTRUCTURE ONLY -- imported by tests/, __graft_entry__.smoke() and the cpu_baseline
+leg of bench.py, never by the product path.  Nothing here is tuned: every step is the direct
+definition, in int64 for integer data and FP64 for real numbers.
+
+The paper names the search stages (Sect. 6b.2 "AMBER": downsampling, dedispersion, integration,
+S/N evaluation, candidate selection) but does not write out the dispersion law, the boxcar, the
+S/N estimator or the candidate rule.  The readings taken here are listed per function and in the
+design notes of the repository; each is marked "reading".
+
+Parity status per function:
+  channel_freqs, delay_table, tie_audit, downsample, sb_synthesize, dedisperse,
+  dedisperse_at, boxcar, moments, snr, candidates  -- pinned by closed forms / invariants in
+  tests/test_oracle_pins.py (no function here is "parity unpinned").
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Cold-plasma dispersion constant, s MHz^2 pc^-1 cm^3.  Reading: the paper does not state the
+# delay law; the standard one, t(f) = K_DM * DM / f^2 with f in MHz, is used.
+K_DM = 4.148808e3
+
+
+def channel_freqs(nchan: int, f_lo_mhz: float, df_mhz: float) -> np.ndarray:
+    """Centre frequency of channel c: f_lo + c * df (MHz, FP64).
+
+    The Stokes-I beams have 1536 channels over 300 MHz at 81.92 us (Sect. 4d, dedicated TABF
+    output).  Reading: channels are equally spaced, c = 0 at f_lo, index increasing with df.
+    """
+    if nchan < 1:
+        raise ValueError("nchan must be >= 1")
+    return f_lo_mhz + np.arange(nchan, dtype=np.float64) * df_mhz
+
+
+def delay_table(nchan, f_lo_mhz, df_mhz, tsamp_s, dms, downsample=1, return_exact=False):
+    """Per-trial, per-channel dispersion delay in (downsampled) samples, int64 [ndm][nchan].
+
+    Dedispersion shifts every channel by the delay of a trial DM (Sect. 6b.2, "Dedispersion").
+    Reading: x = K_DM * DM * (1/f_c^2 - 1/f_ref^2) / (D * tsamp) with f_ref the highest channel
+    frequency, so every delay is >= 0; delay = x rounded half-to-even (numpy.rint).
+    With return_exact the unrounded FP64 x is returned as well.
+    """
+    if tsamp_s <= 0 or downsample < 1:
+        raise ValueError("tsamp must be > 0 and downsample >= 1")
+    f = channel_freqs(nchan, f_lo_mhz, df_mhz)
+    dms = np.asarray(dms, dtype=np.float64)
+    if dms.ndim != 1 or not np.all(np.isfinite(dms)) or np.any(dms < 0):
+        raise ValueError("DMs must be a 1-D array of finite values >= 0")
+    f_ref = f.max()
+    inv = 1.0 / (f * f) - 1.0 / (f_ref * f_ref)
+    x = K_DM * dms[:, None] * inv[None, :] / (downsample * tsamp_s)
+    d = np.rint(x).astype(np.int64)
+    return (d, x) if return_exact else d
+
+
+def tie_audit(x_exact: np.ndarray) -> float:
+    """Smallest distance of any unrounded delay from a rounding tie (k + 0.5).
+
+    A delay table is only well defined if no x sits on a tie within floating-point noise; this
+    returns min |frac(x) - 0.5| so a caller can check it against the FP64 evaluation error.
+    """
+    if x_exact.size == 0:
+        return float("inf")
+    return float(np.min(np.abs((x_exact - np.floor(x_exact)) - 0.5)))
+
+
+def downsample(data: np.ndarray, factor: int) -> np.ndarray:
+    """Lower the time resolution by summing `factor` consecutive samples (Sect. 6b.2,
+    "Downsampling").  Reading: a sum, not a mean, so integers stay exact; trailing samples that
+    do not fill a group are dropped.  data [..., nsamp] -> int64 [..., nsamp // factor]."""
+    if factor < 1:
+        raise ValueError("factor must be >= 1")
+    a = np.asarray(data).astype(np.int64)
+    n = a.shape[-1] // factor
+    return a[..., : n * factor].reshape(a.shape[:-1] + (n, factor)).sum(axis=-1)
+
+
+def sb_synthesize(tab: np.ndarray, sb_table: np.ndarray) -> np.ndarray:
+    """Form synthesized beams from tied-array beams: SB[s][c][t] = TAB[sb_table[s][c]][c][t].
+
+    Each SB takes, per frequency channel, the data of the TAB whose grating response points at
+    the SB's sky position at that frequency (Sect. 3d.beam; Appendix "Synthesized Beams").
+    tab [ntab][nchan][nsamp], sb_table [nsb][nchan] -> [nsb][nchan][nsamp] (same dtype)."""
+    tab = np.asarray(tab)
+    sb_table = np.asarray(sb_table)
+    ntab, nchan, _ = tab.shape
+    if sb_table.ndim != 2 or sb_table.shape[1] != nchan:
+        raise ValueError("sb_table must be [nsb][nchan]")
+    if sb_table.size and (sb_table.min() < 0 or sb_table.max() >= ntab):
+        raise ValueError("sb_table entry out of range")
+    out = np.empty((sb_table.shape[0], nchan, tab.shape[2]), dtype=tab.dtype)
+    for s in range(sb_table.shape[0]):
+        for c in range(nchan):
+            out[s, c, :] = tab[sb_table[s, c], c, :]
+    return out
+
+
+def dedisperse(data: np.ndarray, delays: np.ndarray) -> np.ndarray:
+    """Brute-force incoherent dedispersion: X[d][t] = sum_c I[c][t + delay[d][c]] (int64).
+
+    The brute-force approach of Sect. 6b.2 ("Dedispersion"), single step.  The output length is
+    the same for every trial: nout = nsamp - max(delay) over the whole table, so every output
+    sample sees every channel.  data [nchan][nsamp] (any integer dtype), delays [ndm][nchan]."""
+    data = np.asarray(data).astype(np.int64)
+    delays = np.asarray(delays).astype(np.int64)
+    nchan, nsamp = data.shape
+    if delays.shape[1] != nchan:
+        raise ValueError("delay table channel count does not match the data")
+    dmax = int(delays.max()) if delays.size else 0
+    nout = nsamp - dmax
+    if nout <= 0:
+        raise ValueError("input shorter than the largest delay")
+    out = np.zeros((delays.shape[0], nout), dtype=np.int64)
+    for d in range(delays.shape[0]):
+        for c in range(nchan):
+            s = delays[d, c]
+            out[d] += data[c, s : s + nout]
+    return out
+
+
+def dedisperse_at(data: np.ndarray, delays: np.ndarray, d: int, t: int) -> int:
+    """One dedispersed sample X[d][t] = sum_c I[c][t + delay[d][c]], for spot checks at sizes
+    where the full table is too slow (same definition as `dedisperse`)."""
+    cs = np.arange(data.shape[0])
+    return int(np.asarray(data)[cs, t + np.asarray(delays)[d]].astype(np.int64).sum())
+
+
+def boxcar(series: np.ndarray, width: int, nrep: int) -> np.ndarray:
+    """Boxcar matched filter: B_w[..., t] = sum_{j<w} X[..., t + j] for t < nrep (int64).
+
+    Integration convolves each dedispersed series with trial-width kernels so that S/N peaks at
+    the pulse width (Sect. 6b.2, "Integration"; offline, a box-car matched filter over many
+    widths, Sect. 6b.1).  Reading: sliding (every t), window [t, t + w - 1] indexed by its start."""
+    x = np.asarray(series).astype(np.int64)
+    if width < 1 or nrep < 0 or nrep + width - 1 > x.shape[-1]:
+        raise ValueError("boxcar window runs past the series")
+    out = x[..., 0:nrep].copy()
+    for j in range(1, width):
+        out += x[..., j : j + nrep]
+    return out
+
+
+def moments(series: np.ndarray, nrep: int):
+    """Per-series mean and population standard deviation over t < nrep (FP64).
+
+    Reading of the S/N normalisation (Sect. 6b.2, "S/N evaluation" leaves the method open):
+    noise statistics of the unsmoothed dedispersed series over the reported window, which is the
+    1.024 s chunk the real-time S/N is based on (Sect. 6b.1)."""
+    x = np.asarray(series)[..., :nrep].astype(np.float64)
+    mu = x.mean(axis=-1)
+    sigma = np.sqrt(((x - mu[..., None]) ** 2).mean(axis=-1))
+    return mu, sigma
+
+
+def snr(box: np.ndarray, width: int, mu, sigma) -> np.ndarray:
+    """S/N of boxcar sums: (B_w - w * mu) / (sigma * sqrt(w)), FP64; 0 where sigma == 0.
+
+    Reading: white noise, so the standard deviation of a w-sample sum is sigma * sqrt(w)."""
+    mu = np.asarray(mu, dtype=np.float64)[..., None]
+    sigma = np.asarray(sigma, dtype=np.float64)[..., None]
+    b = np.asarray(box).astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = (b - width * mu) / (sigma * np.sqrt(float(width)))
+    return np.where(sigma > 0, s, 0.0)
+
+
+def candidates(series: np.ndarray, widths, nrep: int, threshold: float, beam: int = 0,
+               t_offset: int = 0):
+    """Threshold candidates of one beam's dedispersed series X [ndm][L].
+
+    Candidates whose S/N exceeds the threshold are kept (Sect. 6b.2, "Candidate selection");
+    S/N is evaluated at all peaks ("S/N evaluation").  Reading: for every (DM, width) each
+    maximal run of consecutive samples with S/N > threshold (strict) gives one candidate at the
+    run's largest boxcar sum, the earliest sample on ties; no clustering across widths or DMs.
+    Returns a list of (beam, dm_index, width, t + t_offset, snr) sorted by (beam, dm, width, t).
+    """
+    x = np.asarray(series).astype(np.int64)
+    mu, sigma = moments(x, nrep)
+    out = []
+    for w in widths:
+        b = boxcar(x, w, nrep)
+        s = snr(b, w, mu, sigma)
+        for d in range(x.shape[0]):
+            above = s[d] > threshold
+            t = 0
+            while t < nrep:
+                if not above[t]:
+                    t += 1
+                    continue
+                e = t
+                while e < nrep and above[e]:
+                    e += 1
+                k = t + int(np.argmax(b[d, t:e]))
+                out.append((beam, d, int(w), k + t_offset, float(s[d, k])))
+                t = e
+    out.sort(key=lambda r: (r[0], r[1], r[2], r[3]))
+    return out
+
+
+def search(data: np.ndarray, delays: np.ndarray, widths, threshold: float, beam: int = 0,
+           nrep: int | None = None, t_offset: int = 0):
+    """The whole path on one beam: dedisperse, then boxcar / S/N / candidates over the reported
+    window nrep (default: every t whose widest boxcar fits).  Returns (X, candidates)."""
+    x = dedisperse(data, delays)
+    wmax = max(widths)
+    if nrep is None:
+        nrep = x.shape[1] - wmax + 1
+    return x, candidates(x, widths, nrep, threshold, beam=beam, t_offset=t_offset)

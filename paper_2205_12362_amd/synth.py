@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs for the ARTS search: quantised Stokes-I noise, injected bursts, the
+synthetic SB table and the workload configurations.
+
+This module holds no search arithmetic (no delay law, no dedispersion, no S/N): where a burst
+must follow a dispersion sweep, the caller passes the per-channel sample offsets.  It is the
+only code shared between the oracle-side tests and the GPU-side tests and benchmark.
+
+Stokes-I data are uint8, channel-major with time fastest (the TABF re-orders its output so the
+time index changes fastest; TABs are requantised to 8 bit with clipping, Appendix on data loads
+and requantisation).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+TSAMP = 81.92e-6          # s, native Stokes-I sample time (Sect. 4d)
+BAND_LO, BAND_HI = 1220.0, 1520.0   # MHz, 300 MHz band
+CHUNK = 12500             # new samples per 1.024 s chunk
+
+
+def band(nchan: int, lo: float = BAND_LO, hi: float = BAND_HI):
+    """(f_lo, df) for nchan channel centres evenly spanning [lo, hi] MHz, ascending."""
+    df = (hi - lo) / nchan
+    return lo + df / 2.0, df
+
+
+def _noise_lut(mean: float, sigma: float) -> np.ndarray:
+    """uint8 value for each of 65536 equiprobable uniform codes: clip(rint(mean + sigma*z))
+    with z the normal quantile at the code's centre, i.e. quantised N(mean, sigma) noise."""
+    k = (np.arange(65536, dtype=np.float64) + 0.5) / 65536.0
+    z = np.sqrt(2.0) * _erfinv(2.0 * k - 1.0)
+    return np.clip(np.rint(mean + sigma * z), 0, 255).astype(np.uint8)
+
+
+def _erfinv(y: np.ndarray) -> np.ndarray:
+    from scipy.special import erfinv
+    return erfinv(y)
+
+
+def _codes_to_float(codes: np.ndarray, mean: float, sigma: float) -> np.ndarray:
+    k = (codes.astype(np.float64) + 0.5) / 65536.0
+    return mean + sigma * np.sqrt(2.0) * _erfinv(2.0 * k - 1.0)
+
+
+@dataclass
+class Burst:
+    """A dispersed burst: per-channel arrival sample offsets (from the caller's delay law),
+    its profile width in samples and amplitude in counts per channel."""
+    arrival: np.ndarray          # int64 [nchan], absolute sample index of the burst per channel
+    width: float                 # FWHM (gaussian) or exact width (tophat), samples
+    amplitude: float             # counts per channel
+    kind: str = "gaussian"
+
+
+def noise(shape, seed: int, mean: float = 128.0, sigma: float = 16.0, bursts=(),
+          return_codes: bool = False):
+    """Quantised N(mean, sigma) noise of the given shape (last axis = time), uint8.
+
+    Gaussian bursts are added in floating point before rounding, so sub-count amplitudes are
+    dithered by the noise.  For multi-row shapes, each burst applies to rows [..., c, :] with
+    channel c = the second-to-last index, on every leading index (use shape [nchan][nsamp] to
+    target one beam)."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(s) for s in shape)
+    codes = rng.integers(0, 65536, size=shape, dtype=np.uint16)
+    out = _noise_lut(mean, sigma)[codes]
+    for b in bursts:
+        if b.kind != "gaussian":
+            raise ValueError("noise() takes gaussian bursts; use add_tophat for exact ones")
+        nsamp = shape[-1]
+        half = int(math.ceil(3.0 * b.width)) + 1
+        for c, a in enumerate(np.asarray(b.arrival, dtype=np.int64)):
+            lo, hi = max(0, a - half), min(nsamp, a + half + 1)
+            if lo >= hi:
+                continue
+            t = np.arange(lo, hi, dtype=np.float64)
+            prof = b.amplitude * np.exp(-4.0 * math.log(2.0) * ((t - a) / b.width) ** 2)
+            sl = (Ellipsis, c, slice(lo, hi))
+            x = _codes_to_float(codes[sl], mean, sigma) + prof
+            out[sl] = np.clip(np.rint(x), 0, 255).astype(np.uint8)
+    return (out, codes) if return_codes else out
+
+
+def add_tophat(data: np.ndarray, arrival, width: int, amplitude: int) -> np.ndarray:
+    """Add an integer top-hat of `width` samples and `amplitude` counts to channel c starting at
+    arrival[c] (data [nchan][nsamp] uint8, in place), clipping at 255.  Returns the int64 array
+    of what was actually added, so a test can account for clipping exactly."""
+    added = np.zeros(data.shape, dtype=np.int64)
+    for c, a in enumerate(np.asarray(arrival, dtype=np.int64)):
+        lo, hi = max(0, a), min(data.shape[-1], a + width)
+        if lo >= hi:
+            continue
+        old = data[c, lo:hi].astype(np.int64)
+        new = np.minimum(old + amplitude, 255)
+        data[c, lo:hi] = new.astype(np.uint8)
+        added[c, lo:hi] = new - old
+    return added
+
+
+def sb_table_synthetic(nsb: int = 71, ntab: int = 12, nchan: int = 1536) -> np.ndarray:
+    """Synthetic SB table: channel c of SB s takes TAB (s + floor(6 c (s - centre) / nchan))
+    mod ntab, centre = nsb // 2, in exact integer arithmetic (floor toward -inf, non-negative
+    mod).  The centre SB takes one TAB across the band; the edge SBs switch TAB most often."""
+    centre = nsb // 2
+    s = np.arange(nsb, dtype=np.int64)[:, None]
+    c = np.arange(nchan, dtype=np.int64)[None, :]
+    return np.mod(s + np.floor_divide(6 * c * (s - centre), nchan), ntab).astype(np.uint8)
+
+
+@dataclass
+class Workload:
+    """Shape and search parameters of one synthetic search request."""
+    name: str
+    nchan: int
+    f_lo: float
+    df: float
+    tsamp: float
+    dms: np.ndarray
+    widths: list
+    nbeam: int = 1
+    downsample: int = 1
+    threshold: float = 8.0
+    sigma: float = 16.0
+    seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+def cfg_small(seed: int = 1) -> Workload:
+    """1 beam, 128 channels over 1220-1520 MHz, 256 trials DM 0..127.5 step 0.5, widths
+    1..16, 16384 samples, threshold 8."""
+    f_lo, df = band(128)
+    return Workload("small-128ch-256dm", 128, f_lo, df, TSAMP,
+                    np.arange(256, dtype=np.float64) * 0.5, [1, 2, 4, 8, 16],
+                    seed=seed, extra={"nsamp": 16384})
+
+
+def cfg_apertif(seed: int = 2) -> Workload:
+    """1 beam, Apertif shape: 1536 channels, 2048 trials DM 0..2047, widths 1..256."""
+    f_lo, df = band(1536)
+    return Workload("apertif-1536ch-2048dm", 1536, f_lo, df, TSAMP,
+                    np.arange(2048, dtype=np.float64), [1 << k for k in range(9)], seed=seed)
+
+
+def cfg_apertif_ds(seed: int = 5) -> Workload:
+    """High-DM, time-downsampled trials of the serving stream: D = 4, DM 2048..4998 step 2
+    (1476 trials), widths 1..64 downsampled samples (4..256 native)."""
+    f_lo, df = band(1536)
+    return Workload("apertif-1536ch-ds4-1476dm", 1536, f_lo, df, TSAMP,
+                    np.arange(2048, 5000, 2, dtype=np.float64), [1 << k for k in range(7)],
+                    downsample=4, seed=seed)
+
+
+def uneven_requests(n: int = 64, seed: int = 4):
+    """Uneven batch: nchan in {384, 768, 1536}, 0.5-4 s long, DM ranges 0-500 / 0-2000 /
+    0-5000 with 512-4096 linearly spaced trials, noise sigma in [8, 24]."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        nchan = int(rng.choice([384, 768, 1536]))
+        f_lo, df = band(nchan)
+        nsamp = int(round(float(rng.uniform(0.5, 4.0)) / TSAMP))
+        dm_hi = float(rng.choice([500.0, 2000.0, 5000.0]))
+        ntrial = int(rng.integers(512, 4097))
+        sigma = float(rng.uniform(8.0, 24.0))
+        w = Workload(f"req{i}", nchan, f_lo, df, TSAMP, np.linspace(0.0, dm_hi, ntrial),
+                     [1 << k for k in range(9)], sigma=sigma, seed=1000 + i,
+                     extra={"nsamp": nsamp})
+        reqs.append(w)
+    return reqs

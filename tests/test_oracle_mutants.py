@@ -1,0 +1,178 @@
+"""Plant plausible mistakes in a copy of the oracle (on the CPU) and check that the pins catch
+each one: a pin set that a dropped term, flipped sign or shifted index survives would not pin
+anything."""
+import types
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.test_oracle_pins import ALL_CHECKS
+
+
+def _copy(**over):
+    ns = types.SimpleNamespace(**{k: getattr(O, k) for k in dir(O) if not k.startswith("_")})
+    for k, v in over.items():
+        setattr(ns, k, v)
+    # functions that call siblings must see the mutant, so rebind the composite ones
+    if "search" not in over:
+        def search(data, delays, widths, threshold, beam=0, nrep=None, t_offset=0):
+            x = ns.dedisperse(data, delays)
+            if nrep is None:
+                nrep = x.shape[1] - max(widths) + 1
+            return x, ns.candidates(x, widths, nrep, threshold, beam=beam, t_offset=t_offset)
+        ns.search = search
+    if "candidates" not in over:
+        ns.candidates = _candidates_using(ns)
+    return ns
+
+
+def _candidates_using(ns, first_peak=True):
+    def candidates(series, widths, nrep, threshold, beam=0, t_offset=0):
+        x = np.asarray(series).astype(np.int64)
+        mu, sigma = ns.moments(x, nrep)
+        out = []
+        for w in widths:
+            b = ns.boxcar(x, w, nrep)
+            s = ns.snr(b, w, mu, sigma)
+            for d in range(x.shape[0]):
+                above = s[d] > threshold
+                t = 0
+                while t < nrep:
+                    if not above[t]:
+                        t += 1
+                        continue
+                    e = t
+                    while e < nrep and above[e]:
+                        e += 1
+                    seg = b[d, t:e]
+                    k = t + (int(np.argmax(seg)) if first_peak
+                             else len(seg) - 1 - int(np.argmax(seg[::-1])))
+                    out.append((beam, d, int(w), k + t_offset, float(s[d, k])))
+                    t = e
+        out.sort(key=lambda r: (r[0], r[1], r[2], r[3]))
+        return out
+    return candidates
+
+
+def _delay_variant(ref="max", rounding=np.rint, use_ds=True):
+    def delay_table(nchan, f_lo_mhz, df_mhz, tsamp_s, dms, downsample=1, return_exact=False):
+        f = O.channel_freqs(nchan, f_lo_mhz, df_mhz)
+        dms = np.asarray(dms, dtype=np.float64)
+        if tsamp_s <= 0 or not np.all(np.isfinite(dms)) or np.any(dms < 0):
+            raise ValueError("bad args")
+        f_ref = f.max() if ref == "max" else f.min()
+        x = O.K_DM * dms[:, None] * (1 / (f * f) - 1 / (f_ref * f_ref))[None, :] / (
+            (downsample if use_ds else 1) * tsamp_s)
+        d = rounding(x).astype(np.int64)
+        return (d, x) if return_exact else d
+    return delay_table
+
+
+def _dedisperse_variant(kind):
+    def dedisperse(data, delays):
+        data = np.asarray(data).astype(np.int64)
+        delays = np.asarray(delays).astype(np.int64)
+        nchan, nsamp = data.shape
+        dmax = int(delays.max())
+        nout = nsamp - dmax - (1 if kind == "short" else 0)
+        if nout <= 0:
+            raise ValueError("short")
+        out = np.zeros((delays.shape[0], nout), dtype=np.int64)
+        for d in range(delays.shape[0]):
+            for c in range(nchan - (1 if kind == "dropchan" else 0)):
+                s = delays[d, c] if kind != "negdelay" else dmax - delays[d, c]
+                out[d] += data[c, s: s + nout]
+        return out
+    return dedisperse
+
+
+def _shift_back(series, width, nrep):
+    # window [t - w + 1, t] instead of [t, t + w - 1]
+    x = np.asarray(series).astype(np.int64)
+    if width < 1 or nrep + width - 1 > x.shape[-1]:
+        raise ValueError("bad")
+    out = np.zeros(x.shape[:-1] + (nrep,), np.int64)
+    for t in range(nrep):
+        out[..., t] = x[..., max(0, t - width + 1): t + 1].sum(axis=-1)
+    return out
+
+
+def _boxcar_short(series, width, nrep):
+    x = np.asarray(series).astype(np.int64)
+    if width < 1 or nrep + width - 1 > x.shape[-1]:
+        raise ValueError("bad")
+    out = x[..., 0:nrep].copy()
+    for j in range(1, width - 1):
+        out += x[..., j: j + nrep]
+    return out
+
+
+def _moments_ddof1(series, nrep):
+    x = np.asarray(series)[..., :nrep].astype(np.float64)
+    return x.mean(axis=-1), x.std(axis=-1, ddof=1)
+
+
+def _snr_linear(box, width, mu, sigma):
+    mu = np.asarray(mu, dtype=np.float64)[..., None]
+    sigma = np.asarray(sigma, dtype=np.float64)[..., None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = (np.asarray(box, np.float64) - width * mu) / (sigma * width)
+    return np.where(sigma > 0, s, 0.0)
+
+
+def _downsample_mean(data, factor):
+    a = np.asarray(data).astype(np.int64)
+    n = a.shape[-1] // factor
+    return a[..., : n * factor].reshape(a.shape[:-1] + (n, factor)).mean(axis=-1).astype(np.int64)
+
+
+def _sb_transposed(tab, sb_table):
+    tab = np.asarray(tab)
+    t = np.asarray(sb_table)
+    out = np.empty((t.shape[0], tab.shape[1], tab.shape[2]), dtype=tab.dtype)
+    for s in range(t.shape[0]):
+        for c in range(tab.shape[1]):
+            out[s, c] = tab[t[s, c], (c + 1) % tab.shape[1]]
+    return out
+
+
+MUTANTS = {
+    "reference at lowest channel": dict(delay_table=_delay_variant(ref="min")),
+    "floor instead of round": dict(delay_table=_delay_variant(rounding=np.floor)),
+    "downsample ignored in delays": dict(delay_table=_delay_variant(use_ds=False)),
+    "delay sign flipped": dict(dedisperse=_dedisperse_variant("negdelay")),
+    "last channel dropped": dict(dedisperse=_dedisperse_variant("dropchan")),
+    "output one sample short": dict(dedisperse=_dedisperse_variant("short")),
+    "boxcar trailing window": dict(boxcar=_shift_back),
+    "boxcar one term short": dict(boxcar=_boxcar_short),
+    "sample variance": dict(moments=_moments_ddof1),
+    "S/N scaled by w not sqrt(w)": dict(snr=_snr_linear),
+    "downsample mean": dict(downsample=_downsample_mean),
+    "SB channel index shifted": dict(sb_synthesize=_sb_transposed),
+}
+
+
+def _run_all(ns):
+    failed = []
+    for chk in ALL_CHECKS:
+        try:
+            chk(ns)
+        except (AssertionError, ValueError, IndexError):
+            failed.append(chk.__name__)
+    return failed
+
+
+def test_unmutated_copy_passes():
+    assert _run_all(_copy()) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name):
+    assert _run_all(_copy(**MUTANTS[name])), f"no pin catches: {name}"
+
+
+def test_last_peak_mutant_is_caught():
+    ns = _copy()
+    ns.candidates = _candidates_using(ns, first_peak=False)
+    assert _run_all(ns), "no pin catches a latest-peak rule"

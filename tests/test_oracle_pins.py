@@ -1,0 +1,399 @@
+"""Pins for the CPU oracle: closed forms, invariants, hand-worked fixtures and brute force on
+tiny inputs -- none of them re-types the oracle's own expressions.  Each `check_*` takes the
+oracle module so `test_oracle_mutants.py` can run the same pins against planted mistakes."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2205_12362_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _tiny_plan(o, nchan=7, ndm=6, seed=0):
+    f_lo, df = synth.band(nchan)
+    dms = np.linspace(0.0, 40.0, ndm)
+    return o.delay_table(nchan, f_lo, df, 1e-3, dms)
+
+
+def _tiny_data(nchan=7, nsamp=96, seed=0):
+    return np.random.default_rng(seed).integers(0, 256, size=(nchan, nsamp), dtype=np.uint8)
+
+
+# ---------------------------------------------------------------- delay table
+def check_delays_textbook(o):
+    for case in _load("delays_textbook.json")["cases"]:
+        got = o.delay_table(case["nchan"], case["f_lo"], case["df"], case["tsamp"], case["dms"])
+        assert got.tolist() == case["delays"], case["note"]
+
+
+def check_delay_invariants(o):
+    f_lo, df = synth.band(64)
+    dms = np.array([0.0, 3.0, 6.0, 50.0, 100.0, 2000.0])
+    d, x = o.delay_table(64, f_lo, df, synth.TSAMP, dms, return_exact=True)
+    assert np.all(d[0] == 0)                       # DM 0: no delay
+    assert np.all(d[:, -1] == 0)                   # highest channel is the reference
+    assert np.all(np.diff(d, axis=1) <= 0)         # lower frequency arrives later
+    assert np.all(np.diff(d, axis=0) >= 0)         # delay grows with DM
+    assert np.allclose(x[2], 2.0 * x[1], rtol=1e-14)          # linear in DM
+    assert np.allclose(x[4], 2.0 * x[3], rtol=1e-14)
+    # halving the sample time doubles the unrounded delay; downsampling by D divides it by D
+    _, x2 = o.delay_table(64, f_lo, df, synth.TSAMP / 2, dms, return_exact=True)
+    assert np.allclose(x2, 2.0 * x, rtol=1e-14)
+    _, x4 = o.delay_table(64, f_lo, df, synth.TSAMP, dms, downsample=4, return_exact=True)
+    assert np.allclose(4.0 * x4, x, rtol=1e-14)
+    # rounding: every delay is within half a sample of the exact value
+    assert np.all(np.abs(d - x) <= 0.5)
+    # descending channel order gives the same delays, reversed along channels
+    f_hi = f_lo + 63 * df
+    dr = o.delay_table(64, f_hi, -df, synth.TSAMP, dms)
+    assert np.array_equal(dr, d[:, ::-1])
+
+
+def check_delay_apertif_span(o):
+    # Across the 300 MHz band (1220-1520 MHz) the sweep is 4.148808 ms * (1/1.22^2 - 1/1.52^2)
+    # = 0.99 ms per DM unit, i.e. about 12.1 samples of 81.92 us: DM 2047 spans ~24 770 samples
+    # between the band edges; channel centres sit half a channel inside the edges.
+    f_lo, df = synth.band(1536)
+    d = o.delay_table(1536, f_lo, df, synth.TSAMP, [2047.0])
+    edge = 4.148808e-3 * 2047 * (1 / 1.22 ** 2 - 1 / 1.52 ** 2) / synth.TSAMP
+    assert d[0, 0] < edge and d[0, 0] > edge - 2 * 12.1 * 2047 * df / 300.0
+    assert d.max() == d[0, 0]
+
+
+def test_delays_textbook():
+    check_delays_textbook(O)
+
+
+def test_delay_invariants():
+    check_delay_invariants(O)
+
+
+def test_delay_apertif_span():
+    check_delay_apertif_span(O)
+
+
+def test_tie_audit():
+    assert O.tie_audit(np.array([0.0, 1.25, 2.5])) == 0.0
+    assert abs(O.tie_audit(np.array([0.1, 3.9])) - 0.4) < 1e-12
+    # the synthetic plans used here sit far from rounding ties compared with FP64 noise
+    for w in (synth.cfg_small(), synth.cfg_apertif(), synth.cfg_apertif_ds()):
+        _, x = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms, w.downsample,
+                             return_exact=True)
+        # a few ulps of FP64 at the largest delay bound any evaluation-order difference
+        assert O.tie_audit(x) > 64 * np.finfo(np.float64).eps * max(1.0, float(x.max()))
+
+
+def test_delay_rejects_bad_args():
+    with pytest.raises(ValueError):
+        O.delay_table(4, 1400.0, 1.0, 0.0, [1.0])
+    with pytest.raises(ValueError):
+        O.delay_table(4, 1400.0, 1.0, 1e-3, [-1.0])
+    with pytest.raises(ValueError):
+        O.delay_table(4, 1400.0, 1.0, 1e-3, [float("nan")])
+
+
+# ---------------------------------------------------------------- dedispersion
+def check_zero_dm(o):
+    data = _tiny_data()
+    f_lo, df = synth.band(7)
+    delays = o.delay_table(7, f_lo, df, 1e-3, [0.0, 30.0])
+    x = o.dedisperse(data, delays)
+    nout = data.shape[1] - int(delays.max())
+    assert x.shape == (2, nout)
+    assert np.array_equal(x[0], data.astype(np.int64).sum(axis=0)[:nout])
+
+
+def check_impulse(o):
+    delays = _tiny_plan(o)
+    nchan, nsamp = 7, 96
+    nout = nsamp - int(delays.max())
+    for c0, s0, v in [(0, 60, 5), (3, 40, 255), (6, 10, 1)]:
+        data = np.zeros((nchan, nsamp), dtype=np.uint8)
+        data[c0, s0] = v
+        x = o.dedisperse(data, delays)
+        for d in range(delays.shape[0]):
+            t = s0 - int(delays[d, c0])
+            expect = np.zeros(nout, dtype=np.int64)
+            if 0 <= t < nout:
+                expect[t] = v
+            assert np.array_equal(x[d], expect), (c0, s0, d)
+
+
+def check_sum_conservation(o):
+    data = _tiny_data(seed=3)
+    delays = _tiny_plan(o)
+    x = o.dedisperse(data, delays)
+    nout = x.shape[1]
+    for d in range(delays.shape[0]):
+        tot = sum(int(data[c, delays[d, c]: delays[d, c] + nout].astype(np.int64).sum())
+                  for c in range(data.shape[0]))
+        assert int(x[d].sum()) == tot
+
+
+def check_brute_force(o):
+    # explicit loops over (d, t, c) on a random tiny case
+    rng = np.random.default_rng(11)
+    for trial in range(3):
+        nchan, nsamp, ndm = int(rng.integers(1, 9)), int(rng.integers(40, 65)), int(rng.integers(1, 7))
+        data = rng.integers(0, 256, size=(nchan, nsamp), dtype=np.uint8)
+        delays = rng.integers(0, 20, size=(ndm, nchan))
+        x = o.dedisperse(data, delays)
+        nout = nsamp - int(delays.max())
+        ref = np.zeros((ndm, nout), dtype=np.int64)
+        for d in range(ndm):
+            for t in range(nout):
+                acc = 0
+                for c in range(nchan):
+                    acc += int(data[c][t + delays[d][c]])
+                ref[d][t] = acc
+        assert np.array_equal(x, ref)
+        for d in range(ndm):
+            for t in (0, nout - 1):
+                assert o.dedisperse_at(data, delays, d, t) == ref[d][t]
+
+
+def check_linearity_shift_permutation(o):
+    a, b = _tiny_data(seed=4), _tiny_data(seed=5)
+    delays = _tiny_plan(o)
+    xa, xb = o.dedisperse(a, delays), o.dedisperse(b, delays)
+    xab = o.dedisperse(a.astype(np.int64) + b.astype(np.int64), delays)
+    assert np.array_equal(xab, xa + xb)
+    k = 9                                                   # time-shift equivariance
+    xs = o.dedisperse(a[:, k:], delays)
+    assert np.array_equal(xs, xa[:, k:])
+    perm = np.random.default_rng(6).permutation(a.shape[0])  # channel order is irrelevant
+    assert np.array_equal(o.dedisperse(a[perm], delays[:, perm]), xa)
+
+
+def check_chunked_stream(o):
+    # streaming: each chunk carries the previous halo samples; outputs concatenate to one shot
+    data = _tiny_data(nsamp=160, seed=7)
+    delays = _tiny_plan(o)
+    halo = int(delays.max())
+    full = o.dedisperse(data, delays)
+    new = 25
+    parts = []
+    for s in range(0, full.shape[1], new):
+        e = min(s + new, full.shape[1])
+        parts.append(o.dedisperse(data[:, s: e + halo], delays))
+    assert np.array_equal(np.concatenate(parts, axis=1), full)
+
+
+def check_tophat_exact(o):
+    # an integer top-hat injected along the trial-d sweep adds exactly A*w*nchan to B_w at the
+    # injection time (minus whatever clipping removed, which the injector reports)
+    w = synth.cfg_small()
+    nsamp = 4096
+    delays = o.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    data = synth.noise((w.nchan, nsamp), seed=21)
+    base = o.dedisperse(data, delays)
+    d0, t0, width, amp = 140, 1500, 8, 5
+    added = synth.add_tophat(data, t0 + delays[d0], width, amp)
+    x = o.dedisperse(data, delays)
+    nrep = x.shape[1] - 16 + 1
+    bx = o.boxcar(x, width, nrep)
+    bb = o.boxcar(base, width, nrep)
+    assert bx[d0, t0] - bb[d0, t0] == int(added.sum()) == amp * width * w.nchan
+    # the series changes only where some channel overlaps the top-hat
+    assert np.array_equal(x[d0, :t0], base[d0, :t0])
+
+
+def test_zero_dm():
+    check_zero_dm(O)
+
+
+def test_impulse():
+    check_impulse(O)
+
+
+def test_sum_conservation():
+    check_sum_conservation(O)
+
+
+def test_brute_force():
+    check_brute_force(O)
+
+
+def test_linearity_shift_permutation():
+    check_linearity_shift_permutation(O)
+
+
+def test_chunked_stream():
+    check_chunked_stream(O)
+
+
+def test_tophat_exact():
+    check_tophat_exact(O)
+
+
+def test_dedisperse_rejects_short_input():
+    with pytest.raises(ValueError):
+        O.dedisperse(np.zeros((2, 5), np.uint8), np.array([[0, 5]]))
+
+
+# ---------------------------------------------------------------- downsampling, SB synthesis
+def check_downsample(o):
+    ramp = np.arange(23, dtype=np.int64)[None, :]
+    for D in (1, 2, 4, 5):
+        y = o.downsample(ramp, D)
+        n = 23 // D
+        t = np.arange(n)
+        assert y.shape == (1, n)
+        assert np.array_equal(y[0], D * D * t + D * (D - 1) // 2)   # sum_{j<D} (D t + j)
+    assert np.array_equal(o.downsample(np.full((2, 9), 255, np.uint8), 4), np.full((2, 2), 1020))
+
+
+def check_sb_synth(o):
+    rng = np.random.default_rng(8)
+    tab = rng.integers(0, 256, size=(12, 16, 40), dtype=np.uint8)
+    for j in (0, 5, 11):
+        sb = o.sb_synthesize(tab, np.full((1, 16), j))
+        assert np.array_equal(sb[0], tab[j])
+    table = synth.sb_table_synthetic(71, 12, 16)
+    sb = o.sb_synthesize(tab, table)
+    assert np.array_equal(sb[35], tab[11])                 # centre SB: one TAB, all channels
+    c = 9
+    assert np.array_equal(sb[0, c], tab[table[0, c], c])
+    assert np.array_equal(sb[70, 3], tab[table[70, 3], 3])
+
+
+def test_downsample():
+    check_downsample(O)
+
+
+def test_sb_synth():
+    check_sb_synth(O)
+
+
+# ---------------------------------------------------------------- boxcar / moments / S/N
+def check_boxcar(o):
+    x = np.random.default_rng(9).integers(-50, 400, size=(3, 70))
+    assert np.array_equal(o.boxcar(x, 1, 70), x)
+    for w in (1, 2, 4, 8, 16):
+        n = 70 - 2 * w + 1
+        b, b2 = o.boxcar(x, w, n + w), o.boxcar(x, 2 * w, n)
+        assert np.array_equal(b2, b[:, :n] + b[:, w: w + n])    # doubling identity
+    ramp = np.arange(40, dtype=np.int64)
+    for w in (1, 3, 8):
+        t = np.arange(40 - w + 1)
+        assert np.array_equal(o.boxcar(ramp, w, 40 - w + 1), w * t + w * (w - 1) // 2)
+    with pytest.raises(ValueError):
+        o.boxcar(ramp, 8, 34)
+
+
+def check_moments(o):
+    n = 1000
+    ramp = np.arange(n + 17, dtype=np.int64)
+    mu, sig = o.moments(ramp, n)
+    assert abs(mu - (n - 1) / 2) < 1e-9
+    assert abs(sig - math.sqrt((n * n - 1) / 12.0)) < 1e-9   # population, not sample, variance
+    mu, sig = o.moments(np.full(50, 7), 40)
+    assert mu == 7.0 and sig == 0.0
+
+
+def check_snr_noise(o):
+    # pure quantised N(128, 16) noise, 128 channels: S/N of every boxcar has mean ~0, std ~1;
+    # the dedispersed series has sigma ~ 16 sqrt(128) = 181
+    w = synth.cfg_small()
+    delays = o.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms[::16])
+    data = synth.noise((w.nchan, 8192), seed=31)
+    x = o.dedisperse(data, delays)
+    nrep = x.shape[1] - 15
+    mu, sig = o.moments(x, nrep)
+    assert np.all(np.abs(sig / (16 * math.sqrt(128)) - 1) < 0.05)
+    for width in (1, 4, 16):
+        s = o.snr(o.boxcar(x, width, nrep), width, mu, sig)
+        assert abs(s.mean()) < 0.05
+        assert abs(s.std() - 1) < 0.05 + 0.02 * width
+    assert np.all(o.snr(np.ones((1, 5)), 4, [1.0], [0.0]) == 0)
+
+
+def check_candidates_golden(o):
+    g = _load("candidates_tiny.json")
+    x = np.array([g["series"]])
+    mu, sig = o.moments(x, g["nrep"])
+    assert abs(mu[0] - g["mean"]) < 1e-12 and abs(sig[0] - g["sigma"]) < 1e-12
+    got = o.candidates(x, g["widths"], g["nrep"], g["threshold"])
+    assert [c[:4] for c in got] == [tuple(c[:4]) for c in g["candidates"]]
+    for c, e in zip(got, g["candidates"]):
+        assert abs(c[4] - e[4]) < 1e-9
+    assert o.candidates(x, g["widths"], g["nrep"], 5.0) == []
+
+
+def check_injected_recovery(o):
+    # three dispersed gaussian bursts at DM 30 / 70 / 110 (on-grid), FWHM 2..8, 3 sigma/channel
+    w = synth.cfg_small()
+    delays = o.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    nsamp = 16384
+    bursts = []
+    for dm, t0, fwhm in [(30.0, 3000, 2.0), (70.0, 8000, 4.0), (110.0, 12500, 8.0)]:
+        d = int(np.argmin(np.abs(w.dms - dm)))
+        bursts.append((d, t0, fwhm, synth.Burst(t0 + delays[d], fwhm, 48.0)))
+    data = synth.noise((w.nchan, nsamp), seed=w.seed, bursts=[b[3] for b in bursts])
+    x, cands = o.search(data, delays, w.widths, w.threshold)
+    assert cands, "no candidates"
+    for d, t0, fwhm, _ in bursts:
+        near = [c for c in cands if abs(c[3] - t0) <= 16]
+        assert near, (d, t0)
+        best = max(near, key=lambda c: c[4])
+        assert abs(best[1] - d) <= 1                      # detected at its DM trial
+        assert fwhm / 2 <= best[2] * 1.0 <= 2 * fwhm + 1  # best width near the pulse width
+    # nothing far from the bursts
+    assert all(min(abs(c[3] - b[1]) for b in bursts) < 400 for c in cands)
+
+
+def check_tophat_snr(o):
+    # S/N of an exact top-hat at matched DM and width ~ A w nchan / (sigma sqrt w)
+    w = synth.cfg_small()
+    delays = o.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    data = synth.noise((w.nchan, 16384), seed=41)
+    d0, t0, width, amp = 100, 7000, 4, 6
+    synth.add_tophat(data, t0 + delays[d0], width, amp)
+    x = o.dedisperse(data, delays)
+    nrep = x.shape[1] - 15
+    mu, sig = o.moments(x, nrep)
+    s = o.snr(o.boxcar(x[d0:d0 + 1], width, nrep), width, mu[d0:d0 + 1], sig[d0:d0 + 1])
+    expect = amp * width * w.nchan / (sig[d0] * math.sqrt(width))
+    assert abs(s[0, t0] - expect) < 4.0            # noise of one S/N sample is ~1
+    assert s[0, t0] > 8
+
+
+def test_boxcar():
+    check_boxcar(O)
+
+
+def test_moments():
+    check_moments(O)
+
+
+def test_snr_noise():
+    check_snr_noise(O)
+
+
+def test_candidates_golden():
+    check_candidates_golden(O)
+
+
+def test_injected_recovery():
+    check_injected_recovery(O)
+
+
+def test_tophat_snr():
+    check_tophat_snr(O)
+
+
+ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif_span,
+              check_zero_dm, check_impulse, check_sum_conservation, check_brute_force,
+              check_linearity_shift_permutation, check_chunked_stream, check_tophat_exact,
+              check_downsample, check_sb_synth, check_boxcar, check_moments, check_snr_noise,
+              check_candidates_golden, check_injected_recovery, check_tophat_snr]
