@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the search hot path on one MI355X.
+
+One step = one 1.024 s chunk (12 500 new samples) of the serving stream: 12 TABs x 1536
+channels arrive; 71 synthesized beams are formed from them on the fly; each SB is dedispersed
+over 2048 trials (DM 0..2047, native 81.92 us) and 1476 time-downsampled trials (D = 4,
+DM 2048..4998 step 2); boxcars 1..256 native / 1..64 downsampled samples; per-series S/N and
+threshold-8 candidates.  The overlap (halo) stays on the device between steps.  Inputs are
+resident in HBM before the timed region; each step copies its chunk from a device pool.
+
+Prints ONE JSON line.  Metric: DM-trial samples per second (reported samples, all SBs, both
+trial sets); also the real-time factor and chunk latency percentiles.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+CHUNK = 12500
+NTAB, NSB, NCHAN = 12, 71, 1536
+THRESHOLD = 8.0
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  Exact integer adds: one 32-bit add per lane
+# per clock (v_add_u32), two with packed 16-bit adds (v_pk_add_u16).
+PEAK_INT32_ADDS = 256 * 64 * 2.4e9
+PEAK_PK16_ADDS = 2 * PEAK_INT32_ADDS
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def _oracle_rows(args):
+    """cpu_baseline worker: the oracle's dedispersion + boxcar/S/N/candidates on DM rows (the
+    last row is padding that fixes the output length, see cpu_baseline)."""
+    import oracle as O
+    beam, delays, widths, nrep, thr = args
+    x = O.dedisperse(beam, delays)[:-1]
+    O.candidates(x, widths, nrep, thr)
+    return x.shape[0]
+
+
+def cpu_baseline(beam, w_native):
+    """Time the CPU oracle on a bounded sample of the same workload: one beam of the chunk
+    (1536 channels, 12500 new samples plus the overlap), every 8th native DM trial, all widths,
+    parallelised over DM blocks on the host cores."""
+    import multiprocessing as mp
+
+    import oracle as O
+    delays = O.delay_table(w_native.nchan, w_native.f_lo, w_native.df, w_native.tsamp,
+                           w_native.dms)
+    dmax = int(delays.max())
+    rows = np.arange(0, delays.shape[0], 8)
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    jobs = []
+    for b in np.array_split(rows, cores):
+        if len(b):
+            # a padding trial with the table's largest delay keeps the output length (and so
+            # the reported window) equal to the full plan's
+            pad = np.zeros((1, delays.shape[1]), dtype=delays.dtype)
+            pad[0, 0] = dmax
+            jobs.append((beam, np.concatenate([delays[b], pad]), w_native.widths, CHUNK,
+                         THRESHOLD))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        done = sum(pool.map(_oracle_rows, jobs))
+    dt = time.perf_counter() - t0
+    return {"value": done * CHUNK / dt, "unit": "DM-trial samples/s", "cores": cores,
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"one beam of one chunk (1536 ch, 12500 reported samples), {done} of the "
+                      f"2048 native DM trials (every 8th), widths 1-256, threshold 8: "
+                      f"{dt:.1f} s wall on {cores} processes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--graph", action="store_true", help="replay each step as a hipGraph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", type=int, default=None, help="native dedispersion tiling")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
+              "design note, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2205_12362_amd.arts as arts
+    from paper_2205_12362_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w_nat = synth.cfg_apertif()
+    w_ds = synth.cfg_apertif_ds()
+    p_nat = arts.Plan.from_workload(w_nat)
+    p_ds = arts.Plan.from_workload(w_ds)
+    if args.variant is not None:
+        p_nat.set_tiling(args.variant)
+    table = synth.sb_table_synthetic(NSB, NTAB, NCHAN)
+
+    log("generating inputs ...")
+    t0 = time.perf_counter()
+    # two distinct noise chunks; bursts in TAB 11 (which SB 35 sees across the whole band)
+    delays = p_nat.delays()
+    pool = []
+    for k in range(2):
+        chunk = synth.noise((NTAB, NCHAN, CHUNK), seed=500 + k)
+        rng = np.random.default_rng(600 + k)
+        for _ in range(4):
+            d = int(rng.integers(100, 2000))
+            t = int(rng.integers(0, CHUNK - 300))
+            synth.add_tophat(chunk[11], t + delays[d] - int(delays[d].max()), 16, 6)
+        pool.append(torch.from_numpy(chunk).cuda())
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s")
+    tbl = torch.from_numpy(table).cuda()
+
+    stream = arts.Stream([p_nat, p_ds], NTAB, CHUNK, THRESHOLD, sb_table=tbl, nbeam=NSB,
+                         cand_capacity=1 << 20, graph=args.graph, profile=not args.graph)
+    info = stream.info()
+    cur = torch.cuda.current_stream()
+
+    def step(k):
+        stream.push(pool[k % 2], stream=cur)
+        return stream.wait()
+
+    for k in range(args.warmup):
+        step(k)
+        log(f"warmup {k + 1}/{args.warmup}")
+    base_ms = {ph: stream.timing(ph) for ph in range(4)} if not args.graph else None
+    torch.cuda.synchronize()
+    lat = []
+    ncand = 0
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        t1 = time.perf_counter()
+        c, _ = step(args.warmup + k)
+        lat.append(time.perf_counter() - t1)
+        ncand += len(c)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+
+    ms_step = 1e3 * elapsed / args.steps
+    units_nat = NSB * w_nat.dms.size * CHUNK
+    units_ds = NSB * w_ds.dms.size * (CHUNK // 4)
+    value = (units_nat + units_ds) * args.steps / elapsed
+
+    # dominant kernel: native dedispersion (phase 1), timed by events on its own stream
+    roofline = None
+    phases = None
+    if not args.graph:
+        phases = {}
+        names = ["ring_advance", "dedisperse_native", "dedisperse_ds4", "stats_candidates"]
+        for ph, name in enumerate(names):
+            ms, n = stream.timing(ph)
+            ms0, n0 = base_ms[ph]
+            phases[name] = (ms - ms0) / max(1, n - n0)
+        L_nat = CHUNK + max(w_nat.widths) - 1
+        adds = NSB * w_nat.dms.size * L_nat * NCHAN        # algorithmic adds per launch
+        dur = phases["dedisperse_native"] * 1e-3
+        achieved = adds / dur
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_PK16_ADDS / 1e12,
+                    "unit": "Tadd/s", "frac": achieved / PEAK_PK16_ADDS,
+                    "frac_int32_peak": achieved / PEAK_INT32_ADDS, "traffic": None,
+                    "kernel": "dedisperse_kernel<4,5,4,8>",
+                    "kernel_ms": phases["dedisperse_native"],
+                    "adds_per_launch": adds}
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": "DM-trial samples/s",
+        "value": value,
+        "unit": "DM-trial samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "serving stream chunk: 12 TABs x 1536 ch (1220-1520 MHz, "
+                               "81.92 us) -> 71 SBs; 2048 DMs 0-2047 + 1476 D=4 DMs 2048-4998; "
+                               "widths 1-256; 12500 new samples per step",
+                   "nchan": NCHAN, "nsb": NSB, "ntab": NTAB, "chunk": CHUNK,
+                   "ndm_native": int(w_nat.dms.size), "ndm_ds4": int(w_ds.dms.size),
+                   "graph": bool(args.graph), "threshold": THRESHOLD,
+                   "device_bytes": info["device_bytes"]},
+        "adds_per_s": (units_nat + units_ds) * NCHAN * args.steps / elapsed,
+        "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
+        "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                             "p99": float(np.percentile(lat_ms, 99)),
+                             "max": float(lat_ms.max())},
+        "candidates_per_step": ncand / args.steps,
+        "phases_ms": phases,
+        "roofline": roofline,
+    }
+    stream.close()
+    del pool
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle ...")
+        beam = synth.noise((NCHAN, CHUNK + p_nat.halo), seed=777)
+        out["cpu_baseline"] = cpu_baseline(beam, w_nat)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

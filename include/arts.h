@@ -1,0 +1,251 @@
+/*
+ * arts.h -- C ABI of the MI355X (gfx950) single-pulse search library, libarts.so.
+ *
+ * The library implements the data-parallel hot path of the Apertif Radio Transient System's
+ * real-time search (van Leeuwen et al., arXiv:2205.12362, Sect. 6b.2 "AMBER"): synthesized-beam
+ * formation from tied-array beams, brute-force incoherent dedispersion over DM trials,
+ * optional time downsampling, boxcar matched filtering, S/N normalisation and threshold
+ * candidate extraction.
+ *
+ * Conventions shared by every entry point:
+ *  - Filterbank data are uint8 Stokes-I samples, channel-major with time fastest, i.e. a beam is
+ *    [nchan][nsamp] and a set of beams is [nbeam][nchan][nsamp] contiguous (the TABF re-orders
+ *    its output so that time is the fastest index, Appendix "Data loads"; samples are 8 bit,
+ *    Appendix "Requantization in the TABF").
+ *  - Every data pointer is DEVICE memory owned by the caller (e.g. a torch tensor's data_ptr());
+ *    the library never frees it.  A plan owns only its own tables and workspace.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are asynchronous on it unless
+ *    stated otherwise; the caller must keep buffers alive until the stream has passed them.
+ *  - Return value: ARTS_OK (0) or a negative status; arts_strerror() names it and
+ *    arts_last_error() gives the message of the last failure on the calling thread.  No C++
+ *    exception and no abort crosses this boundary.
+ *  - Integer results (delays, dedispersed series, boxcar sums, candidate positions) are exact.
+ */
+#ifndef ARTS_H
+#define ARTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum arts_status {
+  ARTS_OK = 0,
+  ARTS_E_INVAL = -1,    /* an argument is out of range or inconsistent                       */
+  ARTS_E_SHAPE = -2,    /* input shorter than the plan's halo (no complete output sample)    */
+  ARTS_E_NOMEM = -3,    /* a device or host allocation failed                                */
+  ARTS_E_DEVICE = -4,   /* a HIP runtime call or kernel launch failed                        */
+  ARTS_E_CAPACITY = -5, /* candidate buffer too small; *count holds the number required      */
+  ARTS_E_BUDGET = -6,   /* admission refused: the request does not fit the HBM budget        */
+  ARTS_E_STATE = -7     /* call not valid in the object's current state                      */
+};
+
+typedef struct arts_plan_s* arts_plan_t;
+
+/* One threshold candidate (32 bytes).  The paper's real-time candidates carry beam number,
+ * downsampling factor, arrival time, width, DM and S/N (Sect. 6b.1, "Real-time analysis").
+ *   sample     : start of the boxcar window, in (downsampled) samples, plus the caller's t_offset
+ *   beam       : beam (or synthesized beam) index within the call, plus the caller's beam_offset
+ *   dm_index   : index into the plan's DM list;  dm: that DM (pc cm^-3) as float
+ *   width      : boxcar width in (downsampled) samples;  downsample: the plan's factor D
+ *   snr        : (B_w - w mu) / (sigma sqrt(w)), FP32, see arts_boxcar_snr                   */
+typedef struct arts_candidate {
+  int64_t sample;
+  int32_t beam;
+  int32_t dm_index;
+  int32_t width;
+  int32_t downsample;
+  float snr;
+  float dm;
+} arts_candidate;
+
+/* ------------------------------------------------------------------------------ plans ---- */
+
+/* Host only (no device call): the plan's delay table.
+ * Dedispersion shifts each channel by the delay of the trial DM (Sect. 6b.2, "Dedispersion").
+ * Channel c has centre frequency f_c = f_lo_mhz + c * df_mhz; the reference is the highest
+ * f_c.  delay[d][c] = round_half_even( 4.148808e3 * dm[d] * (1/f_c^2 - 1/f_ref^2)
+ *                                      / (downsample * tsamp_s) )   in FP64.
+ * delays_out: host int32 [ndm][nchan].  tie_margin_out (nullable): smallest distance of any
+ * unrounded delay from a rounding tie, so callers can confirm the table is well defined.
+ * Errors: ARTS_E_INVAL for nchan < 1, df == 0, tsamp <= 0, downsample < 1, ndm < 1, a DM
+ * that is negative or not finite, a channel frequency <= 0, or a delay above 2^30.          */
+int arts_delay_table(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp_s,
+                     const double* dm_list, int32_t ndm, int32_t downsample,
+                     int32_t* delays_out, double* tie_margin_out);
+
+/* Create a search plan on the current HIP device: validates the arguments (as above; widths
+ * must be strictly increasing and >= 1), computes the FP64 delay table, and uploads it with the
+ * tiling tables of the dedispersion kernel.  dm_list [ndm] and widths [nwidth] are host arrays,
+ * copied.  The boxcar widths are the integration trials (Sect. 6b.2, "Integration").
+ * *out receives the plan; destroy it with arts_plan_destroy.  Errors: ARTS_E_INVAL,
+ * ARTS_E_NOMEM, ARTS_E_DEVICE.                                                              */
+int arts_plan_create(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp_s,
+                     const double* dm_list, int32_t ndm, const int32_t* widths, int32_t nwidth,
+                     arts_plan_t* out);
+
+/* As arts_plan_create, with time downsampling by an integer factor D >= 1 (Sect. 6b.2,
+ * "Downsampling": a lower time resolution for high DMs).  Input stays native-rate uint8; the
+ * kernels sum D consecutive samples (dropping a trailing partial group), delays use D*tsamp
+ * and widths and output samples are in downsampled units.  D <= 257 keeps sums in 16 bits.   */
+int arts_plan_create_ds(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp_s,
+                        const double* dm_list, int32_t ndm, const int32_t* widths,
+                        int32_t nwidth, int32_t downsample, arts_plan_t* out);
+
+/* Release the plan's device tables and workspace.  NULL is ignored.  The caller must make
+ * sure no stream still uses the plan.                                                      */
+void arts_plan_destroy(arts_plan_t plan);
+
+/* Plan geometry.  max_delay: largest delay in the table (downsampled samples).  halo =
+ * max_delay + wmax - 1: an input of nin native samples yields L = nin/D - max_delay
+ * dedispersed samples and nrep = nin/D - halo reported (boxcar start) samples.  Any pointer
+ * may be NULL.                                                                              */
+int arts_plan_info(arts_plan_t plan, int32_t* nchan, int32_t* ndm, int32_t* nwidth,
+                   int32_t* downsample, int32_t* max_delay, int32_t* halo);
+
+/* Copy the plan's delay table to host memory int32 [ndm][nchan] (for parity checks).        */
+int arts_plan_delays(arts_plan_t plan, int32_t* host_out);
+
+/* Dedispersion tiling.  variant indexes the compiled kernel shapes listed by
+ * arts_tiling_count / arts_tiling_describe; dm_per_block is implied by the variant.  Changing
+ * it rebuilds the plan's tiling tables (device allocation).  The autotuner calls this.        */
+int arts_plan_set_tiling(arts_plan_t plan, int32_t variant);
+int arts_plan_get_tiling(arts_plan_t plan, int32_t* variant);
+int32_t arts_tiling_count(void);
+/* Writes "J=<dwords per lane> ACC=<DMs per wave> WAVES=<waves per block> SPD=<samples per
+ * dword>" for a variant into buf (NUL-terminated, at most len bytes).                       */
+int arts_tiling_describe(int32_t variant, char* buf, int32_t len);
+
+/* ------------------------------------------------------------------------ hot path ---- */
+
+/* Synthesized-beam formation (Sect. 3d.beam; Appendix "Synthesized Beams"): an SB takes, in
+ * each channel, the TAB whose grating response points at the SB's position at that frequency:
+ *     sb_out[s][c][t] = tab[sb_table[s][c]][c][t],  t < nsamp.
+ * tab: device uint8 [ntab][nchan][nsamp]; sb_table: device uint8 [nsb][nchan], entries < ntab
+ * (an entry >= ntab yields zeros for that row); sb_out: device uint8 [nsb][nchan][nsamp].
+ * Errors: ARTS_E_INVAL (sizes, NULL pointers, ntab > 256), ARTS_E_DEVICE.                   */
+int arts_sb_synthesize(const uint8_t* tab, int32_t ntab, const uint8_t* sb_table, int32_t nsb,
+                       int32_t nchan, int64_t nsamp, uint8_t* sb_out, void* stream);
+
+/* Brute-force incoherent dedispersion (Sect. 6b.2, "Dedispersion", single step):
+ *     out[b][d][t] = sum_c I_D[b][c][t + delay[d][c]],   t < L = nin/D - max_delay,
+ * with I_D the input summed over groups of D samples.  in: device uint8 [nbeam][nchan][nin];
+ * out: device int32 [nbeam][ndm][L] (exact: the sum is at most 255 * D * nchan < 2^31).
+ * Errors: ARTS_E_SHAPE if L < 1; ARTS_E_INVAL for nbeam < 1 or NULL pointers;
+ * ARTS_E_DEVICE.                                                                             */
+int arts_dedisperse(arts_plan_t plan, const uint8_t* in, int32_t nbeam, int64_t nin,
+                    int32_t* out, void* stream);
+
+/* Dedispersion of synthesized beams formed on the fly from TABs, without materialising them
+ * (SB formation folded into dedispersion, Sect. 3d.beam): identical to arts_sb_synthesize
+ * followed by arts_dedisperse over the nsb SBs.  tab: device uint8 [ntab][nchan][nin];
+ * sb_table: device uint8 [nsb][nchan] with entries < ntab; out: int32 [nsb][ndm][L].        */
+int arts_dedisperse_sb(arts_plan_t plan, const uint8_t* tab, int32_t ntab,
+                       const uint8_t* sb_table, int32_t nsb, int64_t nin, int32_t* out,
+                       void* stream);
+
+/* Boxcar matched filter and S/N of dedispersed series (Sect. 6b.2, "Integration" and
+ * "S/N evaluation"; the paper leaves the estimator open, this library takes):
+ *   window   nrep = L - wmax + 1 start samples, t < nrep
+ *   stats    mu, sigma: mean and population standard deviation of X[b][d][t], t < nrep
+ *   sums     B_w[t] = sum_{j<w} X[t + j]                       (exact int32)
+ *   snr      (B_w - w mu) / (sigma sqrt(w)), 0 when sigma == 0   (FP32 from an exact integer
+ *            numerator N*B_w - w*S1, relative error ~1e-7)
+ * series: device int32 [nbeam][ndm][L].  Outputs, each optional (NULL = not written):
+ * stats device double [nbeam][ndm][2] (mu, sigma); sums device int32 [nbeam][nwidth][ndm][nrep];
+ * snr device float [nbeam][nwidth][ndm][nrep].  Errors: ARTS_E_SHAPE if nrep < 1.           */
+int arts_boxcar_snr(arts_plan_t plan, const int32_t* series, int32_t nbeam, int64_t L,
+                    double* stats, int32_t* sums, float* snr, void* stream);
+
+/* Threshold candidate extraction (Sect. 6b.2, "Candidate selection": candidates whose S/N
+ * exceeds a threshold are kept).  For every beam, DM trial and width, each maximal run of
+ * consecutive start samples t < nrep with S/N > threshold (strict) yields one candidate at the
+ * run's largest boxcar sum, the earliest t on ties.  The test is exact: S/N > thr is evaluated
+ * as B_w > floor(w mu + thr sigma sqrt(w)) with mu, sigma in FP64; sigma == 0 gives none.
+ * Candidates are copied to host_out [capacity] sorted by (beam, dm_index, width, sample);
+ * *count receives the number found.  If it exceeds capacity, the first `capacity` in that
+ * order are NOT guaranteed: the call returns ARTS_E_CAPACITY and the caller retries with a
+ * buffer of *count.  This call SYNCHRONISES `stream`.  t_offset and beam_offset are added to
+ * the reported sample and beam.                                                             */
+int arts_candidates(arts_plan_t plan, const int32_t* series, int32_t nbeam, int64_t L,
+                    float threshold, int64_t t_offset, int32_t beam_offset,
+                    arts_candidate* host_out, int64_t capacity, int64_t* count, void* stream);
+
+/* ------------------------------------------------------------------------ streaming ---- */
+
+/* A streaming search over consecutive chunks (the real-time search processes 1.024 s chunks
+ * and evaluates S/N over them, Sect. 6b.2 and Sect. 6b.1).  The stream keeps the overlap each
+ * plan needs -- D * (max_delay + wmax - 1) native samples per row -- resident on the device, so
+ * chunk k is searched exactly as a one-shot search of the concatenated input would search it;
+ * before the first chunk the history is zeros.
+ *
+ *   plans[nplan]  plans sharing one channel count (e.g. native trials plus downsampled
+ *                 high-DM trials); the stream keeps pointers, the plans must outlive it
+ *   nsrc          source rows per chunk (beams, or TABs when sb_table is given)
+ *   sb_table      device uint8 [nbeam][nchan] forming nbeam SBs from the nsrc TABs on the fly,
+ *                 or NULL (then nbeam == nsrc)
+ *   chunk         new native samples per push (a multiple of every plan's D)
+ *   threshold     candidate S/N threshold;  cand_capacity: device candidate buffer entries
+ *   flags         ARTS_STREAM_GRAPH: each push replays a captured hipGraph (two graphs, one per
+ *                 ring parity);  ARTS_STREAM_PROFILE: time each phase with HIP events (phase 0
+ *                 ring advance, 1..nplan dedispersion of plan i-1, nplan+1 statistics +
+ *                 candidates of all plans).  The two flags are exclusive.
+ * The stream owns its rings, series, workspace and a HIP stream of default priority.  Errors:
+ * ARTS_E_INVAL, ARTS_E_NOMEM, ARTS_E_DEVICE.                                                  */
+#define ARTS_STREAM_GRAPH 1u
+#define ARTS_STREAM_PROFILE 2u
+typedef struct arts_stream_s* arts_stream_t;
+int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
+                       const uint8_t* sb_table, int32_t nbeam, int64_t chunk, float threshold,
+                       int64_t cand_capacity, uint32_t flags, arts_stream_t* out);
+
+/* Device staging buffer [nsrc][nchan][chunk] owned by the stream: a producer may copy the next
+ * chunk straight into it and push with chunk = that pointer (or NULL), avoiding a copy.        */
+int arts_stream_input(arts_stream_t s, uint8_t** chunk_buffer);
+
+/* Search the next chunk: device uint8 [nsrc][nchan][chunk] (NULL = the staging buffer).
+ * Asynchronous; ordered after the work already queued on `stream`.  One chunk may be in flight:
+ * collect it with arts_stream_wait before the next push (ARTS_E_STATE otherwise).              */
+int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream);
+
+/* Wait for the last pushed chunk and copy its candidates to host_out [capacity], sorted by
+ * (beam, downsample, dm_index, width, sample).  `sample` is absolute: the boxcar start in the
+ * plan's (downsampled) samples counted from the first sample of chunk 0 at the reference
+ * frequency, i.e. k * chunk / D - D-halo + t for output t of chunk k (negative while the
+ * history is still the initial zeros).  *count = number found; ARTS_E_CAPACITY if it exceeds
+ * capacity or the stream's own cand_capacity.  *chunk_index (nullable) = k.                   */
+int arts_stream_wait(arts_stream_t s, arts_candidate* host_out, int64_t capacity,
+                     int64_t* count, int64_t* chunk_index);
+
+/* Chunks pushed so far, device bytes the stream holds, and the ring overlap in native samples. */
+int arts_stream_info(arts_stream_t s, int64_t* chunks_pushed, int64_t* device_bytes,
+                     int64_t* halo_native);
+
+/* Accumulated milliseconds and push count of one profiled phase (see ARTS_STREAM_PROFILE).    */
+int arts_stream_timing(arts_stream_t s, int32_t phase, double* total_ms, int64_t* count);
+
+/* Device pointer to plan_index's dedispersed series of the last chunk, int32 [nbeam][ndm][L],
+ * L = chunk / D + wmax - 1 (valid until the next push).                                       */
+int arts_stream_series(arts_stream_t s, int32_t plan_index, const int32_t** series, int64_t* L);
+
+/* Checkpoint / resume: copy the device ring (nsrc * nchan * (halo + chunk) bytes) and the chunk
+ * count to the host, and restore them into a stream created with the same arguments.  After a
+ * restore the stream continues bit-exactly as the original would have.                       */
+int arts_stream_snapshot(arts_stream_t s, uint8_t* host, int64_t bytes, int64_t* chunks_pushed);
+int arts_stream_restore(arts_stream_t s, const uint8_t* host, int64_t bytes,
+                        int64_t chunks_pushed);
+
+/* Release everything the stream owns (waits for its queued work first).  NULL is ignored.      */
+void arts_stream_destroy(arts_stream_t s);
+
+/* ----------------------------------------------------------------------- diagnostics ---- */
+const char* arts_strerror(int status);
+const char* arts_last_error(void);
+/* Library version string, and the gfx target the device code was built for.               */
+const char* arts_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARTS_H */

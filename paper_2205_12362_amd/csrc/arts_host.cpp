@@ -1,0 +1,484 @@
+// Host runtime of libarts: argument validation, the FP64 delay table, plan lifecycle, tiling
+// tables of the dedispersion kernel, workspace management and the C entry points of the
+// plain (one call per step) path.
+#include <algorithm>
+#include <cfenv>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+
+#include "arts_internal.h"
+
+namespace arts {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+// Cold-plasma dispersion constant, s MHz^2 pc^-1 cm^3 (the paper does not state the law; this
+// is the standard t = k DM / f^2).
+static constexpr double kDispersion = 4.148808e3;
+
+static int compute_delays(int32_t nchan, double f_lo, double df, double tsamp,
+                          const double* dms, int32_t ndm, int32_t ds, int32_t* out,
+                          double* tie_margin) {
+  if (nchan < 1) return fail(ARTS_E_INVAL, "nchan must be >= 1 (got %d)", nchan);
+  if (ndm < 1 || !dms) return fail(ARTS_E_INVAL, "need at least one DM trial");
+  if (!std::isfinite(f_lo) || !std::isfinite(df) || df == 0.0)
+    return fail(ARTS_E_INVAL, "f_lo and df must be finite and df != 0");
+  if (!(tsamp > 0.0) || !std::isfinite(tsamp))
+    return fail(ARTS_E_INVAL, "tsamp must be finite and > 0");
+  if (ds < 1) return fail(ARTS_E_INVAL, "downsample must be >= 1");
+  std::vector<double> f(nchan);
+  double f_ref = -std::numeric_limits<double>::infinity();
+  for (int32_t c = 0; c < nchan; ++c) {
+    f[c] = f_lo + static_cast<double>(c) * df;
+    if (!(f[c] > 0.0)) return fail(ARTS_E_INVAL, "channel %d has frequency <= 0", c);
+    f_ref = std::max(f_ref, f[c]);
+  }
+  const double inv_ref = 1.0 / (f_ref * f_ref);
+  const double step = static_cast<double>(ds) * tsamp;
+  double margin = std::numeric_limits<double>::infinity();
+  const int old_round = std::fegetround();
+  std::fesetround(FE_TONEAREST);  // nearbyint below rounds half to even
+  for (int32_t d = 0; d < ndm; ++d) {
+    const double dm = dms[d];
+    if (!std::isfinite(dm) || dm < 0.0) {
+      std::fesetround(old_round);
+      return fail(ARTS_E_INVAL, "DM %d is negative or not finite", d);
+    }
+    for (int32_t c = 0; c < nchan; ++c) {
+      const double x = kDispersion * dm * (1.0 / (f[c] * f[c]) - inv_ref) / step;
+      if (!(x <= 1073741824.0)) {
+        std::fesetround(old_round);
+        return fail(ARTS_E_INVAL, "delay of DM %g in channel %d exceeds 2^30 samples", dm, c);
+      }
+      const double r = std::nearbyint(x);
+      margin = std::min(margin, std::fabs((x - std::floor(x)) - 0.5));
+      out[static_cast<int64_t>(d) * nchan + c] = static_cast<int32_t>(r);
+    }
+  }
+  std::fesetround(old_round);
+  if (tie_margin) *tie_margin = margin;
+  return ARTS_OK;
+}
+
+void free_tiling(Tiling& t) {
+  if (t.d_base) (void)hipFree(t.d_base);
+  if (t.d_list) (void)hipFree(t.d_list);
+  if (t.d_cnt) (void)hipFree(t.d_cnt);
+  t = Tiling{};
+}
+
+// Tables for the dedispersion kernel (see the kernel's description): for each DM block, the
+// window base per channel; for each DM of the block and each channel chunk, the chunk's
+// channels sorted by sub-dword offset m, stored as LDS dword offsets, plus the run lengths.
+int build_tiling(arts_plan_s* p, int variant) {
+  if (variant < 0 || variant >= kNumVariants)
+    return fail(ARTS_E_INVAL, "tiling variant %d out of range [0, %d)", variant, kNumVariants);
+  const TileVariant& v = kVariants[variant];
+  if ((p->ds == 1) != (v.spd == 4))
+    return fail(ARTS_E_INVAL, "variant %d is for %s data", variant,
+                v.spd == 4 ? "native (D = 1)" : "downsampled (D > 1)");
+  Tiling t;
+  t.variant = variant;
+  t.m_blk = v.acc * v.waves;
+  t.nblk = static_cast<int>((p->ndm + t.m_blk - 1) / t.m_blk);
+  const int64_t nchan = p->nchan;
+  const int shift = v.spd == 4 ? 2 : 1;
+  std::vector<int32_t> rel(static_cast<size_t>(t.nblk) * t.m_blk * nchan, 0);
+  std::vector<int32_t> base(static_cast<size_t>(t.nblk) * nchan, 0);
+  int rmax = 0;
+  for (int b = 0; b < t.nblk; ++b) {
+    const int d0 = b * t.m_blk, d1 = std::min<int>(p->ndm, d0 + t.m_blk);
+    for (int64_t c = 0; c < nchan; ++c) {
+      int32_t lo = std::numeric_limits<int32_t>::max();
+      for (int d = d0; d < d1; ++d) lo = std::min(lo, p->delays[d * nchan + c]);
+      base[b * nchan + c] = lo;
+      for (int d = d0; d < d1; ++d) {
+        const int32_t r = p->delays[d * nchan + c] - lo;
+        rel[(static_cast<int64_t>(b) * t.m_blk + (d - d0)) * nchan + c] = r;
+        rmax = std::max(rmax, r);
+      }
+    }
+  }
+  t.rmax = rmax;
+  // lane 63 reads dwords 63 j + (rel >> shift) .. + j (the last only when m > 0)
+  t.win_dwords = 64 * v.j + (rmax >> shift) + 1;
+  const int64_t budget = p->lds_budget > 0 ? p->lds_budget
+                                          : std::max<int64_t>(16 * 1024, 160 * 1024 * v.waves / 16 - 1024);
+  int cc = static_cast<int>(std::min<int64_t>({nchan, 255, budget / (4LL * t.win_dwords)}));
+  if (cc >= v.waves) cc -= cc % v.waves;
+  if (cc < 1)
+    return fail(ARTS_E_INVAL,
+                "variant %d: one channel's window (%d B) exceeds the LDS budget (%lld B); the DM "
+                "trials are too widely spaced for this block size",
+                variant, t.win_dwords * 4, (long long)budget);
+  t.cc = cc;
+  t.nchunk = static_cast<int>((nchan + cc - 1) / cc);
+  std::vector<int32_t> list(rel.size() + 4, 0);  // +4: the kernel prefetches past a run
+  std::vector<uint32_t> cnt(static_cast<size_t>(t.nblk) * t.nchunk * t.m_blk, 0);
+  for (int b = 0; b < t.nblk; ++b) {
+    for (int x = 0; x < t.m_blk; ++x) {
+      const int32_t* r = &rel[(static_cast<int64_t>(b) * t.m_blk + x) * nchan];
+      int32_t* l = &list[(static_cast<int64_t>(b) * t.m_blk + x) * nchan];
+      for (int ch = 0; ch < t.nchunk; ++ch) {
+        const int c0 = ch * cc, c1 = static_cast<int>(std::min<int64_t>(nchan, c0 + cc));
+        int k = c0;
+        uint32_t packed = 0;
+        for (int m = 0; m < v.spd; ++m) {
+          int n = 0;
+          for (int c = c0; c < c1; ++c) {
+            if ((r[c] & (v.spd - 1)) != m) continue;
+            l[k++] = (c - c0) * t.win_dwords + (r[c] >> shift);
+            ++n;
+          }
+          packed |= static_cast<uint32_t>(n) << (8 * m);
+        }
+        cnt[(static_cast<int64_t>(b) * t.nchunk + ch) * t.m_blk + x] = packed;
+      }
+    }
+  }
+  hipError_t e = hipMalloc(&t.d_base, base.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&t.d_list, list.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&t.d_cnt, cnt.size() * sizeof(uint32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(t.d_base, base.data(), base.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(t.d_list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(t.d_cnt, cnt.data(), cnt.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_tiling(t);
+    return fail(e == hipErrorOutOfMemory ? ARTS_E_NOMEM : ARTS_E_DEVICE,
+                "tiling tables: %s", hipGetErrorString(e));
+  }
+  free_tiling(p->tiling);
+  p->tiling = t;
+  return ARTS_OK;
+}
+
+int ensure_stats(arts_plan_s* p, int64_t rows) {
+  if (rows <= p->stats_cap) return ARTS_OK;
+  if (p->d_s1) (void)hipFree(p->d_s1);
+  if (p->d_musig) (void)hipFree(p->d_musig);
+  p->d_s1 = nullptr;
+  p->d_musig = nullptr;
+  p->stats_cap = 0;
+  ARTS_HIP(hipMalloc(&p->d_s1, rows * sizeof(int64_t)));
+  ARTS_HIP(hipMalloc(&p->d_musig, rows * 2 * sizeof(double)));
+  p->stats_cap = rows;
+  return ARTS_OK;
+}
+
+int ensure_cand(arts_plan_s* p, int64_t cap) {
+  if (!p->d_count) ARTS_HIP(hipMalloc(&p->d_count, 2 * sizeof(unsigned long long)));
+  if (cap <= p->cand_cap && p->d_cand) return ARTS_OK;
+  if (p->d_cand) (void)hipFree(p->d_cand);
+  p->d_cand = nullptr;
+  p->cand_cap = 0;
+  const int64_t n = std::max<int64_t>(cap, 1024);
+  ARTS_HIP(hipMalloc(&p->d_cand, n * sizeof(arts_candidate)));
+  p->cand_cap = n;
+  return ARTS_OK;
+}
+
+static void plan_free(arts_plan_s* p) {
+  if (!p) return;
+  free_tiling(p->tiling);
+  if (p->d_delays) (void)hipFree(p->d_delays);
+  if (p->d_widths) (void)hipFree(p->d_widths);
+  if (p->d_dms) (void)hipFree(p->d_dms);
+  if (p->d_s1) (void)hipFree(p->d_s1);
+  if (p->d_musig) (void)hipFree(p->d_musig);
+  if (p->d_cand) (void)hipFree(p->d_cand);
+  if (p->d_count) (void)hipFree(p->d_count);
+  delete p;
+}
+
+static int plan_create(int32_t nchan, double f_lo, double df, double tsamp, const double* dms,
+                       int32_t ndm, const int32_t* widths, int32_t nwidth, int32_t ds,
+                       arts_plan_t* out) {
+  if (!out) return fail(ARTS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (ds > 257) return fail(ARTS_E_INVAL, "downsample must be <= 257 (16-bit sums)");
+  if (nwidth < 1 || !widths) return fail(ARTS_E_INVAL, "need at least one boxcar width");
+  for (int32_t i = 0; i < nwidth; ++i) {
+    if (widths[i] < 1 || (i > 0 && widths[i] <= widths[i - 1]))
+      return fail(ARTS_E_INVAL, "widths must be >= 1 and strictly increasing");
+  }
+  if (widths[nwidth - 1] > kMaxWidth)
+    return fail(ARTS_E_INVAL, "widths above %d samples are not supported", kMaxWidth);
+  if (static_cast<int64_t>(nchan) * 255 * ds * widths[nwidth - 1] >= (int64_t(1) << 31))
+    return fail(ARTS_E_INVAL, "nchan * 255 * D * wmax must stay below 2^31 (exact int32 sums)");
+  arts_plan_s* p = new (std::nothrow) arts_plan_s;
+  if (!p) return fail(ARTS_E_NOMEM, "host allocation failed");
+  p->nchan = nchan;
+  p->ndm = ndm;
+  p->nwidth = nwidth;
+  p->ds = ds;
+  p->f_lo = f_lo;
+  p->df = df;
+  p->tsamp = tsamp;
+  if (ndm >= 1 && dms) p->dms.assign(dms, dms + ndm);
+  p->widths.assign(widths, widths + nwidth);
+  p->delays.resize(static_cast<size_t>(std::max(ndm, 1)) * std::max(nchan, 1));
+  int st = compute_delays(nchan, f_lo, df, tsamp, dms, ndm, ds, p->delays.data(),
+                          &p->tie_margin);
+  if (st != ARTS_OK) {
+    delete p;
+    return st;
+  }
+  p->max_delay = *std::max_element(p->delays.begin(), p->delays.end());
+  p->wmax = widths[nwidth - 1];
+  p->halo = p->max_delay + p->wmax - 1;
+  if (hipError_t ge = hipGetDevice(&p->device); ge != hipSuccess) {
+    delete p;
+    return fail(ARTS_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(ge));
+  }
+  hipError_t e = hipMalloc(&p->d_delays, p->delays.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_widths, nwidth * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_dms, ndm * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_delays, p->delays.data(), p->delays.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_widths, widths, nwidth * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_dms, dms, ndm * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return fail(e == hipErrorOutOfMemory ? ARTS_E_NOMEM : ARTS_E_DEVICE, "plan upload: %s",
+                hipGetErrorString(e));
+  }
+  st = build_tiling(p, default_variant(ds, ndm));
+  if (st != ARTS_OK) {
+    // wide DM spacing: fall back to the variant with the fewest DMs per block
+    int best = -1;
+    for (int v = 0; v < kNumVariants; ++v) {
+      if ((ds == 1) != (kVariants[v].spd == 4)) continue;
+      if (best < 0 || kVariants[v].acc * kVariants[v].waves <
+                          kVariants[best].acc * kVariants[best].waves)
+        best = v;
+    }
+    st = best >= 0 ? build_tiling(p, best) : st;
+    if (st != ARTS_OK) {
+      plan_free(p);
+      return st;
+    }
+  }
+  *out = p;
+  return ARTS_OK;
+}
+
+static int check_plan(const arts_plan_s* p) {
+  if (!p) return fail(ARTS_E_INVAL, "plan is NULL");
+  return ARTS_OK;
+}
+
+static int64_t nrep_of(const arts_plan_s* p, int64_t L) { return L - p->wmax + 1; }
+
+}  // namespace arts
+
+using namespace arts;
+
+extern "C" {
+
+const char* arts_strerror(int status) {
+  switch (status) {
+    case ARTS_OK: return "ok";
+    case ARTS_E_INVAL: return "invalid argument";
+    case ARTS_E_SHAPE: return "input shorter than the plan's halo";
+    case ARTS_E_NOMEM: return "out of memory";
+    case ARTS_E_DEVICE: return "HIP device error";
+    case ARTS_E_CAPACITY: return "candidate buffer too small";
+    case ARTS_E_BUDGET: return "request exceeds the HBM budget";
+    case ARTS_E_STATE: return "call not valid in the current state";
+    default: return "unknown status";
+  }
+}
+
+const char* arts_last_error(void) { return g_last_error.c_str(); }
+
+const char* arts_version(void) { return "arts-mi355x 0.1 (gfx950)"; }
+
+int arts_delay_table(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp_s,
+                     const double* dm_list, int32_t ndm, int32_t downsample,
+                     int32_t* delays_out, double* tie_margin_out) {
+  if (!delays_out) return fail(ARTS_E_INVAL, "delays_out is NULL");
+  return compute_delays(nchan, f_lo_mhz, df_mhz, tsamp_s, dm_list, ndm, downsample, delays_out,
+                        tie_margin_out);
+}
+
+int arts_plan_create(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp_s,
+                     const double* dm_list, int32_t ndm, const int32_t* widths, int32_t nwidth,
+                     arts_plan_t* out) {
+  return plan_create(nchan, f_lo_mhz, df_mhz, tsamp_s, dm_list, ndm, widths, nwidth, 1, out);
+}
+
+int arts_plan_create_ds(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp_s,
+                        const double* dm_list, int32_t ndm, const int32_t* widths,
+                        int32_t nwidth, int32_t downsample, arts_plan_t* out) {
+  return plan_create(nchan, f_lo_mhz, df_mhz, tsamp_s, dm_list, ndm, widths, nwidth,
+                     downsample, out);
+}
+
+void arts_plan_destroy(arts_plan_t plan) { plan_free(plan); }
+
+int arts_plan_info(arts_plan_t p, int32_t* nchan, int32_t* ndm, int32_t* nwidth,
+                   int32_t* downsample, int32_t* max_delay, int32_t* halo) {
+  if (int st = check_plan(p)) return st;
+  if (nchan) *nchan = p->nchan;
+  if (ndm) *ndm = p->ndm;
+  if (nwidth) *nwidth = p->nwidth;
+  if (downsample) *downsample = p->ds;
+  if (max_delay) *max_delay = p->max_delay;
+  if (halo) *halo = p->halo;
+  return ARTS_OK;
+}
+
+int arts_plan_delays(arts_plan_t p, int32_t* host_out) {
+  if (int st = check_plan(p)) return st;
+  if (!host_out) return fail(ARTS_E_INVAL, "host_out is NULL");
+  std::memcpy(host_out, p->delays.data(), p->delays.size() * sizeof(int32_t));
+  return ARTS_OK;
+}
+
+int arts_plan_set_tiling(arts_plan_t p, int32_t variant) {
+  if (int st = check_plan(p)) return st;
+  if (p->tiling.variant == variant) return ARTS_OK;
+  return build_tiling(p, variant);
+}
+
+int arts_plan_get_tiling(arts_plan_t p, int32_t* variant) {
+  if (int st = check_plan(p)) return st;
+  if (variant) *variant = p->tiling.variant;
+  return ARTS_OK;
+}
+
+int32_t arts_tiling_count(void) { return kNumVariants; }
+
+int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
+  if (variant < 0 || variant >= kNumVariants || !buf || len < 1)
+    return fail(ARTS_E_INVAL, "bad variant or buffer");
+  const TileVariant& v = kVariants[variant];
+  snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d", v.j, v.acc, v.waves, v.spd);
+  return ARTS_OK;
+}
+
+int arts_sb_synthesize(const uint8_t* tab, int32_t ntab, const uint8_t* sb_table, int32_t nsb,
+                       int32_t nchan, int64_t nsamp, uint8_t* sb_out, void* stream) {
+  if (!tab || !sb_table || !sb_out) return fail(ARTS_E_INVAL, "NULL pointer");
+  if (ntab < 1 || ntab > 256 || nsb < 1 || nchan < 1 || nsamp < 1)
+    return fail(ARTS_E_INVAL, "sizes out of range (ntab 1..256, nsb, nchan, nsamp >= 1)");
+  return launch_sb_gather(tab, ntab, sb_table, nsb, nchan, nsamp, sb_out,
+                          static_cast<hipStream_t>(stream));
+}
+
+int arts_dedisperse(arts_plan_t p, const uint8_t* in, int32_t nbeam, int64_t nin, int32_t* out,
+                    void* stream) {
+  if (int st = check_plan(p)) return st;
+  if (!in || !out || nbeam < 1) return fail(ARTS_E_INVAL, "NULL pointer or nbeam < 1");
+  const int64_t L = nin / p->ds - p->max_delay;
+  if (nin < 1 || L < 1)
+    return fail(ARTS_E_SHAPE, "nin = %lld gives no output sample (max delay %d, D %d)",
+                (long long)nin, p->max_delay, p->ds);
+  DedispJob job;
+  job.in = in;
+  job.in_bytes = static_cast<int64_t>(nbeam) * p->nchan * nin;
+  job.nin = nin;
+  job.pitch = nin;
+  job.nsrc = nbeam;
+  job.nbeam = nbeam;
+  job.out = out;
+  job.nout = L;
+  return launch_dedisperse(p, job, static_cast<hipStream_t>(stream));
+}
+
+int arts_dedisperse_sb(arts_plan_t p, const uint8_t* tab, int32_t ntab, const uint8_t* sb_table,
+                       int32_t nsb, int64_t nin, int32_t* out, void* stream) {
+  if (int st = check_plan(p)) return st;
+  if (!tab || !sb_table || !out) return fail(ARTS_E_INVAL, "NULL pointer");
+  if (ntab < 1 || ntab > 256 || nsb < 1) return fail(ARTS_E_INVAL, "ntab 1..256, nsb >= 1");
+  const int64_t L = nin / p->ds - p->max_delay;
+  if (nin < 1 || L < 1)
+    return fail(ARTS_E_SHAPE, "nin = %lld gives no output sample", (long long)nin);
+  DedispJob job;
+  job.in = tab;
+  job.in_bytes = static_cast<int64_t>(ntab) * p->nchan * nin;
+  job.nin = nin;
+  job.pitch = nin;
+  job.nsrc = ntab;
+  job.sb_table = sb_table;
+  job.nbeam = nsb;
+  job.out = out;
+  job.nout = L;
+  return launch_dedisperse(p, job, static_cast<hipStream_t>(stream));
+}
+
+int arts_boxcar_snr(arts_plan_t p, const int32_t* series, int32_t nbeam, int64_t L,
+                    double* stats, int32_t* sums, float* snr, void* stream) {
+  if (int st = check_plan(p)) return st;
+  if (!series || nbeam < 1) return fail(ARTS_E_INVAL, "NULL series or nbeam < 1");
+  const int64_t nrep = nrep_of(p, L);
+  if (nrep < 1) return fail(ARTS_E_SHAPE, "L = %lld shorter than wmax", (long long)L);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t rows = static_cast<int64_t>(nbeam) * p->ndm;
+  if (int st = ensure_stats(p, rows)) return st;
+  if (int st = launch_row_stats(series, L, nrep, rows, p->d_s1, p->d_musig, s)) return st;
+  if (stats)
+    ARTS_HIP(hipMemcpyAsync(stats, p->d_musig, rows * 2 * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  if (sums || snr)
+    return launch_boxcar_snr(p, series, nbeam, L, nrep, p->d_s1, p->d_musig, sums, snr, s);
+  return ARTS_OK;
+}
+
+int arts_candidates(arts_plan_t p, const int32_t* series, int32_t nbeam, int64_t L,
+                    float threshold, int64_t t_offset, int32_t beam_offset,
+                    arts_candidate* host_out, int64_t capacity, int64_t* count, void* stream) {
+  if (int st = check_plan(p)) return st;
+  if (!series || nbeam < 1 || !count || capacity < 0 || (capacity > 0 && !host_out))
+    return fail(ARTS_E_INVAL, "bad pointer or size");
+  if (!std::isfinite(threshold)) return fail(ARTS_E_INVAL, "threshold must be finite");
+  const int64_t nrep = nrep_of(p, L);
+  if (nrep < 1) return fail(ARTS_E_SHAPE, "L = %lld shorter than wmax", (long long)L);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t rows = static_cast<int64_t>(nbeam) * p->ndm;
+  if (int st = ensure_stats(p, rows)) return st;
+  if (int st = ensure_cand(p, capacity)) return st;
+  if (int st = launch_zero_u64(p->d_count, 1, s)) return st;
+  if (int st = launch_row_stats(series, L, nrep, rows, p->d_s1, p->d_musig, s)) return st;
+  if (int st = launch_candidates(p, series, nbeam, L, nrep, threshold, t_offset, beam_offset,
+                                 p->d_s1, p->d_musig, p->d_cand, p->d_count, capacity, s))
+    return st;
+  unsigned long long n = 0;
+  ARTS_HIP(hipMemcpyAsync(&n, p->d_count, sizeof n, hipMemcpyDeviceToHost, s));
+  ARTS_HIP(hipStreamSynchronize(s));
+  *count = static_cast<int64_t>(n);
+  if (static_cast<int64_t>(n) > capacity)
+    return fail(ARTS_E_CAPACITY, "%llu candidates, capacity %lld", n, (long long)capacity);
+  if (n == 0) return ARTS_OK;
+  ARTS_HIP(hipMemcpyAsync(host_out, p->d_cand, n * sizeof(arts_candidate),
+                          hipMemcpyDeviceToHost, s));
+  ARTS_HIP(hipStreamSynchronize(s));
+  std::sort(host_out, host_out + n, [](const arts_candidate& a, const arts_candidate& b) {
+    if (a.beam != b.beam) return a.beam < b.beam;
+    if (a.dm_index != b.dm_index) return a.dm_index < b.dm_index;
+    if (a.width != b.width) return a.width < b.width;
+    return a.sample < b.sample;
+  });
+  return ARTS_OK;
+}
+
+}  // extern "C"

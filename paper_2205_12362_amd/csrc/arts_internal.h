@@ -1,0 +1,115 @@
+// Internal declarations shared by the host runtime (arts_host.cpp, arts_batch.cpp,
+// arts_stream.cpp) and the device code (arts_kernels.hip).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/arts.h"
+
+namespace arts {
+
+// Dedispersion kernel shapes compiled into the library.  A workgroup of `waves` wave64s owns
+// `waves * acc` consecutive DM trials and one time tile of 64 * j * spd output samples; each
+// lane accumulates `acc` DMs x `j * spd` consecutive samples in int32 registers.  spd is the
+// number of samples per LDS dword: 4 for native uint8 data, 2 for downsampled 16-bit sums.
+struct TileVariant {
+  int spd, j, acc, waves;
+};
+extern const TileVariant kVariants[];
+extern const int kNumVariants;
+int default_variant(int downsample, int64_t ndm);
+
+// Widest supported boxcar (the candidate kernels stage a segment plus wmax samples in LDS).
+constexpr int kMaxWidth = 16384;
+
+// Tiling tables of a plan for one variant.
+struct Tiling {
+  int variant = -1;
+  int m_blk = 0;        // DM trials per workgroup
+  int nblk = 0;         // DM blocks
+  int rmax = 0;         // largest delay spread inside a block (samples)
+  int win_dwords = 0;   // LDS dwords staged per channel
+  int cc = 0;           // channels per LDS chunk (<= 255)
+  int nchunk = 0;
+  int32_t* d_base = nullptr;   // [nblk][nchan] smallest delay of the block in that channel
+  int32_t* d_list = nullptr;   // [nblk][m_blk][nchan] LDS dword offsets, by chunk then m
+  uint32_t* d_cnt = nullptr;   // [nblk][nchunk][m_blk] 4 x 8-bit channel counts per m
+};
+
+}  // namespace arts
+
+struct arts_plan_s {
+  int device = 0;
+  int32_t nchan = 0, ndm = 0, nwidth = 0, ds = 1;
+  double f_lo = 0, df = 0, tsamp = 0;
+  std::vector<double> dms;
+  std::vector<int32_t> widths;
+  std::vector<int32_t> delays;  // host [ndm][nchan]
+  int32_t max_delay = 0, wmax = 0, halo = 0;
+  double tie_margin = 0;
+  int32_t* d_delays = nullptr;
+  int32_t* d_widths = nullptr;
+  double* d_dms = nullptr;
+  arts::Tiling tiling;
+  int lds_budget = 0;  // bytes of LDS per dedispersion workgroup; 0 = by wave count
+  // workspace, grown on demand outside any timed loop
+  int64_t* d_s1 = nullptr;
+  double* d_musig = nullptr;
+  int64_t stats_cap = 0;  // rows
+  arts_candidate* d_cand = nullptr;
+  unsigned long long* d_count = nullptr;
+  int64_t cand_cap = 0;
+};
+
+namespace arts {
+
+// Error reporting: record a message for arts_last_error() and return the status.
+int fail(int status, const char* fmt, ...);
+#define ARTS_HIP(call)                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return ::arts::fail(ARTS_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
+  } while (0)
+
+int build_tiling(arts_plan_s* p, int variant);
+void free_tiling(Tiling& t);
+int ensure_stats(arts_plan_s* p, int64_t rows);
+int ensure_cand(arts_plan_s* p, int64_t cap);
+
+// One dedispersion job: which rows to read and where to write.
+struct DedispJob {
+  const uint8_t* in = nullptr;     // row (src, c) starts at in + (src * nchan + c) * pitch
+  int64_t in_bytes = 0;            // extent of `in` (bounds for vector loads)
+  int64_t nin = 0;                 // native samples per row
+  int64_t pitch = 0;               // bytes between rows (>= nin)
+  int32_t nsrc = 0;                // source beams in `in`
+  const uint8_t* sb_table = nullptr;  // optional [nbeam][nchan] -> source beam index
+  int32_t nbeam = 0;
+  int32_t* out = nullptr;          // [nbeam][ndm][nout]
+  int64_t nout = 0;
+};
+
+int launch_dedisperse(const arts_plan_s* p, const DedispJob& job, hipStream_t s);
+int launch_row_stats(const int32_t* series, int64_t L, int64_t nrep, int64_t nrows,
+                     int64_t* s1, double* musig, hipStream_t s);
+int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
+                      int64_t nrep, float thr, int64_t t_offset, int32_t beam_offset,
+                      const int64_t* s1, const double* musig, arts_candidate* cand,
+                      unsigned long long* count, int64_t cap, hipStream_t s);
+int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
+                      int64_t nrep, const int64_t* s1, const double* musig, int32_t* sums,
+                      float* snr, hipStream_t s);
+int launch_sb_gather(const uint8_t* tab, int32_t ntab, const uint8_t* sb_table, int32_t nsb,
+                     int32_t nchan, int64_t nsamp, uint8_t* out, hipStream_t s);
+int launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+// dst[r * dpitch + i] = src[r * spitch + i] for r < nrows, i < n (byte rows at any alignment)
+int launch_copy_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch,
+                     int64_t nrows, int64_t n, const uint8_t* src_begin, const uint8_t* src_end,
+                     hipStream_t s);
+
+}  // namespace arts

@@ -1,0 +1,746 @@
+// Device code of libarts for gfx950 (CDNA4): dedispersion, row statistics, boxcar / S/N /
+// candidate extraction and synthesized-beam gather.  All arithmetic on data is integer and
+// exact; FP64 is used only for the per-series mean / sigma and thresholds.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "arts_internal.h"
+
+namespace arts {
+
+// ------------------------------------------------------------------ tiling variants ----
+// spd, j, acc, waves.  j is odd so the lane stride of j dwords hits distinct LDS banks.
+const TileVariant kVariants[] = {
+    {4, 5, 4, 8},   // 0: 32 DMs x 1280 samples per block, 80 accumulators per lane
+    {4, 7, 3, 8},   // 1: 24 DMs x 1792
+    {4, 5, 4, 16},  // 2: 64 DMs x 1280, one block per CU
+    {4, 3, 6, 8},   // 3: 48 DMs x 768
+    {4, 5, 2, 4},   // 4:  8 DMs x 1280, small problems
+    {4, 7, 4, 8},   // 5: 32 DMs x 1792, 112 accumulators
+    {2, 5, 4, 8},   // 6: downsampled: 32 DMs x 640
+    {2, 9, 2, 8},   // 7: downsampled: 16 DMs x 1152
+    {2, 7, 3, 8},   // 8: downsampled: 24 DMs x 896
+};
+const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int default_variant(int downsample, int64_t ndm) {
+  if (downsample > 1) return 6;
+  return ndm <= 64 ? 4 : 0;
+}
+
+// ------------------------------------------------------------------ dedispersion ----
+//
+// One workgroup computes out[b][d][t] for a block of m_blk consecutive DM trials and one time
+// tile [t0, t0 + 64*T).  Channels are processed in chunks of `cc`: for each channel of the
+// chunk the window of input samples that every DM of the block needs,
+//     [t0 + base_c, t0 + base_c + 64*T + spread_c),  base_c = min_d delay[d][c],
+// is staged once into LDS and then read by every DM trial of the block (the data reuse across
+// neighbouring DMs the paper's kernel is tuned for, Sect. 6b.2 "Dedispersion").
+//
+// Lane l of a wave owns T = spd*j consecutive output samples t0 + l*T + i of `acc` DM trials
+// and keeps their sums in int32 registers.  For channel c and trial d it reads the j+1 LDS
+// dwords holding samples t0 + l*T + rel .. + T - 1, rel = delay[d][c] - base_c.  rel is the
+// same for every lane, and so is its sub-dword offset m = rel mod spd.  The plan sorts each
+// DM's channels (within a chunk) by m, so the kernel runs spd straight-line loops, one per m,
+// in which every sample is added with one v_add_u32 whose source operand is a byte (spd = 4)
+// or a 16-bit half (spd = 2) of an LDS dword (SDWA operand select) and the accumulators stay
+// in place.  With j odd, lanes read dwords j apart, which spreads a wave's reads over all
+// LDS banks.  Windows are staged byte-exact (funnel-shifted out of aligned loads), so m does
+// not depend on the input pointer.
+
+struct DedispArgs {
+  const uint8_t* in;
+  const uint8_t* in_end;
+  int64_t nin;        // native samples per input row
+  int64_t pitch;      // bytes between input rows
+  int64_t nsamp_d;    // nin / D
+  const uint8_t* sb_table;  // nullable: row (b, c) reads source beam sb_table[b*nchan + c]
+  const int32_t* base;      // [nblk][nchan]
+  const int32_t* list;      // [nblk][m_blk][nchan] LDS dword offsets, by chunk then m
+  const uint32_t* cnt;      // [nblk][nchunk][m_blk] packed per-m channel counts
+  int32_t* out;
+  int64_t nout;
+  int64_t nwg;
+  int32_t nchan, ndm, nsrc, ds, nbeam;
+  int32_t m_blk, nblk, win, cc, nchunk, ntt;
+};
+
+__device__ __forceinline__ const uint8_t* row_ptr(const DedispArgs& a, int b, int c) {
+  int src = b;
+  if (a.sb_table) src = a.sb_table[static_cast<int64_t>(b) * a.nchan + c];
+  if (src >= a.nsrc) return nullptr;
+  return a.in + (static_cast<int64_t>(src) * a.nchan + c) * a.pitch;
+}
+
+// acc += one byte / 16-bit half of w, as a single SDWA add.  Written as (ALU-only) inline asm
+// because the compiler otherwise fuses pairs of such adds into byte extracts + v_add3_u32,
+// which costs 1.5 instructions per sample instead of 1.
+template <int SEL>
+__device__ __forceinline__ void add_byte(uint32_t& acc, uint32_t w) {
+  if constexpr (SEL == 0)
+    asm("v_add_u32_sdwa %0, %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "+v"(acc) : "v"(w));
+  else if constexpr (SEL == 1)
+    asm("v_add_u32_sdwa %0, %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+        : "+v"(acc) : "v"(w));
+  else if constexpr (SEL == 2)
+    asm("v_add_u32_sdwa %0, %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+        : "+v"(acc) : "v"(w));
+  else
+    asm("v_add_u32_sdwa %0, %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+        : "+v"(acc) : "v"(w));
+}
+
+template <int SEL>
+__device__ __forceinline__ void add_half(uint32_t& acc, uint32_t w) {
+  if constexpr (SEL == 0)
+    asm("v_add_u32_sdwa %0, %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+        : "+v"(acc) : "v"(w));
+  else
+    asm("v_add_u32_sdwa %0, %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
+        : "+v"(acc) : "v"(w));
+}
+
+template <int SPD, int J, int MS>
+__device__ __forceinline__ void accum(uint32_t* acc, const uint32_t* w) {
+#pragma unroll
+  for (int i = 0; i < SPD * J; ++i) {
+    const int q = i + MS;
+    if constexpr (SPD == 4) {
+      switch (q % 4) {
+        case 0: add_byte<0>(acc[i], w[q / 4]); break;
+        case 1: add_byte<1>(acc[i], w[q / 4]); break;
+        case 2: add_byte<2>(acc[i], w[q / 4]); break;
+        default: add_byte<3>(acc[i], w[q / 4]); break;
+      }
+    } else {
+      if (q % 2 == 0)
+        add_half<0>(acc[i], w[q / 2]);
+      else
+        add_half<1>(acc[i], w[q / 2]);
+    }
+  }
+}
+
+// Accumulate n channels whose sub-dword offset is MS.  lst holds their LDS dword offsets; the
+// list is padded so that reading two entries past its end is in bounds.
+template <int SPD, int J, int MS>
+__device__ __forceinline__ void accum_run(uint32_t* acc, const int32_t* lst, int n,
+                                          const uint32_t* lane_base) {
+  constexpr int NW = (MS == 0) ? J : J + 1;
+  if (n <= 0) return;
+  int e0 = __builtin_amdgcn_readfirstlane(lst[0]);
+  int e1 = __builtin_amdgcn_readfirstlane(lst[1]);
+  int i = 0;
+  for (; i + 1 < n; i += 2) {
+    const int f0 = __builtin_amdgcn_readfirstlane(lst[i + 2]);
+    const int f1 = __builtin_amdgcn_readfirstlane(lst[i + 3]);
+    const uint32_t* p0 = lane_base + e0;
+    const uint32_t* p1 = lane_base + e1;
+    uint32_t w0[J + 1], w1[J + 1];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w0[k] = p0[k];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w1[k] = p1[k];
+    accum<SPD, J, MS>(acc, w0);
+    accum<SPD, J, MS>(acc, w1);
+    e0 = f0;
+    e1 = f1;
+  }
+  if (i < n) {
+    const uint32_t* p0 = lane_base + e0;
+    uint32_t w0[J + 1];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w0[k] = p0[k];
+    accum<SPD, J, MS>(acc, w0);
+  }
+}
+
+template <int SPD, int J, int ACC, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  constexpr int T = SPD * J;
+  constexpr int TT = 64 * T;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+  // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each XCD runs a
+  // contiguous range of (beam, time tile, DM block) and neighbouring DM blocks, which read
+  // overlapping input windows, share that XCD's L2.
+  const int64_t bid = blockIdx.x;
+  const int64_t q8 = a.nwg >> 3, r8 = a.nwg & 7, xcd = bid & 7, pos = bid >> 3;
+  const int64_t lin = xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
+  const int blk = static_cast<int>(lin % a.nblk);
+  const int64_t rest = lin / a.nblk;
+  const int tt = static_cast<int>(rest % a.ntt);
+  const int b = static_cast<int>(rest / a.ntt);
+  const int64_t t0 = static_cast<int64_t>(tt) * TT;
+  const int dwave0 = blk * a.m_blk + wave * ACC;
+  const bool wave_active = dwave0 < a.ndm;
+
+  uint32_t acc[ACC][T];
+#pragma unroll
+  for (int x = 0; x < ACC; ++x)
+#pragma unroll
+    for (int i = 0; i < T; ++i) acc[x][i] = 0;
+
+  const int32_t* base_blk = a.base + static_cast<int64_t>(blk) * a.nchan;
+  const int32_t* list_wave =
+      a.list + (static_cast<int64_t>(blk) * a.m_blk + wave * ACC) * a.nchan;
+  const uint32_t* cnt_blk = a.cnt + static_cast<int64_t>(blk) * a.nchunk * a.m_blk + wave * ACC;
+  const uint32_t* lane_base = lds + J * lane;
+
+  for (int ch = 0; ch < a.nchunk; ++ch) {
+    const int c0 = ch * a.cc;
+    const int ncc = min(a.cc, a.nchan - c0);
+    // ---- stage the chunk's windows into LDS, one channel per wave at a time
+    for (int jj = wave; jj < ncc; jj += WAVES) {
+      const int c = c0 + jj;
+      const uint8_t* row = row_ptr(a, b, c);
+      const int64_t ws = t0 + base_blk[c];
+      uint32_t* dst = lds + static_cast<int64_t>(jj) * a.win;
+      if constexpr (SPD == 4) {
+        // dword k = samples ws + 4k .. ws + 4k + 3, little-endian
+        const uint8_t* a0 = row ? row + ws : a.in;
+        const int ga = static_cast<int>(reinterpret_cast<uintptr_t>(a0) & 3u);
+        const uint32_t* P = reinterpret_cast<const uint32_t*>(a0 - ga);
+        const uint8_t* rend = row + a.nin;
+        for (int k = lane; k < a.win; k += 64) {
+          uint32_t v = 0;
+          if (row) {
+            const uint8_t* q = a0 + 4 * static_cast<int64_t>(k);
+            const uint32_t* pk = P + k;
+            if (q >= row && q + 4 <= rend &&
+                reinterpret_cast<const uint8_t*>(pk) >= a.in &&
+                reinterpret_cast<const uint8_t*>(pk + (ga ? 2 : 1)) <= a.in_end) {
+              v = ga ? __builtin_amdgcn_alignbyte(pk[1], pk[0], ga) : pk[0];
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (q + i >= row && q + i < rend) v |= static_cast<uint32_t>(q[i]) << (8 * i);
+            }
+          }
+          dst[k] = v;
+        }
+      } else {
+        for (int k = lane; k < a.win; k += 64) {
+          uint32_t v = 0;
+          if (row) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int64_t s = ws + 2 * static_cast<int64_t>(k) + h;
+              if (s < a.nsamp_d) {
+                const uint8_t* q = row + s * a.ds;
+                uint32_t sum = 0;
+                for (int i = 0; i < a.ds; ++i) sum += q[i];
+                v |= sum << (16 * h);
+              }
+            }
+          }
+          dst[k] = v;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- accumulate: each DM trial of the wave over the chunk, one run per sub-dword offset
+    if (wave_active) {
+#pragma unroll
+      for (int x = 0; x < ACC; ++x) {
+        const uint32_t packed = __builtin_amdgcn_readfirstlane(cnt_blk[ch * a.m_blk + x]);
+        const int32_t* lst = list_wave + static_cast<int64_t>(x) * a.nchan + c0;
+        const int n0 = packed & 0xff, n1 = (packed >> 8) & 0xff;
+        accum_run<SPD, J, 0>(acc[x], lst, n0, lane_base);
+        accum_run<SPD, J, 1>(acc[x], lst + n0, n1, lane_base);
+        if constexpr (SPD == 4) {
+          const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
+          accum_run<SPD, J, 2>(acc[x], lst + n0 + n1, n2, lane_base);
+          accum_run<SPD, J, 3>(acc[x], lst + n0 + n1 + n2, n3, lane_base);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!wave_active) return;
+#pragma unroll
+  for (int x = 0; x < ACC; ++x) {
+    const int d = dwave0 + x;
+    if (d >= a.ndm) break;
+    int32_t* o = a.out + (static_cast<int64_t>(b) * a.ndm + d) * a.nout;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      const int64_t t = t0 + static_cast<int64_t>(lane) * T + i;
+      if (t < a.nout) o[t] = static_cast<int32_t>(acc[x][i]);
+    }
+  }
+}
+
+template <int SPD, int J, int ACC, int WAVES>
+static int launch_variant(DedispArgs a, hipStream_t s) {
+  constexpr int T = SPD * J;
+  a.ntt = static_cast<int>((a.nout + 64 * T - 1) / (64 * T));
+  const size_t lds = static_cast<size_t>(a.win) * 4 * a.cc;
+  if (lds > 160 * 1024) return fail(ARTS_E_INVAL, "LDS request %zu B exceeds 160 KiB", lds);
+  a.nwg = static_cast<int64_t>(a.nbeam) * a.ntt * a.nblk;
+  if (a.nwg > INT_MAX) return fail(ARTS_E_INVAL, "grid too large (%lld blocks)", (long long)a.nwg);
+  static bool attr_set = false;  // one flag per template instance
+  if (!attr_set) {
+    ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(
+                                     &dedisperse_kernel<SPD, J, ACC, WAVES>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_set = true;
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((dedisperse_kernel<SPD, J, ACC, WAVES>), dim3(static_cast<unsigned>(a.nwg)),
+                     dim3(WAVES * 64), lds, s, a);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+int launch_dedisperse(const arts_plan_s* p, const DedispJob& job, hipStream_t s) {
+  const Tiling& t = p->tiling;
+  DedispArgs a{};
+  a.in = job.in;
+  a.in_end = job.in + job.in_bytes;
+  a.nin = job.nin;
+  a.pitch = job.pitch > 0 ? job.pitch : job.nin;
+  a.nsamp_d = job.nin / p->ds;
+  a.sb_table = job.sb_table;
+  a.base = t.d_base;
+  a.list = t.d_list;
+  a.cnt = t.d_cnt;
+  a.out = job.out;
+  a.nout = job.nout;
+  a.nchan = p->nchan;
+  a.ndm = p->ndm;
+  a.nsrc = job.nsrc;
+  a.ds = p->ds;
+  a.nbeam = job.nbeam;
+  a.m_blk = t.m_blk;
+  a.nblk = t.nblk;
+  a.win = t.win_dwords;
+  a.cc = t.cc;
+  a.nchunk = t.nchunk;
+  switch (t.variant) {
+    case 0: return launch_variant<4, 5, 4, 8>(a, s);
+    case 1: return launch_variant<4, 7, 3, 8>(a, s);
+    case 2: return launch_variant<4, 5, 4, 16>(a, s);
+    case 3: return launch_variant<4, 3, 6, 8>(a, s);
+    case 4: return launch_variant<4, 5, 2, 4>(a, s);
+    case 5: return launch_variant<4, 7, 4, 8>(a, s);
+    case 6: return launch_variant<2, 5, 4, 8>(a, s);
+    case 7: return launch_variant<2, 9, 2, 8>(a, s);
+    case 8: return launch_variant<2, 7, 3, 8>(a, s);
+    default: return fail(ARTS_E_INVAL, "plan has no tiling");
+  }
+}
+
+// ------------------------------------------------------------------ row statistics ----
+// One workgroup per series row: S1 = sum x, S2 = sum x^2 over t < nrep in int64 (exact for
+// nrep * max|x|^2 < 2^63), then mean and population sigma in FP64 from the exact integers,
+// centred on m0 = S1 / N to avoid cancellation:  N var = S2c - r^2 / N with
+// S2c = sum (x - m0)^2 and r = S1 - N m0.
+__global__ __launch_bounds__(256) void row_stats_kernel(const int32_t* __restrict__ series,
+                                                        int64_t L, int64_t nrep,
+                                                        int64_t* __restrict__ s1_out,
+                                                        double* __restrict__ musig) {
+  const int64_t row = blockIdx.x;
+  const int32_t* x = series + row * L;
+  long long s1 = 0, s2 = 0;
+  int64_t t = threadIdx.x;
+  for (; t + 3 * 256 < nrep; t += 4 * 256) {
+    const long long v0 = x[t], v1 = x[t + 256], v2 = x[t + 512], v3 = x[t + 768];
+    s1 += v0 + v1 + v2 + v3;
+    s2 += v0 * v0 + v1 * v1 + v2 * v2 + v3 * v3;
+  }
+  for (; t < nrep; t += 256) {
+    const long long v = x[t];
+    s1 += v;
+    s2 += v * v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_xor(s1, off, 64);
+    s2 += __shfl_xor(s2, off, 64);
+  }
+  __shared__ long long red[2][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = s1;
+    red[1][wave] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long S1 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const long long S2 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const long long N = nrep;
+    const long long m0 = S1 / N;
+    const long long r = S1 - N * m0;
+    const long long S2c = S2 - 2 * m0 * S1 + N * m0 * m0;
+    const double dn = static_cast<double>(N);
+    const double var = (static_cast<double>(S2c) - static_cast<double>(r) * static_cast<double>(r) / dn) / dn;
+    s1_out[row] = S1;
+    musig[2 * row] = static_cast<double>(m0) + static_cast<double>(r) / dn;
+    musig[2 * row + 1] = var > 0.0 ? sqrt(var) : 0.0;
+  }
+}
+
+int launch_row_stats(const int32_t* series, int64_t L, int64_t nrep, int64_t nrows, int64_t* s1,
+                     double* musig, hipStream_t s) {
+  if (nrows > INT_MAX) return fail(ARTS_E_INVAL, "too many series rows");
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(row_stats_kernel, dim3(static_cast<unsigned>(nrows)), dim3(256), 0, s,
+                     series, L, nrep, s1, musig);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+// ------------------------------------------------------------------ boxcars ----
+// A row's reported window is cut into segments of SEG start samples.  For a segment starting at
+// s0 the workgroup loads x[s0 - 1 .. s0 + n + wmax - 2] into LDS and turns it into an
+// exclusive prefix sum P (uint32, wrapping: differences are exact because every boxcar sum is
+// below 2^31), so B_w(t) = P[t - s0 + 1 + w] - P[t - s0 + 1] for t in [s0 - 1, s0 + n - 1].
+constexpr int kSeg = 2048;
+constexpr int kBoxThreads = 256;
+// dynamic LDS of the boxcar kernels: (kSeg + wmax + 1) words, wmax <= kMaxWidth
+constexpr int kBoxLdsMax = (kSeg + kMaxWidth + 1) * 4;
+
+__device__ void load_prefix(const int32_t* __restrict__ x, int64_t L, int64_t s0, int ne,
+                            uint32_t* P, uint32_t* wsum) {
+  for (int k = threadIdx.x; k < ne; k += kBoxThreads) {
+    const int64_t idx = s0 - 1 + k;
+    P[k] = (idx >= 0 && idx < L) ? static_cast<uint32_t>(x[idx]) : 0u;
+  }
+  __syncthreads();
+  const int per = (ne + kBoxThreads - 1) / kBoxThreads;
+  const int lo = min(ne, static_cast<int>(threadIdx.x) * per), hi = min(ne, lo + per);
+  uint32_t tot = 0;
+  for (int k = lo; k < hi; ++k) tot += P[k];
+  // inclusive scan of per-thread totals: within the wave, then across the 4 waves
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = tot;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t v = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += v;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int w = 0; w < wave; ++w) pre += wsum[w];
+  uint32_t run = pre + inc - tot;  // exclusive prefix of this thread's range
+  for (int k = lo; k < hi; ++k) {
+    const uint32_t v = P[k];
+    P[k] = run;
+    run += v;
+  }
+  if (threadIdx.x == kBoxThreads - 1) P[ne] = pre + inc;
+  __syncthreads();
+}
+
+struct WidthParams {
+  long long thr_int;  // B_w > thr_int  <=>  S/N > threshold
+  float scale;        // S/N = (N B_w - w S1) * scale
+};
+
+__device__ __forceinline__ WidthParams width_params(int w, int64_t N, double mu, double sigma,
+                                                    double thr) {
+  WidthParams wp;
+  const double sw = sqrt(static_cast<double>(w));
+  double rhs = floor(static_cast<double>(w) * mu + thr * sigma * sw);
+  if (rhs > 4.0e18) rhs = 4.0e18;
+  if (rhs < -4.0e18) rhs = -4.0e18;
+  wp.thr_int = static_cast<long long>(rhs);
+  wp.scale = sigma > 0.0 ? static_cast<float>(1.0 / (static_cast<double>(N) * sigma * sw)) : 0.0f;
+  return wp;
+}
+
+__global__ __launch_bounds__(kBoxThreads) void boxcar_snr_kernel(
+    const int32_t* __restrict__ series, int64_t L, int64_t nrep, int32_t ndm, int64_t nseg,
+    const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, const int64_t* __restrict__ s1,
+    const double* __restrict__ musig, int32_t* __restrict__ sums, float* __restrict__ snr) {
+  extern __shared__ uint32_t P[];
+  __shared__ uint32_t wsum[4];
+  const int64_t row = blockIdx.x / nseg;
+  const int64_t s0 = (blockIdx.x % nseg) * kSeg;
+  const int n = static_cast<int>(min<int64_t>(kSeg, nrep - s0));
+  const int ne = n + wmax;
+  load_prefix(series + row * L, L, s0, ne, P, wsum);
+  const int64_t b = row / ndm, d = row % ndm;
+  const double mu = musig[2 * row], sigma = musig[2 * row + 1];
+  const long long S1 = s1[row];
+  for (int wi = 0; wi < nw; ++wi) {
+    const int w = widths[wi];
+    const WidthParams wp = width_params(w, nrep, mu, sigma, 0.0);
+    const int64_t obase = ((b * nw + wi) * ndm + d) * nrep + s0;
+    for (int k = threadIdx.x; k < n; k += kBoxThreads) {
+      const int32_t B = static_cast<int32_t>(P[k + 1 + w] - P[k + 1]);
+      if (sums) sums[obase + k] = B;
+      if (snr) {
+        const long long num = static_cast<long long>(nrep) * B - static_cast<long long>(w) * S1;
+        snr[obase + k] = sigma > 0.0 ? static_cast<float>(num) * wp.scale : 0.0f;
+      }
+    }
+  }
+}
+
+int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
+                      int64_t nrep, const int64_t* s1, const double* musig, int32_t* sums,
+                      float* snr, hipStream_t s) {
+  const int64_t nseg = (nrep + kSeg - 1) / kSeg;
+  const int64_t nblocks = static_cast<int64_t>(nbeam) * p->ndm * nseg;
+  if (nblocks > INT_MAX) return fail(ARTS_E_INVAL, "boxcar grid too large");
+  const size_t lds = (kSeg + p->wmax + 1) * sizeof(uint32_t);
+  static bool attr = false;
+  if (!attr) {
+    ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&boxcar_snr_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kBoxLdsMax));
+    attr = true;
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(boxcar_snr_kernel, dim3(static_cast<unsigned>(nblocks)), dim3(kBoxThreads),
+                     lds, s, series, L, nrep, p->ndm, nseg, p->d_widths, p->nwidth, p->wmax, s1,
+                     musig, sums, snr);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+// ------------------------------------------------------------------ candidates ----
+// Per (row, segment): for each width, every start sample t of the segment with S/N above the
+// threshold whose predecessor is not above begins a run; the thread that owns t follows the
+// run (into later segments if needed, recomputing B_w from global memory there) and emits one
+// candidate at its largest B_w, earliest on ties.  Runs are rare and short, so the serial walk
+// costs nothing measurable; the test itself is one integer compare per (t, w).
+__device__ __forceinline__ int32_t boxcar_direct(const int32_t* x, int64_t t, int w) {
+  uint32_t acc = 0;
+  for (int j = 0; j < w; ++j) acc += static_cast<uint32_t>(x[t + j]);
+  return static_cast<int32_t>(acc);
+}
+
+__global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
+    const int32_t* __restrict__ series, int64_t L, int64_t nrep, int32_t ndm, int64_t nseg,
+    const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, const int64_t* __restrict__ s1,
+    const double* __restrict__ musig, const double* __restrict__ dms, double thr,
+    int64_t t_offset, int32_t beam_offset, int32_t ds, arts_candidate* __restrict__ cand,
+    unsigned long long* __restrict__ count, int64_t cap) {
+  extern __shared__ uint32_t P[];
+  __shared__ uint32_t wsum[4];
+  const int64_t row = blockIdx.x / nseg;
+  const double mu = musig[2 * row], sigma = musig[2 * row + 1];
+  if (!(sigma > 0.0)) return;  // uniform: flat series give no candidates
+  const int64_t s0 = (blockIdx.x % nseg) * kSeg;
+  const int n = static_cast<int>(min<int64_t>(kSeg, nrep - s0));
+  const int ne = n + wmax;
+  const int32_t* x = series + row * L;
+  load_prefix(x, L, s0, ne, P, wsum);
+  const int64_t b = row / ndm, d = row % ndm;
+  const long long S1 = s1[row];
+  constexpr int PT = kSeg / kBoxThreads;
+  const int k0 = threadIdx.x * PT;
+  for (int wi = 0; wi < nw; ++wi) {
+    const int w = widths[wi];
+    const WidthParams wp = width_params(w, nrep, mu, sigma, thr);
+    if (k0 >= n) continue;
+    // B_w(t) for t = s0 + k lives at P[k + 1 + w] - P[k + 1]; t = s0 - 1 at k = -1
+    auto Bl = [&](int k) { return static_cast<int32_t>(P[k + 1 + w] - P[k + 1]); };
+    bool prev = (s0 + k0 > 0) && (Bl(k0 - 1) > wp.thr_int);
+    for (int i = 0; i < PT; ++i) {
+      const int k = k0 + i;
+      if (k >= n) break;
+      const int32_t B = Bl(k);
+      const bool above = B > wp.thr_int;
+      if (above && !prev) {
+        int32_t best = B;
+        int64_t bt = s0 + k;
+        for (int64_t u = s0 + k + 1; u < nrep; ++u) {
+          const int32_t Bu = (u < s0 + n) ? Bl(static_cast<int>(u - s0)) : boxcar_direct(x, u, w);
+          if (!(Bu > wp.thr_int)) break;
+          if (Bu > best) {
+            best = Bu;
+            bt = u;
+          }
+        }
+        const unsigned long long idx = atomicAdd(count, 1ULL);
+        if (static_cast<int64_t>(idx) < cap) {
+          arts_candidate c;
+          c.sample = bt + t_offset;
+          c.beam = static_cast<int32_t>(b) + beam_offset;
+          c.dm_index = static_cast<int32_t>(d);
+          c.width = w;
+          c.downsample = ds;
+          const long long num = static_cast<long long>(nrep) * best - static_cast<long long>(w) * S1;
+          c.snr = static_cast<float>(num) * wp.scale;
+          c.dm = static_cast<float>(dms[d]);
+          cand[idx] = c;
+        }
+      }
+      prev = above;
+    }
+  }
+}
+
+int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
+                      int64_t nrep, float thr, int64_t t_offset, int32_t beam_offset,
+                      const int64_t* s1, const double* musig, arts_candidate* cand,
+                      unsigned long long* count, int64_t cap, hipStream_t s) {
+  const int64_t nseg = (nrep + kSeg - 1) / kSeg;
+  const int64_t nblocks = static_cast<int64_t>(nbeam) * p->ndm * nseg;
+  if (nblocks > INT_MAX) return fail(ARTS_E_INVAL, "candidate grid too large");
+  const size_t lds = (kSeg + p->wmax + 1) * sizeof(uint32_t);
+  static bool attr = false;
+  if (!attr) {
+    ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kBoxLdsMax));
+    attr = true;
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(candidates_kernel, dim3(static_cast<unsigned>(nblocks)), dim3(kBoxThreads),
+                     lds, s, series, L, nrep, p->ndm, nseg, p->d_widths, p->nwidth, p->wmax, s1,
+                     musig, p->d_dms, static_cast<double>(thr), t_offset, beam_offset, p->ds,
+                     cand, count, cap);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ULL;
+}
+
+int launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+// ------------------------------------------------------------------ SB gather ----
+// sb_out[s][c][:] = tab[sb_table[s][c]][c][:].  Rows start at arbitrary byte offsets, so each
+// thread writes whole destination-aligned dwords; the matching source bytes are funnel-shifted
+// out of two aligned source dwords.  Destination dwords shared with a neighbouring row (at row
+// ends) are written bytewise so rows never race.
+constexpr int kGatherThreads = 256;
+constexpr int kGatherDw = 4;  // dwords per thread
+
+__global__ __launch_bounds__(kGatherThreads) void sb_gather_kernel(
+    const uint8_t* __restrict__ tab, int32_t ntab, const uint8_t* __restrict__ table,
+    int32_t nchan, int64_t nsamp, uint8_t* __restrict__ out, int64_t nchunk,
+    const uint8_t* tab_end) {
+  const uint8_t* tab_begin = tab;
+  const int64_t row = blockIdx.x / nchunk;
+  const int64_t chunk = blockIdx.x % nchunk;
+  const int64_t c = row % nchan;
+  const int src_beam = table[row];
+  uint8_t* drow = out + row * nsamp;
+  const uint8_t* srow = src_beam < ntab ? tab + (static_cast<int64_t>(src_beam) * nchan + c) * nsamp : nullptr;
+  const uintptr_t dalign = reinterpret_cast<uintptr_t>(drow) & ~static_cast<uintptr_t>(3);
+  const int64_t lead = reinterpret_cast<uintptr_t>(drow) - dalign;  // bytes before the row
+  const int64_t ndw = (lead + nsamp + 3) / 4;
+  const int64_t k0 = (chunk * kGatherThreads + threadIdx.x) * kGatherDw;
+  for (int i = 0; i < kGatherDw; ++i) {
+    const int64_t k = k0 + i;
+    if (k >= ndw) break;
+    const int64_t off = 4 * k - lead;  // row offset of the dword's first byte
+    uint8_t* dq = reinterpret_cast<uint8_t*>(dalign) + 4 * k;
+    if (off >= 0 && off + 4 <= nsamp) {
+      uint32_t v = 0;
+      if (srow) {
+        const uint8_t* sq = srow + off;
+        const uintptr_t sa = reinterpret_cast<uintptr_t>(sq);
+        const int h = static_cast<int>(sa & 3u);
+        const uint32_t* sp = reinterpret_cast<const uint32_t*>(sa - h);
+        if (h == 0) {
+          v = sp[0];
+        } else if (reinterpret_cast<const uint8_t*>(sp) >= tab_begin &&
+                   reinterpret_cast<const uint8_t*>(sp + 2) <= tab_end) {
+          v = __builtin_amdgcn_alignbyte(sp[1], sp[0], h);
+        } else {
+          for (int j = 0; j < 4; ++j) v |= static_cast<uint32_t>(sq[j]) << (8 * j);
+        }
+      }
+      *reinterpret_cast<uint32_t*>(dq) = v;
+    } else {
+      for (int j = 0; j < 4; ++j) {
+        const int64_t o = off + j;
+        if (o >= 0 && o < nsamp) drow[o] = srow ? srow[o] : 0;
+      }
+    }
+  }
+}
+
+int launch_sb_gather(const uint8_t* tab, int32_t ntab, const uint8_t* sb_table, int32_t nsb,
+                     int32_t nchan, int64_t nsamp, uint8_t* out, hipStream_t s) {
+  const int64_t per_block = static_cast<int64_t>(kGatherThreads) * kGatherDw * 4;
+  const int64_t nchunk = (nsamp + 3 + per_block) / per_block;
+  const int64_t rows = static_cast<int64_t>(nsb) * nchan;
+  if (rows * nchunk > INT_MAX) return fail(ARTS_E_INVAL, "gather grid too large");
+  const uint8_t* tab_end = tab + static_cast<int64_t>(ntab) * nchan * nsamp;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(sb_gather_kernel, dim3(static_cast<unsigned>(rows * nchunk)),
+                     dim3(kGatherThreads), 0, s, tab, ntab, sb_table, nchan, nsamp, out, nchunk,
+                     tab_end);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+// ------------------------------------------------------------------ row copy ----
+// Copies byte rows at arbitrary alignment: each thread writes destination-aligned dwords whose
+// source bytes are funnel-shifted out of two aligned source dwords; dwords a row shares with
+// its neighbour are written bytewise so rows never race.
+__global__ __launch_bounds__(kGatherThreads) void copy_rows_kernel(
+    uint8_t* __restrict__ dst, int64_t dpitch, const uint8_t* __restrict__ src, int64_t spitch,
+    int64_t n, int64_t nchunk, const uint8_t* src_begin, const uint8_t* src_end) {
+  const int64_t row = blockIdx.x / nchunk;
+  const int64_t chunk = blockIdx.x % nchunk;
+  uint8_t* drow = dst + row * dpitch;
+  const uint8_t* srow = src + row * spitch;
+  const uintptr_t dalign = reinterpret_cast<uintptr_t>(drow) & ~static_cast<uintptr_t>(3);
+  const int64_t lead = reinterpret_cast<uintptr_t>(drow) - dalign;
+  const int64_t ndw = (lead + n + 3) / 4;
+  const int64_t k0 = (chunk * kGatherThreads + threadIdx.x) * kGatherDw;
+  for (int i = 0; i < kGatherDw; ++i) {
+    const int64_t k = k0 + i;
+    if (k >= ndw) break;
+    const int64_t off = 4 * k - lead;
+    uint8_t* dq = reinterpret_cast<uint8_t*>(dalign) + 4 * k;
+    if (off >= 0 && off + 4 <= n) {
+      const uint8_t* sq = srow + off;
+      const uintptr_t sa = reinterpret_cast<uintptr_t>(sq);
+      const int h = static_cast<int>(sa & 3u);
+      const uint32_t* sp = reinterpret_cast<const uint32_t*>(sa - h);
+      uint32_t v = 0;
+      if (h == 0) {
+        v = sp[0];
+      } else if (reinterpret_cast<const uint8_t*>(sp) >= src_begin &&
+                 reinterpret_cast<const uint8_t*>(sp + 2) <= src_end) {
+        v = __builtin_amdgcn_alignbyte(sp[1], sp[0], h);
+      } else {
+        for (int j = 0; j < 4; ++j) v |= static_cast<uint32_t>(sq[j]) << (8 * j);
+      }
+      *reinterpret_cast<uint32_t*>(dq) = v;
+    } else {
+      for (int j = 0; j < 4; ++j) {
+        const int64_t o = off + j;
+        if (o >= 0 && o < n) drow[o] = srow[o];
+      }
+    }
+  }
+}
+
+int launch_copy_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch,
+                     int64_t nrows, int64_t n, const uint8_t* src_begin, const uint8_t* src_end,
+                     hipStream_t s) {
+  if (nrows <= 0 || n <= 0) return ARTS_OK;
+  const int64_t per_block = static_cast<int64_t>(kGatherThreads) * kGatherDw * 4;
+  const int64_t nchunk = (n + 3 + per_block) / per_block;
+  if (nrows * nchunk > INT_MAX) return fail(ARTS_E_INVAL, "copy grid too large");
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(static_cast<unsigned>(nrows * nchunk)),
+                     dim3(kGatherThreads), 0, s, dst, dpitch, src, spitch, n, nchunk, src_begin,
+                     src_end);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+}  // namespace arts

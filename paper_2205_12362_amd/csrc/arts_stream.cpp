@@ -1,0 +1,370 @@
+// Streaming search: chunks of Stokes-I data arrive one by one (the real-time search processes
+// 1.024 s chunks, Sect. 6b.2; the S/N is based on those 1.024 s, Sect. 6b.1).  The stream keeps
+// the previous samples every trial still needs (the overlap, or halo) resident in device memory,
+// so a chunk's search sees exactly the data a one-shot search of the concatenated series sees.
+//
+// Layout: one ring of nsrc * nchan rows, W = Hmax + chunk bytes each, where Hmax is the largest
+// halo of the stream's plans in native samples (D * (max_delay + wmax - 1)).  Two such rings are
+// used alternately: a push copies the last Hmax samples of the previous ring and the new chunk
+// into the other one.  Plan p reads each row's last H_p + chunk samples.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "arts_internal.h"
+
+using namespace arts;
+
+struct arts_stream_s {
+  std::vector<arts_plan_s*> plans;
+  int32_t nsrc = 0, nbeam = 0, nchan = 0;
+  const uint8_t* sb_table = nullptr;
+  int64_t chunk = 0, hmax = 0, W = 0;
+  float thr = 0;
+  uint32_t flags = 0;
+  uint8_t* ring[2] = {nullptr, nullptr};
+  uint8_t* input = nullptr;  // stream-owned staging buffer [nsrc][nchan][chunk]
+  std::vector<int32_t*> series;
+  std::vector<int64_t> L, H;
+  std::vector<int64_t*> s1;
+  std::vector<double*> musig;
+  arts_candidate* d_cand = nullptr;
+  unsigned long long* d_count = nullptr;
+  unsigned long long* h_count = nullptr;  // pinned
+  int64_t cap = 0;
+  hipStream_t hs = nullptr;
+  hipEvent_t ev_in = nullptr, ev_done = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int64_t pushed = 0, waited = 0;
+  int64_t device_bytes = 0;
+  // profiling: events bracketing each phase of the last push
+  std::vector<hipEvent_t> pev;
+  std::vector<double> phase_ms;
+  std::vector<int64_t> phase_n;
+  bool pending_profile = false;
+};
+
+namespace {
+
+constexpr uint32_t kGraph = 1u, kProfile = 2u;
+
+int nphases(const arts_stream_s* s) { return static_cast<int>(s->plans.size()) + 2; }
+
+void stream_free(arts_stream_s* s) {
+  if (!s) return;
+  if (s->hs) (void)hipStreamSynchronize(s->hs);
+  for (auto& g : s->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (auto* r : s->ring)
+    if (r) (void)hipFree(r);
+  if (s->input) (void)hipFree(s->input);
+  for (auto* p : s->series)
+    if (p) (void)hipFree(p);
+  for (auto* p : s->s1)
+    if (p) (void)hipFree(p);
+  for (auto* p : s->musig)
+    if (p) (void)hipFree(p);
+  if (s->d_cand) (void)hipFree(s->d_cand);
+  if (s->d_count) (void)hipFree(s->d_count);
+  if (s->h_count) (void)hipHostFree(s->h_count);
+  for (auto e : s->pev)
+    if (e) (void)hipEventDestroy(e);
+  if (s->ev_in) (void)hipEventDestroy(s->ev_in);
+  if (s->ev_done) (void)hipEventDestroy(s->ev_done);
+  if (s->hs) (void)hipStreamDestroy(s->hs);
+  delete s;
+}
+
+int dev_alloc(arts_stream_s* s, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? ARTS_E_NOMEM : ARTS_E_DEVICE,
+                "stream allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
+  s->device_bytes += static_cast<int64_t>(bytes);
+  return ARTS_OK;
+}
+
+// The device work of one push (ring advance, dedispersion per plan, statistics and
+// candidates); enqueued on s->hs, possibly under graph capture.
+int enqueue_push(arts_stream_s* s, int parity, bool profile) {
+  uint8_t* dst = s->ring[parity];
+  const uint8_t* src = s->ring[parity ^ 1];
+  const int64_t rows = static_cast<int64_t>(s->nsrc) * s->nchan;
+  const int64_t ring_bytes = rows * s->W;
+  auto mark = [&](int i) -> int {
+    if (profile) ARTS_HIP(hipEventRecord(s->pev[i], s->hs));
+    return ARTS_OK;
+  };
+  int ev = 0;
+  if (int st = mark(ev++)) return st;
+  if (int st = launch_copy_rows(dst, s->W, src + s->chunk, s->W, rows, s->hmax, src,
+                                src + ring_bytes, s->hs))
+    return st;
+  if (int st = launch_copy_rows(dst + s->hmax, s->W, s->input, s->chunk, rows, s->chunk,
+                                s->input, s->input + rows * s->chunk, s->hs))
+    return st;
+  if (int st = mark(ev++)) return st;
+  for (size_t p = 0; p < s->plans.size(); ++p) {
+    const arts_plan_s* pl = s->plans[p];
+    const int64_t off = s->hmax - s->H[p];
+    DedispJob job;
+    job.in = dst + off;
+    job.in_bytes = ring_bytes - off;
+    job.nin = s->H[p] + s->chunk;
+    job.pitch = s->W;
+    job.nsrc = s->nsrc;
+    job.sb_table = s->sb_table;
+    job.nbeam = s->nbeam;
+    job.out = s->series[p];
+    job.nout = s->L[p];
+    if (int st = launch_dedisperse(pl, job, s->hs)) return st;
+    if (int st = mark(ev++)) return st;
+  }
+  if (int st = launch_zero_u64(s->d_count, 1, s->hs)) return st;
+  for (size_t p = 0; p < s->plans.size(); ++p) {
+    const arts_plan_s* pl = s->plans[p];
+    const int64_t nrep = s->chunk / pl->ds;
+    const int64_t rows_p = static_cast<int64_t>(s->nbeam) * pl->ndm;
+    if (int st = launch_row_stats(s->series[p], s->L[p], nrep, rows_p, s->s1[p], s->musig[p],
+                                  s->hs))
+      return st;
+    // sample numbers are made absolute on the host: chunk-relative start minus the halo
+    if (int st = launch_candidates(pl, s->series[p], s->nbeam, s->L[p], nrep, s->thr,
+                                   -s->H[p] / pl->ds, 0, s->s1[p], s->musig[p], s->d_cand,
+                                   s->d_count, s->cap, s->hs))
+      return st;
+  }
+  ARTS_HIP(hipMemcpyAsync(s->h_count, s->d_count, sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s->hs));
+  if (int st = mark(ev++)) return st;
+  return ARTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
+                       const uint8_t* sb_table, int32_t nbeam, int64_t chunk, float threshold,
+                       int64_t cand_capacity, uint32_t flags, arts_stream_t* out) {
+  if (!out) return fail(ARTS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!plans || nplan < 1) return fail(ARTS_E_INVAL, "need at least one plan");
+  if (nsrc < 1 || nbeam < 1 || chunk < 1 || cand_capacity < 1 || !std::isfinite(threshold))
+    return fail(ARTS_E_INVAL, "nsrc, nbeam, chunk, capacity must be >= 1; finite threshold");
+  if (!sb_table && nbeam != nsrc)
+    return fail(ARTS_E_INVAL, "without an SB table every source row is one beam");
+  if (sb_table && nsrc > 256) return fail(ARTS_E_INVAL, "at most 256 source beams with a table");
+  if ((flags & kGraph) && (flags & kProfile))
+    return fail(ARTS_E_INVAL, "profiling events are not recorded inside graphs");
+  arts_stream_s* s = new (std::nothrow) arts_stream_s;
+  if (!s) return fail(ARTS_E_NOMEM, "host allocation failed");
+  s->nsrc = nsrc;
+  s->nbeam = nbeam;
+  s->sb_table = sb_table;
+  s->chunk = chunk;
+  s->thr = threshold;
+  s->flags = flags;
+  s->cap = cand_capacity;
+  for (int32_t i = 0; i < nplan; ++i) {
+    arts_plan_s* p = plans[i];
+    if (!p) {
+      stream_free(s);
+      return fail(ARTS_E_INVAL, "plan %d is NULL", i);
+    }
+    if (i > 0 && p->nchan != plans[0]->nchan) {
+      stream_free(s);
+      return fail(ARTS_E_INVAL, "all plans of a stream must have the same channel count");
+    }
+    if (chunk % p->ds != 0) {
+      stream_free(s);
+      return fail(ARTS_E_INVAL, "chunk %lld is not a multiple of plan %d's downsampling %d",
+                  (long long)chunk, i, p->ds);
+    }
+    s->plans.push_back(p);
+    s->H.push_back(static_cast<int64_t>(p->ds) * p->halo);
+    s->L.push_back(chunk / p->ds + p->wmax - 1);
+  }
+  s->nchan = plans[0]->nchan;
+  s->hmax = *std::max_element(s->H.begin(), s->H.end());
+  s->W = s->hmax + chunk;
+  const int64_t rows = static_cast<int64_t>(nsrc) * s->nchan;
+  int st = ARTS_OK;
+  for (int r = 0; r < 2 && st == ARTS_OK; ++r) {
+    st = dev_alloc(s, reinterpret_cast<void**>(&s->ring[r]), rows * s->W);
+    if (st == ARTS_OK && hipMemset(s->ring[r], 0, rows * s->W) != hipSuccess)
+      st = fail(ARTS_E_DEVICE, "ring clear failed");
+  }
+  if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&s->input), rows * chunk);
+  for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
+    int32_t* ser = nullptr;
+    int64_t* a = nullptr;
+    double* b = nullptr;
+    const int64_t nrow = static_cast<int64_t>(nbeam) * s->plans[p]->ndm;
+    st = dev_alloc(s, reinterpret_cast<void**>(&ser), nrow * s->L[p] * sizeof(int32_t));
+    if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&a), nrow * sizeof(int64_t));
+    if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&b), nrow * 2 * sizeof(double));
+    s->series.push_back(ser);
+    s->s1.push_back(a);
+    s->musig.push_back(b);
+  }
+  if (st == ARTS_OK)
+    st = dev_alloc(s, reinterpret_cast<void**>(&s->d_cand), cand_capacity * sizeof(arts_candidate));
+  if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&s->d_count), 64);
+  if (st == ARTS_OK && hipHostMalloc(reinterpret_cast<void**>(&s->h_count), 64) != hipSuccess)
+    st = fail(ARTS_E_NOMEM, "pinned allocation failed");
+  if (st == ARTS_OK && hipStreamCreateWithFlags(&s->hs, hipStreamNonBlocking) != hipSuccess)
+    st = fail(ARTS_E_DEVICE, "stream creation failed");
+  if (st == ARTS_OK && (hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming) != hipSuccess ||
+                        hipEventCreateWithFlags(&s->ev_done, hipEventDisableTiming) != hipSuccess))
+    st = fail(ARTS_E_DEVICE, "event creation failed");
+  if (st == ARTS_OK && (flags & kProfile)) {
+    s->pev.assign(nphases(s) + 1, nullptr);
+    for (auto& e : s->pev)
+      if (hipEventCreate(&e) != hipSuccess) st = fail(ARTS_E_DEVICE, "event creation failed");
+    s->phase_ms.assign(nphases(s), 0.0);
+    s->phase_n.assign(nphases(s), 0);
+  }
+  if (st != ARTS_OK) {
+    stream_free(s);
+    return st;
+  }
+  *out = s;
+  return ARTS_OK;
+}
+
+int arts_stream_input(arts_stream_t s, uint8_t** chunk_buffer) {
+  if (!s || !chunk_buffer) return fail(ARTS_E_INVAL, "NULL argument");
+  *chunk_buffer = s->input;
+  return ARTS_OK;
+}
+
+int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
+  if (!s) return fail(ARTS_E_INVAL, "stream is NULL");
+  if (s->pushed != s->waited)
+    return fail(ARTS_E_STATE, "the previous chunk has not been collected with arts_stream_wait");
+  hipStream_t caller = static_cast<hipStream_t>(stream);
+  ARTS_HIP(hipEventRecord(s->ev_in, caller));
+  ARTS_HIP(hipStreamWaitEvent(s->hs, s->ev_in, 0));
+  const int64_t rows = static_cast<int64_t>(s->nsrc) * s->nchan;
+  if (chunk && chunk != s->input)
+    ARTS_HIP(hipMemcpyAsync(s->input, chunk, rows * s->chunk, hipMemcpyDeviceToDevice, s->hs));
+  const int parity = static_cast<int>(s->pushed & 1);
+  if (s->flags & kGraph) {
+    if (!s->gexec[parity]) {
+      hipGraph_t g = nullptr;
+      ARTS_HIP(hipStreamBeginCapture(s->hs, hipStreamCaptureModeThreadLocal));
+      const int st = enqueue_push(s, parity, false);
+      const hipError_t ce = hipStreamEndCapture(s->hs, &g);
+      if (st != ARTS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (ce != hipSuccess) return fail(ARTS_E_DEVICE, "graph capture: %s", hipGetErrorString(ce));
+      const hipError_t ie = hipGraphInstantiate(&s->gexec[parity], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess)
+        return fail(ARTS_E_DEVICE, "graph instantiate: %s", hipGetErrorString(ie));
+    }
+    ARTS_HIP(hipGraphLaunch(s->gexec[parity], s->hs));
+  } else {
+    if (int st = enqueue_push(s, parity, (s->flags & kProfile) != 0)) return st;
+    s->pending_profile = (s->flags & kProfile) != 0;
+  }
+  ARTS_HIP(hipEventRecord(s->ev_done, s->hs));
+  ++s->pushed;
+  return ARTS_OK;
+}
+
+int arts_stream_wait(arts_stream_t s, arts_candidate* host_out, int64_t capacity, int64_t* count,
+                     int64_t* chunk_index) {
+  if (!s || !count) return fail(ARTS_E_INVAL, "NULL argument");
+  if (s->pushed == s->waited) return fail(ARTS_E_STATE, "nothing pushed");
+  ARTS_HIP(hipEventSynchronize(s->ev_done));
+  const int64_t k = s->pushed - 1;
+  if (chunk_index) *chunk_index = k;
+  if (s->pending_profile) {
+    for (int i = 0; i < nphases(s); ++i) {
+      float ms = 0;
+      ARTS_HIP(hipEventElapsedTime(&ms, s->pev[i], s->pev[i + 1]));
+      s->phase_ms[i] += ms;
+      s->phase_n[i] += 1;
+    }
+    s->pending_profile = false;
+  }
+  s->waited = s->pushed;
+  const int64_t n = static_cast<int64_t>(*s->h_count);
+  *count = n;
+  if (n > s->cap) return fail(ARTS_E_CAPACITY, "%lld candidates, stream capacity %lld",
+                              (long long)n, (long long)s->cap);
+  if (n > capacity) return fail(ARTS_E_CAPACITY, "%lld candidates, capacity %lld",
+                                (long long)n, (long long)capacity);
+  if (n == 0) return ARTS_OK;
+  if (!host_out) return fail(ARTS_E_INVAL, "host_out is NULL");
+  ARTS_HIP(hipMemcpy(host_out, s->d_cand, n * sizeof(arts_candidate), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i) host_out[i].sample += k * s->chunk / host_out[i].downsample;
+  std::sort(host_out, host_out + n, [](const arts_candidate& a, const arts_candidate& b) {
+    if (a.beam != b.beam) return a.beam < b.beam;
+    if (a.downsample != b.downsample) return a.downsample < b.downsample;
+    if (a.dm_index != b.dm_index) return a.dm_index < b.dm_index;
+    if (a.width != b.width) return a.width < b.width;
+    return a.sample < b.sample;
+  });
+  return ARTS_OK;
+}
+
+int arts_stream_info(arts_stream_t s, int64_t* chunks_pushed, int64_t* device_bytes,
+                     int64_t* halo_native) {
+  if (!s) return fail(ARTS_E_INVAL, "stream is NULL");
+  if (chunks_pushed) *chunks_pushed = s->pushed;
+  if (device_bytes) *device_bytes = s->device_bytes;
+  if (halo_native) *halo_native = s->hmax;
+  return ARTS_OK;
+}
+
+int arts_stream_timing(arts_stream_t s, int32_t phase, double* total_ms, int64_t* n) {
+  if (!s || !total_ms || !n) return fail(ARTS_E_INVAL, "NULL argument");
+  if (!(s->flags & kProfile)) return fail(ARTS_E_STATE, "stream was created without profiling");
+  if (phase < 0 || phase >= nphases(s)) return fail(ARTS_E_INVAL, "phase out of range");
+  *total_ms = s->phase_ms[phase];
+  *n = s->phase_n[phase];
+  return ARTS_OK;
+}
+
+int arts_stream_series(arts_stream_t s, int32_t plan_index, const int32_t** series, int64_t* L) {
+  if (!s || !series || !L) return fail(ARTS_E_INVAL, "NULL argument");
+  if (plan_index < 0 || plan_index >= static_cast<int32_t>(s->plans.size()))
+    return fail(ARTS_E_INVAL, "plan index out of range");
+  *series = s->series[plan_index];
+  *L = s->L[plan_index];
+  return ARTS_OK;
+}
+
+int arts_stream_snapshot(arts_stream_t s, uint8_t* host, int64_t bytes, int64_t* chunks_pushed) {
+  if (!s || !chunks_pushed) return fail(ARTS_E_INVAL, "NULL argument");
+  const int64_t need = static_cast<int64_t>(s->nsrc) * s->nchan * s->W;
+  *chunks_pushed = s->pushed;
+  if (!host || bytes < need) return fail(ARTS_E_CAPACITY, "snapshot needs %lld bytes", (long long)need);
+  if (s->pushed != s->waited) return fail(ARTS_E_STATE, "collect the last chunk first");
+  ARTS_HIP(hipStreamSynchronize(s->hs));
+  const uint8_t* cur = s->ring[(s->pushed + 1) & 1];  // ring written by the last push
+  ARTS_HIP(hipMemcpy(host, cur, need, hipMemcpyDeviceToHost));
+  return ARTS_OK;
+}
+
+int arts_stream_restore(arts_stream_t s, const uint8_t* host, int64_t bytes,
+                        int64_t chunks_pushed) {
+  if (!s || !host || chunks_pushed < 0) return fail(ARTS_E_INVAL, "bad argument");
+  const int64_t need = static_cast<int64_t>(s->nsrc) * s->nchan * s->W;
+  if (bytes < need) return fail(ARTS_E_CAPACITY, "restore needs %lld bytes", (long long)need);
+  if (s->pushed != s->waited) return fail(ARTS_E_STATE, "collect the last chunk first");
+  ARTS_HIP(hipStreamSynchronize(s->hs));
+  ARTS_HIP(hipMemcpy(s->ring[(chunks_pushed + 1) & 1], host, need, hipMemcpyHostToDevice));
+  s->pushed = s->waited = chunks_pushed;
+  return ARTS_OK;
+}
+
+void arts_stream_destroy(arts_stream_t s) { stream_free(s); }
+
+}  // extern "C"

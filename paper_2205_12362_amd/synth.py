@@ -170,3 +170,28 @@ def uneven_requests(n: int = 64, seed: int = 4):
                      extra={"nsamp": nsamp})
         reqs.append(w)
     return reqs
+
+
+def random_bursts(delays: np.ndarray, nrep: int, seed: int, n: int = 20, dm_range=(50, 2000),
+                  dms=None, snr_range=(8.0, 40.0), width_range=(1.0, 256.0), sigma=16.0,
+                  margin: int = 600):
+    """n gaussian bursts on trial DMs drawn uniformly in dm_range (dms: the trial DM values),
+    start times uniform over the reported window, log-uniform FWHM, and per-channel amplitude
+    chosen for a target S/N of A * sqrt(w * nchan) / sigma.  delays: the caller's delay table
+    [ndm][nchan] (the arrival sweep).  Returns (bursts, meta) with meta = (dm_index, t0, fwhm,
+    target_snr)."""
+    rng = np.random.default_rng(seed)
+    nchan = delays.shape[1]
+    dms = np.arange(delays.shape[0], dtype=np.float64) if dms is None else np.asarray(dms)
+    lo = int(np.searchsorted(dms, dm_range[0]))
+    hi = int(np.searchsorted(dms, dm_range[1], side="right")) - 1
+    bursts, meta = [], []
+    for _ in range(n):
+        d = int(rng.integers(lo, hi + 1))
+        t0 = int(rng.integers(margin, max(margin + 1, nrep - margin)))
+        fwhm = float(np.exp(rng.uniform(np.log(width_range[0]), np.log(width_range[1]))))
+        target = float(rng.uniform(*snr_range))
+        amp = target * sigma / math.sqrt(max(fwhm, 1.0) * nchan)
+        bursts.append(Burst(t0 + delays[d].astype(np.int64), fwhm, amp))
+        meta.append((d, t0, fwhm, target))
+    return bursts, meta

@@ -1,0 +1,319 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+Integer outputs (delays, dedispersed series, boxcar sums, SB data) must match bit for bit;
+FP32 S/N within 1e-4 relative of the oracle's FP64; candidate sets equal except in (DM, width)
+rows holding an S/N within 1e-4 of the threshold."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2205_12362_amd import arts, synth
+from tests._parity import (compare_candidates, near_threshold_rows, oracle_rows_candidates,
+                           to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _plan(w, variant=None):
+    p = arts.Plan.from_workload(w)
+    if variant is not None:
+        p.set_tiling(variant)
+    return p
+
+
+def _native_variants():
+    return [v for v in range(arts.arts_tiling_count()) if "SPD=4" in arts.arts_tiling_describe(v)]
+
+
+def _ds_variants():
+    return [v for v in range(arts.arts_tiling_count()) if "SPD=2" in arts.arts_tiling_describe(v)]
+
+
+# ------------------------------------------------------------------------ delays / plans
+def test_plan_delays_match_oracle():
+    for w in (synth.cfg_small(), synth.cfg_apertif(), synth.cfg_apertif_ds()):
+        with _plan(w) as p:
+            ref = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms, w.downsample)
+            assert np.array_equal(p.delays(), ref)
+            assert p.max_delay == int(ref.max())
+            assert p.halo == int(ref.max()) + max(w.widths) - 1
+
+
+# ------------------------------------------------------------------------ dedispersion
+def test_dedisperse_small_full():
+    w = synth.cfg_small()
+    _say("dedisperse small full", w.name)
+    delays = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    data = synth.noise((w.nchan, 16384), seed=w.seed)
+    ref = O.dedisperse(data, delays)
+    with _plan(w) as p:
+        got = p.dedisperse(to_dev(data)).cpu().numpy()
+    assert got.shape == (1,) + ref.shape
+    assert np.array_equal(got[0], ref)
+
+
+@pytest.mark.parametrize("variant", _native_variants())
+def test_dedisperse_variants_ragged(variant):
+    # 2 beams, DM count not a multiple of any block, nin odd, several time tiles + ragged tail
+    _say("dedisperse variant", variant, arts.arts_tiling_describe(variant))
+    f_lo, df = synth.band(80)
+    dms = np.arange(101) * 1.7
+    delays = O.delay_table(80, f_lo, df, synth.TSAMP, dms)
+    nin = int(delays.max()) + 3 * 1792 + 77
+    data = np.stack([synth.noise((80, nin), seed=s) for s in (11, 12)])
+    w = synth.Workload("ragged", 80, f_lo, df, synth.TSAMP, dms, [1, 2, 4])
+    with _plan(w, variant) as p:
+        got = p.dedisperse(to_dev(data)).cpu().numpy()
+    for b in range(2):
+        assert np.array_equal(got[b], O.dedisperse(data[b], delays)), b
+
+
+@pytest.mark.parametrize("nchan,ndm,extra", [(1, 1, 1), (3, 5, 2), (37, 33, 1000), (7, 70, 5),
+                                             (255, 9, 300), (256, 40, 64), (300, 3, 33)])
+def test_dedisperse_edge_shapes(nchan, ndm, extra):
+    _say("edge shape", nchan, ndm, extra)
+    f_lo, df = synth.band(nchan)
+    rng = np.random.default_rng(nchan * 1000 + ndm)
+    dms = rng.uniform(0, 300, size=ndm)            # unsorted DM list
+    delays = O.delay_table(nchan, f_lo, df, synth.TSAMP, dms)
+    nin = int(delays.max()) + extra
+    data = rng.integers(0, 256, size=(nchan, nin), dtype=np.uint8)
+    w = synth.Workload("edge", nchan, f_lo, df, synth.TSAMP, dms, [1])
+    with _plan(w) as p:
+        got = p.dedisperse(to_dev(data)).cpu().numpy()[0]
+    assert np.array_equal(got, O.dedisperse(data, delays))
+
+
+def test_dedisperse_extreme_values():
+    # all-255 input: every output equals 255 * nchan (no overflow, no lost channel)
+    w = synth.cfg_apertif()
+    with _plan(w) as p:
+        nin = p.max_delay + 700
+        data = np.full((1536, nin), 255, np.uint8)
+        got = p.dedisperse(to_dev(data)).cpu().numpy()
+    assert got.shape == (1, 2048, 700)
+    assert np.all(got == 255 * 1536)
+
+
+def test_dedisperse_short_input_rejected():
+    w = synth.cfg_small()
+    with _plan(w) as p:
+        data = to_dev(np.zeros((w.nchan, p.max_delay), np.uint8))
+        with pytest.raises(arts.ArtsError) as e:
+            p.dedisperse(data)
+        assert e.value.status == arts.ARTS_E_SHAPE
+
+
+def test_dedisperse_apertif_sampled():
+    # full Apertif shape (1536 ch, 2048 DMs, 12500 new samples + overlap) in the bench's tiling;
+    # the oracle checks 4000 sampled outputs one by one and 6 complete DM rows
+    w = synth.cfg_apertif()
+    delays = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    nin = synth.CHUNK + int(delays.max()) + max(w.widths) - 1
+    bursts, meta = synth.random_bursts(delays, synth.CHUNK, seed=w.seed)
+    data = synth.noise((w.nchan, nin), seed=w.seed, bursts=bursts)
+    _say("apertif sampled: nin", nin)
+    with _plan(w) as p:
+        got = p.dedisperse(to_dev(data)).cpu().numpy()[0]
+    rng = np.random.default_rng(5)
+    L = got.shape[1]
+    for d, t in zip(rng.integers(0, 2048, 4000), rng.integers(0, L, 4000)):
+        assert got[d, t] == O.dedisperse_at(data, delays, d, t), (d, t)
+    rows = [0, 1, 2047, meta[0][0], meta[1][0], int(rng.integers(0, 2048))]
+    full = O.dedisperse(data, delays[rows])
+    # the row-subset oracle's output is shorter when the subset's max delay is smaller
+    for i, d in enumerate(rows):
+        assert np.array_equal(got[d], full[i, :L]), d
+
+
+# ------------------------------------------------------------------------ SB synthesis
+def test_sb_synthesize_small():
+    rng = np.random.default_rng(3)
+    tab = rng.integers(0, 256, size=(12, 96, 1001), dtype=np.uint8)
+    table = synth.sb_table_synthetic(71, 12, 96)
+    got = arts.arts_sb_synthesize(to_dev(tab), to_dev(table)).cpu().numpy()
+    assert np.array_equal(got, O.sb_synthesize(tab, table))
+
+
+def test_sb_synthesize_apertif_rows():
+    tab = synth.noise((12, 1536, 37519), seed=33)
+    table = synth.sb_table_synthetic()
+    got = arts.arts_sb_synthesize(to_dev(tab), to_dev(table))
+    for s in (0, 17, 35, 70):
+        ref = O.sb_synthesize(tab, table[s: s + 1])[0]
+        assert np.array_equal(got[s].cpu().numpy(), ref), s
+
+
+def test_dedisperse_sb_fused_small():
+    f_lo, df = synth.band(64)
+    dms = np.arange(70) * 2.0
+    w = synth.Workload("sb", 64, f_lo, df, synth.TSAMP, dms, [1, 2])
+    delays = O.delay_table(64, f_lo, df, synth.TSAMP, dms)
+    nin = int(delays.max()) + 2000
+    tab = synth.noise((12, 64, nin), seed=44)
+    table = synth.sb_table_synthetic(71, 12, 64)
+    sb = O.sb_synthesize(tab, table)
+    with _plan(w) as p:
+        got = p.dedisperse_sb(to_dev(tab), to_dev(table)).cpu().numpy()
+    for s in range(71):
+        assert np.array_equal(got[s], O.dedisperse(sb[s], delays)), s
+
+
+def test_dedisperse_sb_fused_apertif_sampled():
+    w = synth.cfg_apertif()
+    delays = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    nin = synth.CHUNK + int(delays.max()) + 255
+    tab = synth.noise((12, 1536, nin), seed=55)
+    table = synth.sb_table_synthetic()
+    _say("fused SB apertif")
+    with _plan(w) as p:
+        out = p.dedisperse_sb(to_dev(tab), to_dev(table))
+        rng = np.random.default_rng(9)
+        for s in (0, 35, 70, 23):
+            sb = O.sb_synthesize(tab, table[s: s + 1])[0]
+            got = out[s].cpu().numpy()
+            for d, t in zip(rng.integers(0, 2048, 500), rng.integers(0, got.shape[1], 500)):
+                assert got[d, t] == O.dedisperse_at(sb, delays, d, t), (s, d, t)
+
+
+# ------------------------------------------------------------------------ downsampling
+@pytest.mark.parametrize("variant", _ds_variants())
+@pytest.mark.parametrize("D", [2, 4, 5])
+def test_dedisperse_downsampled(variant, D):
+    f_lo, df = synth.band(96)
+    dms = np.arange(2048, 2200, 2, dtype=np.float64)
+    delays = O.delay_table(96, f_lo, df, synth.TSAMP, dms, downsample=D)
+    nin = (int(delays.max()) + 1500) * D + (D - 1)       # trailing partial group dropped
+    data = synth.noise((2, 96, nin), seed=66 + D)
+    w = synth.Workload("ds", 96, f_lo, df, synth.TSAMP, dms, [1, 2, 4], downsample=D)
+    with _plan(w, variant) as p:
+        got = p.dedisperse(to_dev(data)).cpu().numpy()
+    for b in range(2):
+        ref = O.dedisperse(O.downsample(data[b], D), delays)
+        assert np.array_equal(got[b], ref)
+
+
+# ------------------------------------------------------------------------ boxcar / S/N
+def test_boxcar_snr_small():
+    w = synth.cfg_small()
+    delays = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    data = synth.noise((w.nchan, 16384), seed=w.seed)
+    x = O.dedisperse(data, delays)
+    nrep = x.shape[1] - max(w.widths) + 1
+    with _plan(w) as p:
+        stats, sums, snr = p.boxcar_snr(to_dev(x.astype(np.int32)[None]))
+        stats, sums, snr = stats.cpu().numpy()[0], sums.cpu().numpy()[0], snr.cpu().numpy()[0]
+    mu, sig = O.moments(x, nrep)
+    assert np.allclose(stats[:, 0], mu, rtol=1e-13)
+    assert np.allclose(stats[:, 1], sig, rtol=1e-12)
+    for wi, width in enumerate(w.widths):
+        b = O.boxcar(x, width, nrep)
+        assert np.array_equal(sums[wi], b), width
+        ref = O.snr(b, width, mu, sig)
+        err = np.abs(snr[wi] - ref) / np.maximum(np.abs(ref), 1e-30)
+        ok = (np.abs(ref) < 1e-6) & (np.abs(snr[wi]) < 1e-5) | (err <= 1e-4)
+        assert ok.all(), (width, float(err.max()))
+
+
+def test_boxcar_snr_flat_series():
+    w = synth.cfg_small()
+    with _plan(w) as p:
+        x = np.full((2, w.dms.size, 3000), 777, np.int32)
+        stats, sums, snr = p.boxcar_snr(to_dev(x))
+        assert np.all(stats.cpu().numpy()[..., 1] == 0)
+        assert np.all(snr.cpu().numpy() == 0)
+        assert np.all(sums.cpu().numpy()[:, 2] == 777 * 4)
+        assert len(p.candidates(to_dev(x), 8.0)) == 0
+
+
+# ------------------------------------------------------------------------ candidates
+def test_candidates_small_with_bursts():
+    w = synth.cfg_small()
+    delays = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    bursts = []
+    for dm, t0, fwhm in [(30.0, 3000, 2.0), (70.0, 8000, 4.0), (110.0, 12500, 8.0)]:
+        d = int(np.argmin(np.abs(w.dms - dm)))
+        bursts.append(synth.Burst(t0 + delays[d], fwhm, 48.0))
+    data = synth.noise((w.nchan, 16384), seed=w.seed, bursts=bursts)
+    x, ora = O.search(data, delays, w.widths, w.threshold)
+    nrep = x.shape[1] - max(w.widths) + 1
+    rows = np.arange(x.shape[0])
+    near = near_threshold_rows(x, w.widths, nrep, w.threshold, rows)
+    with _plan(w) as p:
+        series = p.dedisperse(to_dev(data))
+        assert np.array_equal(series.cpu().numpy()[0], x)
+        got = p.candidates(series, w.threshold)
+    assert len(ora) > 10
+    n = compare_candidates(got, ora, near)
+    assert n >= len(ora) - 4
+    assert np.all(got["downsample"] == 1)
+    assert np.allclose(got["dm"], w.dms[got["dm_index"]].astype(np.float32))
+
+
+def test_candidates_offsets_and_capacity():
+    w = synth.cfg_small()
+    delays = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    d = 140
+    data = synth.noise((w.nchan, 16384), seed=7)
+    synth.add_tophat(data, 5000 + delays[d], 8, 40)
+    with _plan(w) as p:
+        series = p.dedisperse(to_dev(data))
+        full = p.candidates(series, 8.0)
+        assert len(full) > 3
+        shifted = p.candidates(series, 8.0, t_offset=1000, beam_offset=7)
+        assert np.array_equal(shifted["sample"], full["sample"] + 1000)
+        assert np.all(shifted["beam"] == 7)
+        with pytest.raises(arts.ArtsError) as e:
+            arts.lib()  # capacity too small: the raw call reports the count
+            import ctypes
+            n = ctypes.c_int64(0)
+            buf = np.zeros(1, dtype=arts.CANDIDATE_DTYPE)
+            st = arts.lib().arts_candidates(p.handle, series.data_ptr(), 1, series.shape[2],
+                                            8.0, 0, 0, buf.ctypes.data, 1, ctypes.byref(n),
+                                            arts._stream(None))
+            assert st == arts.ARTS_E_CAPACITY and n.value == len(full)
+            arts._check(st)
+        assert e.value.status == arts.ARTS_E_CAPACITY
+
+
+def test_candidates_pure_noise_empty():
+    w = synth.cfg_small()
+    data = synth.noise((w.nchan, 16384), seed=99)
+    with _plan(w) as p:
+        got = p.candidates(p.dedisperse(to_dev(data)), 8.0)
+    assert len(got) == 0
+
+
+def test_candidates_apertif_rows():
+    # full-size Apertif chunk with 20 bursts: candidates of 48 DM rows (around the bursts and
+    # random) against the oracle on those rows; the moments use the reported window only
+    w = synth.cfg_apertif()
+    delays = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms)
+    nin = synth.CHUNK + int(delays.max()) + 255
+    bursts, meta = synth.random_bursts(delays, synth.CHUNK, seed=w.seed)
+    data = synth.noise((w.nchan, nin), seed=w.seed, bursts=bursts)
+    _say("apertif candidates")
+    with _plan(w) as p:
+        series = p.dedisperse(to_dev(data))
+        got = p.candidates(series, w.threshold)
+        x_all = series.cpu().numpy()[0]
+    rng = np.random.default_rng(1)
+    rows = sorted(set([m[0] + k for m in meta[:8] for k in (-1, 0, 1)] +
+                      list(rng.integers(0, 2048, 24))))
+    rows = [r for r in rows if 0 <= r < 2048]
+    x_rows = O.dedisperse(data, delays[rows])[:, : x_all.shape[1]]
+    assert np.array_equal(x_rows, x_all[rows])
+    nrep = x_all.shape[1] - 255
+    assert nrep == synth.CHUNK
+    ora = oracle_rows_candidates(x_rows, w.widths, nrep, w.threshold, rows)
+    near = near_threshold_rows(x_rows, w.widths, nrep, w.threshold, rows)
+    sel = got[np.isin(got["dm_index"], rows)]
+    compare_candidates(sel, ora, near)
+    assert len(ora) > 0
