@@ -218,7 +218,8 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream);
 int arts_stream_wait(arts_stream_t s, arts_candidate* host_out, int64_t capacity,
                      int64_t* count, int64_t* chunk_index);
 
-/* Chunks pushed so far, device bytes the stream holds, and the ring overlap in native samples. */
+/* Chunks pushed so far, device bytes the stream holds, and the native ring's overlap in native
+ * samples (0 when every plan is downsampled).                                                 */
 int arts_stream_info(arts_stream_t s, int64_t* chunks_pushed, int64_t* device_bytes,
                      int64_t* halo_native);
 
@@ -229,9 +230,11 @@ int arts_stream_timing(arts_stream_t s, int32_t phase, double* total_ms, int64_t
  * L = chunk / D + wmax - 1 (valid until the next push).                                       */
 int arts_stream_series(arts_stream_t s, int32_t plan_index, const int32_t** series, int64_t* L);
 
-/* Checkpoint / resume: copy the device ring (nsrc * nchan * (halo + chunk) bytes) and the chunk
- * count to the host, and restore them into a stream created with the same arguments.  After a
- * restore the stream continues bit-exactly as the original would have.                       */
+/* Checkpoint / resume: copy the device rings (arts_stream_snapshot_bytes bytes: the native ring,
+ * then each downsampled plan's 16-bit ring) and the chunk count to the host, and restore them
+ * into a stream created with the same arguments.  After a restore the stream continues
+ * bit-exactly as the original would have.  Both need the last chunk collected first.           */
+int arts_stream_snapshot_bytes(arts_stream_t s, int64_t* bytes);
 int arts_stream_snapshot(arts_stream_t s, uint8_t* host, int64_t bytes, int64_t* chunks_pushed);
 int arts_stream_restore(arts_stream_t s, const uint8_t* host, int64_t bytes,
                         int64_t chunks_pushed);

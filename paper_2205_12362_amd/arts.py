@@ -66,6 +66,7 @@ _SIGNATURES = {
     "arts_stream_info": (C.c_int, [_vp, _pi64, _pi64, _pi64]),
     "arts_stream_timing": (C.c_int, [_vp, _i32, _pf64, _pi64]),
     "arts_stream_series": (C.c_int, [_vp, _i32, C.POINTER(_vp), _pi64]),
+    "arts_stream_snapshot_bytes": (C.c_int, [_vp, _pi64]),
     "arts_stream_snapshot": (C.c_int, [_vp, _vp, _i64, _pi64]),
     "arts_stream_restore": (C.c_int, [_vp, _vp, _i64, _i64]),
     "arts_stream_destroy": (None, [_vp]),
@@ -423,7 +424,15 @@ def arts_stream_series(stream_h, plan_index, nbeam, ndm):
     return p.value, L.value
 
 
-def arts_stream_snapshot(stream_h, nbytes):
+def arts_stream_snapshot_bytes(stream_h):
+    n = C.c_int64()
+    _check(lib().arts_stream_snapshot_bytes(stream_h, C.byref(n)))
+    return n.value
+
+
+def arts_stream_snapshot(stream_h, nbytes=None):
+    if nbytes is None:
+        nbytes = arts_stream_snapshot_bytes(stream_h)
     buf = np.zeros(int(nbytes), dtype=np.uint8)
     k = C.c_int64()
     _check(lib().arts_stream_snapshot(stream_h, buf.ctypes.data, buf.size, C.byref(k)))
@@ -481,10 +490,7 @@ class Stream:
         return _tensor_from_ptr(ptr, (self.nbeam, ndm, L), torch.int32, self)
 
     def snapshot(self):
-        info = self.info()
-        nchan = self.plans[0].info["nchan"]
-        return arts_stream_snapshot(self.handle, self.nsrc * nchan * (info["halo_native"] +
-                                                                     self.chunk))
+        return arts_stream_snapshot(self.handle)
 
     def restore(self, buf, chunks_pushed):
         arts_stream_restore(self.handle, buf, chunks_pushed)

@@ -194,8 +194,33 @@ int ensure_cand(arts_plan_s* p, int64_t cap) {
   return ARTS_OK;
 }
 
+int ensure_ds16(arts_plan_s* p, int64_t elems) {
+  if (elems <= p->ds16_cap) return ARTS_OK;
+  if (p->d_ds16) (void)hipFree(p->d_ds16);
+  p->d_ds16 = nullptr;
+  p->ds16_cap = 0;
+  ARTS_HIP(hipMalloc(&p->d_ds16, elems * sizeof(uint16_t)));
+  p->ds16_cap = elems;
+  return ARTS_OK;
+}
+
+// One-shot dedispersion: plans with D > 1 first downsample every source row once.
+static int run_dedisperse(arts_plan_s* p, DedispJob job, hipStream_t s) {
+  if (p->ds > 1) {
+    const int64_t rows = static_cast<int64_t>(job.nsrc) * p->nchan;
+    const int64_t nd = job.nin / p->ds;
+    if (int st = ensure_ds16(p, rows * nd)) return st;
+    if (int st = launch_downsample(p->d_ds16, nd, job.in, job.pitch, rows, nd, p->ds, s))
+      return st;
+    job.in16 = p->d_ds16;
+    job.pitch16 = nd;
+  }
+  return launch_dedisperse(p, job, s);
+}
+
 static void plan_free(arts_plan_s* p) {
   if (!p) return;
+  if (p->d_ds16) (void)hipFree(p->d_ds16);
   free_tiling(p->tiling);
   if (p->d_delays) (void)hipFree(p->d_delays);
   if (p->d_widths) (void)hipFree(p->d_widths);
@@ -218,6 +243,7 @@ static int plan_create(int32_t nchan, double f_lo, double df, double tsamp, cons
     if (widths[i] < 1 || (i > 0 && widths[i] <= widths[i - 1]))
       return fail(ARTS_E_INVAL, "widths must be >= 1 and strictly increasing");
   }
+  if (nwidth > 64) return fail(ARTS_E_INVAL, "at most 64 boxcar widths");
   if (widths[nwidth - 1] > kMaxWidth)
     return fail(ARTS_E_INVAL, "widths above %d samples are not supported", kMaxWidth);
   if (static_cast<int64_t>(nchan) * 255 * ds * widths[nwidth - 1] >= (int64_t(1) << 31))
@@ -402,7 +428,7 @@ int arts_dedisperse(arts_plan_t p, const uint8_t* in, int32_t nbeam, int64_t nin
   job.nbeam = nbeam;
   job.out = out;
   job.nout = L;
-  return launch_dedisperse(p, job, static_cast<hipStream_t>(stream));
+  return run_dedisperse(p, job, static_cast<hipStream_t>(stream));
 }
 
 int arts_dedisperse_sb(arts_plan_t p, const uint8_t* tab, int32_t ntab, const uint8_t* sb_table,
@@ -423,7 +449,7 @@ int arts_dedisperse_sb(arts_plan_t p, const uint8_t* tab, int32_t ntab, const ui
   job.nbeam = nsb;
   job.out = out;
   job.nout = L;
-  return launch_dedisperse(p, job, static_cast<hipStream_t>(stream));
+  return run_dedisperse(p, job, static_cast<hipStream_t>(stream));
 }
 
 int arts_boxcar_snr(arts_plan_t p, const int32_t* series, int32_t nbeam, int64_t L,
@@ -458,7 +484,6 @@ int arts_candidates(arts_plan_t p, const int32_t* series, int32_t nbeam, int64_t
   if (int st = ensure_stats(p, rows)) return st;
   if (int st = ensure_cand(p, capacity)) return st;
   if (int st = launch_zero_u64(p->d_count, 1, s)) return st;
-  if (int st = launch_row_stats(series, L, nrep, rows, p->d_s1, p->d_musig, s)) return st;
   if (int st = launch_candidates(p, series, nbeam, L, nrep, threshold, t_offset, beam_offset,
                                  p->d_s1, p->d_musig, p->d_cand, p->d_count, capacity, s))
     return st;

@@ -63,6 +63,8 @@ struct arts_plan_s {
   arts_candidate* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
   int64_t cand_cap = 0;
+  uint16_t* d_ds16 = nullptr;  // downsampled rows of one-shot calls with D > 1
+  int64_t ds16_cap = 0;        // elements
 };
 
 namespace arts {
@@ -80,6 +82,7 @@ int build_tiling(arts_plan_s* p, int variant);
 void free_tiling(Tiling& t);
 int ensure_stats(arts_plan_s* p, int64_t rows);
 int ensure_cand(arts_plan_s* p, int64_t cap);
+int ensure_ds16(arts_plan_s* p, int64_t elems);
 
 // One dedispersion job: which rows to read and where to write.
 struct DedispJob {
@@ -88,6 +91,8 @@ struct DedispJob {
   int64_t nin = 0;                 // native samples per row
   int64_t pitch = 0;               // bytes between rows (>= nin)
   int32_t nsrc = 0;                // source beams in `in`
+  const uint16_t* in16 = nullptr;  // downsampled rows for plans with D > 1 (nin / D valid)
+  int64_t pitch16 = 0;             // elements between downsampled rows
   const uint8_t* sb_table = nullptr;  // optional [nbeam][nchan] -> source beam index
   int32_t nbeam = 0;
   int32_t* out = nullptr;          // [nbeam][ndm][nout]
@@ -107,6 +112,9 @@ int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam
 int launch_sb_gather(const uint8_t* tab, int32_t ntab, const uint8_t* sb_table, int32_t nsb,
                      int32_t nchan, int64_t nsamp, uint8_t* out, hipStream_t s);
 int launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+// dst[r][s] = sum of D consecutive src bytes, s < nout (16-bit rows, pitches in elements/bytes)
+int launch_downsample(uint16_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch,
+                      int64_t nrows, int64_t nout, int32_t D, hipStream_t s);
 // dst[r * dpitch + i] = src[r * spitch + i] for r < nrows, i < n (byte rows at any alignment)
 int launch_copy_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch,
                      int64_t nrows, int64_t n, const uint8_t* src_begin, const uint8_t* src_end,

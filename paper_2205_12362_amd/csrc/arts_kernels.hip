@@ -56,6 +56,8 @@ struct DedispArgs {
   int64_t nin;        // native samples per input row
   int64_t pitch;      // bytes between input rows
   int64_t nsamp_d;    // nin / D
+  const uint16_t* in16;     // downsampled 16-bit rows (spd = 2 kernels)
+  int64_t pitch16;          // elements between downsampled rows
   const uint8_t* sb_table;  // nullable: row (b, c) reads source beam sb_table[b*nchan + c]
   const int32_t* base;      // [nblk][nchan]
   const int32_t* list;      // [nblk][m_blk][nchan] LDS dword offsets, by chunk then m
@@ -101,6 +103,13 @@ __device__ __forceinline__ void add_half(uint32_t& acc, uint32_t w) {
   else
     asm("v_add_u32_sdwa %0, %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
         : "+v"(acc) : "v"(w));
+}
+
+__device__ __forceinline__ const uint16_t* row_ptr16(const DedispArgs& a, int b, int c) {
+  int src = b;
+  if (a.sb_table) src = a.sb_table[static_cast<int64_t>(b) * a.nchan + c];
+  if (src >= a.nsrc) return nullptr;
+  return a.in16 + (static_cast<int64_t>(src) * a.nchan + c) * a.pitch16;
 }
 
 template <int SPD, int J, int MS>
@@ -225,18 +234,18 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
           dst[k] = v;
         }
       } else {
+        // dword k = downsampled samples ws + 2k, ws + 2k + 1 (16 bits each)
+        const uint16_t* r16 = row_ptr16(a, b, c);
         for (int k = lane; k < a.win; k += 64) {
           uint32_t v = 0;
-          if (row) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int64_t s = ws + 2 * static_cast<int64_t>(k) + h;
-              if (s < a.nsamp_d) {
-                const uint8_t* q = row + s * a.ds;
-                uint32_t sum = 0;
-                for (int i = 0; i < a.ds; ++i) sum += q[i];
-                v |= sum << (16 * h);
-              }
+          if (r16) {
+            const int64_t sidx = ws + 2 * static_cast<int64_t>(k);
+            const uint16_t* q = r16 + sidx;
+            if (sidx + 1 < a.nsamp_d && (reinterpret_cast<uintptr_t>(q) & 3u) == 0) {
+              v = *reinterpret_cast<const uint32_t*>(q);
+            } else {
+              if (sidx < a.nsamp_d) v = q[0];
+              if (sidx + 1 < a.nsamp_d) v |= static_cast<uint32_t>(q[1]) << 16;
             }
           }
           dst[k] = v;
@@ -306,6 +315,9 @@ int launch_dedisperse(const arts_plan_s* p, const DedispJob& job, hipStream_t s)
   a.nin = job.nin;
   a.pitch = job.pitch > 0 ? job.pitch : job.nin;
   a.nsamp_d = job.nin / p->ds;
+  a.in16 = job.in16;
+  a.pitch16 = job.pitch16;
+  if (p->ds > 1 && !job.in16) return fail(ARTS_E_INVAL, "downsampled plan needs 16-bit rows");
   a.sb_table = job.sb_table;
   a.base = t.d_base;
   a.list = t.d_list;
@@ -507,98 +519,260 @@ int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam
 }
 
 // ------------------------------------------------------------------ candidates ----
-// Per (row, segment): for each width, every start sample t of the segment with S/N above the
-// threshold whose predecessor is not above begins a run; the thread that owns t follows the
-// run (into later segments if needed, recomputing B_w from global memory there) and emits one
-// candidate at its largest B_w, earliest on ties.  Runs are rare and short, so the serial walk
-// costs nothing measurable; the test itself is one integer compare per (t, w).
-__device__ __forceinline__ int32_t boxcar_direct(const int32_t* x, int64_t t, int w) {
-  uint32_t acc = 0;
-  for (int j = 0; j < w; ++j) acc += static_cast<uint32_t>(x[t + j]);
-  return static_cast<int32_t>(acc);
+// One workgroup per series row (beam, DM).  Pass 1 computes the row's moments over the
+// reported window exactly as row_stats_kernel does.  Pass 2 walks the window in segments of
+// kCandSeg start samples staged as a prefix sum in LDS; for every width each thread classifies
+// its kCandPT consecutive starts (S/N above threshold <=> B_w > floor(w mu + thr sigma sqrt w)):
+// runs that begin and end inside its range are emitted at once; the leading run fragment (from
+// its first start) and the trailing one (to its last start) are summarised in LDS.  The thread
+// that holds a run's first start then walks the following threads' summaries to the run's end,
+// or to the segment's end, in which case the open run is carried into the next segment.  Every
+// run therefore yields exactly one candidate at its largest B_w (earliest on ties), whatever its
+// length, with O(threads) work for the longest run.
+constexpr int kCandSeg = 4096;
+constexpr int kCandPT = kCandSeg / kBoxThreads;
+constexpr int kMaxWidthsCand = 64;
+
+struct CandOut {
+  arts_candidate* cand;
+  unsigned long long* count;
+  int64_t cap;
+  int64_t t_offset;
+  int32_t beam, dm_index, ds;
+  float dm;
+  long long S1;
+  int64_t N;
+};
+
+__device__ __forceinline__ void emit_cand(const CandOut& o, int64_t t, int32_t best, int w,
+                                          float scale) {
+  const unsigned long long idx = atomicAdd(o.count, 1ULL);
+  if (static_cast<int64_t>(idx) < o.cap) {
+    arts_candidate c;
+    c.sample = t + o.t_offset;
+    c.beam = o.beam;
+    c.dm_index = o.dm_index;
+    c.width = w;
+    c.downsample = o.ds;
+    const long long num = static_cast<long long>(o.N) * best - static_cast<long long>(w) * o.S1;
+    c.snr = static_cast<float>(num) * scale;
+    c.dm = o.dm;
+    o.cand[idx] = c;
+  }
 }
 
 __global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
-    const int32_t* __restrict__ series, int64_t L, int64_t nrep, int32_t ndm, int64_t nseg,
-    const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, const int64_t* __restrict__ s1,
-    const double* __restrict__ musig, const double* __restrict__ dms, double thr,
-    int64_t t_offset, int32_t beam_offset, int32_t ds, arts_candidate* __restrict__ cand,
-    unsigned long long* __restrict__ count, int64_t cap) {
+    const int32_t* __restrict__ series, int64_t L, int64_t nrep, int32_t ndm,
+    const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, const double* __restrict__ dms,
+    double thr, int64_t t_offset, int32_t beam_offset, int32_t ds,
+    arts_candidate* __restrict__ cand, unsigned long long* __restrict__ count, int64_t cap) {
   extern __shared__ uint32_t P[];
   __shared__ uint32_t wsum[4];
-  const int64_t row = blockIdx.x / nseg;
-  const double mu = musig[2 * row], sigma = musig[2 * row + 1];
-  if (!(sigma > 0.0)) return;  // uniform: flat series give no candidates
-  const int64_t s0 = (blockIdx.x % nseg) * kSeg;
-  const int n = static_cast<int>(min<int64_t>(kSeg, nrep - s0));
-  const int ne = n + wmax;
+  __shared__ long long red[2][4];
+  __shared__ long long s_thr[kMaxWidthsCand];
+  __shared__ float s_scale[kMaxWidthsCand];
+  __shared__ int32_t s_wid[kMaxWidthsCand];
+  __shared__ int32_t c_open[2][kMaxWidthsCand], c_best[2][kMaxWidthsCand];
+  __shared__ int64_t c_arg[2][kMaxWidthsCand];
+  __shared__ int32_t t_full[kBoxThreads], t_prelen[kBoxThreads], t_premax[kBoxThreads];
+  __shared__ int32_t t_prearg[kBoxThreads], t_suf[kBoxThreads];
+  __shared__ double s_musig[2];
+
+  const int64_t row = blockIdx.x;
   const int32_t* x = series + row * L;
-  load_prefix(x, L, s0, ne, P, wsum);
-  const int64_t b = row / ndm, d = row % ndm;
-  const long long S1 = s1[row];
-  constexpr int PT = kSeg / kBoxThreads;
-  const int k0 = threadIdx.x * PT;
-  for (int wi = 0; wi < nw; ++wi) {
-    const int w = widths[wi];
-    const WidthParams wp = width_params(w, nrep, mu, sigma, thr);
-    if (k0 >= n) continue;
-    // B_w(t) for t = s0 + k lives at P[k + 1 + w] - P[k + 1]; t = s0 - 1 at k = -1
-    auto Bl = [&](int k) { return static_cast<int32_t>(P[k + 1 + w] - P[k + 1]); };
-    bool prev = (s0 + k0 > 0) && (Bl(k0 - 1) > wp.thr_int);
-    for (int i = 0; i < PT; ++i) {
-      const int k = k0 + i;
-      if (k >= n) break;
-      const int32_t B = Bl(k);
-      const bool above = B > wp.thr_int;
-      if (above && !prev) {
-        int32_t best = B;
-        int64_t bt = s0 + k;
-        for (int64_t u = s0 + k + 1; u < nrep; ++u) {
-          const int32_t Bu = (u < s0 + n) ? Bl(static_cast<int>(u - s0)) : boxcar_direct(x, u, w);
-          if (!(Bu > wp.thr_int)) break;
-          if (Bu > best) {
-            best = Bu;
-            bt = u;
-          }
-        }
-        const unsigned long long idx = atomicAdd(count, 1ULL);
-        if (static_cast<int64_t>(idx) < cap) {
-          arts_candidate c;
-          c.sample = bt + t_offset;
-          c.beam = static_cast<int32_t>(b) + beam_offset;
-          c.dm_index = static_cast<int32_t>(d);
-          c.width = w;
-          c.downsample = ds;
-          const long long num = static_cast<long long>(nrep) * best - static_cast<long long>(w) * S1;
-          c.snr = static_cast<float>(num) * wp.scale;
-          c.dm = static_cast<float>(dms[d]);
-          cand[idx] = c;
-        }
-      }
-      prev = above;
+  const int tid = threadIdx.x;
+  // ---- pass 1: moments over t < nrep (exact int64 sums)
+  {
+    long long s1 = 0, s2 = 0;
+    for (int64_t t = tid; t < nrep; t += kBoxThreads) {
+      const long long v = x[t];
+      s1 += v;
+      s2 += v * v;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s1 += __shfl_xor(s1, off, 64);
+      s2 += __shfl_xor(s2, off, 64);
+    }
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = s1;
+      red[1][tid >> 6] = s2;
     }
   }
+  __syncthreads();
+  const long long S1 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  if (tid == 0) {
+    const long long S2 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const long long N = nrep, m0 = S1 / N, r = S1 - N * m0;
+    const long long S2c = S2 - 2 * m0 * S1 + N * m0 * m0;
+    const double dn = static_cast<double>(N);
+    const double var =
+        (static_cast<double>(S2c) - static_cast<double>(r) * static_cast<double>(r) / dn) / dn;
+    s_musig[0] = static_cast<double>(m0) + static_cast<double>(r) / dn;
+    s_musig[1] = var > 0.0 ? sqrt(var) : 0.0;
+  }
+  __syncthreads();
+  const double mu = s_musig[0], sigma = s_musig[1];
+  if (!(sigma > 0.0)) return;  // uniform: a flat series gives no candidates
+  if (tid < nw) {
+    const WidthParams wp = width_params(widths[tid], nrep, mu, sigma, thr);
+    s_thr[tid] = wp.thr_int;
+    s_scale[tid] = wp.scale;
+    s_wid[tid] = widths[tid];
+    c_open[0][tid] = 0;
+  }
+  CandOut o;
+  o.cand = cand;
+  o.count = count;
+  o.cap = cap;
+  o.t_offset = t_offset;
+  o.beam = static_cast<int32_t>(row / ndm) + beam_offset;
+  o.dm_index = static_cast<int32_t>(row % ndm);
+  o.ds = ds;
+  o.dm = static_cast<float>(dms[row % ndm]);
+  o.S1 = S1;
+  o.N = nrep;
+  int cin = 0;  // carry buffer holding runs open at the previous segment's end
+  const int k0 = tid * kCandPT;
+  for (int64_t s0 = 0; s0 < nrep; s0 += kCandSeg) {
+    const int n = static_cast<int>(min<int64_t>(kCandSeg, nrep - s0));
+    load_prefix(x, L, s0, n + wmax, P, wsum);  // ends with a barrier
+    if (tid < nw) c_open[cin ^ 1][tid] = 0;
+    for (int wi = 0; wi < nw; ++wi) {
+      const int w = s_wid[wi];
+      const long long T = s_thr[wi];
+      // ---- fast path: nothing above threshold in this segment and no run carried in
+      {
+        int32_t bmax = INT_MIN;
+#pragma unroll
+        for (int i = 0; i < kCandPT; ++i) {
+          const int k = k0 + i;
+          if (k < n) bmax = max(bmax, static_cast<int32_t>(P[k + 1 + w] - P[k + 1]));
+        }
+        const bool any = static_cast<long long>(bmax) > T;
+        if (!__syncthreads_or(any ? 1 : 0) && !c_open[cin][wi]) continue;
+      }
+      // ---- classify this thread's starts
+      bool in_pre = true, open = false;
+      int pre_len = 0;
+      int32_t pre_max = 0, best = 0;
+      int pre_arg = 0, arg = 0;
+#pragma unroll
+      for (int i = 0; i < kCandPT; ++i) {
+        const int k = k0 + i;
+        const bool valid = k < n;
+        const int32_t B = valid ? static_cast<int32_t>(P[k + 1 + w] - P[k + 1]) : 0;
+        const bool a = valid && static_cast<long long>(B) > T;
+        if (in_pre) {
+          if (a) {
+            if (pre_len == 0 || B > pre_max) {
+              pre_max = B;
+              pre_arg = k;
+            }
+            ++pre_len;
+          } else {
+            in_pre = false;
+          }
+        } else if (a) {
+          if (!open || B > best) {
+            best = B;
+            arg = k;
+          }
+          open = true;
+        } else if (open) {
+          emit_cand(o, s0 + arg, best, w, s_scale[wi]);  // run inside this thread's range
+          open = false;
+        }
+      }
+      t_full[tid] = in_pre ? 1 : 0;
+      t_prelen[tid] = pre_len;
+      t_premax[tid] = pre_max;
+      t_prearg[tid] = pre_arg;
+      t_suf[tid] = open ? 1 : 0;
+      __syncthreads();
+      // ---- owners: a run whose first start lies in this thread's range.  A thread can own
+      // two runs: one at its first start (or, for thread 0, the run carried over from the
+      // previous segment) and its trailing fragment; at most one of them reaches its last
+      // start, and only that one walks on through the following threads' summaries.
+      bool walk = false;
+      int32_t rb = 0;
+      int64_t ra = 0;
+      if (pre_len > 0) {
+        const bool prev_above =
+            tid == 0 ? (c_open[cin][wi] != 0) : (t_full[tid - 1] || t_suf[tid - 1]);
+        bool own = false;
+        if (!prev_above) {
+          own = true;
+          rb = pre_max;
+          ra = s0 + pre_arg;
+        } else if (tid == 0) {          // continue the run carried from the last segment
+          own = true;
+          rb = c_best[cin][wi];
+          ra = c_arg[cin][wi];
+          if (pre_max > rb) {
+            rb = pre_max;
+            ra = s0 + pre_arg;
+          }
+        }
+        if (own) {
+          if (in_pre)
+            walk = true;                // covers the whole range: continues past it
+          else
+            emit_cand(o, ra, rb, w, s_scale[wi]);
+        }
+      } else if (tid == 0 && c_open[cin][wi]) {
+        // the carried run ended exactly at the segment boundary
+        emit_cand(o, c_arg[cin][wi], c_best[cin][wi], w, s_scale[wi]);
+      }
+      if (open) {                       // trailing fragment begun after a gap
+        walk = true;
+        rb = best;
+        ra = s0 + arg;
+      }
+      if (walk) {
+        bool closed = false;
+        for (int u = tid + 1; !closed && u < kBoxThreads; ++u) {
+          if (t_prelen[u] > 0 && t_premax[u] > rb) {
+            rb = t_premax[u];
+            ra = s0 + t_prearg[u];
+          }
+          if (!t_full[u]) closed = true;
+        }
+        if (closed) {
+          emit_cand(o, ra, rb, w, s_scale[wi]);
+        } else {                        // open at the segment's end: carry it
+          c_open[cin ^ 1][wi] = 1;
+          c_best[cin ^ 1][wi] = rb;
+          c_arg[cin ^ 1][wi] = ra;
+        }
+      }
+      __syncthreads();
+    }
+    cin ^= 1;
+  }
+  if (tid < nw && c_open[cin][tid]) emit_cand(o, c_arg[cin][tid], c_best[cin][tid], s_wid[tid],
+                                              s_scale[tid]);
 }
 
 int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
                       int64_t nrep, float thr, int64_t t_offset, int32_t beam_offset,
-                      const int64_t* s1, const double* musig, arts_candidate* cand,
+                      const int64_t*, const double*, arts_candidate* cand,
                       unsigned long long* count, int64_t cap, hipStream_t s) {
-  const int64_t nseg = (nrep + kSeg - 1) / kSeg;
-  const int64_t nblocks = static_cast<int64_t>(nbeam) * p->ndm * nseg;
-  if (nblocks > INT_MAX) return fail(ARTS_E_INVAL, "candidate grid too large");
-  const size_t lds = (kSeg + p->wmax + 1) * sizeof(uint32_t);
+  const int64_t nrows = static_cast<int64_t>(nbeam) * p->ndm;
+  if (nrows > INT_MAX) return fail(ARTS_E_INVAL, "candidate grid too large");
+  if (p->nwidth > kMaxWidthsCand) return fail(ARTS_E_INVAL, "at most %d widths", kMaxWidthsCand);
+  const size_t lds = (kCandSeg + p->wmax + 1) * sizeof(uint32_t);
   static bool attr = false;
   if (!attr) {
     ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, kBoxLdsMax));
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (kCandSeg + kMaxWidth + 1) * 4));
     attr = true;
   }
   (void)hipGetLastError();
-  hipLaunchKernelGGL(candidates_kernel, dim3(static_cast<unsigned>(nblocks)), dim3(kBoxThreads),
-                     lds, s, series, L, nrep, p->ndm, nseg, p->d_widths, p->nwidth, p->wmax, s1,
-                     musig, p->d_dms, static_cast<double>(thr), t_offset, beam_offset, p->ds,
-                     cand, count, cap);
+  hipLaunchKernelGGL(candidates_kernel, dim3(static_cast<unsigned>(nrows)), dim3(kBoxThreads),
+                     lds, s, series, L, nrep, p->ndm, p->d_widths, p->nwidth, p->wmax, p->d_dms,
+                     static_cast<double>(thr), t_offset, beam_offset, p->ds, cand, count, cap);
   ARTS_HIP(hipGetLastError());
   return ARTS_OK;
 }
@@ -739,6 +913,46 @@ int launch_copy_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t s
   hipLaunchKernelGGL(copy_rows_kernel, dim3(static_cast<unsigned>(nrows * nchunk)),
                      dim3(kGatherThreads), 0, s, dst, dpitch, src, spitch, n, nchunk, src_begin,
                      src_end);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+// ------------------------------------------------------------------ downsampling ----
+// dst[r][s] = sum_{i<D} src[r][D s + i] for s < nout (16-bit: D <= 257).  Each thread makes
+// 4 consecutive outputs; rows whose start is 4-byte aligned are read with dword loads.
+__global__ __launch_bounds__(256) void downsample_rows_kernel(
+    uint16_t* __restrict__ dst, int64_t dpitch, const uint8_t* __restrict__ src, int64_t spitch,
+    int64_t nout, int32_t D, int64_t nblk_row) {
+  const int64_t row = blockIdx.x / nblk_row;
+  const int64_t s0 = ((blockIdx.x % nblk_row) * 256 + threadIdx.x) * 4;
+  if (s0 >= nout) return;
+  const uint8_t* sr = src + row * spitch;
+  uint16_t* dr = dst + row * dpitch;
+  const int nv = static_cast<int>(min<int64_t>(4, nout - s0));
+  uint32_t acc[4] = {0, 0, 0, 0};
+  const uint8_t* q = sr + s0 * D;
+  if ((reinterpret_cast<uintptr_t>(q) & 3u) == 0 && nv == 4) {
+    const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
+    for (int j = 0; j < D; ++j) {  // 4 D bytes = D dwords
+      const uint32_t w = qw[j];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[(4 * j + b) / D] += (w >> (8 * b)) & 0xffu;
+    }
+  } else {
+    for (int i = 0; i < nv; ++i)
+      for (int j = 0; j < D; ++j) acc[i] += q[i * D + j];
+  }
+  for (int i = 0; i < nv; ++i) dr[s0 + i] = static_cast<uint16_t>(acc[i]);
+}
+
+int launch_downsample(uint16_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch,
+                      int64_t nrows, int64_t nout, int32_t D, hipStream_t s) {
+  if (nrows <= 0 || nout <= 0) return ARTS_OK;
+  const int64_t nblk_row = (nout + 1023) / 1024;
+  if (nrows * nblk_row > INT_MAX) return fail(ARTS_E_INVAL, "downsample grid too large");
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(downsample_rows_kernel, dim3(static_cast<unsigned>(nrows * nblk_row)),
+                     dim3(256), 0, s, dst, dpitch, src, spitch, nout, D, nblk_row);
   ARTS_HIP(hipGetLastError());
   return ARTS_OK;
 }

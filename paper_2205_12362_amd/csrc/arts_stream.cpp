@@ -3,10 +3,11 @@
 // the previous samples every trial still needs (the overlap, or halo) resident in device memory,
 // so a chunk's search sees exactly the data a one-shot search of the concatenated series sees.
 //
-// Layout: one ring of nsrc * nchan rows, W = Hmax + chunk bytes each, where Hmax is the largest
-// halo of the stream's plans in native samples (D * (max_delay + wmax - 1)).  Two such rings are
-// used alternately: a push copies the last Hmax samples of the previous ring and the new chunk
-// into the other one.  Plan p reads each row's last H_p + chunk samples.
+// Layout: native plans (D = 1) share one uint8 ring of nsrc * nchan rows of W = Hmax + chunk
+// bytes, Hmax the largest of their halos; plan p reads each row's last H_p + chunk samples.
+// Each downsampled plan (D > 1) has its own 16-bit ring of rows of halo_p + chunk / D sums.
+// Every ring exists twice and the two copies alternate: a push copies the overlap out of the
+// previous copy and appends the new chunk (downsampled for the 16-bit rings) to the other.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -23,12 +24,12 @@ struct arts_stream_s {
   int64_t chunk = 0, hmax = 0, W = 0;
   float thr = 0;
   uint32_t flags = 0;
-  uint8_t* ring[2] = {nullptr, nullptr};
+  uint8_t* ring[2] = {nullptr, nullptr};  // native rows (only if a plan has D = 1)
   uint8_t* input = nullptr;  // stream-owned staging buffer [nsrc][nchan][chunk]
+  std::vector<uint16_t*> ring16[2];        // per plan: downsampled rows (D > 1), else null
+  std::vector<int64_t> W16;                // per plan: 16-bit ring row length
   std::vector<int32_t*> series;
   std::vector<int64_t> L, H;
-  std::vector<int64_t*> s1;
-  std::vector<double*> musig;
   arts_candidate* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
   unsigned long long* h_count = nullptr;  // pinned
@@ -58,12 +59,11 @@ void stream_free(arts_stream_s* s) {
     if (g) (void)hipGraphExecDestroy(g);
   for (auto* r : s->ring)
     if (r) (void)hipFree(r);
+  for (auto& v : s->ring16)
+    for (auto* r : v)
+      if (r) (void)hipFree(r);
   if (s->input) (void)hipFree(s->input);
   for (auto* p : s->series)
-    if (p) (void)hipFree(p);
-  for (auto* p : s->s1)
-    if (p) (void)hipFree(p);
-  for (auto* p : s->musig)
     if (p) (void)hipFree(p);
   if (s->d_cand) (void)hipFree(s->d_cand);
   if (s->d_count) (void)hipFree(s->d_count);
@@ -98,26 +98,50 @@ int enqueue_push(arts_stream_s* s, int parity, bool profile) {
   };
   int ev = 0;
   if (int st = mark(ev++)) return st;
-  if (int st = launch_copy_rows(dst, s->W, src + s->chunk, s->W, rows, s->hmax, src,
-                                src + ring_bytes, s->hs))
-    return st;
-  if (int st = launch_copy_rows(dst + s->hmax, s->W, s->input, s->chunk, rows, s->chunk,
-                                s->input, s->input + rows * s->chunk, s->hs))
-    return st;
+  if (dst) {
+    if (int st = launch_copy_rows(dst, s->W, src + s->chunk, s->W, rows, s->hmax, src,
+                                  src + ring_bytes, s->hs))
+      return st;
+    if (int st = launch_copy_rows(dst + s->hmax, s->W, s->input, s->chunk, rows, s->chunk,
+                                  s->input, s->input + rows * s->chunk, s->hs))
+      return st;
+  }
+  for (size_t p = 0; p < s->plans.size(); ++p) {
+    uint16_t* d16 = s->ring16[parity][p];
+    if (!d16) continue;
+    const uint16_t* s16 = s->ring16[parity ^ 1][p];
+    const int32_t D = s->plans[p]->ds;
+    const int64_t W16 = s->W16[p], new16 = s->chunk / D, keep = W16 - new16;
+    const uint8_t* sb = reinterpret_cast<const uint8_t*>(s16);
+    if (int st = launch_copy_rows(reinterpret_cast<uint8_t*>(d16), 2 * W16, sb + 2 * new16,
+                                  2 * W16, rows, 2 * keep, sb, sb + rows * W16 * 2, s->hs))
+      return st;
+    if (int st = launch_downsample(d16 + keep, W16, s->input, s->chunk, rows, new16, D, s->hs))
+      return st;
+  }
   if (int st = mark(ev++)) return st;
   for (size_t p = 0; p < s->plans.size(); ++p) {
     const arts_plan_s* pl = s->plans[p];
-    const int64_t off = s->hmax - s->H[p];
     DedispJob job;
-    job.in = dst + off;
-    job.in_bytes = ring_bytes - off;
-    job.nin = s->H[p] + s->chunk;
-    job.pitch = s->W;
     job.nsrc = s->nsrc;
     job.sb_table = s->sb_table;
     job.nbeam = s->nbeam;
     job.out = s->series[p];
     job.nout = s->L[p];
+    if (pl->ds == 1) {
+      const int64_t off = s->hmax - s->H[p];
+      job.in = dst + off;
+      job.in_bytes = ring_bytes - off;
+      job.nin = s->H[p] + s->chunk;
+      job.pitch = s->W;
+    } else {
+      job.in = s->input;  // bounds only; the kernel reads the 16-bit ring
+      job.in_bytes = rows * s->chunk;
+      job.nin = s->W16[p] * pl->ds;
+      job.pitch = s->chunk;
+      job.in16 = s->ring16[parity][p];
+      job.pitch16 = s->W16[p];
+    }
     if (int st = launch_dedisperse(pl, job, s->hs)) return st;
     if (int st = mark(ev++)) return st;
   }
@@ -125,13 +149,9 @@ int enqueue_push(arts_stream_s* s, int parity, bool profile) {
   for (size_t p = 0; p < s->plans.size(); ++p) {
     const arts_plan_s* pl = s->plans[p];
     const int64_t nrep = s->chunk / pl->ds;
-    const int64_t rows_p = static_cast<int64_t>(s->nbeam) * pl->ndm;
-    if (int st = launch_row_stats(s->series[p], s->L[p], nrep, rows_p, s->s1[p], s->musig[p],
-                                  s->hs))
-      return st;
     // sample numbers are made absolute on the host: chunk-relative start minus the halo
     if (int st = launch_candidates(pl, s->series[p], s->nbeam, s->L[p], nrep, s->thr,
-                                   -s->H[p] / pl->ds, 0, s->s1[p], s->musig[p], s->d_cand,
+                                   -s->H[p] / pl->ds, 0, nullptr, nullptr, s->d_cand,
                                    s->d_count, s->cap, s->hs))
       return st;
   }
@@ -139,6 +159,23 @@ int enqueue_push(arts_stream_s* s, int parity, bool profile) {
                           hipMemcpyDeviceToHost, s->hs));
   if (int st = mark(ev++)) return st;
   return ARTS_OK;
+}
+
+// Ring segments in snapshot order: the native ring, then each plan's 16-bit ring.
+std::vector<std::pair<uint8_t*, int64_t>> ring_parts(arts_stream_s* s, int parity) {
+  const int64_t rows = static_cast<int64_t>(s->nsrc) * s->nchan;
+  std::vector<std::pair<uint8_t*, int64_t>> v;
+  if (s->ring[parity]) v.push_back({s->ring[parity], rows * s->W});
+  for (size_t p = 0; p < s->plans.size(); ++p)
+    if (s->ring16[parity][p])
+      v.push_back({reinterpret_cast<uint8_t*>(s->ring16[parity][p]), rows * s->W16[p] * 2});
+  return v;
+}
+
+int64_t ring_bytes_total(arts_stream_s* s) {
+  int64_t n = 0;
+  for (auto& pr : ring_parts(s, 0)) n += pr.second;
+  return n;
 }
 
 }  // namespace
@@ -185,29 +222,40 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
     s->plans.push_back(p);
     s->H.push_back(static_cast<int64_t>(p->ds) * p->halo);
     s->L.push_back(chunk / p->ds + p->wmax - 1);
+    s->W16.push_back(p->ds > 1 ? p->halo + chunk / p->ds : 0);
   }
   s->nchan = plans[0]->nchan;
-  s->hmax = *std::max_element(s->H.begin(), s->H.end());
+  s->hmax = 0;
+  bool native = false;
+  for (size_t p = 0; p < s->plans.size(); ++p)
+    if (s->plans[p]->ds == 1) {
+      native = true;
+      s->hmax = std::max(s->hmax, s->H[p]);
+    }
   s->W = s->hmax + chunk;
   const int64_t rows = static_cast<int64_t>(nsrc) * s->nchan;
   int st = ARTS_OK;
   for (int r = 0; r < 2 && st == ARTS_OK; ++r) {
-    st = dev_alloc(s, reinterpret_cast<void**>(&s->ring[r]), rows * s->W);
-    if (st == ARTS_OK && hipMemset(s->ring[r], 0, rows * s->W) != hipSuccess)
-      st = fail(ARTS_E_DEVICE, "ring clear failed");
+    s->ring16[r].assign(s->plans.size(), nullptr);
+    if (native) {
+      st = dev_alloc(s, reinterpret_cast<void**>(&s->ring[r]), rows * s->W);
+      if (st == ARTS_OK && hipMemset(s->ring[r], 0, rows * s->W) != hipSuccess)
+        st = fail(ARTS_E_DEVICE, "ring clear failed");
+    }
+    for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
+      if (s->plans[p]->ds == 1) continue;
+      const int64_t bytes = rows * s->W16[p] * 2;
+      st = dev_alloc(s, reinterpret_cast<void**>(&s->ring16[r][p]), bytes);
+      if (st == ARTS_OK && hipMemset(s->ring16[r][p], 0, bytes) != hipSuccess)
+        st = fail(ARTS_E_DEVICE, "ring clear failed");
+    }
   }
   if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&s->input), rows * chunk);
   for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
     int32_t* ser = nullptr;
-    int64_t* a = nullptr;
-    double* b = nullptr;
     const int64_t nrow = static_cast<int64_t>(nbeam) * s->plans[p]->ndm;
     st = dev_alloc(s, reinterpret_cast<void**>(&ser), nrow * s->L[p] * sizeof(int32_t));
-    if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&a), nrow * sizeof(int64_t));
-    if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&b), nrow * 2 * sizeof(double));
     s->series.push_back(ser);
-    s->s1.push_back(a);
-    s->musig.push_back(b);
   }
   if (st == ARTS_OK)
     st = dev_alloc(s, reinterpret_cast<void**>(&s->d_cand), cand_capacity * sizeof(arts_candidate));
@@ -343,25 +391,39 @@ int arts_stream_series(arts_stream_t s, int32_t plan_index, const int32_t** seri
 
 int arts_stream_snapshot(arts_stream_t s, uint8_t* host, int64_t bytes, int64_t* chunks_pushed) {
   if (!s || !chunks_pushed) return fail(ARTS_E_INVAL, "NULL argument");
-  const int64_t need = static_cast<int64_t>(s->nsrc) * s->nchan * s->W;
+  const int64_t need = ring_bytes_total(s);
   *chunks_pushed = s->pushed;
-  if (!host || bytes < need) return fail(ARTS_E_CAPACITY, "snapshot needs %lld bytes", (long long)need);
+  if (!host || bytes < need)
+    return fail(ARTS_E_CAPACITY, "snapshot needs %lld bytes", (long long)need);
   if (s->pushed != s->waited) return fail(ARTS_E_STATE, "collect the last chunk first");
   ARTS_HIP(hipStreamSynchronize(s->hs));
-  const uint8_t* cur = s->ring[(s->pushed + 1) & 1];  // ring written by the last push
-  ARTS_HIP(hipMemcpy(host, cur, need, hipMemcpyDeviceToHost));
+  int64_t off = 0;
+  for (auto& pr : ring_parts(s, static_cast<int>((s->pushed + 1) & 1))) {  // last written
+    ARTS_HIP(hipMemcpy(host + off, pr.first, pr.second, hipMemcpyDeviceToHost));
+    off += pr.second;
+  }
   return ARTS_OK;
 }
 
 int arts_stream_restore(arts_stream_t s, const uint8_t* host, int64_t bytes,
                         int64_t chunks_pushed) {
   if (!s || !host || chunks_pushed < 0) return fail(ARTS_E_INVAL, "bad argument");
-  const int64_t need = static_cast<int64_t>(s->nsrc) * s->nchan * s->W;
+  const int64_t need = ring_bytes_total(s);
   if (bytes < need) return fail(ARTS_E_CAPACITY, "restore needs %lld bytes", (long long)need);
   if (s->pushed != s->waited) return fail(ARTS_E_STATE, "collect the last chunk first");
   ARTS_HIP(hipStreamSynchronize(s->hs));
-  ARTS_HIP(hipMemcpy(s->ring[(chunks_pushed + 1) & 1], host, need, hipMemcpyHostToDevice));
+  int64_t off = 0;
+  for (auto& pr : ring_parts(s, static_cast<int>((chunks_pushed + 1) & 1))) {
+    ARTS_HIP(hipMemcpy(pr.first, host + off, pr.second, hipMemcpyHostToDevice));
+    off += pr.second;
+  }
   s->pushed = s->waited = chunks_pushed;
+  return ARTS_OK;
+}
+
+int arts_stream_snapshot_bytes(arts_stream_t s, int64_t* bytes) {
+  if (!s || !bytes) return fail(ARTS_E_INVAL, "NULL argument");
+  *bytes = ring_bytes_total(s);
   return ARTS_OK;
 }
 
