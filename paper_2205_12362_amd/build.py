@@ -56,7 +56,10 @@ def build(verbose: bool = False) -> str:
                      src, "-o", obj])
     for src in cpp_srcs:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-        jobs.append([hipcc, "-c", *COMMON, "-D__HIP_PLATFORM_AMD__", src, "-o", obj])
+        # host-only C++ (no device pass)
+        rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+        jobs.append([hipcc, "-c", "-x", "c++", *COMMON, "-D__HIP_PLATFORM_AMD__",
+                     f"-I{rocm}/include", src, "-o", obj])
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:

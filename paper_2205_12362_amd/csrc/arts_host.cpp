@@ -76,14 +76,16 @@ static int compute_delays(int32_t nchan, double f_lo, double df, double tsamp,
 
 void free_tiling(Tiling& t) {
   if (t.d_base) (void)hipFree(t.d_base);
-  if (t.d_list) (void)hipFree(t.d_list);
-  if (t.d_cnt) (void)hipFree(t.d_cnt);
+  for (int g = 0; g < 4; ++g) {
+    if (t.d_list[g]) (void)hipFree(t.d_list[g]);
+    if (t.d_cnt[g]) (void)hipFree(t.d_cnt[g]);
+  }
   t = Tiling{};
 }
 
-// Tables for the dedispersion kernel (see the kernel's description): for each DM block, the
-// window base per channel; for each DM of the block and each channel chunk, the chunk's
-// channels sorted by sub-dword offset m, stored as LDS dword offsets, plus the run lengths.
+// Geometry of the dedispersion kernel for one variant (see the kernel's description): DM
+// blocks, per-block window base per channel, window length and chunking.  The per-alignment
+// offset lists are made by ensure_tables.
 int build_tiling(arts_plan_s* p, int variant) {
   if (variant < 0 || variant >= kNumVariants)
     return fail(ARTS_E_INVAL, "tiling variant %d out of range [0, %d)", variant, kNumVariants);
@@ -93,32 +95,35 @@ int build_tiling(arts_plan_s* p, int variant) {
                 v.spd == 4 ? "native (D = 1)" : "downsampled (D > 1)");
   Tiling t;
   t.variant = variant;
+  t.spd = v.spd;
   t.m_blk = v.acc * v.waves;
   t.nblk = static_cast<int>((p->ndm + t.m_blk - 1) / t.m_blk);
   const int64_t nchan = p->nchan;
   const int shift = v.spd == 4 ? 2 : 1;
-  std::vector<int32_t> rel(static_cast<size_t>(t.nblk) * t.m_blk * nchan, 0);
-  std::vector<int32_t> base(static_cast<size_t>(t.nblk) * nchan, 0);
+  t.rel.assign(static_cast<size_t>(t.nblk) * t.m_blk * nchan, 0);
+  t.base.assign(static_cast<size_t>(t.nblk) * nchan, 0);
   int rmax = 0;
   for (int b = 0; b < t.nblk; ++b) {
     const int d0 = b * t.m_blk, d1 = std::min<int>(p->ndm, d0 + t.m_blk);
     for (int64_t c = 0; c < nchan; ++c) {
       int32_t lo = std::numeric_limits<int32_t>::max();
       for (int d = d0; d < d1; ++d) lo = std::min(lo, p->delays[d * nchan + c]);
-      base[b * nchan + c] = lo;
+      t.base[b * nchan + c] = lo;
       for (int d = d0; d < d1; ++d) {
         const int32_t r = p->delays[d * nchan + c] - lo;
-        rel[(static_cast<int64_t>(b) * t.m_blk + (d - d0)) * nchan + c] = r;
+        t.rel[(static_cast<int64_t>(b) * t.m_blk + (d - d0)) * nchan + c] = r;
         rmax = std::max(rmax, r);
       }
     }
   }
   t.rmax = rmax;
-  // lane 63 reads dwords 63 j + (rel >> shift) .. + j (the last only when m > 0)
-  t.win_dwords = 64 * v.j + (rmax >> shift) + 1;
+  // lane 63 reads dwords 63 j + ((r + g) >> shift) .. + j, with g < spd the window's alignment
+  t.win_dwords = (64 * v.j + ((rmax + v.spd - 1) >> shift) + 1 + 3) & ~3;
   const int64_t budget = p->lds_budget > 0 ? p->lds_budget
                                           : std::max<int64_t>(16 * 1024, 160 * 1024 * v.waves / 16 - 1024);
-  int cc = static_cast<int>(std::min<int64_t>({nchan, 255, budget / (4LL * t.win_dwords)}));
+  // two buffers; per channel its window plus one offset-list entry per DM of the block
+  int cc = static_cast<int>(
+      std::min<int64_t>({nchan, 255, (budget / 2 - 8) / (4LL * (t.win_dwords + t.m_blk))}));
   if (cc >= v.waves) cc -= cc % v.waves;
   if (cc < 1)
     return fail(ARTS_E_INVAL,
@@ -127,21 +132,45 @@ int build_tiling(arts_plan_s* p, int variant) {
                 variant, t.win_dwords * 4, (long long)budget);
   t.cc = cc;
   t.nchunk = static_cast<int>((nchan + cc - 1) / cc);
-  std::vector<int32_t> list(rel.size() + 4, 0);  // +4: the kernel prefetches past a run
+  hipError_t e = hipMalloc(&t.d_base, t.base.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(t.d_base, t.base.data(), t.base.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_tiling(t);
+    return fail(e == hipErrorOutOfMemory ? ARTS_E_NOMEM : ARTS_E_DEVICE,
+                "tiling tables: %s", hipGetErrorString(e));
+  }
+  free_tiling(p->tiling);
+  p->tiling = std::move(t);
+  return ARTS_OK;
+}
+
+// Offset lists for inputs whose pointer has alignment class g0: channel c's window then starts
+// g_c = (g0 + base_c) mod spd samples before its first needed sample, so trial d reads from
+// r = rel + g_c; channels are ordered by m = r mod spd within each chunk.
+int ensure_tables(arts_plan_s* p, int g0) {
+  Tiling& t = p->tiling;
+  if (g0 < 0 || g0 >= t.spd) return fail(ARTS_E_INVAL, "alignment class %d", g0);
+  if (t.d_list[g0]) return ARTS_OK;
+  const int64_t nchan = p->nchan;
+  const int shift = t.spd == 4 ? 2 : 1;
+  std::vector<int32_t> list(t.rel.size(), 0);
   std::vector<uint32_t> cnt(static_cast<size_t>(t.nblk) * t.nchunk * t.m_blk, 0);
   for (int b = 0; b < t.nblk; ++b) {
+    const int32_t* base = &t.base[static_cast<int64_t>(b) * nchan];
     for (int x = 0; x < t.m_blk; ++x) {
-      const int32_t* r = &rel[(static_cast<int64_t>(b) * t.m_blk + x) * nchan];
+      const int32_t* r = &t.rel[(static_cast<int64_t>(b) * t.m_blk + x) * nchan];
       int32_t* l = &list[(static_cast<int64_t>(b) * t.m_blk + x) * nchan];
       for (int ch = 0; ch < t.nchunk; ++ch) {
-        const int c0 = ch * cc, c1 = static_cast<int>(std::min<int64_t>(nchan, c0 + cc));
+        const int c0 = ch * t.cc, c1 = static_cast<int>(std::min<int64_t>(nchan, c0 + t.cc));
         int k = c0;
         uint32_t packed = 0;
-        for (int m = 0; m < v.spd; ++m) {
+        for (int m = 0; m < t.spd; ++m) {
           int n = 0;
           for (int c = c0; c < c1; ++c) {
-            if ((r[c] & (v.spd - 1)) != m) continue;
-            l[k++] = (c - c0) * t.win_dwords + (r[c] >> shift);
+            const int32_t rr = r[c] + ((g0 + base[c]) & (t.spd - 1));
+            if ((rr & (t.spd - 1)) != m) continue;
+            l[k++] = 4 * ((c - c0) * t.win_dwords + (rr >> shift));  // LDS byte offset
             ++n;
           }
           packed |= static_cast<uint32_t>(n) << (8 * m);
@@ -150,22 +179,22 @@ int build_tiling(arts_plan_s* p, int variant) {
       }
     }
   }
-  hipError_t e = hipMalloc(&t.d_base, base.size() * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc(&t.d_list, list.size() * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc(&t.d_cnt, cnt.size() * sizeof(uint32_t));
+  int32_t* dl = nullptr;
+  uint32_t* dc = nullptr;
+  hipError_t e = hipMalloc(&dl, list.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&dc, cnt.size() * sizeof(uint32_t));
   if (e == hipSuccess)
-    e = hipMemcpy(t.d_base, base.data(), base.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(dl, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpy(t.d_list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(t.d_cnt, cnt.data(), cnt.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(dc, cnt.data(), cnt.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    free_tiling(t);
-    return fail(e == hipErrorOutOfMemory ? ARTS_E_NOMEM : ARTS_E_DEVICE,
-                "tiling tables: %s", hipGetErrorString(e));
+    if (dl) (void)hipFree(dl);
+    if (dc) (void)hipFree(dc);
+    return fail(e == hipErrorOutOfMemory ? ARTS_E_NOMEM : ARTS_E_DEVICE, "offset tables: %s",
+                hipGetErrorString(e));
   }
-  free_tiling(p->tiling);
-  p->tiling = t;
+  t.d_list[g0] = dl;
+  t.d_cnt[g0] = dc;
   return ARTS_OK;
 }
 
@@ -204,16 +233,39 @@ int ensure_ds16(arts_plan_s* p, int64_t elems) {
   return ARTS_OK;
 }
 
-// One-shot dedispersion: plans with D > 1 first downsample every source row once.
+int ensure_align(arts_plan_s* p, int64_t bytes) {
+  if (bytes <= p->align_cap) return ARTS_OK;
+  if (p->d_align) (void)hipFree(p->d_align);
+  p->d_align = nullptr;
+  p->align_cap = 0;
+  ARTS_HIP(hipMalloc(&p->d_align, bytes));
+  p->align_cap = bytes;
+  return ARTS_OK;
+}
+
+// One-shot dedispersion.  The kernel needs dword-aligned rows: inputs whose row pitch is not a
+// multiple of 4 are first copied into a padded workspace; plans with D > 1 first downsample
+// every source row once into 16-bit rows of even pitch.
 static int run_dedisperse(arts_plan_s* p, DedispJob job, hipStream_t s) {
+  const int64_t rows = static_cast<int64_t>(job.nsrc) * p->nchan;
   if (p->ds > 1) {
-    const int64_t rows = static_cast<int64_t>(job.nsrc) * p->nchan;
     const int64_t nd = job.nin / p->ds;
-    if (int st = ensure_ds16(p, rows * nd)) return st;
-    if (int st = launch_downsample(p->d_ds16, nd, job.in, job.pitch, rows, nd, p->ds, s))
+    const int64_t pitch16 = (nd + 1) & ~int64_t(1);
+    if (int st = ensure_ds16(p, rows * pitch16)) return st;
+    if (int st = launch_downsample(p->d_ds16, pitch16, job.in, job.pitch, rows, nd, p->ds, s))
       return st;
     job.in16 = p->d_ds16;
-    job.pitch16 = nd;
+    job.in16_elems = rows * pitch16;
+    job.pitch16 = pitch16;
+  } else if (job.pitch % 4 != 0) {
+    const int64_t pitch = (job.nin + 3) & ~int64_t(3);
+    if (int st = ensure_align(p, rows * pitch)) return st;
+    if (int st = launch_copy_rows(p->d_align, pitch, job.in, job.pitch, rows, job.nin, job.in,
+                                  job.in + job.in_bytes, s))
+      return st;
+    job.in = p->d_align;
+    job.pitch = pitch;
+    job.in_bytes = rows * pitch;
   }
   return launch_dedisperse(p, job, s);
 }
@@ -221,6 +273,7 @@ static int run_dedisperse(arts_plan_s* p, DedispJob job, hipStream_t s) {
 static void plan_free(arts_plan_s* p) {
   if (!p) return;
   if (p->d_ds16) (void)hipFree(p->d_ds16);
+  if (p->d_align) (void)hipFree(p->d_align);
   free_tiling(p->tiling);
   if (p->d_delays) (void)hipFree(p->d_delays);
   if (p->d_widths) (void)hipFree(p->d_widths);

@@ -26,18 +26,22 @@ int default_variant(int downsample, int64_t ndm);
 // Widest supported boxcar (the candidate kernels stage a segment plus wmax samples in LDS).
 constexpr int kMaxWidth = 16384;
 
-// Tiling tables of a plan for one variant.
+// Tiling tables of a plan for one variant.  The offset lists depend on the alignment class g0
+// of the input pointer (0..3 for byte rows, 0..1 for 16-bit rows) and are built on first use.
 struct Tiling {
   int variant = -1;
   int m_blk = 0;        // DM trials per workgroup
   int nblk = 0;         // DM blocks
   int rmax = 0;         // largest delay spread inside a block (samples)
-  int win_dwords = 0;   // LDS dwords staged per channel
+  int win_dwords = 0;   // LDS dwords staged per channel (a multiple of 4)
   int cc = 0;           // channels per LDS chunk (<= 255)
   int nchunk = 0;
+  int spd = 4;
+  std::vector<int32_t> rel;    // host [nblk][m_blk][nchan] delay - block base
+  std::vector<int32_t> base;   // host [nblk][nchan]
   int32_t* d_base = nullptr;   // [nblk][nchan] smallest delay of the block in that channel
-  int32_t* d_list = nullptr;   // [nblk][m_blk][nchan] LDS dword offsets, by chunk then m
-  uint32_t* d_cnt = nullptr;   // [nblk][nchunk][m_blk] 4 x 8-bit channel counts per m
+  int32_t* d_list[4] = {};     // per g0: [nblk][m_blk][nchan] LDS byte offsets, chunk then m
+  uint32_t* d_cnt[4] = {};     // per g0: [nblk][nchunk][m_blk] 4 x 8-bit channel counts per m
 };
 
 }  // namespace arts
@@ -65,6 +69,8 @@ struct arts_plan_s {
   int64_t cand_cap = 0;
   uint16_t* d_ds16 = nullptr;  // downsampled rows of one-shot calls with D > 1
   int64_t ds16_cap = 0;        // elements
+  uint8_t* d_align = nullptr;  // dword-aligned copy of one-shot inputs with odd row pitch
+  int64_t align_cap = 0;       // bytes
 };
 
 namespace arts {
@@ -79,10 +85,12 @@ int fail(int status, const char* fmt, ...);
   } while (0)
 
 int build_tiling(arts_plan_s* p, int variant);
+int ensure_tables(arts_plan_s* p, int g0);
 void free_tiling(Tiling& t);
 int ensure_stats(arts_plan_s* p, int64_t rows);
 int ensure_cand(arts_plan_s* p, int64_t cap);
 int ensure_ds16(arts_plan_s* p, int64_t elems);
+int ensure_align(arts_plan_s* p, int64_t bytes);
 
 // One dedispersion job: which rows to read and where to write.
 struct DedispJob {
@@ -92,14 +100,15 @@ struct DedispJob {
   int64_t pitch = 0;               // bytes between rows (>= nin)
   int32_t nsrc = 0;                // source beams in `in`
   const uint16_t* in16 = nullptr;  // downsampled rows for plans with D > 1 (nin / D valid)
-  int64_t pitch16 = 0;             // elements between downsampled rows
+  int64_t in16_elems = 0;          // extent of in16
+  int64_t pitch16 = 0;             // elements between downsampled rows (even)
   const uint8_t* sb_table = nullptr;  // optional [nbeam][nchan] -> source beam index
   int32_t nbeam = 0;
   int32_t* out = nullptr;          // [nbeam][ndm][nout]
   int64_t nout = 0;
 };
 
-int launch_dedisperse(const arts_plan_s* p, const DedispJob& job, hipStream_t s);
+int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s);
 int launch_row_stats(const int32_t* series, int64_t L, int64_t nrep, int64_t nrows,
                      int64_t* s1, double* musig, hipStream_t s);
 int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,

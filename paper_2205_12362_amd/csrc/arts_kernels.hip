@@ -39,16 +39,21 @@ int default_variant(int downsample, int64_t ndm) {
 // is staged once into LDS and then read by every DM trial of the block (the data reuse across
 // neighbouring DMs the paper's kernel is tuned for, Sect. 6b.2 "Dedispersion").
 //
+// Staging is asynchronous and double-buffered: while the waves sum chunk k out of one LDS
+// buffer, direct global->LDS loads (global_load_lds_dwordx4: 16 bytes per lane, no registers)
+// fill the other buffer with chunk k + 1.  A window is loaded from the dword-aligned address at
+// or below its first sample, so channel c's window starts g_c = (row address + base_c) mod 4
+// samples early; the plan folds g_c into its per-channel offsets (one table set per alignment
+// class of the input pointer; rows must be dword-aligned, which the host arranges).
+//
 // Lane l of a wave owns T = spd*j consecutive output samples t0 + l*T + i of `acc` DM trials
 // and keeps their sums in int32 registers.  For channel c and trial d it reads the j+1 LDS
-// dwords holding samples t0 + l*T + rel .. + T - 1, rel = delay[d][c] - base_c.  rel is the
-// same for every lane, and so is its sub-dword offset m = rel mod spd.  The plan sorts each
-// DM's channels (within a chunk) by m, so the kernel runs spd straight-line loops, one per m,
-// in which every sample is added with one v_add_u32 whose source operand is a byte (spd = 4)
-// or a 16-bit half (spd = 2) of an LDS dword (SDWA operand select) and the accumulators stay
-// in place.  With j odd, lanes read dwords j apart, which spreads a wave's reads over all
-// LDS banks.  Windows are staged byte-exact (funnel-shifted out of aligned loads), so m does
-// not depend on the input pointer.
+// dwords holding samples t0 + l*T + r .. + T - 1, r = delay[d][c] - base_c + g_c.  r is the
+// same for every lane, and so is its sub-dword offset m = r mod spd.  The plan sorts each DM's
+// channels (within a chunk) by m, so the kernel runs spd straight-line loops, one per m, in
+// which every sample is added with one v_add_u32 whose source operand is a byte (spd = 4) or a
+// 16-bit half (spd = 2) of an LDS dword (SDWA operand select) and the accumulators stay in
+// place.  With j odd, lanes read dwords j apart, which spreads a wave's reads over all banks.
 
 struct DedispArgs {
   const uint8_t* in;
@@ -57,10 +62,11 @@ struct DedispArgs {
   int64_t pitch;      // bytes between input rows
   int64_t nsamp_d;    // nin / D
   const uint16_t* in16;     // downsampled 16-bit rows (spd = 2 kernels)
+  const uint16_t* in16_end;
   int64_t pitch16;          // elements between downsampled rows
   const uint8_t* sb_table;  // nullable: row (b, c) reads source beam sb_table[b*nchan + c]
   const int32_t* base;      // [nblk][nchan]
-  const int32_t* list;      // [nblk][m_blk][nchan] LDS dword offsets, by chunk then m
+  const int32_t* list;      // [nblk][m_blk][nchan] LDS byte offsets, by chunk then m
   const uint32_t* cnt;      // [nblk][nchunk][m_blk] packed per-m channel counts
   int32_t* out;
   int64_t nout;
@@ -133,38 +139,94 @@ __device__ __forceinline__ void accum(uint32_t* acc, const uint32_t* w) {
   }
 }
 
-// Accumulate n channels whose sub-dword offset is MS.  lst holds their LDS dword offsets; the
-// list is padded so that reading two entries past its end is in bounds.
+// Accumulate n channels whose sub-dword offset is MS.  ent (LDS) holds their byte offsets into
+// the staged windows and is padded so that reading two entries past a run stays in bounds.
+// Software-pipelined one channel deep: the words of the next channel are read from LDS while
+// the current channel's samples are added (two buffers, unrolled by two so no copies remain).
 template <int SPD, int J, int MS>
-__device__ __forceinline__ void accum_run(uint32_t* acc, const int32_t* lst, int n,
-                                          const uint32_t* lane_base) {
+__device__ __forceinline__ void accum_run(uint32_t* acc, const int32_t* ent, int n,
+                                          const uint8_t* lane_base) {
   constexpr int NW = (MS == 0) ? J : J + 1;
   if (n <= 0) return;
-  int e0 = __builtin_amdgcn_readfirstlane(lst[0]);
-  int e1 = __builtin_amdgcn_readfirstlane(lst[1]);
+  uint32_t wa[J + 1], wb[J + 1];
+  {
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[0]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) wa[k] = p[k];
+  }
+  int e = ent[1];
   int i = 0;
-  for (; i + 1 < n; i += 2) {
-    const int f0 = __builtin_amdgcn_readfirstlane(lst[i + 2]);
-    const int f1 = __builtin_amdgcn_readfirstlane(lst[i + 3]);
-    const uint32_t* p0 = lane_base + e0;
-    const uint32_t* p1 = lane_base + e1;
-    uint32_t w0[J + 1], w1[J + 1];
+  for (; i + 2 <= n; i += 2) {
+    const uint32_t* pb = reinterpret_cast<const uint32_t*>(lane_base + e);
 #pragma unroll
-    for (int k = 0; k < NW; ++k) w0[k] = p0[k];
+    for (int k = 0; k < NW; ++k) wb[k] = pb[k];
+    e = ent[i + 2];
+    accum<SPD, J, MS>(acc, wa);
+    const uint32_t* pa = reinterpret_cast<const uint32_t*>(lane_base + e);
 #pragma unroll
-    for (int k = 0; k < NW; ++k) w1[k] = p1[k];
-    accum<SPD, J, MS>(acc, w0);
-    accum<SPD, J, MS>(acc, w1);
-    e0 = f0;
-    e1 = f1;
+    for (int k = 0; k < NW; ++k) wa[k] = pa[k];
+    e = ent[i + 3];
+    accum<SPD, J, MS>(acc, wb);
   }
-  if (i < n) {
-    const uint32_t* p0 = lane_base + e0;
-    uint32_t w0[J + 1];
-#pragma unroll
-    for (int k = 0; k < NW; ++k) w0[k] = p0[k];
-    accum<SPD, J, MS>(acc, w0);
+  if (i < n) accum<SPD, J, MS>(acc, wa);
+}
+
+typedef __attribute__((address_space(1))) const void* global_ptr_t;
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Stage channel windows [c0, c0 + ncc) into buf (cc windows of win dwords, win % 4 == 0), one
+// channel per wave at a time.  Windows that lie inside the input buffer are fetched with
+// asynchronous global->LDS loads (completion: vmcnt); others (input buffer edges, absent rows)
+// are read through registers with per-dword bounds checks.  Samples a window holds beyond its
+// row's valid range only ever feed output samples that are not stored.
+template <int SPD, int WAVES>
+__device__ __forceinline__ void stage_windows(const DedispArgs& a, int b, int64_t t0,
+                                              const int32_t* base_blk, int c0, int ncc,
+                                              uint32_t* buf, int lane, int wave) {
+  for (int jj = wave; jj < ncc; jj += WAVES) {
+    const int c = c0 + jj;
+    const int64_t ws = t0 + base_blk[c];
+    uint32_t* dst = buf + jj * a.win;
+    const uint8_t* first = nullptr;  // byte address of the window's first sample
+    const uint8_t* lo = nullptr;
+    const uint8_t* hi = nullptr;
+    if constexpr (SPD == 4) {
+      const uint8_t* row = row_ptr(a, b, c);
+      if (row) first = row + ws;
+      lo = a.in;
+      hi = a.in_end;
+    } else {
+      const uint16_t* r16 = row_ptr16(a, b, c);
+      if (r16) first = reinterpret_cast<const uint8_t*>(r16 + ws);
+      lo = reinterpret_cast<const uint8_t*>(a.in16);
+      hi = reinterpret_cast<const uint8_t*>(a.in16_end);
+    }
+    const uint32_t* P = reinterpret_cast<const uint32_t*>(
+        reinterpret_cast<uintptr_t>(first) & ~static_cast<uintptr_t>(3));
+    const uint8_t* pb = reinterpret_cast<const uint8_t*>(P);
+    if (first && pb >= lo && pb + 4 * static_cast<int64_t>(a.win) <= hi) {
+      for (int k4 = 4 * lane; k4 < a.win; k4 += 256)  // 16 bytes per lane, 1 KiB per wave
+        __builtin_amdgcn_global_load_lds((global_ptr_t)(P + k4),
+                                         (lds_ptr_t)(dst + (k4 - 4 * lane)), 16, 0, 0);
+    } else {
+      for (int k = lane; k < a.win; k += 64) {
+        uint32_t v = 0;
+        if (first && pb + 4 * k >= lo && pb + 4 * k + 4 <= hi) v = P[k];
+        dst[k] = v;
+      }
+    }
   }
+}
+
+// Copy the chunk's offset lists (all DMs of the block) into ent (m_blk x cc, then 2 pad words).
+template <int WAVES>
+__device__ __forceinline__ void stage_lists(const DedispArgs& a, const int32_t* list_blk, int c0,
+                                            int ncc, int32_t* ent) {
+  for (int q = threadIdx.x; q < a.m_blk * ncc; q += WAVES * 64) {
+    const int x = q / ncc, j = q - x * ncc;
+    ent[x * a.cc + j] = list_blk[static_cast<int64_t>(x) * a.nchan + c0 + j];
+  }
+  if (threadIdx.x < 2) ent[a.m_blk * a.cc + threadIdx.x] = 0;
 }
 
 template <int SPD, int J, int ACC, int WAVES>
@@ -174,6 +236,8 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
   constexpr int TT = 64 * T;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // LDS: two buffers, each cc windows of win dwords followed by the chunk's offset lists
+  const int buf_words = a.cc * a.win + a.m_blk * a.cc + 2;
 
   // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each XCD runs a
   // contiguous range of (beam, time tile, DM block) and neighbouring DM blocks, which read
@@ -196,79 +260,46 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
     for (int i = 0; i < T; ++i) acc[x][i] = 0;
 
   const int32_t* base_blk = a.base + static_cast<int64_t>(blk) * a.nchan;
-  const int32_t* list_wave =
-      a.list + (static_cast<int64_t>(blk) * a.m_blk + wave * ACC) * a.nchan;
+  const int32_t* list_blk = a.list + static_cast<int64_t>(blk) * a.m_blk * a.nchan;
   const uint32_t* cnt_blk = a.cnt + static_cast<int64_t>(blk) * a.nchunk * a.m_blk + wave * ACC;
-  const uint32_t* lane_base = lds + J * lane;
+
+  // prologue: chunk 0 into buffer 0
+  stage_windows<SPD, WAVES>(a, b, t0, base_blk, 0, min(a.cc, a.nchan), lds, lane, wave);
+  stage_lists<WAVES>(a, list_blk, 0, min(a.cc, a.nchan), reinterpret_cast<int32_t*>(lds + a.cc * a.win));
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
   for (int ch = 0; ch < a.nchunk; ++ch) {
+    uint32_t* cur = lds + (ch & 1) * buf_words;
     const int c0 = ch * a.cc;
-    const int ncc = min(a.cc, a.nchan - c0);
-    // ---- stage the chunk's windows into LDS, one channel per wave at a time
-    for (int jj = wave; jj < ncc; jj += WAVES) {
-      const int c = c0 + jj;
-      const uint8_t* row = row_ptr(a, b, c);
-      const int64_t ws = t0 + base_blk[c];
-      uint32_t* dst = lds + static_cast<int64_t>(jj) * a.win;
-      if constexpr (SPD == 4) {
-        // dword k = samples ws + 4k .. ws + 4k + 3, little-endian
-        const uint8_t* a0 = row ? row + ws : a.in;
-        const int ga = static_cast<int>(reinterpret_cast<uintptr_t>(a0) & 3u);
-        const uint32_t* P = reinterpret_cast<const uint32_t*>(a0 - ga);
-        const uint8_t* rend = row + a.nin;
-        for (int k = lane; k < a.win; k += 64) {
-          uint32_t v = 0;
-          if (row) {
-            const uint8_t* q = a0 + 4 * static_cast<int64_t>(k);
-            const uint32_t* pk = P + k;
-            if (q >= row && q + 4 <= rend &&
-                reinterpret_cast<const uint8_t*>(pk) >= a.in &&
-                reinterpret_cast<const uint8_t*>(pk + (ga ? 2 : 1)) <= a.in_end) {
-              v = ga ? __builtin_amdgcn_alignbyte(pk[1], pk[0], ga) : pk[0];
-            } else {
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-                if (q + i >= row && q + i < rend) v |= static_cast<uint32_t>(q[i]) << (8 * i);
-            }
-          }
-          dst[k] = v;
-        }
-      } else {
-        // dword k = downsampled samples ws + 2k, ws + 2k + 1 (16 bits each)
-        const uint16_t* r16 = row_ptr16(a, b, c);
-        for (int k = lane; k < a.win; k += 64) {
-          uint32_t v = 0;
-          if (r16) {
-            const int64_t sidx = ws + 2 * static_cast<int64_t>(k);
-            const uint16_t* q = r16 + sidx;
-            if (sidx + 1 < a.nsamp_d && (reinterpret_cast<uintptr_t>(q) & 3u) == 0) {
-              v = *reinterpret_cast<const uint32_t*>(q);
-            } else {
-              if (sidx < a.nsamp_d) v = q[0];
-              if (sidx + 1 < a.nsamp_d) v |= static_cast<uint32_t>(q[1]) << 16;
-            }
-          }
-          dst[k] = v;
-        }
-      }
+    // ---- start fetching the next chunk into the other buffer
+    if (ch + 1 < a.nchunk) {
+      uint32_t* nxt = lds + ((ch + 1) & 1) * buf_words;
+      const int c1 = c0 + a.cc;
+      const int ncc1 = min(a.cc, a.nchan - c1);
+      stage_windows<SPD, WAVES>(a, b, t0, base_blk, c1, ncc1, nxt, lane, wave);
+      stage_lists<WAVES>(a, list_blk, c1, ncc1, reinterpret_cast<int32_t*>(nxt + a.cc * a.win));
     }
-    __syncthreads();
     // ---- accumulate: each DM trial of the wave over the chunk, one run per sub-dword offset
     if (wave_active) {
+      const int32_t* ent_cur = reinterpret_cast<const int32_t*>(cur + a.cc * a.win);
+      const uint8_t* lane_base = reinterpret_cast<const uint8_t*>(cur) + 4 * J * lane;
 #pragma unroll
       for (int x = 0; x < ACC; ++x) {
         const uint32_t packed = __builtin_amdgcn_readfirstlane(cnt_blk[ch * a.m_blk + x]);
-        const int32_t* lst = list_wave + static_cast<int64_t>(x) * a.nchan + c0;
+        const int32_t* ent = ent_cur + (wave * ACC + x) * a.cc;
         const int n0 = packed & 0xff, n1 = (packed >> 8) & 0xff;
-        accum_run<SPD, J, 0>(acc[x], lst, n0, lane_base);
-        accum_run<SPD, J, 1>(acc[x], lst + n0, n1, lane_base);
+        accum_run<SPD, J, 0>(acc[x], ent, n0, lane_base);
+        accum_run<SPD, J, 1>(acc[x], ent + n0, n1, lane_base);
         if constexpr (SPD == 4) {
           const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
-          accum_run<SPD, J, 2>(acc[x], lst + n0 + n1, n2, lane_base);
-          accum_run<SPD, J, 3>(acc[x], lst + n0 + n1 + n2, n3, lane_base);
+          accum_run<SPD, J, 2>(acc[x], ent + n0 + n1, n2, lane_base);
+          accum_run<SPD, J, 3>(acc[x], ent + n0 + n1 + n2, n3, lane_base);
         }
       }
     }
+    // the next chunk has landed and nobody reads the current buffer any more
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
   if (!wave_active) return;
@@ -289,7 +320,7 @@ template <int SPD, int J, int ACC, int WAVES>
 static int launch_variant(DedispArgs a, hipStream_t s) {
   constexpr int T = SPD * J;
   a.ntt = static_cast<int>((a.nout + 64 * T - 1) / (64 * T));
-  const size_t lds = static_cast<size_t>(a.win) * 4 * a.cc;
+  const size_t lds = 2 * (static_cast<size_t>(a.win) * a.cc + static_cast<size_t>(a.m_blk) * a.cc + 2) * 4;
   if (lds > 160 * 1024) return fail(ARTS_E_INVAL, "LDS request %zu B exceeds 160 KiB", lds);
   a.nwg = static_cast<int64_t>(a.nbeam) * a.ntt * a.nblk;
   if (a.nwg > INT_MAX) return fail(ARTS_E_INVAL, "grid too large (%lld blocks)", (long long)a.nwg);
@@ -307,21 +338,34 @@ static int launch_variant(DedispArgs a, hipStream_t s) {
   return ARTS_OK;
 }
 
-int launch_dedisperse(const arts_plan_s* p, const DedispJob& job, hipStream_t s) {
-  const Tiling& t = p->tiling;
+// Rows must start on dword boundaries (pitch and pointer); the alignment class g0 of the input
+// pointer selects the plan's offset tables.
+int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   DedispArgs a{};
+  int g0 = 0;
+  if (p->ds == 1) {
+    if (job.pitch % 4 != 0) return fail(ARTS_E_INVAL, "internal: row pitch not a multiple of 4");
+    g0 = static_cast<int>(reinterpret_cast<uintptr_t>(job.in) & 3u);
+  } else {
+    if (!job.in16) return fail(ARTS_E_INVAL, "downsampled plan needs 16-bit rows");
+    if (job.pitch16 % 2 != 0 || (reinterpret_cast<uintptr_t>(job.in16) & 1u))
+      return fail(ARTS_E_INVAL, "internal: 16-bit row pitch must be even");
+    g0 = static_cast<int>((reinterpret_cast<uintptr_t>(job.in16) >> 1) & 1u);
+  }
+  if (int st = ensure_tables(p, g0)) return st;
+  const Tiling& t = p->tiling;
   a.in = job.in;
   a.in_end = job.in + job.in_bytes;
   a.nin = job.nin;
   a.pitch = job.pitch > 0 ? job.pitch : job.nin;
   a.nsamp_d = job.nin / p->ds;
   a.in16 = job.in16;
+  a.in16_end = job.in16 ? job.in16 + job.in16_elems : nullptr;
   a.pitch16 = job.pitch16;
-  if (p->ds > 1 && !job.in16) return fail(ARTS_E_INVAL, "downsampled plan needs 16-bit rows");
   a.sb_table = job.sb_table;
   a.base = t.d_base;
-  a.list = t.d_list;
-  a.cnt = t.d_cnt;
+  a.list = t.d_list[g0];
+  a.cnt = t.d_cnt[g0];
   a.out = job.out;
   a.nout = job.nout;
   a.nchan = p->nchan;
@@ -425,7 +469,8 @@ __device__ void load_prefix(const int32_t* __restrict__ x, int64_t L, int64_t s0
     P[k] = (idx >= 0 && idx < L) ? static_cast<uint32_t>(x[idx]) : 0u;
   }
   __syncthreads();
-  const int per = (ne + kBoxThreads - 1) / kBoxThreads;
+  // an odd stride between threads' ranges spreads them over all LDS banks
+  const int per = ((ne + kBoxThreads - 1) / kBoxThreads) | 1;
   const int lo = min(ne, static_cast<int>(threadIdx.x) * per), hi = min(ne, lo + per);
   uint32_t tot = 0;
   for (int k = lo; k < hi; ++k) tot += P[k];
@@ -643,10 +688,11 @@ __global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
       const long long T = s_thr[wi];
       // ---- fast path: nothing above threshold in this segment and no run carried in
       {
+        // starts interleaved across lanes: consecutive lanes read consecutive LDS words
         int32_t bmax = INT_MIN;
 #pragma unroll
         for (int i = 0; i < kCandPT; ++i) {
-          const int k = k0 + i;
+          const int k = tid + i * kBoxThreads;
           if (k < n) bmax = max(bmax, static_cast<int32_t>(P[k + 1 + w] - P[k + 1]));
         }
         const bool any = static_cast<long long>(bmax) > T;

@@ -3,9 +3,10 @@
 // the previous samples every trial still needs (the overlap, or halo) resident in device memory,
 // so a chunk's search sees exactly the data a one-shot search of the concatenated series sees.
 //
-// Layout: native plans (D = 1) share one uint8 ring of nsrc * nchan rows of W = Hmax + chunk
-// bytes, Hmax the largest of their halos; plan p reads each row's last H_p + chunk samples.
-// Each downsampled plan (D > 1) has its own 16-bit ring of rows of halo_p + chunk / D sums.
+// Layout: native plans (D = 1) share one uint8 ring of nsrc * nchan rows holding Hmax + chunk
+// samples (Hmax the largest of their halos; the row pitch W is rounded up to a multiple of 4 so
+// rows stay dword-aligned); plan p reads each row's last H_p + chunk samples.  Each downsampled
+// plan (D > 1) has its own 16-bit ring of rows of halo_p + chunk / D sums (even pitch).
 // Every ring exists twice and the two copies alternate: a push copies the overlap out of the
 // previous copy and appends the new chunk (downsampled for the 16-bit rings) to the other.
 #include <algorithm>
@@ -27,7 +28,8 @@ struct arts_stream_s {
   uint8_t* ring[2] = {nullptr, nullptr};  // native rows (only if a plan has D = 1)
   uint8_t* input = nullptr;  // stream-owned staging buffer [nsrc][nchan][chunk]
   std::vector<uint16_t*> ring16[2];        // per plan: downsampled rows (D > 1), else null
-  std::vector<int64_t> W16;                // per plan: 16-bit ring row length
+  std::vector<int64_t> W16;                // per plan: 16-bit ring row pitch (even)
+  std::vector<int64_t> N16;                // per plan: 16-bit samples held per row
   std::vector<int32_t*> series;
   std::vector<int64_t> L, H;
   arts_candidate* d_cand = nullptr;
@@ -111,7 +113,7 @@ int enqueue_push(arts_stream_s* s, int parity, bool profile) {
     if (!d16) continue;
     const uint16_t* s16 = s->ring16[parity ^ 1][p];
     const int32_t D = s->plans[p]->ds;
-    const int64_t W16 = s->W16[p], new16 = s->chunk / D, keep = W16 - new16;
+    const int64_t W16 = s->W16[p], new16 = s->chunk / D, keep = s->N16[p] - new16;
     const uint8_t* sb = reinterpret_cast<const uint8_t*>(s16);
     if (int st = launch_copy_rows(reinterpret_cast<uint8_t*>(d16), 2 * W16, sb + 2 * new16,
                                   2 * W16, rows, 2 * keep, sb, sb + rows * W16 * 2, s->hs))
@@ -121,7 +123,7 @@ int enqueue_push(arts_stream_s* s, int parity, bool profile) {
   }
   if (int st = mark(ev++)) return st;
   for (size_t p = 0; p < s->plans.size(); ++p) {
-    const arts_plan_s* pl = s->plans[p];
+    arts_plan_s* pl = s->plans[p];
     DedispJob job;
     job.nsrc = s->nsrc;
     job.sb_table = s->sb_table;
@@ -135,11 +137,12 @@ int enqueue_push(arts_stream_s* s, int parity, bool profile) {
       job.nin = s->H[p] + s->chunk;
       job.pitch = s->W;
     } else {
-      job.in = s->input;  // bounds only; the kernel reads the 16-bit ring
+      job.in = s->input;  // unused: the kernel reads the 16-bit ring
       job.in_bytes = rows * s->chunk;
-      job.nin = s->W16[p] * pl->ds;
+      job.nin = s->N16[p] * pl->ds;
       job.pitch = s->chunk;
       job.in16 = s->ring16[parity][p];
+      job.in16_elems = rows * s->W16[p];
       job.pitch16 = s->W16[p];
     }
     if (int st = launch_dedisperse(pl, job, s->hs)) return st;
@@ -222,7 +225,8 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
     s->plans.push_back(p);
     s->H.push_back(static_cast<int64_t>(p->ds) * p->halo);
     s->L.push_back(chunk / p->ds + p->wmax - 1);
-    s->W16.push_back(p->ds > 1 ? p->halo + chunk / p->ds : 0);
+    s->N16.push_back(p->ds > 1 ? p->halo + chunk / p->ds : 0);
+    s->W16.push_back((s->N16.back() + 1) & ~int64_t(1));
   }
   s->nchan = plans[0]->nchan;
   s->hmax = 0;
@@ -232,7 +236,7 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
       native = true;
       s->hmax = std::max(s->hmax, s->H[p]);
     }
-  s->W = s->hmax + chunk;
+  s->W = (s->hmax + chunk + 3) & ~int64_t(3);
   const int64_t rows = static_cast<int64_t>(nsrc) * s->nchan;
   int st = ARTS_OK;
   for (int r = 0; r < 2 && st == ARTS_OK; ++r) {
@@ -251,6 +255,14 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
     }
   }
   if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&s->input), rows * chunk);
+  // offset tables for the alignment class of each plan's window start, made now so that no
+  // allocation happens inside a push (or a captured graph)
+  for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
+    const int g0 = s->plans[p]->ds == 1
+                       ? static_cast<int>((reinterpret_cast<uintptr_t>(s->ring[0]) + s->hmax - s->H[p]) & 3u)
+                       : static_cast<int>((reinterpret_cast<uintptr_t>(s->ring16[0][p]) >> 1) & 1u);
+    st = ensure_tables(s->plans[p], g0);
+  }
   for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
     int32_t* ser = nullptr;
     const int64_t nrow = static_cast<int64_t>(nbeam) * s->plans[p]->ndm;
