@@ -121,10 +121,11 @@ int build_tiling(arts_plan_s* p, int variant) {
   t.win_dwords = (64 * v.j + ((rmax + v.spd - 1) >> shift) + 1 + 3) & ~3;
   const int64_t budget = p->lds_budget > 0 ? p->lds_budget
                                           : std::max<int64_t>(16 * 1024, 160 * 1024 * v.waves / 16 - 1024);
-  // two buffers; per channel its window plus one offset-list entry per DM of the block
+  // two buffers (each with 4 pad words) and an SB-table row; per channel its window plus one
+  // offset-list entry per DM of the block
+  const int64_t per_buf = (budget - ((nchan + 3) & ~int64_t(3))) / 2 - 16;
   int cc = static_cast<int>(
-      std::min<int64_t>({nchan, 255, (budget / 2 - 8) / (4LL * (t.win_dwords + t.m_blk))}));
-  if (cc >= v.waves) cc -= cc % v.waves;
+      std::min<int64_t>({nchan, 255, per_buf / (4LL * (t.win_dwords + t.m_blk))}));
   if (cc < 1)
     return fail(ARTS_E_INVAL,
                 "variant %d: one channel's window (%d B) exceeds the LDS budget (%lld B); the DM "

@@ -75,9 +75,14 @@ struct DedispArgs {
   int32_t m_blk, nblk, win, cc, nchunk, ntt;
 };
 
-__device__ __forceinline__ const uint8_t* row_ptr(const DedispArgs& a, int b, int c) {
-  int src = b;
-  if (a.sb_table) src = a.sb_table[static_cast<int64_t>(b) * a.nchan + c];
+// Source beam of channel c of beam b: b itself, or the SB table entry (read from the LDS copy
+// of the beam's table row, so that staging issues no vector-memory load that would have to be
+// waited for behind the asynchronous window loads).
+__device__ __forceinline__ int src_beam(const DedispArgs& a, const uint8_t* sbrow, int b, int c) {
+  return a.sb_table ? __builtin_amdgcn_readfirstlane(sbrow[c]) : b;
+}
+
+__device__ __forceinline__ const uint8_t* row_ptr(const DedispArgs& a, int src, int c) {
   if (src >= a.nsrc) return nullptr;
   return a.in + (static_cast<int64_t>(src) * a.nchan + c) * a.pitch;
 }
@@ -111,9 +116,7 @@ __device__ __forceinline__ void add_half(uint32_t& acc, uint32_t w) {
         : "+v"(acc) : "v"(w));
 }
 
-__device__ __forceinline__ const uint16_t* row_ptr16(const DedispArgs& a, int b, int c) {
-  int src = b;
-  if (a.sb_table) src = a.sb_table[static_cast<int64_t>(b) * a.nchan + c];
+__device__ __forceinline__ const uint16_t* row_ptr16(const DedispArgs& a, int src, int c) {
   if (src >= a.nsrc) return nullptr;
   return a.in16 + (static_cast<int64_t>(src) * a.nchan + c) * a.pitch16;
 }
@@ -140,35 +143,32 @@ __device__ __forceinline__ void accum(uint32_t* acc, const uint32_t* w) {
 }
 
 // Accumulate n channels whose sub-dword offset is MS.  ent (LDS) holds their byte offsets into
-// the staged windows and is padded so that reading two entries past a run stays in bounds.
-// Software-pipelined one channel deep: the words of the next channel are read from LDS while
-// the current channel's samples are added (two buffers, unrolled by two so no copies remain).
+// the staged windows and is padded so that reading past a run stays in bounds.  Channels are
+// taken four at a time: the four offsets, then the four channels' words are read before any of
+// their samples is added, so one LDS round trip is paid per four channels.
 template <int SPD, int J, int MS>
 __device__ __forceinline__ void accum_run(uint32_t* acc, const int32_t* ent, int n,
                                           const uint8_t* lane_base) {
   constexpr int NW = (MS == 0) ? J : J + 1;
-  if (n <= 0) return;
-  uint32_t wa[J + 1], wb[J + 1];
-  {
-    const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[0]);
-#pragma unroll
-    for (int k = 0; k < NW; ++k) wa[k] = p[k];
-  }
-  int e = ent[1];
   int i = 0;
-  for (; i + 2 <= n; i += 2) {
-    const uint32_t* pb = reinterpret_cast<const uint32_t*>(lane_base + e);
+  for (; i + 4 <= n; i += 4) {
+    uint32_t w[4][J + 1];
 #pragma unroll
-    for (int k = 0; k < NW; ++k) wb[k] = pb[k];
-    e = ent[i + 2];
-    accum<SPD, J, MS>(acc, wa);
-    const uint32_t* pa = reinterpret_cast<const uint32_t*>(lane_base + e);
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i + u]);
 #pragma unroll
-    for (int k = 0; k < NW; ++k) wa[k] = pa[k];
-    e = ent[i + 3];
-    accum<SPD, J, MS>(acc, wb);
+      for (int k = 0; k < NW; ++k) w[u][k] = p[k];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) accum<SPD, J, MS>(acc, w[u]);
   }
-  if (i < n) accum<SPD, J, MS>(acc, wa);
+  for (; i < n; ++i) {
+    uint32_t w[J + 1];
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = p[k];
+    accum<SPD, J, MS>(acc, w);
+  }
 }
 
 typedef __attribute__((address_space(1))) const void* global_ptr_t;
@@ -180,23 +180,24 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 // are read through registers with per-dword bounds checks.  Samples a window holds beyond its
 // row's valid range only ever feed output samples that are not stored.
 template <int SPD, int WAVES>
-__device__ __forceinline__ void stage_windows(const DedispArgs& a, int b, int64_t t0,
-                                              const int32_t* base_blk, int c0, int ncc,
-                                              uint32_t* buf, int lane, int wave) {
+__device__ __forceinline__ void stage_windows(const DedispArgs& a, const uint8_t* sbrow, int b,
+                                              int64_t t0, const int32_t* base_blk, int c0,
+                                              int ncc, uint32_t* buf, int lane, int wave) {
   for (int jj = wave; jj < ncc; jj += WAVES) {
     const int c = c0 + jj;
     const int64_t ws = t0 + base_blk[c];
+    const int src = src_beam(a, sbrow, b, c);
     uint32_t* dst = buf + jj * a.win;
     const uint8_t* first = nullptr;  // byte address of the window's first sample
     const uint8_t* lo = nullptr;
     const uint8_t* hi = nullptr;
     if constexpr (SPD == 4) {
-      const uint8_t* row = row_ptr(a, b, c);
+      const uint8_t* row = row_ptr(a, src, c);
       if (row) first = row + ws;
       lo = a.in;
       hi = a.in_end;
     } else {
-      const uint16_t* r16 = row_ptr16(a, b, c);
+      const uint16_t* r16 = row_ptr16(a, src, c);
       if (r16) first = reinterpret_cast<const uint8_t*>(r16 + ws);
       lo = reinterpret_cast<const uint8_t*>(a.in16);
       hi = reinterpret_cast<const uint8_t*>(a.in16_end);
@@ -218,15 +219,18 @@ __device__ __forceinline__ void stage_windows(const DedispArgs& a, int b, int64_
   }
 }
 
-// Copy the chunk's offset lists (all DMs of the block) into ent (m_blk x cc, then 2 pad words).
+// Fetch the chunk's offset lists (all DMs of the block) into ent (m_blk x cc words) with
+// asynchronous dword global->LDS loads, one DM's list per wave instruction.
 template <int WAVES>
 __device__ __forceinline__ void stage_lists(const DedispArgs& a, const int32_t* list_blk, int c0,
-                                            int ncc, int32_t* ent) {
-  for (int q = threadIdx.x; q < a.m_blk * ncc; q += WAVES * 64) {
-    const int x = q / ncc, j = q - x * ncc;
-    ent[x * a.cc + j] = list_blk[static_cast<int64_t>(x) * a.nchan + c0 + j];
+                                            int ncc, int32_t* ent, int lane, int wave) {
+  for (int x = wave; x < a.m_blk; x += WAVES) {
+    const int32_t* src = list_blk + static_cast<int64_t>(x) * a.nchan + c0;
+    for (int j0 = 0; j0 < ncc; j0 += 64)
+      if (j0 + lane < ncc)
+        __builtin_amdgcn_global_load_lds((global_ptr_t)(src + j0 + lane),
+                                         (lds_ptr_t)(ent + x * a.cc + j0), 4, 0, 0);
   }
-  if (threadIdx.x < 2) ent[a.m_blk * a.cc + threadIdx.x] = 0;
 }
 
 template <int SPD, int J, int ACC, int WAVES>
@@ -236,8 +240,10 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
   constexpr int TT = 64 * T;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // LDS: two buffers, each cc windows of win dwords followed by the chunk's offset lists
-  const int buf_words = a.cc * a.win + a.m_blk * a.cc + 2;
+  // LDS: two buffers, each cc windows of win dwords followed by the chunk's offset lists and
+  // 4 pad words; then (for SB formation) the beam's SB-table row
+  const int buf_words = a.cc * a.win + a.m_blk * a.cc + 4;
+  uint8_t* sbrow = reinterpret_cast<uint8_t*>(lds + 2 * buf_words);
 
   // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each XCD runs a
   // contiguous range of (beam, time tile, DM block) and neighbouring DM blocks, which read
@@ -263,9 +269,16 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
   const int32_t* list_blk = a.list + static_cast<int64_t>(blk) * a.m_blk * a.nchan;
   const uint32_t* cnt_blk = a.cnt + static_cast<int64_t>(blk) * a.nchunk * a.m_blk + wave * ACC;
 
-  // prologue: chunk 0 into buffer 0
-  stage_windows<SPD, WAVES>(a, b, t0, base_blk, 0, min(a.cc, a.nchan), lds, lane, wave);
-  stage_lists<WAVES>(a, list_blk, 0, min(a.cc, a.nchan), reinterpret_cast<int32_t*>(lds + a.cc * a.win));
+  // prologue: pad words, the SB-table row, then chunk 0 into buffer 0
+  if (threadIdx.x < 8) lds[(threadIdx.x >> 2) * buf_words + a.cc * a.win + a.m_blk * a.cc +
+                           (threadIdx.x & 3)] = 0;
+  if (a.sb_table)
+    for (int c = threadIdx.x; c < a.nchan; c += WAVES * 64)
+      sbrow[c] = a.sb_table[static_cast<int64_t>(b) * a.nchan + c];
+  __syncthreads();
+  stage_windows<SPD, WAVES>(a, sbrow, b, t0, base_blk, 0, min(a.cc, a.nchan), lds, lane, wave);
+  stage_lists<WAVES>(a, list_blk, 0, min(a.cc, a.nchan),
+                     reinterpret_cast<int32_t*>(lds + a.cc * a.win), lane, wave);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
@@ -277,8 +290,9 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
       uint32_t* nxt = lds + ((ch + 1) & 1) * buf_words;
       const int c1 = c0 + a.cc;
       const int ncc1 = min(a.cc, a.nchan - c1);
-      stage_windows<SPD, WAVES>(a, b, t0, base_blk, c1, ncc1, nxt, lane, wave);
-      stage_lists<WAVES>(a, list_blk, c1, ncc1, reinterpret_cast<int32_t*>(nxt + a.cc * a.win));
+      stage_windows<SPD, WAVES>(a, sbrow, b, t0, base_blk, c1, ncc1, nxt, lane, wave);
+      stage_lists<WAVES>(a, list_blk, c1, ncc1, reinterpret_cast<int32_t*>(nxt + a.cc * a.win),
+                         lane, wave);
     }
     // ---- accumulate: each DM trial of the wave over the chunk, one run per sub-dword offset
     if (wave_active) {
@@ -320,7 +334,8 @@ template <int SPD, int J, int ACC, int WAVES>
 static int launch_variant(DedispArgs a, hipStream_t s) {
   constexpr int T = SPD * J;
   a.ntt = static_cast<int>((a.nout + 64 * T - 1) / (64 * T));
-  const size_t lds = 2 * (static_cast<size_t>(a.win) * a.cc + static_cast<size_t>(a.m_blk) * a.cc + 2) * 4;
+  const size_t lds = 2 * (static_cast<size_t>(a.win) * a.cc + static_cast<size_t>(a.m_blk) * a.cc + 4) * 4 +
+                     (a.sb_table ? ((static_cast<size_t>(a.nchan) + 3) & ~static_cast<size_t>(3)) : 0);
   if (lds > 160 * 1024) return fail(ARTS_E_INVAL, "LDS request %zu B exceeds 160 KiB", lds);
   a.nwg = static_cast<int64_t>(a.nbeam) * a.ntt * a.nblk;
   if (a.nwg > INT_MAX) return fail(ARTS_E_INVAL, "grid too large (%lld blocks)", (long long)a.nwg);
