@@ -93,7 +93,100 @@ def cpu_baseline(beam, w_native):
                       f"{dt:.1f} s wall on {cores} processes"}
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_2205_12362_amd", "csrc", "arts_kernels.hip")
+PROFILE_JSON = os.path.join(ROOT, "profiles", "dedisperse_serving_chunk.json")
+DOMINANT = "dedisperse_kernel<4, 5, 4, 8>"
+
+
+def kernel_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, if the
+    kernel source has not changed since the counters were taken (else None)."""
+    try:
+        with open(PROFILE_JSON) as f:
+            prof = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if prof.get("kernel_sha") != kernel_hash():
+        return None
+    return prof.get("hbm_bytes_per_launch")
+
+
+def summarize_profile(stats_dir, fetch_dir, write_dir):
+    """Turn rocprofv3 outputs of this script (kernel stats + FETCH_SIZE + WRITE_SIZE passes, each
+    run with --copy-probe) into profiles/dedisperse_serving_chunk.{txt,json}."""
+    import csv
+    import glob
+
+    def rows(d, pattern):
+        f = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+        return list(csv.DictReader(open(f[0]))) if f else []
+
+    stats = rows(stats_dir, "*kernel_stats.csv")
+
+    def per_kernel(d, counter):
+        out = {}
+        for r in rows(d, "*counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+    copy_bytes = float(1 << 30)
+
+    def pick(d, key, largest=False):
+        vals = [x for k, v in d.items() if key in k for x in v]
+        if not vals:
+            return None
+        return max(vals) if largest else sum(vals) / len(vals)
+
+    # the calibration copies are the largest dispatches of the copy kernel (1 GiB each)
+    copy_name = "copyBuffer" if pick(fetch, "copyBuffer") else "elementwise"
+    cf, cw = pick(fetch, copy_name, True), pick(write, copy_name, True)
+    df, dw = pick(fetch, "dedisperse_kernel<4, 5, 4, 8>"), pick(write, "dedisperse_kernel<4, 5, 4, 8>")
+    f_scale = copy_bytes / (cf * 1024) if cf else None   # bytes per KiB reported
+    w_scale = copy_bytes / (cw * 1024) if cw else None
+    traffic = (df * 1024 * f_scale + dw * 1024 * w_scale) if (df and dw and f_scale and w_scale) else None
+    lines = ["rocprofv3 summary: 71-SB serving chunk (bench.py), dominant kernel " + DOMINANT, ""]
+    lines.append("kernel stats (rocprofv3 --kernel-trace --stats):")
+    for r in stats:
+        lines.append(f"  {r['Name'][:70]:70s} calls {r['Calls']:>4s}  avg {float(r['AverageNs'])/1e6:9.3f} ms")
+    lines.append("")
+    lines.append(f"FETCH_SIZE per dispatch (KiB): dedisperse {df}, 1 GiB copy {cf} -> scale {f_scale}")
+    lines.append(f"WRITE_SIZE per dispatch (KiB): dedisperse {dw}, 1 GiB copy {cw} -> scale {w_scale}")
+    lines.append(f"HBM bytes per dedisperse launch (scaled): {traffic}")
+    lines.append("")
+    lines.append("commands (from the repository root, TMPDIR=/tmp):")
+    lines.append("  rocprofv3 --kernel-trace --stats --output-format csv -d <stats_dir> -o bench -- "
+                 "python3 bench.py --steps 4 --warmup 3 --no-cpu-baseline --copy-probe")
+    lines.append("  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o pmc -- "
+                 "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-probe")
+    lines.append("  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write_dir> -o pmc -- "
+                 "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-probe")
+    lines.append("  python3 bench.py --summarize-profile <stats_dir> <fetch_dir> <write_dir>")
+    os.makedirs(os.path.dirname(PROFILE_JSON), exist_ok=True)
+    with open(PROFILE_JSON[:-5] + ".txt", "w") as f:
+        f.write("\n".join(lines) + "\n")
+    dom = [r for r in stats if "dedisperse_kernel<4, 5, 4, 8>" in r["Name"]]
+    with open(PROFILE_JSON, "w") as f:
+        json.dump({"kernel": DOMINANT, "kernel_sha": kernel_hash(),
+                   "avg_ms": float(dom[0]["AverageNs"]) / 1e6 if dom else None,
+                   "fetch_kib": df, "write_kib": dw, "copy_fetch_kib": cf, "copy_write_kib": cw,
+                   "hbm_bytes_per_launch": traffic}, f, indent=1)
+    print("\n".join(lines))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profile":
+        summarize_profile(*sys.argv[2:5])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -101,6 +194,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay each step as a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=None, help="native dedispersion tiling")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, copy 1 GiB twice (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
@@ -185,7 +280,7 @@ def main():
         achieved = adds / dur
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_PK16_ADDS / 1e12,
                     "unit": "Tadd/s", "frac": achieved / PEAK_PK16_ADDS,
-                    "frac_int32_peak": achieved / PEAK_INT32_ADDS, "traffic": None,
+                    "frac_int32_peak": achieved / PEAK_INT32_ADDS, "traffic": measured_traffic(),
                     "kernel": "dedisperse_kernel<4,5,4,8>",
                     "kernel_ms": phases["dedisperse_native"],
                     "adds_per_launch": adds}
@@ -221,6 +316,13 @@ def main():
     }
     stream.close()
     del pool
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
