@@ -172,6 +172,43 @@ int arts_candidates(arts_plan_t plan, const int32_t* series, int32_t nbeam, int6
                     float threshold, int64_t t_offset, int32_t beam_offset,
                     arts_candidate* host_out, int64_t capacity, int64_t* count, void* stream);
 
+/* -------------------------------------------------------------------------- batches ---- */
+
+/* One search request of an uneven batch: its own plan (channel count, DM range, widths, D),
+ * input device uint8 [nbeam][nchan][nin] and output device int32 [nbeam][ndm][L],
+ * L = nin/D - max_delay (as for arts_dedisperse).                                            */
+typedef struct arts_request {
+  arts_plan_t plan;
+  const uint8_t* in;
+  int32_t nbeam;
+  int64_t nin;
+  int32_t* out;
+} arts_request;
+
+typedef struct arts_batch_s* arts_batch_t;
+/* A batch context: descriptor storage and per-request workspaces reused across calls.        */
+int arts_batch_create(arts_batch_t* out);
+void arts_batch_destroy(arts_batch_t b);
+
+/* Dedisperse n requests: every request's tiles (beam, time tile, DM block) go into one
+ * persistent launch per tiling variant present (the DM trials of the paper's search are
+ * spread over GPUs by range, Sect. 9h; here uneven requests share one GPU launch).  Tiles
+ * are taken from one device work queue, most expensive first.  status (nullable, [n]) gets
+ * ARTS_OK, ARTS_E_INVAL (bad request) or ARTS_E_SHAPE (input shorter than the plan's halo;
+ * skipped) per request.  Each output equals the request's own arts_dedisperse call bit for
+ * bit.  Requests must not share an output buffer.  Asynchronous on `stream`.                 */
+int arts_batch_dedisperse(arts_batch_t b, const arts_request* reqs, int32_t n, int32_t* status,
+                          void* stream);
+
+/* Threshold candidates of n dedispersed requests (as arts_candidates, request by request) into
+ * one list: a candidate's beam is the request's first beam index (the sum of nbeam of the
+ * requests before it) plus its beam within the request.  Sorted by (beam, dm_index, width,
+ * sample); synchronises `stream`; ARTS_E_CAPACITY with *count = required if too small.
+ * Requests skipped as too short contribute nothing.                                          */
+int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, float threshold,
+                          arts_candidate* host_out, int64_t capacity, int64_t* count,
+                          void* stream);
+
 /* ------------------------------------------------------------------------ streaming ---- */
 
 /* A streaming search over consecutive chunks (the real-time search processes 1.024 s chunks

@@ -25,6 +25,11 @@ class ArtsError(RuntimeError):
         super().__init__(what)
 
 
+class Request(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("in_", C.c_void_p), ("nbeam", C.c_int32),
+                ("nin", C.c_int64), ("out", C.c_void_p)]
+
+
 class Candidate(C.Structure):
     _fields_ = [("sample", C.c_int64), ("beam", C.c_int32), ("dm_index", C.c_int32),
                 ("width", C.c_int32), ("downsample", C.c_int32), ("snr", C.c_float),
@@ -70,6 +75,10 @@ _SIGNATURES = {
     "arts_stream_snapshot": (C.c_int, [_vp, _vp, _i64, _pi64]),
     "arts_stream_restore": (C.c_int, [_vp, _vp, _i64, _i64]),
     "arts_stream_destroy": (None, [_vp]),
+    "arts_batch_create": (C.c_int, [C.POINTER(_vp)]),
+    "arts_batch_destroy": (None, [_vp]),
+    "arts_batch_dedisperse": (C.c_int, [_vp, _vp, _i32, _pi32, _vp]),
+    "arts_batch_candidates": (C.c_int, [_vp, _vp, _i32, _f32, _vp, _i64, _pi64, _vp]),
     "arts_strerror": (C.c_char_p, [C.c_int]),
     "arts_last_error": (C.c_char_p, []),
     "arts_version": (C.c_char_p, []),
@@ -526,3 +535,85 @@ def _tensor_from_ptr(ptr, shape, dtype, owner):
     t = torch.as_tensor(_Holder(ptr, 0, tuple(shape), typestr), device="cuda")
     t._arts_owner = owner
     return t
+
+
+# ---------------------------------------------------------------------------- batches
+def arts_batch_create():
+    h = _vp()
+    _check(lib().arts_batch_create(C.byref(h)))
+    return h
+
+
+def arts_batch_destroy(batch_h):
+    lib().arts_batch_destroy(batch_h)
+
+
+def _requests(items):
+    """items: (Plan, input tensor [nbeam][nchan][nin] uint8, output tensor int32)."""
+    import torch
+    arr = (Request * len(items))()
+    for i, (plan, data, out) in enumerate(items):
+        nbeam, nchan, nin = data.shape
+        arr[i].plan = plan.handle if isinstance(plan, Plan) else plan
+        arr[i].in_ = _dev(data, torch.uint8, "in")
+        arr[i].nbeam = nbeam
+        arr[i].nin = nin
+        arr[i].out = _dev(out, torch.int32, "out")
+    return arr
+
+
+def arts_batch_dedisperse(batch_h, items, stream=None):
+    """Returns the per-request status list (0 = done, ARTS_E_SHAPE = too short, skipped)."""
+    arr = _requests(items)
+    st = (C.c_int32 * len(items))()
+    _check(lib().arts_batch_dedisperse(batch_h, arr, len(items), st, _stream(stream)))
+    return list(st)
+
+
+def arts_batch_candidates(batch_h, items, threshold, capacity=1 << 18, stream=None):
+    arr = _requests(items)
+    for _ in range(2):
+        buf = np.zeros(max(int(capacity), 1), dtype=CANDIDATE_DTYPE)
+        n = C.c_int64(0)
+        st = lib().arts_batch_candidates(batch_h, arr, len(items), float(threshold),
+                                         buf.ctypes.data, int(capacity), C.byref(n),
+                                         _stream(stream))
+        if st == ARTS_E_CAPACITY:
+            capacity = n.value
+            continue
+        _check(st)
+        return buf[: n.value].copy()
+    _check(st)
+
+
+class Batch:
+    def __init__(self):
+        self.handle = arts_batch_create()
+
+    def dedisperse(self, items, stream=None):
+        return arts_batch_dedisperse(self.handle, items, stream)
+
+    def candidates(self, items, threshold, **kw):
+        return arts_batch_candidates(self.handle, items, threshold, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            arts_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def series_length(plan, nin):
+    info = plan.info if isinstance(plan, Plan) else arts_plan_info(plan)
+    return nin // info["downsample"] - info["max_delay"]

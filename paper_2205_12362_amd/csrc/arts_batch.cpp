@@ -1,0 +1,163 @@
+// Uneven batches: many search requests of different channel counts, lengths and DM ranges
+// dedispersed in one persistent launch per tiling variant (a work queue of tiles over all
+// requests), then thresholded request by request into one candidate list.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <new>
+
+#include "arts_internal.h"
+
+using namespace arts;
+
+struct arts_batch_s {
+  BatchBuffers bb;
+  // per-request workspaces: dword-aligned copies (D = 1, odd row length) or 16-bit rows (D > 1)
+  std::vector<uint8_t*> ws;
+  std::vector<int64_t> ws_cap;
+  arts_candidate* d_cand = nullptr;
+  unsigned long long* d_count = nullptr;
+  int64_t cand_cap = 0;
+};
+
+namespace {
+
+int ensure_ws(arts_batch_s* b, int i, int64_t bytes) {
+  if (static_cast<int>(b->ws.size()) <= i) {
+    b->ws.resize(i + 1, nullptr);
+    b->ws_cap.resize(i + 1, 0);
+  }
+  if (bytes <= b->ws_cap[i]) return ARTS_OK;
+  if (b->ws[i]) (void)hipFree(b->ws[i]);
+  b->ws[i] = nullptr;
+  b->ws_cap[i] = 0;
+  ARTS_HIP(hipMalloc(&b->ws[i], bytes));
+  b->ws_cap[i] = bytes;
+  return ARTS_OK;
+}
+
+int64_t series_len(const arts_plan_s* p, int64_t nin) { return nin / p->ds - p->max_delay; }
+
+}  // namespace
+
+extern "C" {
+
+int arts_batch_create(arts_batch_t* out) {
+  if (!out) return fail(ARTS_E_INVAL, "out is NULL");
+  *out = new (std::nothrow) arts_batch_s;
+  return *out ? ARTS_OK : fail(ARTS_E_NOMEM, "host allocation failed");
+}
+
+void arts_batch_destroy(arts_batch_t b) {
+  if (!b) return;
+  for (auto* p : b->ws)
+    if (p) (void)hipFree(p);
+  if (b->d_cand) (void)hipFree(b->d_cand);
+  if (b->d_count) (void)hipFree(b->d_count);
+  delete b;
+}
+
+int arts_batch_dedisperse(arts_batch_t b, const arts_request* reqs, int32_t n, int32_t* status,
+                          void* stream) {
+  if (!b || (!reqs && n > 0) || n < 0) return fail(ARTS_E_INVAL, "bad batch arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::map<int, std::pair<std::vector<arts_plan_s*>, std::vector<DedispJob>>> groups;
+  int nok = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const arts_request& r = reqs[i];
+    int st = ARTS_OK;
+    if (!r.plan || !r.in || !r.out || r.nbeam < 1 || r.nin < 1) st = ARTS_E_INVAL;
+    else if (series_len(r.plan, r.nin) < 1) st = ARTS_E_SHAPE;
+    if (status) status[i] = st;
+    if (st != ARTS_OK) continue;
+    arts_plan_s* p = r.plan;
+    DedispJob job;
+    job.in = r.in;
+    job.in_bytes = static_cast<int64_t>(r.nbeam) * p->nchan * r.nin;
+    job.nin = r.nin;
+    job.pitch = r.nin;
+    job.nsrc = r.nbeam;
+    job.nbeam = r.nbeam;
+    job.out = r.out;
+    job.nout = series_len(p, r.nin);
+    const int64_t rows = static_cast<int64_t>(r.nbeam) * p->nchan;
+    if (p->ds > 1) {
+      const int64_t nd = r.nin / p->ds, pitch16 = (nd + 1) & ~int64_t(1);
+      if (int e = ensure_ws(b, i, rows * pitch16 * 2)) return e;
+      uint16_t* w16 = reinterpret_cast<uint16_t*>(b->ws[i]);
+      if (int e = launch_downsample(w16, pitch16, r.in, r.nin, rows, nd, p->ds, s)) return e;
+      job.in16 = w16;
+      job.in16_elems = rows * pitch16;
+      job.pitch16 = pitch16;
+    } else if (r.nin % 4 != 0) {
+      const int64_t pitch = (r.nin + 3) & ~int64_t(3);
+      if (int e = ensure_ws(b, i, rows * pitch)) return e;
+      if (int e = launch_copy_rows(b->ws[i], pitch, r.in, r.nin, rows, r.nin, r.in,
+                                   r.in + job.in_bytes, s))
+        return e;
+      job.in = b->ws[i];
+      job.pitch = pitch;
+      job.in_bytes = rows * pitch;
+    }
+    auto& g = groups[p->tiling.variant];
+    g.first.push_back(p);
+    g.second.push_back(job);
+    ++nok;
+  }
+  for (auto& kv : groups) {
+    auto& g = kv.second;
+    if (int e = launch_dedisperse_batch(g.first.data(), g.second.data(),
+                                        static_cast<int>(g.first.size()), b->bb, s))
+      return e;
+  }
+  (void)nok;
+  return ARTS_OK;
+}
+
+int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, float threshold,
+                          arts_candidate* host_out, int64_t capacity, int64_t* count,
+                          void* stream) {
+  if (!b || (!reqs && n > 0) || n < 0 || !count || capacity < 0 || (capacity > 0 && !host_out))
+    return fail(ARTS_E_INVAL, "bad batch arguments");
+  if (!std::isfinite(threshold)) return fail(ARTS_E_INVAL, "threshold must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!b->d_count) ARTS_HIP(hipMalloc(&b->d_count, 64));
+  if (capacity > b->cand_cap || !b->d_cand) {
+    if (b->d_cand) (void)hipFree(b->d_cand);
+    b->d_cand = nullptr;
+    const int64_t cap = std::max<int64_t>(capacity, 1024);
+    ARTS_HIP(hipMalloc(&b->d_cand, cap * sizeof(arts_candidate)));
+    b->cand_cap = cap;
+  }
+  if (int e = launch_zero_u64(b->d_count, 1, s)) return e;
+  int32_t beam0 = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const arts_request& r = reqs[i];
+    if (r.plan && r.nbeam >= 1 && r.nin >= 1) {
+      const int64_t L = series_len(r.plan, r.nin);
+      const int64_t nrep = L - r.plan->wmax + 1;
+      if (L >= 1 && nrep >= 1)
+        if (int e = launch_candidates(r.plan, r.out, r.nbeam, L, nrep, threshold, 0, beam0, nullptr,
+                                      nullptr, b->d_cand, b->d_count, capacity, s))
+          return e;
+    }
+    beam0 += std::max(0, r.nbeam);
+  }
+  unsigned long long nc = 0;
+  ARTS_HIP(hipMemcpyAsync(&nc, b->d_count, sizeof nc, hipMemcpyDeviceToHost, s));
+  ARTS_HIP(hipStreamSynchronize(s));
+  *count = static_cast<int64_t>(nc);
+  if (*count > capacity)
+    return fail(ARTS_E_CAPACITY, "%llu candidates, capacity %lld", nc, (long long)capacity);
+  if (nc == 0) return ARTS_OK;
+  ARTS_HIP(hipMemcpy(host_out, b->d_cand, nc * sizeof(arts_candidate), hipMemcpyDeviceToHost));
+  std::sort(host_out, host_out + nc, [](const arts_candidate& x, const arts_candidate& y) {
+    if (x.beam != y.beam) return x.beam < y.beam;
+    if (x.dm_index != y.dm_index) return x.dm_index < y.dm_index;
+    if (x.width != y.width) return x.width < y.width;
+    return x.sample < y.sample;
+  });
+  return ARTS_OK;
+}
+
+}  // extern "C"

@@ -109,6 +109,21 @@ struct DedispJob {
 };
 
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s);
+
+// Device descriptor storage of persistent batch launches (reused across calls).
+struct BatchBuffers {
+  void* d_jobs = nullptr;      // job descriptors
+  int64_t* d_start = nullptr;  // prefix sums of tiles per job
+  unsigned long long* d_counter = nullptr;
+  void* h_stage = nullptr;     // pinned staging of the descriptors
+  size_t stage_bytes = 0;
+  int cap = 0;
+  hipEvent_t ev = nullptr;     // marks the last descriptor upload
+  ~BatchBuffers();
+};
+// One persistent launch over the tiles of n jobs whose plans share a tiling variant.
+int launch_dedisperse_batch(arts_plan_s* const* plans, const DedispJob* jobs, int n,
+                            BatchBuffers& bb, hipStream_t s);
 int launch_row_stats(const int32_t* series, int64_t L, int64_t nrep, int64_t nrows,
                      int64_t* s1, double* musig, hipStream_t s);
 int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,

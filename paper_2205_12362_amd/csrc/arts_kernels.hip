@@ -3,6 +3,7 @@
 // exact; FP64 is used only for the per-series mean / sigma and thresholds.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -233,9 +234,11 @@ __device__ __forceinline__ void stage_lists(const DedispArgs& a, const int32_t* 
   }
 }
 
+// One tile: DM block blk, time tile tt, beam b.  Used by the one-launch-per-job kernel and by
+// the persistent batch kernel; ends after its global stores with no LDS access pending.
 template <int SPD, int J, int ACC, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
-  extern __shared__ uint32_t lds[];
+__device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, int tt, int b,
+                                                uint32_t* lds) {
   constexpr int T = SPD * J;
   constexpr int TT = 64 * T;
   const int lane = threadIdx.x & 63;
@@ -244,17 +247,6 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
   // 4 pad words; then (for SB formation) the beam's SB-table row
   const int buf_words = a.cc * a.win + a.m_blk * a.cc + 4;
   uint8_t* sbrow = reinterpret_cast<uint8_t*>(lds + 2 * buf_words);
-
-  // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each XCD runs a
-  // contiguous range of (beam, time tile, DM block) and neighbouring DM blocks, which read
-  // overlapping input windows, share that XCD's L2.
-  const int64_t bid = blockIdx.x;
-  const int64_t q8 = a.nwg >> 3, r8 = a.nwg & 7, xcd = bid & 7, pos = bid >> 3;
-  const int64_t lin = xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
-  const int blk = static_cast<int>(lin % a.nblk);
-  const int64_t rest = lin / a.nblk;
-  const int tt = static_cast<int>(rest % a.ntt);
-  const int b = static_cast<int>(rest / a.ntt);
   const int64_t t0 = static_cast<int64_t>(tt) * TT;
   const int dwave0 = blk * a.m_blk + wave * ACC;
   const bool wave_active = dwave0 < a.ndm;
@@ -316,34 +308,122 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
-  if (!wave_active) return;
+  if (wave_active) {
 #pragma unroll
-  for (int x = 0; x < ACC; ++x) {
-    const int d = dwave0 + x;
-    if (d >= a.ndm) break;
-    int32_t* o = a.out + (static_cast<int64_t>(b) * a.ndm + d) * a.nout;
+    for (int x = 0; x < ACC; ++x) {
+      const int d = dwave0 + x;
+      if (d < a.ndm) {
+        int32_t* o = a.out + (static_cast<int64_t>(b) * a.ndm + d) * a.nout;
 #pragma unroll
-    for (int i = 0; i < T; ++i) {
-      const int64_t t = t0 + static_cast<int64_t>(lane) * T + i;
-      if (t < a.nout) o[t] = static_cast<int32_t>(acc[x][i]);
+        for (int i = 0; i < T; ++i) {
+          const int64_t t = t0 + static_cast<int64_t>(lane) * T + i;
+          if (t < a.nout) o[t] = static_cast<int32_t>(acc[x][i]);
+        }
+      }
+    }
+  }
+}
+
+// One launch per job: workgroup -> tile, renumbered so that each of the 8 XCDs (to which
+// workgroups are dealt round-robin) runs a contiguous range of (beam, time tile, DM block):
+// neighbouring DM blocks read overlapping input windows and then share that XCD's L2.
+template <int SPD, int J, int ACC, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  const int64_t bid = blockIdx.x;
+  const int64_t q8 = a.nwg >> 3, r8 = a.nwg & 7, xcd = bid & 7, pos = bid >> 3;
+  const int64_t lin = xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
+  const int blk = static_cast<int>(lin % a.nblk);
+  const int64_t rest = lin / a.nblk;
+  dedisperse_tile<SPD, J, ACC, WAVES>(a, blk, static_cast<int>(rest % a.ntt),
+                                      static_cast<int>(rest / a.ntt), lds);
+}
+
+// Persistent batch kernel: a grid sized to the machine pulls tiles of several jobs from work
+// queues until they are empty (every workgroup reaches that exit).  The host orders the tiles
+// (most expensive job first, then beam, time tile, DM block) and cuts them into 8 contiguous
+// ranges, one per XCD: a workgroup drains the queue of its own XCD first, so neighbouring DM
+// blocks -- which read overlapping windows -- share that XCD's L2, then steals from the others.
+struct BatchArgs {
+  const DedispArgs* jobs;      // [njobs]
+  const int64_t* item_start;   // [njobs + 1] prefix sums of tiles per job
+  unsigned long long* counter; // [8 * 16]: one counter per XCD queue, 128 bytes apart
+  int64_t part[9];             // queue x holds items [part[x], part[x + 1])
+  int32_t njobs;
+};
+
+// Four waves per SIMD (<= 128 VGPRs) so that two 8-wave workgroups share a CU, as in the
+// one-launch-per-job kernel.
+template <int SPD, int J, int ACC, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
+void dedisperse_batch_kernel(BatchArgs q) {
+  extern __shared__ uint32_t lds[];
+  __shared__ long long s_item;
+  const int home = blockIdx.x & 7;
+  for (int k = 0; k < 8; ++k) {
+    const int x = (home + k) & 7;
+    for (;;) {
+      if (threadIdx.x == 0)
+        s_item = q.part[x] + static_cast<long long>(atomicAdd(q.counter + 16 * x, 1ULL));
+      __syncthreads();
+      // the same value in every lane: make that visible so the job lookup and the descriptor
+      // stay in scalar registers
+      const long long raw = s_item;
+      const long long item = static_cast<long long>(
+          (static_cast<unsigned long long>(
+               static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(raw >> 32))))
+           << 32) |
+          static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(raw))));
+      __syncthreads();
+      if (item >= q.part[x + 1]) break;
+      int j = 0;
+      while (j + 1 < q.njobs && q.item_start[j + 1] <= item) ++j;
+      j = __builtin_amdgcn_readfirstlane(j);
+      // copy the descriptor word by word into scalar registers
+      DedispArgs a;
+      {
+        static_assert(sizeof(DedispArgs) % 4 == 0, "descriptor must be whole words");
+        const int* src = reinterpret_cast<const int*>(q.jobs + j);
+        int* dst = reinterpret_cast<int*>(&a);
+#pragma unroll
+        for (int k = 0; k < static_cast<int>(sizeof(DedispArgs) / 4); ++k)
+          dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+      }
+      const int64_t lin = item - q.item_start[j];
+      const int blk = static_cast<int>(lin % a.nblk);
+      const int64_t rest = lin / a.nblk;
+      dedisperse_tile<SPD, J, ACC, WAVES>(a, blk, static_cast<int>(rest % a.ntt),
+                                          static_cast<int>(rest / a.ntt), lds);
     }
   }
 }
 
 template <int SPD, int J, int ACC, int WAVES>
+static size_t lds_bytes(const DedispArgs& a) {
+  return 2 * (static_cast<size_t>(a.win) * a.cc + static_cast<size_t>(a.m_blk) * a.cc + 4) * 4 +
+         (a.sb_table ? ((static_cast<size_t>(a.nchan) + 3) & ~static_cast<size_t>(3)) : 0);
+}
+
+template <typename K>
+static int allow_full_lds(K kernel, int static_bytes = 0) {
+  ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024 - static_bytes));
+  return ARTS_OK;
+}
+
+// static LDS of the persistent kernel (the work-queue slot), rounded to its allocation unit
+constexpr int kBatchStaticLds = 512;
+
+template <int SPD, int J, int ACC, int WAVES>
 static int launch_variant(DedispArgs a, hipStream_t s) {
-  constexpr int T = SPD * J;
-  a.ntt = static_cast<int>((a.nout + 64 * T - 1) / (64 * T));
-  const size_t lds = 2 * (static_cast<size_t>(a.win) * a.cc + static_cast<size_t>(a.m_blk) * a.cc + 4) * 4 +
-                     (a.sb_table ? ((static_cast<size_t>(a.nchan) + 3) & ~static_cast<size_t>(3)) : 0);
+  const size_t lds = lds_bytes<SPD, J, ACC, WAVES>(a);
   if (lds > 160 * 1024) return fail(ARTS_E_INVAL, "LDS request %zu B exceeds 160 KiB", lds);
   a.nwg = static_cast<int64_t>(a.nbeam) * a.ntt * a.nblk;
   if (a.nwg > INT_MAX) return fail(ARTS_E_INVAL, "grid too large (%lld blocks)", (long long)a.nwg);
   static bool attr_set = false;  // one flag per template instance
   if (!attr_set) {
-    ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(
-                                     &dedisperse_kernel<SPD, J, ACC, WAVES>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    if (int st = allow_full_lds(&dedisperse_kernel<SPD, J, ACC, WAVES>)) return st;
     attr_set = true;
   }
   (void)hipGetLastError();
@@ -353,9 +433,33 @@ static int launch_variant(DedispArgs a, hipStream_t s) {
   return ARTS_OK;
 }
 
-// Rows must start on dword boundaries (pitch and pointer); the alignment class g0 of the input
-// pointer selects the plan's offset tables.
-int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
+template <int SPD, int J, int ACC, int WAVES>
+static int launch_batch_variant(BatchArgs q, size_t lds, hipStream_t s) {
+  if (lds + kBatchStaticLds > 160 * 1024)
+    return fail(ARTS_E_INVAL, "LDS request %zu B too large for a persistent launch", lds);
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (int st = allow_full_lds(&dedisperse_batch_kernel<SPD, J, ACC, WAVES>, kBatchStaticLds))
+      return st;
+    attr_set = true;
+  }
+  int per_cu = 0, dev = 0, ncu = 0;
+  ARTS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(&dedisperse_batch_kernel<SPD, J, ACC, WAVES>),
+      WAVES * 64, lds));
+  ARTS_HIP(hipGetDevice(&dev));
+  ARTS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(q.part[8], int64_t(std::max(1, per_cu)) * ncu));
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((dedisperse_batch_kernel<SPD, J, ACC, WAVES>), dim3(static_cast<unsigned>(grid)),
+                     dim3(WAVES * 64), lds, s, q);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+// Kernel arguments of one job.  Rows must start on dword boundaries (pitch and pointer); the
+// alignment class g0 of the input pointer selects the plan's offset tables.
+static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
   DedispArgs a{};
   int g0 = 0;
   if (p->ds == 1) {
@@ -369,6 +473,7 @@ int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   }
   if (int st = ensure_tables(p, g0)) return st;
   const Tiling& t = p->tiling;
+  const TileVariant& v = kVariants[t.variant];
   a.in = job.in;
   a.in_end = job.in + job.in_bytes;
   a.nin = job.nin;
@@ -393,7 +498,16 @@ int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   a.win = t.win_dwords;
   a.cc = t.cc;
   a.nchunk = t.nchunk;
-  switch (t.variant) {
+  const int T = v.spd * v.j;
+  a.ntt = static_cast<int>((a.nout + 64 * T - 1) / (64 * T));
+  *out = a;
+  return ARTS_OK;
+}
+
+int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
+  DedispArgs a;
+  if (int st = make_args(p, job, &a)) return st;
+  switch (p->tiling.variant) {
     case 0: return launch_variant<4, 5, 4, 8>(a, s);
     case 1: return launch_variant<4, 7, 3, 8>(a, s);
     case 2: return launch_variant<4, 5, 4, 16>(a, s);
@@ -403,6 +517,100 @@ int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
     case 6: return launch_variant<2, 5, 4, 8>(a, s);
     case 7: return launch_variant<2, 9, 2, 8>(a, s);
     case 8: return launch_variant<2, 7, 3, 8>(a, s);
+    default: return fail(ARTS_E_INVAL, "plan has no tiling");
+  }
+}
+
+BatchBuffers::~BatchBuffers() {
+  if (ev) (void)hipEventSynchronize(ev);
+  if (ev) (void)hipEventDestroy(ev);
+  if (d_jobs) (void)hipFree(d_jobs);
+  if (d_start) (void)hipFree(d_start);
+  if (d_counter) (void)hipFree(d_counter);
+  if (h_stage) (void)hipHostFree(h_stage);
+}
+
+// All jobs of one launch share the plans' tiling variant.  Jobs are ordered by the cost of one
+// tile (channels staged per tile), most expensive first.
+int launch_dedisperse_batch(arts_plan_s* const* plans, const DedispJob* jobs, int n,
+                            BatchBuffers& bb, hipStream_t s) {
+  if (n <= 0) return ARTS_OK;
+  const int variant = plans[0]->tiling.variant;
+  for (int i = 1; i < n; ++i)
+    if (plans[i]->tiling.variant != variant)
+      return fail(ARTS_E_INVAL, "internal: mixed tiling variants in one batch launch");
+  std::vector<DedispArgs> args(n);
+  std::vector<int> order(n);
+  size_t lds = 0;
+  for (int i = 0; i < n; ++i) {
+    if (int st = make_args(plans[i], jobs[i], &args[i])) return st;
+    order[i] = i;
+  }
+  std::sort(order.begin(), order.end(), [&](int x, int y) {
+    return int64_t(args[x].nchan) * args[x].win > int64_t(args[y].nchan) * args[y].win;
+  });
+  // stage descriptors in pinned memory; the previous launch's upload must have finished
+  const size_t need = n * sizeof(DedispArgs) + (n + 1) * sizeof(int64_t);
+  if (bb.ev) ARTS_HIP(hipEventSynchronize(bb.ev));
+  if (need > bb.stage_bytes || n > bb.cap) {
+    if (bb.h_stage) (void)hipHostFree(bb.h_stage);
+    if (bb.d_jobs) (void)hipFree(bb.d_jobs);
+    if (bb.d_start) (void)hipFree(bb.d_start);
+    bb.h_stage = nullptr;
+    bb.d_jobs = nullptr;
+    bb.d_start = nullptr;
+    bb.stage_bytes = bb.cap = 0;
+    ARTS_HIP(hipHostMalloc(&bb.h_stage, need));
+    ARTS_HIP(hipMalloc(&bb.d_jobs, n * sizeof(DedispArgs)));
+    ARTS_HIP(hipMalloc(&bb.d_start, (n + 1) * sizeof(int64_t)));
+    bb.stage_bytes = need;
+    bb.cap = n;
+  }
+  if (!bb.d_counter) ARTS_HIP(hipMalloc(&bb.d_counter, 8 * 16 * sizeof(unsigned long long)));
+  if (!bb.ev) ARTS_HIP(hipEventCreateWithFlags(&bb.ev, hipEventDisableTiming));
+  DedispArgs* hj = reinterpret_cast<DedispArgs*>(bb.h_stage);
+  int64_t* hs = reinterpret_cast<int64_t*>(static_cast<char*>(bb.h_stage) + n * sizeof(DedispArgs));
+  hs[0] = 0;
+  for (int k = 0; k < n; ++k) {
+    DedispArgs a = args[order[k]];
+    a.nwg = static_cast<int64_t>(a.nbeam) * a.ntt * a.nblk;
+    hj[k] = a;
+    hs[k + 1] = hs[k] + a.nwg;
+    size_t l = 0;
+    switch (variant) {
+      case 0: l = lds_bytes<4, 5, 4, 8>(a); break;
+      case 1: l = lds_bytes<4, 7, 3, 8>(a); break;
+      case 2: l = lds_bytes<4, 5, 4, 16>(a); break;
+      case 3: l = lds_bytes<4, 3, 6, 8>(a); break;
+      case 4: l = lds_bytes<4, 5, 2, 4>(a); break;
+      case 5: l = lds_bytes<4, 7, 4, 8>(a); break;
+      case 6: l = lds_bytes<2, 5, 4, 8>(a); break;
+      case 7: l = lds_bytes<2, 9, 2, 8>(a); break;
+      default: l = lds_bytes<2, 7, 3, 8>(a); break;
+    }
+    lds = std::max(lds, l);
+  }
+  if (lds > 160 * 1024) return fail(ARTS_E_INVAL, "LDS request %zu B exceeds 160 KiB", lds);
+  ARTS_HIP(hipMemcpyAsync(bb.d_jobs, hj, n * sizeof(DedispArgs), hipMemcpyHostToDevice, s));
+  ARTS_HIP(hipMemcpyAsync(bb.d_start, hs, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  ARTS_HIP(hipEventRecord(bb.ev, s));
+  if (int st = launch_zero_u64(bb.d_counter, 8 * 16, s)) return st;
+  BatchArgs q{};
+  q.jobs = static_cast<const DedispArgs*>(bb.d_jobs);
+  q.item_start = bb.d_start;
+  q.counter = bb.d_counter;
+  q.njobs = n;
+  for (int x = 0; x <= 8; ++x) q.part[x] = hs[n] * x / 8;
+  switch (variant) {
+    case 0: return launch_batch_variant<4, 5, 4, 8>(q, lds, s);
+    case 1: return launch_batch_variant<4, 7, 3, 8>(q, lds, s);
+    case 2: return launch_batch_variant<4, 5, 4, 16>(q, lds, s);
+    case 3: return launch_batch_variant<4, 3, 6, 8>(q, lds, s);
+    case 4: return launch_batch_variant<4, 5, 2, 4>(q, lds, s);
+    case 5: return launch_batch_variant<4, 7, 4, 8>(q, lds, s);
+    case 6: return launch_batch_variant<2, 5, 4, 8>(q, lds, s);
+    case 7: return launch_batch_variant<2, 9, 2, 8>(q, lds, s);
+    case 8: return launch_batch_variant<2, 7, 3, 8>(q, lds, s);
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
