@@ -113,6 +113,14 @@ int arts_plan_delays(arts_plan_t plan, int32_t* host_out);
 int arts_plan_set_tiling(arts_plan_t plan, int32_t variant);
 int arts_plan_get_tiling(arts_plan_t plan, int32_t* variant);
 int32_t arts_tiling_count(void);
+/* Autotuner: time every compiled tiling variant that suits the plan on a synthetic input of
+ * nbeam x nchan x nin (device memory allocated and freed by the call), keep the fastest
+ * (`reps` timed launches each) and set it on the plan.  With cache_path (nullable) the result
+ * is looked up in / appended to that text file, keyed by (nchan, ndm, D, max_delay, nbeam,
+ * nin).  *variant_out and *ms_out (nullable) receive the choice and its time per launch.
+ * Errors: ARTS_E_SHAPE (nin too short), ARTS_E_NOMEM, ARTS_E_DEVICE.  Synchronous.          */
+int arts_plan_autotune(arts_plan_t plan, int32_t nbeam, int64_t nin, int32_t reps,
+                       const char* cache_path, int32_t* variant_out, float* ms_out);
 /* Writes "J=<dwords per lane> ACC=<DMs per wave> WAVES=<waves per block> SPD=<samples per
  * dword>" for a variant into buf (NUL-terminated, at most len bytes).                       */
 int arts_tiling_describe(int32_t variant, char* buf, int32_t len);
@@ -278,6 +286,39 @@ int arts_stream_restore(arts_stream_t s, const uint8_t* host, int64_t bytes,
 
 /* Release everything the stream owns (waits for its queued work first).  NULL is ignored.      */
 void arts_stream_destroy(arts_stream_t s);
+
+/* ------------------------------------------------------------------------- serving ---- */
+
+/* Serving engine with continuous batching over streams (see arts_stream_create for the stream
+ * arguments).  Streams are admitted while the device memory they need fits the HBM budget
+ * (ARTS_E_BUDGET otherwise: retry once others have closed) and can join or leave between
+ * ticks.  Each tick runs one search step for every stream with a submitted chunk: the
+ * dedispersion of all of them goes into one persistent launch per tiling variant, so their
+ * work shares the device.  A stream's results are identical to a standalone arts_stream fed
+ * the same chunks.  All engine work runs on one HIP stream of default priority owned by the
+ * server; the calls below are not thread-safe.                                               */
+typedef struct arts_server_s* arts_server_t;
+int arts_server_create(int64_t hbm_budget_bytes, arts_server_t* out);
+void arts_server_destroy(arts_server_t server);  /* closes every stream */
+int arts_server_open(arts_server_t server, const arts_plan_t* plans, int32_t nplan,
+                     int32_t nsrc, const uint8_t* sb_table, int32_t nbeam, int64_t chunk,
+                     float threshold, int64_t cand_capacity, int32_t* stream_id);
+int arts_server_close(arts_server_t server, int32_t stream_id);
+/* Queue the stream's next chunk ([nsrc][nchan][chunk] uint8; host memory if from_host, pinned
+ * for an asynchronous copy, else device memory).  ARTS_E_STATE while the stream's previous
+ * chunk is pending or uncollected.                                                           */
+int arts_server_submit(arts_server_t server, int32_t stream_id, const uint8_t* chunk,
+                       int32_t from_host);
+/* Enqueue one step for every stream with a submitted chunk; returns at once.  *nrun
+ * (nullable) = number of streams stepped.                                                    */
+int arts_server_tick(arts_server_t server, int32_t* nrun);
+/* Wait for a stream's last step and return its candidates (as arts_stream_wait).             */
+int arts_server_collect(arts_server_t server, int32_t stream_id, arts_candidate* host_out,
+                        int64_t capacity, int64_t* count, int64_t* chunk_index);
+/* The stream object behind an id (to read its series with arts_stream_series).              */
+int arts_server_stream(arts_server_t server, int32_t stream_id, arts_stream_t* stream);
+int arts_server_info(arts_server_t server, int64_t* used_bytes, int64_t* budget,
+                     int32_t* nstreams);
 
 /* ----------------------------------------------------------------------- diagnostics ---- */
 const char* arts_strerror(int status);

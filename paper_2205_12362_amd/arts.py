@@ -56,6 +56,8 @@ _SIGNATURES = {
     "arts_plan_set_tiling": (C.c_int, [_vp, _i32]),
     "arts_plan_get_tiling": (C.c_int, [_vp, _pi32]),
     "arts_tiling_count": (_i32, []),
+    "arts_plan_autotune": (C.c_int, [_vp, _i32, _i64, _i32, C.c_char_p, _pi32,
+                                     C.POINTER(C.c_float)]),
     "arts_tiling_describe": (C.c_int, [_i32, C.c_char_p, _i32]),
     "arts_sb_synthesize": (C.c_int, [_vp, _i32, _vp, _i32, _i32, _i64, _vp, _vp]),
     "arts_dedisperse": (C.c_int, [_vp, _vp, _i32, _i64, _vp, _vp]),
@@ -79,6 +81,16 @@ _SIGNATURES = {
     "arts_batch_destroy": (None, [_vp]),
     "arts_batch_dedisperse": (C.c_int, [_vp, _vp, _i32, _pi32, _vp]),
     "arts_batch_candidates": (C.c_int, [_vp, _vp, _i32, _f32, _vp, _i64, _pi64, _vp]),
+    "arts_server_create": (C.c_int, [_i64, C.POINTER(_vp)]),
+    "arts_server_destroy": (None, [_vp]),
+    "arts_server_open": (C.c_int, [_vp, C.POINTER(_vp), _i32, _i32, _vp, _i32, _i64, _f32, _i64,
+                                   _pi32]),
+    "arts_server_close": (C.c_int, [_vp, _i32]),
+    "arts_server_submit": (C.c_int, [_vp, _i32, _vp, _i32]),
+    "arts_server_tick": (C.c_int, [_vp, _pi32]),
+    "arts_server_collect": (C.c_int, [_vp, _i32, _vp, _i64, _pi64, _pi64]),
+    "arts_server_stream": (C.c_int, [_vp, _i32, C.POINTER(_vp)]),
+    "arts_server_info": (C.c_int, [_vp, _pi64, _pi64, _pi32]),
     "arts_strerror": (C.c_char_p, [C.c_int]),
     "arts_last_error": (C.c_char_p, []),
     "arts_version": (C.c_char_p, []),
@@ -214,6 +226,15 @@ def arts_plan_delays(plan):
 
 def arts_plan_set_tiling(plan, variant):
     _check(lib().arts_plan_set_tiling(plan, int(variant)))
+
+
+def arts_plan_autotune(plan, nbeam, nin, reps=3, cache_path=None):
+    """Pick the fastest tiling for this shape (cached in cache_path); returns (variant, ms)."""
+    v, ms = C.c_int32(), C.c_float()
+    path = cache_path.encode() if cache_path else None
+    _check(lib().arts_plan_autotune(plan, int(nbeam), int(nin), int(reps), path, C.byref(v),
+                                    C.byref(ms)))
+    return v.value, ms.value
 
 
 def arts_plan_get_tiling(plan):
@@ -361,6 +382,9 @@ class Plan:
 
     def set_tiling(self, variant):
         arts_plan_set_tiling(self.handle, variant)
+
+    def autotune(self, nbeam, nin, reps=3, cache_path=None):
+        return arts_plan_autotune(self.handle, nbeam, nin, reps, cache_path)
 
     def tiling(self):
         return arts_plan_get_tiling(self.handle)
@@ -617,3 +641,85 @@ class Batch:
 def series_length(plan, nin):
     info = plan.info if isinstance(plan, Plan) else arts_plan_info(plan)
     return nin // info["downsample"] - info["max_delay"]
+
+
+# ---------------------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching serving engine (arts_server_*)."""
+
+    def __init__(self, hbm_budget_bytes):
+        h = _vp()
+        _check(lib().arts_server_create(int(hbm_budget_bytes), C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def open(self, plans, nsrc, chunk, threshold, sb_table=None, nbeam=None,
+             cand_capacity=1 << 16):
+        """Admit a stream; raises ArtsError (status ARTS_E_BUDGET) if it does not fit."""
+        import torch
+        handles = (_vp * len(plans))(*[p.handle if isinstance(p, Plan) else p for p in plans])
+        tbl = _dev(sb_table, torch.uint8, "sb_table") if sb_table is not None else None
+        nbeam = nbeam if nbeam is not None else (sb_table.shape[0] if sb_table is not None
+                                                 else nsrc)
+        sid = C.c_int32()
+        _check(lib().arts_server_open(self.handle, handles, len(plans), int(nsrc), tbl,
+                                      int(nbeam), int(chunk), float(threshold),
+                                      int(cand_capacity), C.byref(sid)))
+        self._keep[sid.value] = (list(plans), sb_table, int(cand_capacity), int(nbeam))
+        return sid.value
+
+    def close_stream(self, sid):
+        _check(lib().arts_server_close(self.handle, int(sid)))
+        self._keep.pop(sid, None)
+
+    def submit(self, sid, chunk):
+        """chunk: torch uint8 tensor [nsrc][nchan][chunk] on the GPU, or pinned on the host."""
+        import torch
+        if not chunk.is_contiguous() or chunk.dtype != torch.uint8:
+            raise TypeError("chunk must be a contiguous uint8 tensor")
+        _check(lib().arts_server_submit(self.handle, int(sid), chunk.data_ptr(),
+                                        0 if chunk.is_cuda else 1))
+
+    def tick(self):
+        n = C.c_int32()
+        _check(lib().arts_server_tick(self.handle, C.byref(n)))
+        return n.value
+
+    def collect(self, sid):
+        cap = self._keep[sid][2]
+        buf = np.zeros(cap, dtype=CANDIDATE_DTYPE)
+        n, k = C.c_int64(), C.c_int64()
+        _check(lib().arts_server_collect(self.handle, int(sid), buf.ctypes.data, cap,
+                                         C.byref(n), C.byref(k)))
+        return buf[: n.value].copy(), k.value
+
+    def series(self, sid, plan_index):
+        import torch
+        sh = _vp()
+        _check(lib().arts_server_stream(self.handle, int(sid), C.byref(sh)))
+        plans, _, _, nbeam = self._keep[sid]
+        ndm = plans[plan_index].info["ndm"]
+        ptr, L = arts_stream_series(sh, plan_index, nbeam, ndm)
+        return _tensor_from_ptr(ptr, (nbeam, ndm, L), torch.int32, self)
+
+    def info(self):
+        u, b, n = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().arts_server_info(self.handle, C.byref(u), C.byref(b), C.byref(n)))
+        return {"used_bytes": u.value, "budget": b.value, "streams": n.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().arts_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

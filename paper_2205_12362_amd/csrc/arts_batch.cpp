@@ -161,3 +161,117 @@ int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, f
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------------ autotuner ----
+// Times every compiled tiling variant that suits the plan on a synthetic input of the caller's
+// shape and keeps the fastest (the paper's search is auto-tuned per platform and
+// observation setup, Sect. 6b.2).  Results are cached in a text file, one line per shape:
+//   <nchan> <ndm> <downsample> <max_delay> <nbeam> <nin> <variant> <ms>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+#include <string>
+
+namespace {
+
+std::string tune_key(const arts_plan_s* p, int32_t nbeam, int64_t nin) {
+  std::ostringstream k;
+  k << p->nchan << ' ' << p->ndm << ' ' << p->ds << ' ' << p->max_delay << ' ' << nbeam << ' '
+    << nin;
+  return k.str();
+}
+
+bool cache_lookup(const char* path, const std::string& key, int* variant, float* ms) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    if (line.compare(0, key.size(), key) != 0 || line.size() <= key.size() ||
+        line[key.size()] != ' ')
+      continue;
+    std::istringstream rest(line.substr(key.size()));
+    int v = -1;
+    float t = 0;
+    if (rest >> v >> t && v >= 0 && v < kNumVariants) {
+      *variant = v;
+      *ms = t;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  return found;
+}
+
+}  // namespace
+
+extern "C" int arts_plan_autotune(arts_plan_t p, int32_t nbeam, int64_t nin, int32_t reps,
+                                  const char* cache_path, int32_t* variant_out, float* ms_out) {
+  if (!p || nbeam < 1 || reps < 1) return fail(ARTS_E_INVAL, "bad autotune arguments");
+  if (nin / p->ds - p->max_delay < 1) return fail(ARTS_E_SHAPE, "nin shorter than the halo");
+  const std::string key = tune_key(p, nbeam, nin);
+  int best = -1;
+  float best_ms = 0;
+  if (cache_lookup(cache_path, key, &best, &best_ms)) {
+    if (int st = arts_plan_set_tiling(p, best)) return st;
+    if (variant_out) *variant_out = best;
+    if (ms_out) *ms_out = best_ms;
+    return ARTS_OK;
+  }
+  const int64_t L = nin / p->ds - p->max_delay;
+  const int64_t in_bytes = static_cast<int64_t>(nbeam) * p->nchan * nin;
+  const int64_t out_bytes = static_cast<int64_t>(nbeam) * p->ndm * L * 4;
+  uint8_t* in = nullptr;
+  int32_t* out = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int st = ARTS_OK;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    if (in) (void)hipFree(in);
+    if (out) (void)hipFree(out);
+  };
+  if (hipMalloc(&in, in_bytes) != hipSuccess || hipMalloc(&out, out_bytes) != hipSuccess ||
+      hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipMemsetAsync(in, 0x5a, in_bytes, s) != hipSuccess) {
+    cleanup();
+    return fail(ARTS_E_NOMEM, "autotune buffers (%lld + %lld bytes)", (long long)in_bytes,
+                (long long)out_bytes);
+  }
+  const int original = p->tiling.variant;
+  for (int v = 0; v < kNumVariants && st == ARTS_OK; ++v) {
+    if ((p->ds == 1) != (kVariants[v].spd == 4)) continue;
+    if (arts_plan_set_tiling(p, v) != ARTS_OK) continue;  // e.g. windows too long for LDS
+    st = arts_dedisperse(p, in, nbeam, nin, out, s);      // warm-up (and table set-up)
+    if (st != ARTS_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) st = fail(ARTS_E_DEVICE, "event record");
+    for (int r = 0; r < reps && st == ARTS_OK; ++r) st = arts_dedisperse(p, in, nbeam, nin, out, s);
+    float ms = 0;
+    if (st == ARTS_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = fail(ARTS_E_DEVICE, "event timing");
+    ms /= reps;
+    if (st == ARTS_OK && (best < 0 || ms < best_ms)) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  cleanup();
+  if (st != ARTS_OK) {
+    (void)arts_plan_set_tiling(p, original);
+    return st;
+  }
+  if (best < 0) return fail(ARTS_E_INVAL, "no tiling variant fits this plan");
+  if (int e = arts_plan_set_tiling(p, best)) return e;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%s %d %.4f\n", key.c_str(), best, best_ms);
+      std::fclose(f);
+    }
+  }
+  if (variant_out) *variant_out = best;
+  if (ms_out) *ms_out = best_ms;
+  return ARTS_OK;
+}

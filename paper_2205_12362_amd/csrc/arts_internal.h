@@ -145,3 +145,44 @@ int launch_copy_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t s
                      hipStream_t s);
 
 }  // namespace arts
+
+struct arts_stream_s {
+  std::vector<arts_plan_s*> plans;
+  int32_t nsrc = 0, nbeam = 0, nchan = 0;
+  const uint8_t* sb_table = nullptr;
+  int64_t chunk = 0, hmax = 0, W = 0;
+  float thr = 0;
+  uint32_t flags = 0;
+  uint8_t* ring[2] = {nullptr, nullptr};  // native rows (only if a plan has D = 1)
+  uint8_t* input = nullptr;  // stream-owned staging buffer [nsrc][nchan][chunk]
+  std::vector<uint16_t*> ring16[2];        // per plan: downsampled rows (D > 1), else null
+  std::vector<int64_t> W16;                // per plan: 16-bit ring row pitch (even)
+  std::vector<int64_t> N16;                // per plan: 16-bit samples held per row
+  std::vector<int32_t*> series;
+  std::vector<int64_t> L, H;
+  arts_candidate* d_cand = nullptr;
+  unsigned long long* d_count = nullptr;
+  unsigned long long* h_count = nullptr;  // pinned
+  int64_t cap = 0;
+  hipStream_t hs = nullptr;
+  hipEvent_t ev_in = nullptr, ev_done = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int64_t pushed = 0, waited = 0;
+  int64_t device_bytes = 0;
+  // profiling: events bracketing each phase of the last push
+  std::vector<hipEvent_t> pev;
+  std::vector<double> phase_ms;
+  std::vector<int64_t> phase_n;
+  bool pending_profile = false;
+};
+
+namespace arts {
+
+// Stream internals (arts_stream.cpp), shared with the serving engine (arts_server.cpp).
+int stream_advance(arts_stream_s* s, int parity, hipStream_t hs);
+DedispJob stream_job(arts_stream_s* s, int parity, size_t plan_index);
+int stream_candidates(arts_stream_s* s, hipStream_t hs);
+int64_t stream_bytes_needed(const arts_plan_t* plans, int32_t nplan, int32_t nsrc, int32_t nbeam,
+                            int64_t chunk, int64_t cand_capacity);
+
+}  // namespace arts

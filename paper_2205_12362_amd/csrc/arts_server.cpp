@@ -1,0 +1,158 @@
+// Serving engine with continuous batching.  Streams (beams or TAB sets of any channel count,
+// chunk length and DM range) are admitted while their device memory fits an HBM budget and
+// leave when closed; chunks are submitted as they arrive.  Each tick runs one search step for
+// every stream that has a chunk waiting: ring advances, then the dedispersion of all those
+// streams and plans in one persistent launch per tiling variant (so the streams' work shares
+// the device), then each stream's statistics and candidates.  The real-time search keeps up
+// with 1.024 s chunks of many beams per GPU node (Sect. 4f, Sect. 9h); a tick here serves all
+// streams that are ready.
+#include <algorithm>
+#include <map>
+#include <new>
+
+#include "arts_internal.h"
+
+using namespace arts;
+
+struct arts_server_s {
+  int64_t budget = 0, used = 0;
+  hipStream_t hs = nullptr;
+  BatchBuffers bb;
+  struct Entry {
+    arts_stream_s* s = nullptr;
+    int64_t bytes = 0;
+    bool ready = false;  // a submitted chunk waits for the next tick
+  };
+  std::map<int32_t, Entry> streams;
+  int32_t next_id = 0;
+};
+
+extern "C" {
+
+int arts_server_create(int64_t hbm_budget_bytes, arts_server_t* out) {
+  if (!out || hbm_budget_bytes < 1) return fail(ARTS_E_INVAL, "bad server arguments");
+  *out = nullptr;
+  arts_server_s* v = new (std::nothrow) arts_server_s;
+  if (!v) return fail(ARTS_E_NOMEM, "host allocation failed");
+  v->budget = hbm_budget_bytes;
+  if (hipStreamCreateWithFlags(&v->hs, hipStreamNonBlocking) != hipSuccess) {
+    delete v;
+    return fail(ARTS_E_DEVICE, "stream creation failed");
+  }
+  *out = v;
+  return ARTS_OK;
+}
+
+void arts_server_destroy(arts_server_t v) {
+  if (!v) return;
+  (void)hipStreamSynchronize(v->hs);
+  for (auto& kv : v->streams) arts_stream_destroy(kv.second.s);
+  (void)hipStreamDestroy(v->hs);
+  delete v;
+}
+
+int arts_server_open(arts_server_t v, const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
+                     const uint8_t* sb_table, int32_t nbeam, int64_t chunk, float threshold,
+                     int64_t cand_capacity, int32_t* stream_id) {
+  if (!v || !stream_id) return fail(ARTS_E_INVAL, "NULL argument");
+  const int64_t need = stream_bytes_needed(plans, nplan, nsrc, nbeam, chunk, cand_capacity);
+  if (need < 0) return fail(ARTS_E_INVAL, "bad plans");
+  if (v->used + need > v->budget)
+    return fail(ARTS_E_BUDGET, "stream needs %lld bytes, %lld of %lld in use", (long long)need,
+                (long long)v->used, (long long)v->budget);
+  arts_stream_t s = nullptr;
+  if (int st = arts_stream_create(plans, nplan, nsrc, sb_table, nbeam, chunk, threshold,
+                                  cand_capacity, 0, &s))
+    return st;
+  const int32_t id = v->next_id++;
+  arts_server_s::Entry e;
+  e.s = s;
+  e.bytes = s->device_bytes;
+  v->streams[id] = e;
+  v->used += e.bytes;
+  *stream_id = id;
+  return ARTS_OK;
+}
+
+int arts_server_close(arts_server_t v, int32_t id) {
+  if (!v) return fail(ARTS_E_INVAL, "server is NULL");
+  auto it = v->streams.find(id);
+  if (it == v->streams.end()) return fail(ARTS_E_INVAL, "no stream %d", id);
+  ARTS_HIP(hipStreamSynchronize(v->hs));
+  v->used -= it->second.bytes;
+  arts_stream_destroy(it->second.s);
+  v->streams.erase(it);
+  return ARTS_OK;
+}
+
+int arts_server_submit(arts_server_t v, int32_t id, const uint8_t* chunk, int32_t from_host) {
+  if (!v || !chunk) return fail(ARTS_E_INVAL, "NULL argument");
+  auto it = v->streams.find(id);
+  if (it == v->streams.end()) return fail(ARTS_E_INVAL, "no stream %d", id);
+  arts_stream_s* s = it->second.s;
+  if (it->second.ready || s->pushed != s->waited)
+    return fail(ARTS_E_STATE, "stream %d: the previous chunk is still pending", id);
+  const int64_t bytes = static_cast<int64_t>(s->nsrc) * s->nchan * s->chunk;
+  ARTS_HIP(hipMemcpyAsync(s->input, chunk, bytes,
+                          from_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, v->hs));
+  it->second.ready = true;
+  return ARTS_OK;
+}
+
+int arts_server_tick(arts_server_t v, int32_t* nrun) {
+  if (!v) return fail(ARTS_E_INVAL, "server is NULL");
+  std::vector<arts_server_s::Entry*> run;
+  for (auto& kv : v->streams)
+    if (kv.second.ready) run.push_back(&kv.second);
+  if (nrun) *nrun = static_cast<int32_t>(run.size());
+  if (run.empty()) return ARTS_OK;
+  std::map<int, std::pair<std::vector<arts_plan_s*>, std::vector<DedispJob>>> groups;
+  for (auto* e : run) {
+    arts_stream_s* s = e->s;
+    const int parity = static_cast<int>(s->pushed & 1);
+    if (int st = stream_advance(s, parity, v->hs)) return st;
+    for (size_t p = 0; p < s->plans.size(); ++p) {
+      auto& g = groups[s->plans[p]->tiling.variant];
+      g.first.push_back(s->plans[p]);
+      g.second.push_back(stream_job(s, parity, p));
+    }
+  }
+  for (auto& kv : groups)
+    if (int st = launch_dedisperse_batch(kv.second.first.data(), kv.second.second.data(),
+                                         static_cast<int>(kv.second.first.size()), v->bb, v->hs))
+      return st;
+  for (auto* e : run) {
+    arts_stream_s* s = e->s;
+    if (int st = stream_candidates(s, v->hs)) return st;
+    ARTS_HIP(hipEventRecord(s->ev_done, v->hs));
+    ++s->pushed;
+    e->ready = false;
+  }
+  return ARTS_OK;
+}
+
+int arts_server_collect(arts_server_t v, int32_t id, arts_candidate* host_out, int64_t capacity,
+                        int64_t* count, int64_t* chunk_index) {
+  if (!v) return fail(ARTS_E_INVAL, "server is NULL");
+  auto it = v->streams.find(id);
+  if (it == v->streams.end()) return fail(ARTS_E_INVAL, "no stream %d", id);
+  return arts_stream_wait(it->second.s, host_out, capacity, count, chunk_index);
+}
+
+int arts_server_stream(arts_server_t v, int32_t id, arts_stream_t* s) {
+  if (!v || !s) return fail(ARTS_E_INVAL, "NULL argument");
+  auto it = v->streams.find(id);
+  if (it == v->streams.end()) return fail(ARTS_E_INVAL, "no stream %d", id);
+  *s = it->second.s;
+  return ARTS_OK;
+}
+
+int arts_server_info(arts_server_t v, int64_t* used_bytes, int64_t* budget, int32_t* nstreams) {
+  if (!v) return fail(ARTS_E_INVAL, "server is NULL");
+  if (used_bytes) *used_bytes = v->used;
+  if (budget) *budget = v->budget;
+  if (nstreams) *nstreams = static_cast<int32_t>(v->streams.size());
+  return ARTS_OK;
+}
+
+}  // extern "C"

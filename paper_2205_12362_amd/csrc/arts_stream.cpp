@@ -18,36 +18,6 @@
 
 using namespace arts;
 
-struct arts_stream_s {
-  std::vector<arts_plan_s*> plans;
-  int32_t nsrc = 0, nbeam = 0, nchan = 0;
-  const uint8_t* sb_table = nullptr;
-  int64_t chunk = 0, hmax = 0, W = 0;
-  float thr = 0;
-  uint32_t flags = 0;
-  uint8_t* ring[2] = {nullptr, nullptr};  // native rows (only if a plan has D = 1)
-  uint8_t* input = nullptr;  // stream-owned staging buffer [nsrc][nchan][chunk]
-  std::vector<uint16_t*> ring16[2];        // per plan: downsampled rows (D > 1), else null
-  std::vector<int64_t> W16;                // per plan: 16-bit ring row pitch (even)
-  std::vector<int64_t> N16;                // per plan: 16-bit samples held per row
-  std::vector<int32_t*> series;
-  std::vector<int64_t> L, H;
-  arts_candidate* d_cand = nullptr;
-  unsigned long long* d_count = nullptr;
-  unsigned long long* h_count = nullptr;  // pinned
-  int64_t cap = 0;
-  hipStream_t hs = nullptr;
-  hipEvent_t ev_in = nullptr, ev_done = nullptr;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  int64_t pushed = 0, waited = 0;
-  int64_t device_bytes = 0;
-  // profiling: events bracketing each phase of the last push
-  std::vector<hipEvent_t> pev;
-  std::vector<double> phase_ms;
-  std::vector<int64_t> phase_n;
-  bool pending_profile = false;
-};
-
 namespace {
 
 constexpr uint32_t kGraph = 1u, kProfile = 2u;
@@ -89,23 +59,23 @@ int dev_alloc(arts_stream_s* s, void** p, size_t bytes) {
 
 // The device work of one push (ring advance, dedispersion per plan, statistics and
 // candidates); enqueued on s->hs, possibly under graph capture.
-int enqueue_push(arts_stream_s* s, int parity, bool profile) {
+}  // namespace
+
+// Phases of one push, reused by the serving engine (which batches the dedispersion of many
+// streams into one launch).  All enqueue on `hs`.
+namespace arts {
+
+int stream_advance(arts_stream_s* s, int parity, hipStream_t hs) {
   uint8_t* dst = s->ring[parity];
   const uint8_t* src = s->ring[parity ^ 1];
   const int64_t rows = static_cast<int64_t>(s->nsrc) * s->nchan;
   const int64_t ring_bytes = rows * s->W;
-  auto mark = [&](int i) -> int {
-    if (profile) ARTS_HIP(hipEventRecord(s->pev[i], s->hs));
-    return ARTS_OK;
-  };
-  int ev = 0;
-  if (int st = mark(ev++)) return st;
   if (dst) {
     if (int st = launch_copy_rows(dst, s->W, src + s->chunk, s->W, rows, s->hmax, src,
-                                  src + ring_bytes, s->hs))
+                                  src + ring_bytes, hs))
       return st;
     if (int st = launch_copy_rows(dst + s->hmax, s->W, s->input, s->chunk, rows, s->chunk,
-                                  s->input, s->input + rows * s->chunk, s->hs))
+                                  s->input, s->input + rows * s->chunk, hs))
       return st;
   }
   for (size_t p = 0; p < s->plans.size(); ++p) {
@@ -116,50 +86,100 @@ int enqueue_push(arts_stream_s* s, int parity, bool profile) {
     const int64_t W16 = s->W16[p], new16 = s->chunk / D, keep = s->N16[p] - new16;
     const uint8_t* sb = reinterpret_cast<const uint8_t*>(s16);
     if (int st = launch_copy_rows(reinterpret_cast<uint8_t*>(d16), 2 * W16, sb + 2 * new16,
-                                  2 * W16, rows, 2 * keep, sb, sb + rows * W16 * 2, s->hs))
+                                  2 * W16, rows, 2 * keep, sb, sb + rows * W16 * 2, hs))
       return st;
-    if (int st = launch_downsample(d16 + keep, W16, s->input, s->chunk, rows, new16, D, s->hs))
+    if (int st = launch_downsample(d16 + keep, W16, s->input, s->chunk, rows, new16, D, hs))
       return st;
   }
-  if (int st = mark(ev++)) return st;
-  for (size_t p = 0; p < s->plans.size(); ++p) {
-    arts_plan_s* pl = s->plans[p];
-    DedispJob job;
-    job.nsrc = s->nsrc;
-    job.sb_table = s->sb_table;
-    job.nbeam = s->nbeam;
-    job.out = s->series[p];
-    job.nout = s->L[p];
-    if (pl->ds == 1) {
-      const int64_t off = s->hmax - s->H[p];
-      job.in = dst + off;
-      job.in_bytes = ring_bytes - off;
-      job.nin = s->H[p] + s->chunk;
-      job.pitch = s->W;
+  return ARTS_OK;
+}
+
+// Device bytes arts_stream_create allocates for these arguments (the serving engine's admission
+// test uses it before allocating anything).
+int64_t stream_bytes_needed(const arts_plan_t* plans, int32_t nplan, int32_t nsrc, int32_t nbeam,
+                            int64_t chunk, int64_t cand_capacity) {
+  if (!plans || nplan < 1 || !plans[0]) return -1;
+  const int64_t rows = static_cast<int64_t>(nsrc) * plans[0]->nchan;
+  int64_t hmax = 0, total = rows * chunk + cand_capacity * sizeof(arts_candidate) + 64;
+  bool native = false;
+  for (int32_t i = 0; i < nplan; ++i) {
+    const arts_plan_s* p = plans[i];
+    if (!p) return -1;
+    total += static_cast<int64_t>(nbeam) * p->ndm * (chunk / p->ds + p->wmax - 1) * 4;
+    if (p->ds == 1) {
+      native = true;
+      hmax = std::max<int64_t>(hmax, static_cast<int64_t>(p->halo));
     } else {
-      job.in = s->input;  // unused: the kernel reads the 16-bit ring
-      job.in_bytes = rows * s->chunk;
-      job.nin = s->N16[p] * pl->ds;
-      job.pitch = s->chunk;
-      job.in16 = s->ring16[parity][p];
-      job.in16_elems = rows * s->W16[p];
-      job.pitch16 = s->W16[p];
+      const int64_t n16 = p->halo + chunk / p->ds;
+      total += 2 * rows * ((n16 + 1) & ~int64_t(1)) * 2;
     }
-    if (int st = launch_dedisperse(pl, job, s->hs)) return st;
-    if (int st = mark(ev++)) return st;
   }
-  if (int st = launch_zero_u64(s->d_count, 1, s->hs)) return st;
+  if (native) total += 2 * rows * ((hmax + chunk + 3) & ~int64_t(3));
+  return total;
+}
+
+DedispJob stream_job(arts_stream_s* s, int parity, size_t p) {
+  const arts_plan_s* pl = s->plans[p];
+  const int64_t rows = static_cast<int64_t>(s->nsrc) * s->nchan;
+  DedispJob job;
+  job.nsrc = s->nsrc;
+  job.sb_table = s->sb_table;
+  job.nbeam = s->nbeam;
+  job.out = s->series[p];
+  job.nout = s->L[p];
+  if (pl->ds == 1) {
+    const int64_t off = s->hmax - s->H[p];
+    job.in = s->ring[parity] + off;
+    job.in_bytes = rows * s->W - off;
+    job.nin = s->H[p] + s->chunk;
+    job.pitch = s->W;
+  } else {
+    job.in = s->input;  // unused: the kernel reads the 16-bit ring
+    job.in_bytes = rows * s->chunk;
+    job.nin = s->N16[p] * pl->ds;
+    job.pitch = s->chunk;
+    job.in16 = s->ring16[parity][p];
+    job.in16_elems = rows * s->W16[p];
+    job.pitch16 = s->W16[p];
+  }
+  return job;
+}
+
+int stream_candidates(arts_stream_s* s, hipStream_t hs) {
+  if (int st = launch_zero_u64(s->d_count, 1, hs)) return st;
   for (size_t p = 0; p < s->plans.size(); ++p) {
     const arts_plan_s* pl = s->plans[p];
     const int64_t nrep = s->chunk / pl->ds;
     // sample numbers are made absolute on the host: chunk-relative start minus the halo
     if (int st = launch_candidates(pl, s->series[p], s->nbeam, s->L[p], nrep, s->thr,
                                    -s->H[p] / pl->ds, 0, nullptr, nullptr, s->d_cand,
-                                   s->d_count, s->cap, s->hs))
+                                   s->d_count, s->cap, hs))
       return st;
   }
   ARTS_HIP(hipMemcpyAsync(s->h_count, s->d_count, sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, s->hs));
+                          hipMemcpyDeviceToHost, hs));
+  return ARTS_OK;
+}
+
+}  // namespace arts
+
+namespace {
+
+int enqueue_push(arts_stream_s* s, int parity, bool profile) {
+  auto mark = [&](int i) -> int {
+    if (profile) ARTS_HIP(hipEventRecord(s->pev[i], s->hs));
+    return ARTS_OK;
+  };
+  int ev = 0;
+  if (int st = mark(ev++)) return st;
+  if (int st = stream_advance(s, parity, s->hs)) return st;
+  if (int st = mark(ev++)) return st;
+  for (size_t p = 0; p < s->plans.size(); ++p) {
+    const DedispJob job = stream_job(s, parity, p);
+    if (int st = launch_dedisperse(s->plans[p], job, s->hs)) return st;
+    if (int st = mark(ev++)) return st;
+  }
+  if (int st = stream_candidates(s, s->hs)) return st;
   if (int st = mark(ev++)) return st;
   return ARTS_OK;
 }

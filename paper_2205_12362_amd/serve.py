@@ -1,0 +1,132 @@
+"""Real-time serving driver: streams whose chunks are released at the real-time rate (one
+chunk of `chunk` samples every chunk * tsamp seconds per stream) are admitted into the
+continuous-batching engine (libarts' arts_server) as the HBM budget allows; every engine turn
+submits whatever chunks have been released, runs one batched step and collects the results.
+Chunk latency = time the candidates are back on the host minus the chunk's release time.
+
+    python -m paper_2205_12362_amd.serve --seconds 20
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import arts, synth
+
+
+@dataclass
+class StreamSpec:
+    """A stream to serve: its plans (Workloads), source rows, optional SB table, chunk length,
+    start offset in seconds and a pool of chunk data (host uint8 arrays, cycled)."""
+    name: str
+    workloads: list
+    nsrc: int
+    chunk: int
+    pool: list
+    sb_table: np.ndarray | None = None
+    start: float = 0.0
+    threshold: float = 8.0
+    latencies: list = field(default_factory=list)
+    ncand: int = 0
+
+
+def serve(specs, seconds: float, budget_bytes: int, log=None):
+    """Serve the streams for `seconds` of wall-clock time; returns per-stream latency stats."""
+    import torch
+    tsamp = synth.TSAMP
+    plans = {s.name: [arts.Plan.from_workload(w) for w in s.workloads] for s in specs}
+    pinned = {s.name: [torch.from_numpy(c).pin_memory() for c in s.pool] for s in specs}
+    tables = {s.name: (torch.from_numpy(s.sb_table).cuda() if s.sb_table is not None else None)
+              for s in specs}
+    srv = arts.Server(budget_bytes)
+    sid, nsub, pending = {}, {}, {}
+    waiting = list(specs)
+    rejected = 0
+    t0 = time.perf_counter()
+    try:
+        while True:
+            now = time.perf_counter() - t0
+            if now >= seconds and not pending:
+                break
+            # admission: streams whose start time has come, while the budget allows
+            for s in list(waiting):
+                if now < s.start:
+                    continue
+                try:
+                    sid[s.name] = srv.open(plans[s.name], s.nsrc, s.chunk, s.threshold,
+                                           sb_table=tables[s.name], cand_capacity=1 << 20)
+                    nsub[s.name] = 0
+                    waiting.remove(s)
+                except arts.ArtsError as e:
+                    if e.status != arts.ARTS_E_BUDGET:
+                        raise
+                    rejected += 1
+            # submit every released chunk (one in flight per stream)
+            for s in specs:
+                if s.name not in sid or s.name in pending:
+                    continue
+                k = nsub[s.name]
+                release = s.start + (k + 1) * s.chunk * tsamp   # chunk k complete at this time
+                if release <= now and release <= seconds:
+                    srv.submit(sid[s.name], pinned[s.name][k % len(s.pool)])
+                    pending[s.name] = release
+                    nsub[s.name] = k + 1
+            if not pending:
+                time.sleep(0.0005)
+                continue
+            srv.tick()
+            for name in list(pending):
+                cands, _ = srv.collect(sid[name])
+                t = time.perf_counter() - t0
+                spec = next(s for s in specs if s.name == name)
+                spec.latencies.append(t - pending.pop(name))
+                spec.ncand += len(cands)
+    finally:
+        srv.close()
+    out = {}
+    for s in specs:
+        lat = np.array(s.latencies) * 1e3
+        out[s.name] = {"chunks": int(lat.size),
+                       "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+                       "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+                       "max_ms": float(lat.max()) if lat.size else None,
+                       "candidates": s.ncand}
+    out["_admission_retries"] = rejected
+    return out
+
+
+def default_specs(seed=7):
+    """The 71-SB Apertif stream (12 TABs, native + D=4 trials) plus two smaller streams of other
+    shapes that join later: a 384-channel beam to DM 500 and a 768-channel beam to DM 2000."""
+    specs = []
+    chunk = synth.CHUNK
+    pool = [synth.noise((12, 1536, chunk), seed=seed + i) for i in range(2)]
+    specs.append(StreamSpec("apertif71", [synth.cfg_apertif(), synth.cfg_apertif_ds()], 12, chunk,
+                            pool, sb_table=synth.sb_table_synthetic()))
+    for name, nchan, dm_hi, ntr, start in (("b384", 384, 500.0, 1024, 2.0),
+                                           ("b768", 768, 2000.0, 2048, 4.0)):
+        f_lo, df = synth.band(nchan)
+        w = synth.Workload(name, nchan, f_lo, df, synth.TSAMP, np.linspace(0, dm_hi, ntr),
+                           [1 << k for k in range(9)])
+        spool = [synth.noise((1, nchan, 6250), seed=seed + 10 + i) for i in range(2)]
+        specs.append(StreamSpec(name, [w], 1, 6250, spool, start=start))
+    return specs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--seconds", type=float, default=20.0)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    res = serve(default_specs(), args.seconds, int(args.budget_gb * 2**30))
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
