@@ -257,9 +257,11 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream);
 /* Wait for the last pushed chunk and copy its candidates to host_out [capacity], sorted by
  * (beam, downsample, dm_index, width, sample).  `sample` is absolute: the boxcar start in the
  * plan's (downsampled) samples counted from the first sample of chunk 0 at the reference
- * frequency, i.e. k * chunk / D - D-halo + t for output t of chunk k (negative while the
- * history is still the initial zeros).  *count = number found; ARTS_E_CAPACITY if it exceeds
- * capacity or the stream's own cand_capacity.  *chunk_index (nullable) = k.                   */
+ * frequency, i.e. k * chunk / D - D-halo + t for output t of chunk k.  Only outputs with
+ * sample >= 0 are searched, and the S/N statistics (Sect. 6b.2) are taken over those same
+ * outputs: earlier ones would read the zero history that precedes the stream (see
+ * arts_stream_warmup).  *count = number found; ARTS_E_CAPACITY if it exceeds capacity or the
+ * stream's own cand_capacity.  *chunk_index (nullable) = k.                                   */
 int arts_stream_wait(arts_stream_t s, arts_candidate* host_out, int64_t capacity,
                      int64_t* count, int64_t* chunk_index);
 
@@ -267,6 +269,13 @@ int arts_stream_wait(arts_stream_t s, arts_candidate* host_out, int64_t capacity
  * samples (0 when every plan is downsampled).                                                 */
 int arts_stream_info(arts_stream_t s, int64_t* chunks_pushed, int64_t* device_bytes,
                      int64_t* halo_native);
+
+/* First output t of chunk `chunk_index` that plan_index searches: max(0, halo - k * chunk / D)
+ * capped at chunk / D (= nothing searched), halo = max delay + wmax - 1 in downsampled samples.
+ * Zero for every plan from chunk ceil(max over plans of halo * D / chunk) on; ARTS_E_INVAL for
+ * a bad index.  With ARTS_STREAM_GRAPH, chunks with a nonzero warm-up run without the graphs. */
+int arts_stream_warmup(arts_stream_t s, int32_t plan_index, int64_t chunk_index,
+                       int64_t* t_begin);
 
 /* Accumulated milliseconds and push count of one profiled phase (see ARTS_STREAM_PROFILE).    */
 int arts_stream_timing(arts_stream_t s, int32_t phase, double* total_ms, int64_t* count);

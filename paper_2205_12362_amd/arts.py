@@ -71,6 +71,7 @@ _SIGNATURES = {
     "arts_stream_push": (C.c_int, [_vp, _vp, _vp]),
     "arts_stream_wait": (C.c_int, [_vp, _vp, _i64, _pi64, _pi64]),
     "arts_stream_info": (C.c_int, [_vp, _pi64, _pi64, _pi64]),
+    "arts_stream_warmup": (C.c_int, [_vp, _i32, _i64, _pi64]),
     "arts_stream_timing": (C.c_int, [_vp, _i32, _pf64, _pi64]),
     "arts_stream_series": (C.c_int, [_vp, _i32, C.POINTER(_vp), _pi64]),
     "arts_stream_snapshot_bytes": (C.c_int, [_vp, _pi64]),
@@ -444,6 +445,12 @@ def arts_stream_info(stream_h):
     return {"chunks": a.value, "device_bytes": b.value, "halo_native": c.value}
 
 
+def arts_stream_warmup(stream_h, plan_index, chunk_index):
+    t = C.c_int64()
+    _check(lib().arts_stream_warmup(stream_h, int(plan_index), int(chunk_index), C.byref(t)))
+    return t.value
+
+
 def arts_stream_timing(stream_h, phase):
     ms, n = C.c_double(), C.c_int64()
     _check(lib().arts_stream_timing(stream_h, int(phase), C.byref(ms), C.byref(n)))
@@ -514,6 +521,17 @@ class Stream:
 
     def timing(self, phase):
         return arts_stream_timing(self.handle, phase)
+
+    def warmup(self, plan_index, chunk_index):
+        """First output sample of that chunk the plan searches (chunk / D: none)."""
+        return arts_stream_warmup(self.handle, plan_index, chunk_index)
+
+    def warm_chunks(self):
+        """Index of the first chunk that every plan searches in full."""
+        k = 0
+        while any(self.warmup(p, k) for p in range(len(self.plans))):
+            k += 1
+        return k
 
     def series(self, plan_index):
         """Last chunk's series of one plan as a torch int32 view [nbeam][ndm][L]."""

@@ -129,7 +129,8 @@ int launch_row_stats(const int32_t* series, int64_t L, int64_t nrep, int64_t nro
 int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
                       int64_t nrep, float thr, int64_t t_offset, int32_t beam_offset,
                       const int64_t* s1, const double* musig, arts_candidate* cand,
-                      unsigned long long* count, int64_t cap, hipStream_t s);
+                      unsigned long long* count, int64_t cap, hipStream_t s,
+                      int64_t t_begin = 0);
 int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
                       int64_t nrep, const int64_t* s1, const double* musig, int32_t* sums,
                       float* snr, hipStream_t s);
@@ -181,6 +182,12 @@ namespace arts {
 // Stream internals (arts_stream.cpp), shared with the serving engine (arts_server.cpp).
 int stream_advance(arts_stream_s* s, int parity, hipStream_t hs);
 DedispJob stream_job(arts_stream_s* s, int parity, size_t plan_index);
+// Output samples of chunk k whose dedispersion window starts before the stream's first input
+// sample (they read the zero history) are left out of the statistics and the search: plan p
+// searches t in [stream_warmup(s, p, k), chunk / D).  All zero once k * chunk >= D * halo.
+int64_t stream_warmup(const arts_stream_s* s, size_t plan_index, int64_t k);
+bool stream_warm(const arts_stream_s* s, int64_t k);
+// Candidate search of chunk k = s->pushed over every plan's series.
 int stream_candidates(arts_stream_s* s, hipStream_t hs);
 int64_t stream_bytes_needed(const arts_plan_t* plans, int32_t nplan, int32_t nsrc, int32_t nbeam,
                             int64_t chunk, int64_t cand_capacity);

@@ -830,7 +830,7 @@ __device__ __forceinline__ void emit_cand(const CandOut& o, int64_t t, int32_t b
 }
 
 __global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
-    const int32_t* __restrict__ series, int64_t L, int64_t nrep, int32_t ndm,
+    const int32_t* __restrict__ series, int64_t pitch, int64_t L, int64_t nrep, int32_t ndm,
     const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, const double* __restrict__ dms,
     double thr, int64_t t_offset, int32_t beam_offset, int32_t ds,
     arts_candidate* __restrict__ cand, unsigned long long* __restrict__ count, int64_t cap) {
@@ -847,7 +847,7 @@ __global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
   __shared__ double s_musig[2];
 
   const int64_t row = blockIdx.x;
-  const int32_t* x = series + row * L;
+  const int32_t* x = series + row * pitch;
   const int tid = threadIdx.x;
   // ---- pass 1: moments over t < nrep (exact int64 sums)
   {
@@ -1026,7 +1026,8 @@ __global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
 int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
                       int64_t nrep, float thr, int64_t t_offset, int32_t beam_offset,
                       const int64_t*, const double*, arts_candidate* cand,
-                      unsigned long long* count, int64_t cap, hipStream_t s) {
+                      unsigned long long* count, int64_t cap, hipStream_t s, int64_t t_begin) {
+  if (t_begin < 0 || t_begin >= nrep) return fail(ARTS_E_INVAL, "t_begin outside [0, nrep)");
   const int64_t nrows = static_cast<int64_t>(nbeam) * p->ndm;
   if (nrows > INT_MAX) return fail(ARTS_E_INVAL, "candidate grid too large");
   if (p->nwidth > kMaxWidthsCand) return fail(ARTS_E_INVAL, "at most %d widths", kMaxWidthsCand);
@@ -1040,8 +1041,9 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
   }
   (void)hipGetLastError();
   hipLaunchKernelGGL(candidates_kernel, dim3(static_cast<unsigned>(nrows)), dim3(kBoxThreads),
-                     lds, s, series, L, nrep, p->ndm, p->d_widths, p->nwidth, p->wmax, p->d_dms,
-                     static_cast<double>(thr), t_offset, beam_offset, p->ds, cand, count, cap);
+                     lds, s, series + t_begin, L, L - t_begin, nrep - t_begin, p->ndm,
+                     p->d_widths, p->nwidth, p->wmax, p->d_dms, static_cast<double>(thr),
+                     t_offset + t_begin, beam_offset, p->ds, cand, count, cap);
   ARTS_HIP(hipGetLastError());
   return ARTS_OK;
 }

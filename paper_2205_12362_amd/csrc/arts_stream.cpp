@@ -145,15 +145,31 @@ DedispJob stream_job(arts_stream_s* s, int parity, size_t p) {
   return job;
 }
 
+int64_t stream_warmup(const arts_stream_s* s, size_t p, int64_t k) {
+  const int64_t nrep = s->chunk / s->plans[p]->ds;
+  const int64_t halo = s->H[p] / s->plans[p]->ds;
+  // output t of chunk k starts its window at downsampled input sample k * nrep - halo + t
+  if (k >= (halo + nrep - 1) / nrep) return 0;
+  return std::min(nrep, halo - k * nrep);
+}
+
+bool stream_warm(const arts_stream_s* s, int64_t k) {
+  for (size_t p = 0; p < s->plans.size(); ++p)
+    if (stream_warmup(s, p, k) > 0) return false;
+  return true;
+}
+
 int stream_candidates(arts_stream_s* s, hipStream_t hs) {
   if (int st = launch_zero_u64(s->d_count, 1, hs)) return st;
   for (size_t p = 0; p < s->plans.size(); ++p) {
     const arts_plan_s* pl = s->plans[p];
     const int64_t nrep = s->chunk / pl->ds;
+    const int64_t t0 = stream_warmup(s, p, s->pushed);
+    if (t0 >= nrep) continue;
     // sample numbers are made absolute on the host: chunk-relative start minus the halo
     if (int st = launch_candidates(pl, s->series[p], s->nbeam, s->L[p], nrep, s->thr,
                                    -s->H[p] / pl->ds, 0, nullptr, nullptr, s->d_cand,
-                                   s->d_count, s->cap, hs))
+                                   s->d_count, s->cap, hs, t0))
       return st;
   }
   ARTS_HIP(hipMemcpyAsync(s->h_count, s->d_count, sizeof(unsigned long long),
@@ -331,7 +347,9 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
   if (chunk && chunk != s->input)
     ARTS_HIP(hipMemcpyAsync(s->input, chunk, rows * s->chunk, hipMemcpyDeviceToDevice, s->hs));
   const int parity = static_cast<int>(s->pushed & 1);
-  if (s->flags & kGraph) {
+  // warm-up chunks search a chunk-dependent part of each series: they run eagerly, and the
+  // graphs are captured once every plan searches its whole chunk
+  if ((s->flags & kGraph) && stream_warm(s, s->pushed)) {
     if (!s->gexec[parity]) {
       hipGraph_t g = nullptr;
       ARTS_HIP(hipStreamBeginCapture(s->hs, hipStreamCaptureModeThreadLocal));
@@ -400,6 +418,15 @@ int arts_stream_info(arts_stream_t s, int64_t* chunks_pushed, int64_t* device_by
   if (chunks_pushed) *chunks_pushed = s->pushed;
   if (device_bytes) *device_bytes = s->device_bytes;
   if (halo_native) *halo_native = s->hmax;
+  return ARTS_OK;
+}
+
+int arts_stream_warmup(arts_stream_t s, int32_t plan_index, int64_t chunk_index,
+                       int64_t* t_begin) {
+  if (!s || !t_begin) return fail(ARTS_E_INVAL, "NULL argument");
+  if (plan_index < 0 || plan_index >= static_cast<int32_t>(s->plans.size()) || chunk_index < 0)
+    return fail(ARTS_E_INVAL, "plan or chunk index out of range");
+  *t_begin = stream_warmup(s, static_cast<size_t>(plan_index), chunk_index);
   return ARTS_OK;
 }
 

@@ -17,9 +17,10 @@ def _spec(nchan, dms, widths, D, chunk):
 
 
 def _stream_a():
-    ws = [_spec(64, np.arange(0, 300, 3.0), [1, 2, 4, 8], 1, 1200),
-          _spec(64, np.arange(300, 900, 6.0), [1, 2, 4], 4, 1200)]
-    return ws, 3, 1200
+    # both plans search their whole chunk from chunk 3 on (a partial search in chunks 1 and 2)
+    ws = [_spec(64, np.arange(0, 300, 3.0), [1, 2, 4, 8], 1, 2400),
+          _spec(64, np.arange(300, 600, 3.0), [1, 2, 4], 4, 2400)]
+    return ws, 3, 2400
 
 
 def _chunks(nsrc, nchan, chunk, n, seed):

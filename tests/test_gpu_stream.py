@@ -1,7 +1,8 @@
 """GPU parity of the streaming path: chunk-by-chunk search with a device-resident overlap equals
 the oracle's one-shot search of the concatenated input (zero history before chunk 0), for
-native and downsampled plans, with and without on-the-fly SB formation; checkpoint/resume and
-hipGraph replay reproduce the plain path bit for bit."""
+native and downsampled plans, with and without on-the-fly SB formation; candidates come only
+from output samples whose dedispersion window starts at or after the stream's first sample;
+checkpoint/resume and hipGraph replay reproduce the plain path bit for bit."""
 import numpy as np
 import pytest
 
@@ -11,7 +12,7 @@ from tests._parity import compare_candidates, near_threshold_rows, to_dev
 
 pytestmark = pytest.mark.gpu
 
-NCHAN, CHUNK = 64, 1200
+NCHAN, CHUNK = 64, 2400
 
 
 def _plans():
@@ -29,7 +30,13 @@ def _chunks(nsrc, n, seed):
         if k % 2 == 1:  # a bright top-hat in source 0 now and then
             c[0, :, 100:140] = np.minimum(255, c[0, :, 100:140].astype(int) + 60).astype(np.uint8)
         out.append(c)
-    return out
+    full = np.concatenate(out, axis=2)
+    # a burst at DM 600 (a downsampled trial) sweeping across chunk boundaries, in source 0
+    f_lo, df = synth.band(NCHAN)
+    d600 = O.delay_table(NCHAN, f_lo, df, synth.TSAMP, np.array([600.0]))[0]
+    if 4000 + int(d600.max()) + 32 <= full.shape[2]:
+        synth.add_tophat(full[0], 4000 + d600, 32, 60)
+    return [full[:, :, k * CHUNK:(k + 1) * CHUNK].copy() for k in range(n)]
 
 
 @pytest.mark.parametrize("use_table", [False, True])
@@ -38,7 +45,7 @@ def test_stream_matches_one_shot(use_table):
     nsrc = 4
     table = synth.sb_table_synthetic(5, nsrc, NCHAN) if use_table else None
     nbeam = 5 if use_table else nsrc
-    chunks = _chunks(nsrc, 5, seed=70 + use_table)
+    chunks = _chunks(nsrc, 8, seed=70 + use_table)
     H = [p.info["downsample"] * p.info["halo"] for p in plans]
     hmax = max(H)
     full = np.concatenate([np.zeros((nsrc, NCHAN, hmax), np.uint8)] + chunks, axis=2)
@@ -46,6 +53,7 @@ def test_stream_matches_one_shot(use_table):
         full = O.sb_synthesize(full, table)
     delays = [O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms, w.downsample) for w in ws]
     thr = 6.0
+    warm_seen, found = [False, False], [0, 0]
     with arts.Stream(plans, nsrc, CHUNK, thr, sb_table=to_dev(table) if use_table else None,
                      nbeam=nbeam) as st:
         for k, c in enumerate(chunks):
@@ -64,13 +72,25 @@ def test_stream_matches_one_shot(use_table):
                     assert np.array_equal(got[b], x), (k, p, b)
                     nrep = CHUNK // w.downsample
                     off = (k * CHUNK - H[p]) // w.downsample
-                    for c_ in O.candidates(x, w.widths, nrep, thr, beam=b, t_offset=off):
+                    # output t reads input from absolute sample off + t on: the search starts
+                    # where that is no longer negative
+                    t0 = min(nrep, max(0, -off))
+                    assert st.warmup(p, k) == t0
+                    warm_seen[p] |= 0 < t0 < nrep
+                    if t0 == nrep:
+                        continue
+                    xs = x[:, t0:]
+                    for c_ in O.candidates(xs, w.widths, nrep - t0, thr, beam=b,
+                                           t_offset=off + t0):
                         oc.append(c_)
-                    for (d, wd) in near_threshold_rows(x, w.widths, nrep, thr,
+                    for (d, wd) in near_threshold_rows(xs, w.widths, nrep - t0, thr,
                                                        np.arange(x.shape[0])):
                         near.add((d, wd))
                 sel = cands[cands["downsample"] == w.downsample]
                 compare_candidates(sel, oc, near)
+                found[p] += len(sel)
+    assert all(warm_seen)                       # a partially warm chunk was checked per plan
+    assert all(f > 0 for f in found)            # both plans reported bursts once warm
 
 
 def test_stream_snapshot_resume():
@@ -103,7 +123,7 @@ def test_stream_graph_replay_matches_eager():
     import torch
     ws, plans = _plans()
     nsrc = 3
-    chunks = _chunks(nsrc, 7, seed=110)
+    chunks = _chunks(nsrc, 10, seed=110)   # graphs once warm (chunk 5), replayed from chunk 7
     out = {}
     for graph in (False, True):
         res = []
