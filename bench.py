@@ -95,7 +95,14 @@ def cpu_baseline(beam, w_native):
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2205_12362_amd", "csrc", "arts_kernels.hip")
 PROFILE_JSON = os.path.join(ROOT, "profiles", "dedisperse_serving_chunk.json")
-DOMINANT = "dedisperse_kernel<4, 5, 4, 8>"
+
+
+def kernel_name(describe):
+    """Template name of the dedispersion kernel of a tiling variant, from its description
+    ("J=5 ACC=3 WAVES=8 SPD=4 packed" -> "dedisperse_kernel<4, 5, 3, 8, 1>")."""
+    f = dict(kv.split("=") for kv in describe.split() if "=" in kv)
+    return (f"dedisperse_kernel<{f['SPD']}, {f['J']}, {f['ACC']}, {f['WAVES']}, "
+            f"{1 if 'packed' in describe else 0}>")
 
 
 def kernel_hash():
@@ -150,11 +157,16 @@ def summarize_profile(stats_dir, fetch_dir, write_dir):
     # the calibration copies are the largest dispatches of the copy kernel (1 GiB each)
     copy_name = "copyBuffer" if pick(fetch, "copyBuffer") else "elementwise"
     cf, cw = pick(fetch, copy_name, True), pick(write, copy_name, True)
-    df, dw = pick(fetch, "dedisperse_kernel<4, 5, 4, 8>"), pick(write, "dedisperse_kernel<4, 5, 4, 8>")
+    # the dominant kernel: the native (byte-sample) dedispersion kernel with the most time
+    nat = [r for r in stats if "dedisperse_kernel<4," in r["Name"]]
+    dom = max(nat, key=lambda r: float(r["TotalDurationNs"])) if nat else None
+    name = dom["Name"] if dom else "dedisperse_kernel<4,"
+    short = name[name.index("dedisperse_kernel"):name.index(">") + 1] if dom else name
+    df, dw = pick(fetch, short), pick(write, short)
     f_scale = copy_bytes / (cf * 1024) if cf else None   # bytes per KiB reported
     w_scale = copy_bytes / (cw * 1024) if cw else None
     traffic = (df * 1024 * f_scale + dw * 1024 * w_scale) if (df and dw and f_scale and w_scale) else None
-    lines = ["rocprofv3 summary: 71-SB serving chunk (bench.py), dominant kernel " + DOMINANT, ""]
+    lines = ["rocprofv3 summary: 71-SB serving chunk (bench.py), dominant kernel " + short, ""]
     lines.append("kernel stats (rocprofv3 --kernel-trace --stats):")
     for r in stats:
         lines.append(f"  {r['Name'][:70]:70s} calls {r['Calls']:>4s}  avg {float(r['AverageNs'])/1e6:9.3f} ms")
@@ -174,10 +186,9 @@ def summarize_profile(stats_dir, fetch_dir, write_dir):
     os.makedirs(os.path.dirname(PROFILE_JSON), exist_ok=True)
     with open(PROFILE_JSON[:-5] + ".txt", "w") as f:
         f.write("\n".join(lines) + "\n")
-    dom = [r for r in stats if "dedisperse_kernel<4, 5, 4, 8>" in r["Name"]]
     with open(PROFILE_JSON, "w") as f:
-        json.dump({"kernel": DOMINANT, "kernel_sha": kernel_hash(),
-                   "avg_ms": float(dom[0]["AverageNs"]) / 1e6 if dom else None,
+        json.dump({"kernel": short, "kernel_sha": kernel_hash(),
+                   "avg_ms": float(dom["AverageNs"]) / 1e6 if dom else None,
                    "fetch_kib": df, "write_kib": dw, "copy_fetch_kib": cf, "copy_write_kib": cw,
                    "hbm_bytes_per_launch": traffic}, f, indent=1)
     print("\n".join(lines))
@@ -284,7 +295,7 @@ def main():
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_PK16_ADDS / 1e12,
                     "unit": "Tadd/s", "frac": achieved / PEAK_PK16_ADDS,
                     "frac_int32_peak": achieved / PEAK_INT32_ADDS, "traffic": measured_traffic(),
-                    "kernel": "dedisperse_kernel<4,5,4,8>",
+                    "kernel": kernel_name(arts.arts_tiling_describe(p_nat.tiling())),
                     "kernel_ms": phases["dedisperse_native"],
                     "adds_per_launch": adds}
     lat_ms = np.array(lat) * 1e3

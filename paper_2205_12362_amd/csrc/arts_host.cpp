@@ -124,8 +124,12 @@ int build_tiling(arts_plan_s* p, int variant) {
   // two buffers (each with 4 pad words) and an SB-table row; per channel its window plus one
   // offset-list entry per DM of the block
   const int64_t per_buf = (budget - ((nchan + 3) & ~int64_t(3))) / 2 - 16;
+  // a chunk's channels must fit the kernels' narrow partial sums: 8-bit counts of each run, and
+  // for packed 16-bit samples (sums of D bytes) a 16-bit half per output
+  const int64_t cc_max = (v.pack && v.spd == 2) ? std::min<int64_t>(255, 65535 / (255LL * p->ds))
+                                                : 255;
   int cc = static_cast<int>(
-      std::min<int64_t>({nchan, 255, per_buf / (4LL * (t.win_dwords + t.m_blk))}));
+      std::min<int64_t>({nchan, cc_max, per_buf / (4LL * (t.win_dwords + t.m_blk))}));
   if (cc < 1)
     return fail(ARTS_E_INVAL,
                 "variant %d: one channel's window (%d B) exceeds the LDS budget (%lld B); the DM "
@@ -452,7 +456,8 @@ int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
   if (variant < 0 || variant >= kNumVariants || !buf || len < 1)
     return fail(ARTS_E_INVAL, "bad variant or buffer");
   const TileVariant& v = kVariants[variant];
-  snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d", v.j, v.acc, v.waves, v.spd);
+  snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d%s", v.j, v.acc, v.waves, v.spd,
+           v.pack ? " packed" : "");
   return ARTS_OK;
 }
 

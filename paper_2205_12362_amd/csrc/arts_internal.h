@@ -17,7 +17,7 @@ namespace arts {
 // lane accumulates `acc` DMs x `j * spd` consecutive samples in int32 registers.  spd is the
 // number of samples per LDS dword: 4 for native uint8 data, 2 for downsampled 16-bit sums.
 struct TileVariant {
-  int spd, j, acc, waves;
+  int spd, j, acc, waves, pack;
 };
 extern const TileVariant kVariants[];
 extern const int kNumVariants;

@@ -12,23 +12,33 @@
 namespace arts {
 
 // ------------------------------------------------------------------ tiling variants ----
-// spd, j, acc, waves.  j is odd so the lane stride of j dwords hits distinct LDS banks.
+// spd, j, acc, waves, pack.  j is odd so the lane stride of j dwords hits distinct LDS banks;
+// pack selects the packed 16-bit partial sums (native data only).
 const TileVariant kVariants[] = {
-    {4, 5, 4, 8},   // 0: 32 DMs x 1280 samples per block, 80 accumulators per lane
-    {4, 7, 3, 8},   // 1: 24 DMs x 1792
-    {4, 5, 4, 16},  // 2: 64 DMs x 1280, one block per CU
-    {4, 3, 6, 8},   // 3: 48 DMs x 768
-    {4, 5, 2, 4},   // 4:  8 DMs x 1280, small problems
-    {4, 7, 4, 8},   // 5: 32 DMs x 1792, 112 accumulators
-    {2, 5, 4, 8},   // 6: downsampled: 32 DMs x 640
-    {2, 9, 2, 8},   // 7: downsampled: 16 DMs x 1152
-    {2, 7, 3, 8},   // 8: downsampled: 24 DMs x 896
+    {4, 5, 4, 8, 0},   // 0: 32 DMs x 1280 samples per block, 80 accumulators per lane
+    {4, 7, 3, 8, 0},   // 1: 24 DMs x 1792
+    {4, 5, 4, 16, 0},  // 2: 64 DMs x 1280, one block per CU
+    {4, 3, 6, 8, 0},   // 3: 48 DMs x 768
+    {4, 5, 2, 4, 0},   // 4:  8 DMs x 1280, small problems
+    {4, 7, 4, 8, 0},   // 5: 32 DMs x 1792, 112 accumulators
+    {2, 5, 4, 8, 0},   // 6: downsampled: 32 DMs x 640
+    {2, 9, 2, 8, 0},   // 7: downsampled: 16 DMs x 1152
+    {2, 7, 3, 8, 0},   // 8: downsampled: 24 DMs x 896
+    {4, 5, 4, 8, 1},   // 9: as 0, packed
+    {4, 5, 3, 8, 1},   // 10: 24 DMs x 1280, packed
+    {4, 3, 6, 8, 1},   // 11: as 3, packed
+    {4, 5, 4, 16, 1},  // 12: as 2, packed
+    {2, 5, 4, 8, 1},   // 13: as 6, packed
+    {2, 9, 2, 8, 1},   // 14: as 7, packed
+    {2, 7, 3, 8, 1},   // 15: as 8, packed
+    {2, 5, 6, 8, 1},   // 16: downsampled, packed: 48 DMs x 640
+    {4, 5, 2, 4, 1},   // 17: as 4, packed
 };
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int default_variant(int downsample, int64_t ndm) {
-  if (downsample > 1) return 6;
-  return ndm <= 64 ? 4 : 0;
+  if (downsample > 1) return 16;
+  return ndm <= 64 ? 17 : 10;
 }
 
 // ------------------------------------------------------------------ dedispersion ----
@@ -172,6 +182,179 @@ __device__ __forceinline__ void accum_run(uint32_t* acc, const int32_t* ent, int
   }
 }
 
+// ---- packed partial sums (spd = 4).  Word e[k] holds, in its low and high 16-bit halves, the
+// partial sums of output samples 4k and 4k + 2 of the lane's tile; o[k] those of 4k + 1 and
+// 4k + 3.  For a channel whose samples start at byte MS of the lane's first LDS dword, the two
+// samples of a word are bytes MS + f and MS + f + 2 of the dword sequence w[k], w[k + 1]
+// (f = 0 for e, 1 for o): one v_perm_b32 (or AND) moves both into their halves, and v_add3_u32
+// adds two channels' words at a time.  Per four samples this is 3 instructions instead of 4
+// single-byte adds.  A staged chunk has at most 255 channels, so a half never exceeds
+// 255 * 255 < 2^16; the halves are widened into the int32 totals once per chunk.
+template <int S>
+__device__ __forceinline__ uint32_t field_pair(const uint32_t* w, int k) {
+  // bytes S and S + 2 of (w[k], w[k + 1]) zero-extended into the low and high halves
+  if constexpr (S == 0)
+    return w[k] & 0x00FF00FFu;
+  else if constexpr (S == 1)
+    return __builtin_amdgcn_perm(w[k], w[k], 0x0C030C01u);
+  else if constexpr (S == 4)
+    return w[k + 1] & 0x00FF00FFu;
+  else  // selector bytes index the 8-byte value w[k + 1]:w[k]; 0x0C yields a zero byte
+    return __builtin_amdgcn_perm(w[k + 1], w[k], 0x0C000C00u | ((S + 2u) << 16) | S);
+}
+
+template <int J, int MS>
+__device__ __forceinline__ void add_pk(uint32_t* e, uint32_t* o, const uint32_t* w1,
+                                       const uint32_t* w2) {
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    e[k] += field_pair<MS>(w1, k) + field_pair<MS>(w2, k);
+    o[k] += field_pair<MS + 1>(w1, k) + field_pair<MS + 1>(w2, k);
+  }
+}
+
+template <int J, int MS>
+__device__ __forceinline__ void add_pk1(uint32_t* e, uint32_t* o, const uint32_t* w) {
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    e[k] += field_pair<MS>(w, k);
+    o[k] += field_pair<MS + 1>(w, k);
+  }
+}
+
+// Packed counterpart of accum_run.  With PF (tiles with at most 60 accumulators per lane, so
+// that the registers suffice) four channels per step, the next step's four offsets being read
+// while this step's words are summed, so the window reads need not wait for the list read (the
+// lists' four pad words keep that read in bounds at the end of the last run); then, and
+// otherwise, two channels per step.
+template <int J, int MS, bool PF>
+__device__ __forceinline__ void accum_run_pk(uint32_t* e, uint32_t* o, const int32_t* ent, int n,
+                                             const uint8_t* lane_base) {
+  constexpr int NW = (MS == 0) ? J : J + 1;
+  int i = 0;
+  if (PF && n >= 4) {
+    int32_t q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = ent[u];
+    for (; i + 4 <= n; i += 4) {
+      uint32_t w[4][J + 1];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + q[u]);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) w[u][k] = p[k];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = ent[i + 4 + u];
+      add_pk<J, MS>(e, o, w[0], w[1]);
+      add_pk<J, MS>(e, o, w[2], w[3]);
+    }
+  }
+  for (; i + 2 <= n; i += 2) {
+    uint32_t w[2][J + 1];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i + u]);
+#pragma unroll
+      for (int k = 0; k < NW; ++k) w[u][k] = p[k];
+    }
+    add_pk<J, MS>(e, o, w[0], w[1]);
+  }
+  if (i < n) {
+    uint32_t w[J + 1];
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = p[k];
+    add_pk1<J, MS>(e, o, w);
+  }
+}
+
+// ---- packed partial sums of 16-bit samples (spd = 2, downsampled data).  Word p[k] holds the
+// partial sums of outputs 2k and 2k + 1 in its halves.  For MS = 0 an LDS dword already is such
+// a pair and is added as it is; for MS = 1 one v_alignbyte_b32 takes the pair out of two
+// neighbouring dwords.  A half holds up to floor(65535 / (255 D)) channels (the plan limits its
+// chunks to that), after which the halves are widened into the int32 totals.
+template <int MS>
+__device__ __forceinline__ uint32_t half_pair(const uint32_t* w, int k) {
+  if constexpr (MS == 0)
+    return w[k];
+  else  // bytes 2..5 of the 8-byte value w[k + 1]:w[k]
+    return __builtin_amdgcn_alignbyte(w[k + 1], w[k], 2);
+}
+
+template <int J, int MS>
+__device__ __forceinline__ void add_pk16(uint32_t* pk, const uint32_t* w1, const uint32_t* w2) {
+#pragma unroll
+  for (int k = 0; k < J; ++k) pk[k] += half_pair<MS>(w1, k) + half_pair<MS>(w2, k);
+}
+
+template <int J, int MS, bool PF>
+__device__ __forceinline__ void accum_run_pk16(uint32_t* pk, const int32_t* ent, int n,
+                                               const uint8_t* lane_base) {
+  constexpr int NW = (MS == 0) ? J : J + 1;
+  int i = 0;
+  if (PF && n >= 4) {
+    int32_t q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = ent[u];
+    for (; i + 4 <= n; i += 4) {
+      uint32_t w[4][J + 1];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + q[u]);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) w[u][k] = p[k];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = ent[i + 4 + u];
+      add_pk16<J, MS>(pk, w[0], w[1]);
+      add_pk16<J, MS>(pk, w[2], w[3]);
+    }
+  }
+  for (; i + 2 <= n; i += 2) {
+    uint32_t w[2][J + 1];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i + u]);
+#pragma unroll
+      for (int k = 0; k < NW; ++k) w[u][k] = p[k];
+    }
+    add_pk16<J, MS>(pk, w[0], w[1]);
+  }
+  if (i < n) {
+    uint32_t w[J + 1];
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = p[k];
+#pragma unroll
+    for (int k = 0; k < J; ++k) pk[k] += half_pair<MS>(w, k);
+  }
+}
+
+template <int J>
+__device__ __forceinline__ void flush_pk16(uint32_t* acc, uint32_t* pk) {
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    add_half<0>(acc[2 * k], pk[k]);
+    add_half<1>(acc[2 * k + 1], pk[k]);
+    pk[k] = 0;
+  }
+}
+
+// Widen the packed halves into the int32 totals (one SDWA add each) and clear them.
+template <int J>
+__device__ __forceinline__ void flush_pk(uint32_t* acc, uint32_t* e, uint32_t* o) {
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    add_half<0>(acc[4 * k], e[k]);
+    add_half<1>(acc[4 * k + 2], e[k]);
+    add_half<0>(acc[4 * k + 1], o[k]);
+    add_half<1>(acc[4 * k + 3], o[k]);
+    e[k] = 0;
+    o[k] = 0;
+  }
+}
+
 typedef __attribute__((address_space(1))) const void* global_ptr_t;
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
@@ -236,7 +419,7 @@ __device__ __forceinline__ void stage_lists(const DedispArgs& a, const int32_t* 
 
 // One tile: DM block blk, time tile tt, beam b.  Used by the one-launch-per-job kernel and by
 // the persistent batch kernel; ends after its global stores with no LDS access pending.
-template <int SPD, int J, int ACC, int WAVES>
+template <int SPD, int J, int ACC, int WAVES, int PK>
 __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, int tt, int b,
                                                 uint32_t* lds) {
   constexpr int T = SPD * J;
@@ -295,12 +478,33 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
         const uint32_t packed = __builtin_amdgcn_readfirstlane(cnt_blk[ch * a.m_blk + x]);
         const int32_t* ent = ent_cur + (wave * ACC + x) * a.cc;
         const int n0 = packed & 0xff, n1 = (packed >> 8) & 0xff;
-        accum_run<SPD, J, 0>(acc[x], ent, n0, lane_base);
-        accum_run<SPD, J, 1>(acc[x], ent + n0, n1, lane_base);
-        if constexpr (SPD == 4) {
+        if constexpr (PK && SPD == 2) {
+          uint32_t pk[J];
+#pragma unroll
+          for (int k = 0; k < J; ++k) pk[k] = 0;
+          constexpr bool PF = ACC * T <= 60;
+          accum_run_pk16<J, 0, PF>(pk, ent, n0, lane_base);
+          accum_run_pk16<J, 1, PF>(pk, ent + n0, n1, lane_base);
+          flush_pk16<J>(acc[x], pk);
+        } else if constexpr (PK) {
           const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
-          accum_run<SPD, J, 2>(acc[x], ent + n0 + n1, n2, lane_base);
-          accum_run<SPD, J, 3>(acc[x], ent + n0 + n1 + n2, n3, lane_base);
+          uint32_t e[J], o[J];
+#pragma unroll
+          for (int k = 0; k < J; ++k) e[k] = o[k] = 0;
+          constexpr bool PF = ACC * T <= 60;
+          accum_run_pk<J, 0, PF>(e, o, ent, n0, lane_base);
+          accum_run_pk<J, 1, PF>(e, o, ent + n0, n1, lane_base);
+          accum_run_pk<J, 2, PF>(e, o, ent + n0 + n1, n2, lane_base);
+          accum_run_pk<J, 3, PF>(e, o, ent + n0 + n1 + n2, n3, lane_base);
+          flush_pk<J>(acc[x], e, o);
+        } else {
+          accum_run<SPD, J, 0>(acc[x], ent, n0, lane_base);
+          accum_run<SPD, J, 1>(acc[x], ent + n0, n1, lane_base);
+          if constexpr (SPD == 4) {
+            const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
+            accum_run<SPD, J, 2>(acc[x], ent + n0 + n1, n2, lane_base);
+            accum_run<SPD, J, 3>(acc[x], ent + n0 + n1 + n2, n3, lane_base);
+          }
         }
       }
     }
@@ -327,7 +531,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
 // One launch per job: workgroup -> tile, renumbered so that each of the 8 XCDs (to which
 // workgroups are dealt round-robin) runs a contiguous range of (beam, time tile, DM block):
 // neighbouring DM blocks read overlapping input windows and then share that XCD's L2.
-template <int SPD, int J, int ACC, int WAVES>
+template <int SPD, int J, int ACC, int WAVES, int PK>
 __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
   extern __shared__ uint32_t lds[];
   const int64_t bid = blockIdx.x;
@@ -335,8 +539,8 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
   const int64_t lin = xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
   const int blk = static_cast<int>(lin % a.nblk);
   const int64_t rest = lin / a.nblk;
-  dedisperse_tile<SPD, J, ACC, WAVES>(a, blk, static_cast<int>(rest % a.ntt),
-                                      static_cast<int>(rest / a.ntt), lds);
+  dedisperse_tile<SPD, J, ACC, WAVES, PK>(a, blk, static_cast<int>(rest % a.ntt),
+                                          static_cast<int>(rest / a.ntt), lds);
 }
 
 // Persistent batch kernel: a grid sized to the machine pulls tiles of several jobs from work
@@ -354,7 +558,7 @@ struct BatchArgs {
 
 // Four waves per SIMD (<= 128 VGPRs) so that two 8-wave workgroups share a CU, as in the
 // one-launch-per-job kernel.
-template <int SPD, int J, int ACC, int WAVES>
+template <int SPD, int J, int ACC, int WAVES, int PK>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
 void dedisperse_batch_kernel(BatchArgs q) {
   extern __shared__ uint32_t lds[];
@@ -392,13 +596,12 @@ void dedisperse_batch_kernel(BatchArgs q) {
       const int64_t lin = item - q.item_start[j];
       const int blk = static_cast<int>(lin % a.nblk);
       const int64_t rest = lin / a.nblk;
-      dedisperse_tile<SPD, J, ACC, WAVES>(a, blk, static_cast<int>(rest % a.ntt),
-                                          static_cast<int>(rest / a.ntt), lds);
+      dedisperse_tile<SPD, J, ACC, WAVES, PK>(a, blk, static_cast<int>(rest % a.ntt),
+                                              static_cast<int>(rest / a.ntt), lds);
     }
   }
 }
 
-template <int SPD, int J, int ACC, int WAVES>
 static size_t lds_bytes(const DedispArgs& a) {
   return 2 * (static_cast<size_t>(a.win) * a.cc + static_cast<size_t>(a.m_blk) * a.cc + 4) * 4 +
          (a.sb_table ? ((static_cast<size_t>(a.nchan) + 3) & ~static_cast<size_t>(3)) : 0);
@@ -415,43 +618,43 @@ static int allow_full_lds(K kernel, int static_bytes = 0) {
 // static LDS of the persistent kernel (the work-queue slot), rounded to its allocation unit
 constexpr int kBatchStaticLds = 512;
 
-template <int SPD, int J, int ACC, int WAVES>
+template <int SPD, int J, int ACC, int WAVES, int PK>
 static int launch_variant(DedispArgs a, hipStream_t s) {
-  const size_t lds = lds_bytes<SPD, J, ACC, WAVES>(a);
+  const size_t lds = lds_bytes(a);
   if (lds > 160 * 1024) return fail(ARTS_E_INVAL, "LDS request %zu B exceeds 160 KiB", lds);
   a.nwg = static_cast<int64_t>(a.nbeam) * a.ntt * a.nblk;
   if (a.nwg > INT_MAX) return fail(ARTS_E_INVAL, "grid too large (%lld blocks)", (long long)a.nwg);
   static bool attr_set = false;  // one flag per template instance
   if (!attr_set) {
-    if (int st = allow_full_lds(&dedisperse_kernel<SPD, J, ACC, WAVES>)) return st;
+    if (int st = allow_full_lds(&dedisperse_kernel<SPD, J, ACC, WAVES, PK>)) return st;
     attr_set = true;
   }
   (void)hipGetLastError();
-  hipLaunchKernelGGL((dedisperse_kernel<SPD, J, ACC, WAVES>), dim3(static_cast<unsigned>(a.nwg)),
+  hipLaunchKernelGGL((dedisperse_kernel<SPD, J, ACC, WAVES, PK>), dim3(static_cast<unsigned>(a.nwg)),
                      dim3(WAVES * 64), lds, s, a);
   ARTS_HIP(hipGetLastError());
   return ARTS_OK;
 }
 
-template <int SPD, int J, int ACC, int WAVES>
+template <int SPD, int J, int ACC, int WAVES, int PK>
 static int launch_batch_variant(BatchArgs q, size_t lds, hipStream_t s) {
   if (lds + kBatchStaticLds > 160 * 1024)
     return fail(ARTS_E_INVAL, "LDS request %zu B too large for a persistent launch", lds);
   static bool attr_set = false;
   if (!attr_set) {
-    if (int st = allow_full_lds(&dedisperse_batch_kernel<SPD, J, ACC, WAVES>, kBatchStaticLds))
+    if (int st = allow_full_lds(&dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>, kBatchStaticLds))
       return st;
     attr_set = true;
   }
   int per_cu = 0, dev = 0, ncu = 0;
   ARTS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(&dedisperse_batch_kernel<SPD, J, ACC, WAVES>),
+      &per_cu, reinterpret_cast<const void*>(&dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>),
       WAVES * 64, lds));
   ARTS_HIP(hipGetDevice(&dev));
   ARTS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(q.part[8], int64_t(std::max(1, per_cu)) * ncu));
   (void)hipGetLastError();
-  hipLaunchKernelGGL((dedisperse_batch_kernel<SPD, J, ACC, WAVES>), dim3(static_cast<unsigned>(grid)),
+  hipLaunchKernelGGL((dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>), dim3(static_cast<unsigned>(grid)),
                      dim3(WAVES * 64), lds, s, q);
   ARTS_HIP(hipGetLastError());
   return ARTS_OK;
@@ -508,15 +711,24 @@ int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   DedispArgs a;
   if (int st = make_args(p, job, &a)) return st;
   switch (p->tiling.variant) {
-    case 0: return launch_variant<4, 5, 4, 8>(a, s);
-    case 1: return launch_variant<4, 7, 3, 8>(a, s);
-    case 2: return launch_variant<4, 5, 4, 16>(a, s);
-    case 3: return launch_variant<4, 3, 6, 8>(a, s);
-    case 4: return launch_variant<4, 5, 2, 4>(a, s);
-    case 5: return launch_variant<4, 7, 4, 8>(a, s);
-    case 6: return launch_variant<2, 5, 4, 8>(a, s);
-    case 7: return launch_variant<2, 9, 2, 8>(a, s);
-    case 8: return launch_variant<2, 7, 3, 8>(a, s);
+    case 0: return launch_variant<4, 5, 4, 8, 0>(a, s);
+    case 1: return launch_variant<4, 7, 3, 8, 0>(a, s);
+    case 2: return launch_variant<4, 5, 4, 16, 0>(a, s);
+    case 3: return launch_variant<4, 3, 6, 8, 0>(a, s);
+    case 4: return launch_variant<4, 5, 2, 4, 0>(a, s);
+    case 5: return launch_variant<4, 7, 4, 8, 0>(a, s);
+    case 6: return launch_variant<2, 5, 4, 8, 0>(a, s);
+    case 7: return launch_variant<2, 9, 2, 8, 0>(a, s);
+    case 8: return launch_variant<2, 7, 3, 8, 0>(a, s);
+    case 9: return launch_variant<4, 5, 4, 8, 1>(a, s);
+    case 10: return launch_variant<4, 5, 3, 8, 1>(a, s);
+    case 11: return launch_variant<4, 3, 6, 8, 1>(a, s);
+    case 12: return launch_variant<4, 5, 4, 16, 1>(a, s);
+    case 13: return launch_variant<2, 5, 4, 8, 1>(a, s);
+    case 14: return launch_variant<2, 9, 2, 8, 1>(a, s);
+    case 15: return launch_variant<2, 7, 3, 8, 1>(a, s);
+    case 16: return launch_variant<2, 5, 6, 8, 1>(a, s);
+    case 17: return launch_variant<4, 5, 2, 4, 1>(a, s);
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
@@ -576,18 +788,7 @@ int launch_dedisperse_batch(arts_plan_s* const* plans, const DedispJob* jobs, in
     a.nwg = static_cast<int64_t>(a.nbeam) * a.ntt * a.nblk;
     hj[k] = a;
     hs[k + 1] = hs[k] + a.nwg;
-    size_t l = 0;
-    switch (variant) {
-      case 0: l = lds_bytes<4, 5, 4, 8>(a); break;
-      case 1: l = lds_bytes<4, 7, 3, 8>(a); break;
-      case 2: l = lds_bytes<4, 5, 4, 16>(a); break;
-      case 3: l = lds_bytes<4, 3, 6, 8>(a); break;
-      case 4: l = lds_bytes<4, 5, 2, 4>(a); break;
-      case 5: l = lds_bytes<4, 7, 4, 8>(a); break;
-      case 6: l = lds_bytes<2, 5, 4, 8>(a); break;
-      case 7: l = lds_bytes<2, 9, 2, 8>(a); break;
-      default: l = lds_bytes<2, 7, 3, 8>(a); break;
-    }
+    const size_t l = lds_bytes(a);
     lds = std::max(lds, l);
   }
   if (lds > 160 * 1024) return fail(ARTS_E_INVAL, "LDS request %zu B exceeds 160 KiB", lds);
@@ -602,15 +803,24 @@ int launch_dedisperse_batch(arts_plan_s* const* plans, const DedispJob* jobs, in
   q.njobs = n;
   for (int x = 0; x <= 8; ++x) q.part[x] = hs[n] * x / 8;
   switch (variant) {
-    case 0: return launch_batch_variant<4, 5, 4, 8>(q, lds, s);
-    case 1: return launch_batch_variant<4, 7, 3, 8>(q, lds, s);
-    case 2: return launch_batch_variant<4, 5, 4, 16>(q, lds, s);
-    case 3: return launch_batch_variant<4, 3, 6, 8>(q, lds, s);
-    case 4: return launch_batch_variant<4, 5, 2, 4>(q, lds, s);
-    case 5: return launch_batch_variant<4, 7, 4, 8>(q, lds, s);
-    case 6: return launch_batch_variant<2, 5, 4, 8>(q, lds, s);
-    case 7: return launch_batch_variant<2, 9, 2, 8>(q, lds, s);
-    case 8: return launch_batch_variant<2, 7, 3, 8>(q, lds, s);
+    case 0: return launch_batch_variant<4, 5, 4, 8, 0>(q, lds, s);
+    case 1: return launch_batch_variant<4, 7, 3, 8, 0>(q, lds, s);
+    case 2: return launch_batch_variant<4, 5, 4, 16, 0>(q, lds, s);
+    case 3: return launch_batch_variant<4, 3, 6, 8, 0>(q, lds, s);
+    case 4: return launch_batch_variant<4, 5, 2, 4, 0>(q, lds, s);
+    case 5: return launch_batch_variant<4, 7, 4, 8, 0>(q, lds, s);
+    case 6: return launch_batch_variant<2, 5, 4, 8, 0>(q, lds, s);
+    case 7: return launch_batch_variant<2, 9, 2, 8, 0>(q, lds, s);
+    case 8: return launch_batch_variant<2, 7, 3, 8, 0>(q, lds, s);
+    case 9: return launch_batch_variant<4, 5, 4, 8, 1>(q, lds, s);
+    case 10: return launch_batch_variant<4, 5, 3, 8, 1>(q, lds, s);
+    case 11: return launch_batch_variant<4, 3, 6, 8, 1>(q, lds, s);
+    case 12: return launch_batch_variant<4, 5, 4, 16, 1>(q, lds, s);
+    case 13: return launch_batch_variant<2, 5, 4, 8, 1>(q, lds, s);
+    case 14: return launch_batch_variant<2, 9, 2, 8, 1>(q, lds, s);
+    case 15: return launch_batch_variant<2, 7, 3, 8, 1>(q, lds, s);
+    case 16: return launch_batch_variant<2, 5, 6, 8, 1>(q, lds, s);
+    case 17: return launch_batch_variant<4, 5, 2, 4, 1>(q, lds, s);
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
