@@ -124,9 +124,14 @@ def measured_traffic():
     return prof.get("hbm_bytes_per_launch")
 
 
-def summarize_profile(stats_dir, fetch_dir, write_dir):
+SQ_COUNTERS = ("SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE "
+               "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_BUSY_CYCLES SQ_WAVES")
+
+
+def summarize_profile(stats_dir, fetch_dir, write_dir, sq_dir=None):
     """Turn rocprofv3 outputs of this script (kernel stats + FETCH_SIZE + WRITE_SIZE passes, each
-    run with --copy-probe) into profiles/dedisperse_serving_chunk.{txt,json}."""
+    run with --copy-probe, and optionally a pass over SQ_COUNTERS) into
+    profiles/dedisperse_serving_chunk.{txt,json}."""
     import csv
     import glob
 
@@ -174,6 +179,19 @@ def summarize_profile(stats_dir, fetch_dir, write_dir):
     lines.append(f"FETCH_SIZE per dispatch (KiB): dedisperse {df}, 1 GiB copy {cf} -> scale {f_scale}")
     lines.append(f"WRITE_SIZE per dispatch (KiB): dedisperse {dw}, 1 GiB copy {cw} -> scale {w_scale}")
     lines.append(f"HBM bytes per dedisperse launch (scaled): {traffic}")
+    sq = {}
+    if sq_dir:
+        for r in rows(sq_dir, "*counter_collection.csv"):
+            if short in r["Kernel_Name"]:
+                sq.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        sq = {k: sum(v) / len(v) for k, v in sq.items()}
+        lines.append("")
+        lines.append("SQ counters per dispatch of the dominant kernel (rocprofv3 --pmc):")
+        for k in sorted(sq):
+            lines.append(f"  {k:24s} {sq[k]:.4e}")
+        if sq.get("SQ_LDS_IDX_ACTIVE"):
+            lines.append(f"  LDS bank-conflict cycles / LDS active cycles: "
+                         f"{sq.get('SQ_LDS_BANK_CONFLICT', 0) / sq['SQ_LDS_IDX_ACTIVE']:.4f}")
     lines.append("")
     lines.append("commands (from the repository root, TMPDIR=/tmp):")
     lines.append("  rocprofv3 --kernel-trace --stats --output-format csv -d <stats_dir> -o bench -- "
@@ -182,7 +200,9 @@ def summarize_profile(stats_dir, fetch_dir, write_dir):
                  "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-probe")
     lines.append("  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write_dir> -o pmc -- "
                  "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-probe")
-    lines.append("  python3 bench.py --summarize-profile <stats_dir> <fetch_dir> <write_dir>")
+    lines.append(f"  rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d <sq_dir> -o pmc -- "
+                 "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline")
+    lines.append("  python3 bench.py --summarize-profile <stats_dir> <fetch_dir> <write_dir> <sq_dir>")
     os.makedirs(os.path.dirname(PROFILE_JSON), exist_ok=True)
     with open(PROFILE_JSON[:-5] + ".txt", "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -190,13 +210,82 @@ def summarize_profile(stats_dir, fetch_dir, write_dir):
         json.dump({"kernel": short, "kernel_sha": kernel_hash(),
                    "avg_ms": float(dom["AverageNs"]) / 1e6 if dom else None,
                    "fetch_kib": df, "write_kib": dw, "copy_fetch_kib": cf, "copy_write_kib": cw,
-                   "hbm_bytes_per_launch": traffic}, f, indent=1)
+                   "hbm_bytes_per_launch": traffic, "sq_counters": sq}, f, indent=1)
     print("\n".join(lines))
+
+
+def uneven_bench(args):
+    """Uneven batch: 64 requests of different channel counts, lengths and DM ranges, searched
+    (dedispersion + candidates) by the persistent batch launch, against the same requests as a
+    loop of per-request plan calls.  Prints one JSON line; value = the batched rate."""
+    import torch
+
+    import paper_2205_12362_amd.arts as arts
+    from paper_2205_12362_amd import synth
+
+    reqs = synth.uneven_requests(64, seed=4)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4)
+    items, units, adds, rejected = [], 0, 0, 0
+    for w in reqs:
+        p = arts.Plan.from_workload(w)
+        nin = w.extra["nsamp"]
+        L = arts.series_length(p, nin)
+        data = torch.randint(0, 256, (1, w.nchan, nin), dtype=torch.uint8, device="cuda",
+                             generator=g)
+        out = torch.empty((1, w.dms.size, max(L, 1)), dtype=torch.int32, device="cuda")
+        items.append((p, data, out))
+        if L >= max(w.widths):
+            units += w.dms.size * (L - max(w.widths) + 1)
+            adds += w.dms.size * L * w.nchan
+        else:
+            rejected += 1
+    ok = [it for it in items if arts.series_length(it[0], it[1].shape[2]) >= 1]
+    batch = arts.Batch()
+    thr = 8.0
+
+    def step_batch():
+        batch.dedisperse(items)
+        return len(batch.candidates(items, thr))
+
+    def step_plain():
+        n = 0
+        for p, d, o in ok:
+            p.dedisperse(d, out=o)
+            if o.shape[2] >= max(p.widths):
+                n += len(p.candidates(o, thr))
+        return n
+
+    res = {}
+    for name, f in (("plain", step_plain), ("batch", step_batch)):
+        for _ in range(args.warmup):
+            f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ncand = f()
+        torch.cuda.synchronize()
+        res[name] = ((time.perf_counter() - t0) / args.steps, ncand)
+    batch.close()
+    ms_b, ms_p = res["batch"][0] * 1e3, res["plain"][0] * 1e3
+    print(json.dumps({
+        "metric": "DM-trial samples/s", "value": units / res["batch"][0],
+        "unit": "DM-trial samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "uneven batch: 64 requests, nchan 384/768/1536, 0.5-4 s, DM "
+                               "0-500/0-2000/0-5000 with 512-4096 trials, widths 1-256, "
+                               "dedispersion + candidates",
+                   "requests": len(items), "rejected_short": rejected, "threshold": thr},
+        "adds_per_s": adds / res["batch"][0],
+        "plain_per_request": {"ms_per_step": ms_p, "value": units / res["plain"][0]},
+        "batch_speedup": ms_p / ms_b,
+        "candidates_per_step": res["batch"][1]}))
 
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profile":
-        summarize_profile(*sys.argv[2:5])
+        summarize_profile(*sys.argv[2:6])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,11 +296,20 @@ def main():
     ap.add_argument("--variant", type=int, default=None, help="native dedispersion tiling")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 1 GiB twice (counter calibration)")
+    ap.add_argument("--workload", choices=["serving", "uneven"], default="serving",
+                    help="serving: the 71-SB stream step (default); uneven: 64 uneven requests, "
+                         "persistent batch vs per-request calls")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
               "design note, not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "uneven":
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        torch.cuda.set_device(0)
+        uneven_bench(args)
+        return
 
     import torch
 

@@ -301,14 +301,12 @@ def arts_boxcar_snr(plan, series, want_stats=True, want_sums=True, want_snr=True
     import torch
     nbeam, ndm, L = series.shape
     info = arts_plan_info(plan)
-    wmax = None
     nrep = L - (info["halo"] - info["max_delay"])
     dev = series.device
     stats = torch.empty((nbeam, ndm, 2), dtype=torch.float64, device=dev) if want_stats else None
     shape = (nbeam, info["nwidth"], ndm, max(nrep, 1))
     sums = torch.empty(shape, dtype=torch.int32, device=dev) if want_sums else None
     snr = torch.empty(shape, dtype=torch.float32, device=dev) if want_snr else None
-    del wmax
     _check(lib().arts_boxcar_snr(plan, _dev(series, torch.int32, "series"), nbeam, L,
                                  stats.data_ptr() if stats is not None else None,
                                  sums.data_ptr() if sums is not None else None,

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import sys
 import time
 from dataclasses import dataclass, field
 
@@ -47,9 +48,14 @@ def serve(specs, seconds: float, budget_bytes: int, log=None):
     waiting = list(specs)
     rejected = 0
     t0 = time.perf_counter()
+    next_log = 10.0
     try:
         while True:
             now = time.perf_counter() - t0
+            if log is not None and now >= next_log:
+                log(f"{now:.0f} s: " + ", ".join(f"{s.name} {len(s.latencies)} chunks"
+                                                 for s in specs))
+                next_log += 10.0
             if now >= seconds and not pending:
                 break
             # admission: streams whose start time has come, while the budget allows
@@ -117,14 +123,57 @@ def default_specs(seed=7):
     return specs
 
 
+def compare_batching(nsb=71, chunks=8, timed=3, budget_bytes=64 << 30):
+    """One search step for nsb single-SB streams (native + D=4 trials, chunks of 12 500
+    samples), run one stream per engine tick versus all streams in one tick (their
+    dedispersion in one persistent launch per tiling).  The first chunks warm the streams up;
+    the last `timed` chunks are timed.  Returns ms per step of each mode."""
+    import torch
+    plans = [arts.Plan.from_workload(synth.cfg_apertif()),
+             arts.Plan.from_workload(synth.cfg_apertif_ds())]
+    chunk = synth.CHUNK
+    pool = [torch.from_numpy(synth.noise((1, 1536, chunk), seed=40 + i)).cuda() for i in range(2)]
+    out = {}
+    for mode in ("one_at_a_time", "batched"):
+        with arts.Server(budget_bytes) as srv:
+            ids = [srv.open(plans, 1, chunk, 8.0) for _ in range(nsb)]
+            times = []
+            for k in range(chunks):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if mode == "batched":
+                    for i in ids:
+                        srv.submit(i, pool[(k + i) % 2])
+                    srv.tick()
+                    for i in ids:
+                        srv.collect(i)
+                else:
+                    for i in ids:
+                        srv.submit(i, pool[(k + i) % 2])
+                        srv.tick()
+                        srv.collect(i)
+                times.append(time.perf_counter() - t0)
+            out[mode] = {"ms_per_step": 1e3 * float(np.mean(times[-timed:])),
+                         "device_bytes": srv.info()["used_bytes"]}
+    out["speedup"] = out["one_at_a_time"]["ms_per_step"] / out["batched"]["ms_per_step"]
+    out["config"] = f"{nsb} single-SB streams x (2048 native + 1476 D=4 trials), chunk {chunk}"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--seconds", type=float, default=20.0)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--compare-batching", action="store_true",
+                    help="time one-stream-per-tick against one batched tick (71 SB streams)")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
-    res = serve(default_specs(), args.seconds, int(args.budget_gb * 2**30))
+    if args.compare_batching:
+        print(json.dumps(compare_batching(budget_bytes=int(args.budget_gb * 2**30))))
+        return
+    res = serve(default_specs(), args.seconds, int(args.budget_gb * 2**30),
+                log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(res))
 
 

@@ -11,12 +11,12 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def oracle_rows_candidates(x_rows, widths, nrep, thr, rows, beam=0):
+def oracle_rows_candidates(x_rows, widths, nrep, thr, rows, beam=0, t_offset=0):
     """Oracle candidates for selected DM rows of one beam (x_rows: [len(rows)][L]); dm index of
     each candidate is mapped back to rows[i]."""
     out = []
     for i, d in enumerate(rows):
-        for c in O.candidates(x_rows[i: i + 1], widths, nrep, thr, beam=beam):
+        for c in O.candidates(x_rows[i: i + 1], widths, nrep, thr, beam=beam, t_offset=t_offset):
             out.append((c[0], int(d), c[2], c[3], c[4]))
     out.sort(key=lambda r: (r[0], r[1], r[2], r[3]))
     return out
