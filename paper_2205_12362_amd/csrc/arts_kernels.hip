@@ -895,18 +895,23 @@ constexpr int kBoxThreads = 256;
 // dynamic LDS of the boxcar kernels: (kSeg + wmax + 1) words, wmax <= kMaxWidth
 constexpr int kBoxLdsMax = (kSeg + kMaxWidth + 1) * 4;
 
-__device__ void load_prefix(const int32_t* __restrict__ x, int64_t L, int64_t s0, int ne,
-                            uint32_t* P, uint32_t* wsum) {
-  for (int k = threadIdx.x; k < ne; k += kBoxThreads) {
-    const int64_t idx = s0 - 1 + k;
-    P[k] = (idx >= 0 && idx < L) ? static_cast<uint32_t>(x[idx]) : 0u;
-  }
+// In place: P[0 .. ne) becomes its exclusive prefix sum and P[ne] the total, by a workgroup of
+// NT threads (wsum: NT / 64 words).  Starts and ends with a barrier.
+template <int NT>
+__device__ void scan_inplace(uint32_t* P, int ne, uint32_t* wsum) {
   __syncthreads();
   // an odd stride between threads' ranges spreads them over all LDS banks
-  const int per = ((ne + kBoxThreads - 1) / kBoxThreads) | 1;
+  const int per = ((ne + NT - 1) / NT) | 1;
   const int lo = min(ne, static_cast<int>(threadIdx.x) * per), hi = min(ne, lo + per);
+  // eight independent LDS reads per step, so that one wait covers all of them
   uint32_t tot = 0;
-  for (int k = lo; k < hi; ++k) tot += P[k];
+  for (int k = lo; k < hi; k += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = k + u < hi ? P[k + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tot += v[u];
+  }
   // inclusive scan of per-thread totals: within the wave, then across the 4 waves
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t inc = tot;
@@ -920,13 +925,29 @@ __device__ void load_prefix(const int32_t* __restrict__ x, int64_t L, int64_t s0
   uint32_t pre = 0;
   for (int w = 0; w < wave; ++w) pre += wsum[w];
   uint32_t run = pre + inc - tot;  // exclusive prefix of this thread's range
-  for (int k = lo; k < hi; ++k) {
-    const uint32_t v = P[k];
-    P[k] = run;
-    run += v;
+  for (int k = lo; k < hi; k += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = k + u < hi ? P[k + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k + u < hi) {
+        P[k + u] = run;
+        run += v[u];
+      }
   }
-  if (threadIdx.x == kBoxThreads - 1) P[ne] = pre + inc;
+  if (threadIdx.x == NT - 1) P[ne] = pre + inc;
   __syncthreads();
+}
+
+template <int NT>
+__device__ void load_prefix(const int32_t* __restrict__ x, int64_t L, int64_t s0, int ne,
+                            uint32_t* P, uint32_t* wsum) {
+  for (int k = threadIdx.x; k < ne; k += NT) {
+    const int64_t idx = s0 - 1 + k;
+    P[k] = (idx >= 0 && idx < L) ? static_cast<uint32_t>(x[idx]) : 0u;
+  }
+  scan_inplace<NT>(P, ne, wsum);
 }
 
 struct WidthParams {
@@ -956,7 +977,7 @@ __global__ __launch_bounds__(kBoxThreads) void boxcar_snr_kernel(
   const int64_t s0 = (blockIdx.x % nseg) * kSeg;
   const int n = static_cast<int>(min<int64_t>(kSeg, nrep - s0));
   const int ne = n + wmax;
-  load_prefix(series + row * L, L, s0, ne, P, wsum);
+  load_prefix<kBoxThreads>(series + row * L, L, s0, ne, P, wsum);
   const int64_t b = row / ndm, d = row % ndm;
   const double mu = musig[2 * row], sigma = musig[2 * row + 1];
   const long long S1 = s1[row];
@@ -1000,7 +1021,8 @@ int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam
 // One workgroup per series row (beam, DM).  Pass 1 computes the row's moments over the
 // reported window exactly as row_stats_kernel does.  Pass 2 walks the window in segments of
 // kCandSeg start samples staged as a prefix sum in LDS; for every width each thread classifies
-// its kCandPT consecutive starts (S/N above threshold <=> B_w > floor(w mu + thr sigma sqrt w)):
+// its kCandSeg / NT consecutive starts (S/N above threshold <=> B_w > floor(w mu + thr sigma
+// sqrt w)):
 // runs that begin and end inside its range are emitted at once; the leading run fragment (from
 // its first start) and the trailing one (to its last start) are summarised in LDS.  The thread
 // that holds a run's first start then walks the following threads' summaries to the run's end,
@@ -1008,7 +1030,11 @@ int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam
 // run therefore yields exactly one candidate at its largest B_w (earliest on ties), whatever its
 // length, with O(threads) work for the longest run.
 constexpr int kCandSeg = 4096;
-constexpr int kCandPT = kCandSeg / kBoxThreads;
+// dynamic LDS limit of a resident row (16 Ki words: rows of up to 16 383 - wmax searched starts)
+constexpr int kCandResLds = 64 * 1024;
+// threads of a candidate workgroup: 8 waves for rows of at least kCandLong starts (a resident
+// row of that length fills 2 workgroups per CU), else 4
+constexpr int kCandLong = 8192;
 constexpr int kMaxWidthsCand = 64;
 
 struct CandOut {
@@ -1039,33 +1065,63 @@ __device__ __forceinline__ void emit_cand(const CandOut& o, int64_t t, int32_t b
   }
 }
 
-__global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
+// RES: the row is resident.  Its n = nrep + wmax - 1 samples are staged into LDS once (direct
+// global->LDS loads), the moments are taken from LDS, one in-place prefix sum serves every
+// segment, and a whole-row test per width (one barrier) leaves the run scan to the widths
+// that exceed the threshold somewhere.  Otherwise (rows too long for LDS) the moments are read
+// from global memory and each segment is loaded and summed on its own.
+template <bool RES, int NT>
+__global__ __launch_bounds__(NT) void candidates_kernel(
     const int32_t* __restrict__ series, int64_t pitch, int64_t L, int64_t nrep, int32_t ndm,
     const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, const double* __restrict__ dms,
     double thr, int64_t t_offset, int32_t beam_offset, int32_t ds,
     arts_candidate* __restrict__ cand, unsigned long long* __restrict__ count, int64_t cap) {
   extern __shared__ uint32_t P[];
-  __shared__ uint32_t wsum[4];
-  __shared__ long long red[2][4];
+  __shared__ uint32_t wsum[NT / 64];
+  __shared__ long long red[2][NT / 64];
   __shared__ long long s_thr[kMaxWidthsCand];
   __shared__ float s_scale[kMaxWidthsCand];
   __shared__ int32_t s_wid[kMaxWidthsCand];
   __shared__ int32_t c_open[2][kMaxWidthsCand], c_best[2][kMaxWidthsCand];
   __shared__ int64_t c_arg[2][kMaxWidthsCand];
-  __shared__ int32_t t_full[kBoxThreads], t_prelen[kBoxThreads], t_premax[kBoxThreads];
-  __shared__ int32_t t_prearg[kBoxThreads], t_suf[kBoxThreads];
+  __shared__ int32_t t_full[NT], t_prelen[NT], t_premax[NT];
+  __shared__ int32_t t_prearg[NT], t_suf[NT];
   __shared__ double s_musig[2];
+  __shared__ int s_hit[kMaxWidthsCand];
 
   const int64_t row = blockIdx.x;
   const int32_t* x = series + row * pitch;
   const int tid = threadIdx.x;
-  // ---- pass 1: moments over t < nrep (exact int64 sums)
+  const int nres = RES ? static_cast<int>(nrep) + wmax - 1 : 0;
+  if constexpr (RES) {
+    // P[1 + t] = x[t], t < nres, by dword global->LDS loads (lane i lands at base + 4 i)
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int k0 = wave * 64; k0 < nres; k0 += NT)
+      if (k0 + lane < nres)
+        __builtin_amdgcn_global_load_lds((global_ptr_t)(x + k0 + lane), (lds_ptr_t)(P + 1 + k0),
+                                         4, 0, 0);
+    if (tid == 0) P[0] = 0u;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  // ---- pass 1: moments over t < nrep (exact int64 sums), eight independent reads per step
   {
     long long s1 = 0, s2 = 0;
-    for (int64_t t = tid; t < nrep; t += kBoxThreads) {
-      const long long v = x[t];
-      s1 += v;
-      s2 += v * v;
+    for (int64_t t0 = tid; t0 < nrep; t0 += 8 * NT) {
+      int32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t t = t0 + u * NT;
+        if constexpr (RES)
+          v[u] = t < nrep ? static_cast<int32_t>(P[1 + static_cast<int>(t)]) : 0;
+        else
+          v[u] = t < nrep ? x[t] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s1 += v[u];
+        s2 += static_cast<long long>(v[u]) * v[u];
+      }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -1078,9 +1134,13 @@ __global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
     }
   }
   __syncthreads();
-  const long long S1 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  long long S1 = 0;
+#pragma unroll
+  for (int v = 0; v < NT / 64; ++v) S1 += red[0][v];
   if (tid == 0) {
-    const long long S2 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    long long S2 = 0;
+#pragma unroll
+    for (int v = 0; v < NT / 64; ++v) S2 += red[1][v];
     const long long N = nrep, m0 = S1 / N, r = S1 - N * m0;
     const long long S2c = S2 - 2 * m0 * S1 + N * m0 * m0;
     const double dn = static_cast<double>(N);
@@ -1110,23 +1170,59 @@ __global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
   o.dm = static_cast<float>(dms[row % ndm]);
   o.S1 = S1;
   o.N = nrep;
+  if constexpr (RES) {
+    // exclusive prefix over x[-1 .. nres) with x[-1] = 0: B_w(t) = P[t + 1 + w] - P[t + 1]
+    scan_inplace<NT>(P, nres + 1, wsum);
+    // whole-row maximum of B_w per width: groups of 8 starts 256 apart, whose 16 reads share
+    // one base address (immediate offsets) and are in flight together; then the last starts
+    const int nr = static_cast<int>(nrep);
+    for (int wi = 0; wi < nw; ++wi) {
+      const int w = s_wid[wi];
+      int32_t bmax = INT_MIN;
+      int t0 = tid;
+      for (; t0 + 7 * NT < nr; t0 += 8 * NT) {
+        const uint32_t* q = P + t0 + 1;
+        const uint32_t* qw = q + w;
+        uint32_t a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = q[u * NT];
+          b[u] = qw[u * NT];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bmax = max(bmax, static_cast<int32_t>(b[u] - a[u]));
+      }
+      for (; t0 < nr; t0 += NT)
+        bmax = max(bmax, static_cast<int32_t>(P[t0 + 1 + w] - P[t0 + 1]));
+      const int hit = __syncthreads_or(static_cast<long long>(bmax) > s_thr[wi] ? 1 : 0);
+      if (tid == 0) s_hit[wi] = hit;
+    }
+  }
   int cin = 0;  // carry buffer holding runs open at the previous segment's end
-  const int k0 = tid * kCandPT;
+  const int k0 = tid * (kCandSeg / NT);
   for (int64_t s0 = 0; s0 < nrep; s0 += kCandSeg) {
     const int n = static_cast<int>(min<int64_t>(kCandSeg, nrep - s0));
-    load_prefix(x, L, s0, n + wmax, P, wsum);  // ends with a barrier
+    const uint32_t* Pseg = P;
+    if constexpr (RES) {
+      Pseg = P + s0;
+      __syncthreads();  // every read of the carry slot cleared below has happened
+    } else {
+      load_prefix<NT>(x, L, s0, n + wmax, P, wsum);  // ends with a barrier
+    }
     if (tid < nw) c_open[cin ^ 1][tid] = 0;
+    if constexpr (RES) __syncthreads();
     for (int wi = 0; wi < nw; ++wi) {
       const int w = s_wid[wi];
       const long long T = s_thr[wi];
+      if (RES && !s_hit[wi] && !c_open[cin][wi]) continue;  // uniform: shared values
       // ---- fast path: nothing above threshold in this segment and no run carried in
       {
         // starts interleaved across lanes: consecutive lanes read consecutive LDS words
         int32_t bmax = INT_MIN;
 #pragma unroll
-        for (int i = 0; i < kCandPT; ++i) {
-          const int k = tid + i * kBoxThreads;
-          if (k < n) bmax = max(bmax, static_cast<int32_t>(P[k + 1 + w] - P[k + 1]));
+        for (int i = 0; i < (kCandSeg / NT); ++i) {
+          const int k = tid + i * NT;
+          if (k < n) bmax = max(bmax, static_cast<int32_t>(Pseg[k + 1 + w] - Pseg[k + 1]));
         }
         const bool any = static_cast<long long>(bmax) > T;
         if (!__syncthreads_or(any ? 1 : 0) && !c_open[cin][wi]) continue;
@@ -1137,10 +1233,10 @@ __global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
       int32_t pre_max = 0, best = 0;
       int pre_arg = 0, arg = 0;
 #pragma unroll
-      for (int i = 0; i < kCandPT; ++i) {
+      for (int i = 0; i < (kCandSeg / NT); ++i) {
         const int k = k0 + i;
         const bool valid = k < n;
-        const int32_t B = valid ? static_cast<int32_t>(P[k + 1 + w] - P[k + 1]) : 0;
+        const int32_t B = valid ? static_cast<int32_t>(Pseg[k + 1 + w] - Pseg[k + 1]) : 0;
         const bool a = valid && static_cast<long long>(B) > T;
         if (in_pre) {
           if (a) {
@@ -1210,7 +1306,7 @@ __global__ __launch_bounds__(kBoxThreads) void candidates_kernel(
       }
       if (walk) {
         bool closed = false;
-        for (int u = tid + 1; !closed && u < kBoxThreads; ++u) {
+        for (int u = tid + 1; !closed && u < NT; ++u) {
           if (t_prelen[u] > 0 && t_premax[u] > rb) {
             rb = t_premax[u];
             ra = s0 + t_prearg[u];
@@ -1241,18 +1337,32 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
   const int64_t nrows = static_cast<int64_t>(nbeam) * p->ndm;
   if (nrows > INT_MAX) return fail(ARTS_E_INVAL, "candidate grid too large");
   if (p->nwidth > kMaxWidthsCand) return fail(ARTS_E_INVAL, "at most %d widths", kMaxWidthsCand);
-  const size_t lds = (kCandSeg + p->wmax + 1) * sizeof(uint32_t);
   static bool attr = false;
   if (!attr) {
-    ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel),
+    ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel<false, 256>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (kCandSeg + kMaxWidth + 1) * 4));
+    ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel<false, 512>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (kCandSeg + kMaxWidth + 1) * 4));
+    ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel<true, 256>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kCandResLds));
+    ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel<true, 512>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kCandResLds));
     attr = true;
   }
+  // resident rows: P[0 .. n] and one spare word, n = searched starts + wmax - 1
+  const size_t res_lds = (static_cast<size_t>(nrep - t_begin) + p->wmax + 1) * sizeof(uint32_t);
+  const bool res = res_lds <= static_cast<size_t>(kCandResLds);
+  const size_t lds = res ? res_lds : (kCandSeg + p->wmax + 1) * sizeof(uint32_t);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(candidates_kernel, dim3(static_cast<unsigned>(nrows)), dim3(kBoxThreads),
-                     lds, s, series + t_begin, L, L - t_begin, nrep - t_begin, p->ndm,
-                     p->d_widths, p->nwidth, p->wmax, p->d_dms, static_cast<double>(thr),
+  const bool wide = nrep - t_begin >= kCandLong;
+  const int nt = wide ? 512 : 256;
+  auto kern = res ? (wide ? candidates_kernel<true, 512> : candidates_kernel<true, 256>)
+                  : (wide ? candidates_kernel<false, 512> : candidates_kernel<false, 256>);
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(nrows)), dim3(nt), lds, s,
+                     series + t_begin, L, L - t_begin, nrep - t_begin, p->ndm, p->d_widths,
+                     p->nwidth, p->wmax, p->d_dms, static_cast<double>(thr),
                      t_offset + t_begin, beam_offset, p->ds, cand, count, cap);
   ARTS_HIP(hipGetLastError());
   return ARTS_OK;

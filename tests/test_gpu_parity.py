@@ -283,6 +283,31 @@ def test_candidates_offsets_and_capacity():
         assert e.value.status == arts.ARTS_E_CAPACITY
 
 
+@pytest.mark.parametrize("nsamp", [16384, 40000])
+def test_candidates_resident_and_segmented_rows(nsamp):
+    # rows up to 16k starts are searched resident in LDS, longer ones segment by segment; both
+    # against the oracle, with wide bright top-hats so that runs cross the 4096-start segments
+    f_lo, df = synth.band(64)
+    dms = np.arange(0, 96, 3.0)
+    widths = [1, 2, 4, 8, 16, 32, 64]
+    w = synth.Workload("seg", 64, f_lo, df, synth.TSAMP, dms, widths)
+    delays = O.delay_table(64, f_lo, df, synth.TSAMP, dms)
+    data = synth.noise((64, nsamp), seed=123 + nsamp)
+    for d, t0, width in ((5, 4000, 300), (20, 8150, 40), (31, 12280, 16)):
+        synth.add_tophat(data, t0 + delays[d], width, 30)
+    x, ora = O.search(data, delays, widths, 8.0)
+    nrep = x.shape[1] - max(widths) + 1
+    near = near_threshold_rows(x, widths, nrep, 8.0, np.arange(x.shape[0]))
+    _say("candidates rows", nsamp, "nrep", nrep)
+    with _plan(w) as p:
+        series = p.dedisperse(to_dev(data))
+        assert np.array_equal(series.cpu().numpy()[0], x)
+        got = p.candidates(series, 8.0)
+    assert len(ora) > 20
+    n = compare_candidates(got, ora, near)
+    assert n >= len(ora) - 4
+
+
 def test_candidates_pure_noise_empty():
     w = synth.cfg_small()
     data = synth.noise((w.nchan, 16384), seed=99)
