@@ -99,10 +99,10 @@ PROFILE_JSON = os.path.join(ROOT, "profiles", "dedisperse_serving_chunk.json")
 
 def kernel_name(describe):
     """Template name of the dedispersion kernel of a tiling variant, from its description
-    ("J=5 ACC=3 WAVES=8 SPD=4 packed" -> "dedisperse_kernel<4, 5, 3, 8, 1>")."""
+    ("J=5 ACC=3 WAVES=8 SPD=4 packed" -> "dedisperse_kernel<4, 5, 3, 8, 1>"; "framed" -> 2)."""
     f = dict(kv.split("=") for kv in describe.split() if "=" in kv)
-    return (f"dedisperse_kernel<{f['SPD']}, {f['J']}, {f['ACC']}, {f['WAVES']}, "
-            f"{1 if 'packed' in describe else 0}>")
+    pack = 2 if "framed" in describe else 1 if "packed" in describe else 0
+    return f"dedisperse_kernel<{f['SPD']}, {f['J']}, {f['ACC']}, {f['WAVES']}, {pack}>"
 
 
 def kernel_hash():

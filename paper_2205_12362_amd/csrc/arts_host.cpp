@@ -457,7 +457,7 @@ int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
     return fail(ARTS_E_INVAL, "bad variant or buffer");
   const TileVariant& v = kVariants[variant];
   snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d%s", v.j, v.acc, v.waves, v.spd,
-           v.pack ? " packed" : "");
+           v.pack == 2 ? " framed" : v.pack ? " packed" : "");
   return ARTS_OK;
 }
 

@@ -33,6 +33,10 @@ const TileVariant kVariants[] = {
     {2, 7, 3, 8, 1},   // 15: as 8, packed
     {2, 5, 6, 8, 1},   // 16: downsampled, packed: 48 DMs x 640
     {4, 5, 2, 4, 1},   // 17: as 4, packed
+    {4, 5, 1, 8, 2},   // 18: framed:  8 DMs x 1280
+    {4, 5, 1, 16, 2},  // 19: framed: 16 DMs x 1280, one block per CU
+    {4, 3, 2, 8, 2},   // 20: framed: 16 DMs x 768
+    {4, 7, 1, 8, 2},   // 21: framed:  8 DMs x 1792
 };
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -355,6 +359,93 @@ __device__ __forceinline__ void flush_pk(uint32_t* acc, uint32_t* e, uint32_t* o
   }
 }
 
+// ---- framed partial sums (spd = 4).  A channel whose samples start at byte MS of the lane's
+// first LDS dword maps byte j of its k-th dword to output 4k + j - MS: a fixed frame per MS.
+// Per DM and frame, A[k] accumulates the dwords as they are (their byte lanes overlap in a
+// 32-bit sum) and O[k] the odd bytes moved into 16-bit halves (one v_perm_b32); v_add3_u32
+// adds two channels at a time.  Because O is known exactly, the even-byte sums follow as
+// E[k] = A[k] - (O[k] << 8) (exact while each 16-bit half stays below 2^16, i.e. for up to
+// 257 channels), so a channel costs one perm and one add per dword: 2 instructions per 4 samples
+// (for MS = 0; MS > 0 reads one dword more).  The four frames are widened into the int32
+// totals only every 257 channels.
+__device__ __forceinline__ uint32_t odd_bytes(uint32_t w) {
+  return __builtin_amdgcn_perm(w, w, 0x0C030C01u);  // bytes 1 and 3 into the two halves
+}
+
+template <int NW>
+__device__ __forceinline__ void add_fr(uint32_t* A, uint32_t* O, const uint32_t* w1,
+                                       const uint32_t* w2) {
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    A[k] += w1[k] + w2[k];
+    O[k] += odd_bytes(w1[k]) + odd_bytes(w2[k]);
+  }
+}
+
+template <int J, int MS, bool PF>
+__device__ __forceinline__ void accum_run_fr(uint32_t* A, uint32_t* O, const int32_t* ent, int n,
+                                             const uint8_t* lane_base) {
+  constexpr int NW = (MS == 0) ? J : J + 1;
+  int i = 0;
+  if (PF && n >= 4) {
+    int32_t q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = ent[u];
+    for (; i + 4 <= n; i += 4) {
+      uint32_t w[4][J + 1];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + q[u]);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) w[u][k] = p[k];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = ent[i + 4 + u];
+      add_fr<NW>(A, O, w[0], w[1]);
+      add_fr<NW>(A, O, w[2], w[3]);
+    }
+  }
+  for (; i + 2 <= n; i += 2) {
+    uint32_t w[2][J + 1];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i + u]);
+#pragma unroll
+      for (int k = 0; k < NW; ++k) w[u][k] = p[k];
+    }
+    add_fr<NW>(A, O, w[0], w[1]);
+  }
+  if (i < n) {
+    uint32_t w[J + 1];
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = p[k];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      A[k] += w[k];
+      O[k] += odd_bytes(w[k]);
+    }
+  }
+}
+
+// Widen frame MS into the int32 totals (one SDWA add per output) and clear it.
+template <int J, int MS>
+__device__ __forceinline__ void flush_fr(uint32_t* acc, uint32_t* A, uint32_t* O) {
+  constexpr int NW = (MS == 0) ? J : J + 1;
+  constexpr int T = 4 * J;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint32_t e = A[k] - (O[k] << 8);
+    const int i0 = 4 * k - MS;
+    if (i0 >= 0 && i0 < T) add_half<0>(acc[i0], e);
+    if (i0 + 1 >= 0 && i0 + 1 < T) add_half<0>(acc[i0 + 1], O[k]);
+    if (i0 + 2 >= 0 && i0 + 2 < T) add_half<1>(acc[i0 + 2], e);
+    if (i0 + 3 >= 0 && i0 + 3 < T) add_half<1>(acc[i0 + 3], O[k]);
+    A[k] = 0;
+    O[k] = 0;
+  }
+}
+
 typedef __attribute__((address_space(1))) const void* global_ptr_t;
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
@@ -439,6 +530,19 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   for (int x = 0; x < ACC; ++x)
 #pragma unroll
     for (int i = 0; i < T; ++i) acc[x][i] = 0;
+  // framed variants: per DM, four frames of J + 1 dword pairs (unused otherwise)
+  constexpr int NF = (PK == 2) ? ACC : 1;
+  constexpr int NFW = (PK == 2) ? J + 1 : 1;
+  uint32_t fa[NF][4][NFW], fo[NF][4][NFW];
+  if constexpr (PK == 2) {
+#pragma unroll
+    for (int x = 0; x < NF; ++x)
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int k = 0; k < NFW; ++k) fa[x][m][k] = fo[x][m][k] = 0;
+  }
+  int since = 0;  // channels in the frames since they were last widened (uniform)
 
   const int32_t* base_blk = a.base + static_cast<int64_t>(blk) * a.nchan;
   const int32_t* list_blk = a.list + static_cast<int64_t>(blk) * a.m_blk * a.nchan;
@@ -469,6 +573,23 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
       stage_lists<WAVES>(a, list_blk, c1, ncc1, reinterpret_cast<int32_t*>(nxt + a.cc * a.win),
                          lane, wave);
     }
+    // ---- framed variants: widen the frames before they could exceed 257 channels
+    if constexpr (PK == 2) {
+      const int ncc = min(a.cc, a.nchan - c0);
+      if (since + ncc > 257) {
+        if (wave_active) {
+#pragma unroll
+          for (int x = 0; x < ACC; ++x) {
+            flush_fr<J, 0>(acc[x], fa[x][0], fo[x][0]);
+            flush_fr<J, 1>(acc[x], fa[x][1], fo[x][1]);
+            flush_fr<J, 2>(acc[x], fa[x][2], fo[x][2]);
+            flush_fr<J, 3>(acc[x], fa[x][3], fo[x][3]);
+          }
+        }
+        since = 0;
+      }
+      since += ncc;
+    }
     // ---- accumulate: each DM trial of the wave over the chunk, one run per sub-dword offset
     if (wave_active) {
       const int32_t* ent_cur = reinterpret_cast<const int32_t*>(cur + a.cc * a.win);
@@ -478,7 +599,15 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
         const uint32_t packed = __builtin_amdgcn_readfirstlane(cnt_blk[ch * a.m_blk + x]);
         const int32_t* ent = ent_cur + (wave * ACC + x) * a.cc;
         const int n0 = packed & 0xff, n1 = (packed >> 8) & 0xff;
-        if constexpr (PK && SPD == 2) {
+        if constexpr (PK == 2) {
+          static_assert(SPD == 4, "framed sums are for byte samples");
+          const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
+          constexpr bool PF = ACC * 8 * (J + 1) + ACC * T <= 80;
+          accum_run_fr<J, 0, PF>(fa[x][0], fo[x][0], ent, n0, lane_base);
+          accum_run_fr<J, 1, PF>(fa[x][1], fo[x][1], ent + n0, n1, lane_base);
+          accum_run_fr<J, 2, PF>(fa[x][2], fo[x][2], ent + n0 + n1, n2, lane_base);
+          accum_run_fr<J, 3, PF>(fa[x][3], fo[x][3], ent + n0 + n1 + n2, n3, lane_base);
+        } else if constexpr (PK && SPD == 2) {
           uint32_t pk[J];
 #pragma unroll
           for (int k = 0; k < J; ++k) pk[k] = 0;
@@ -513,6 +642,15 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
     __syncthreads();
   }
   if (wave_active) {
+    if constexpr (PK == 2) {
+#pragma unroll
+      for (int x = 0; x < ACC; ++x) {
+        flush_fr<J, 0>(acc[x], fa[x][0], fo[x][0]);
+        flush_fr<J, 1>(acc[x], fa[x][1], fo[x][1]);
+        flush_fr<J, 2>(acc[x], fa[x][2], fo[x][2]);
+        flush_fr<J, 3>(acc[x], fa[x][3], fo[x][3]);
+      }
+    }
 #pragma unroll
     for (int x = 0; x < ACC; ++x) {
       const int d = dwave0 + x;
@@ -729,6 +867,10 @@ int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
     case 15: return launch_variant<2, 7, 3, 8, 1>(a, s);
     case 16: return launch_variant<2, 5, 6, 8, 1>(a, s);
     case 17: return launch_variant<4, 5, 2, 4, 1>(a, s);
+    case 18: return launch_variant<4, 5, 1, 8, 2>(a, s);
+    case 19: return launch_variant<4, 5, 1, 16, 2>(a, s);
+    case 20: return launch_variant<4, 3, 2, 8, 2>(a, s);
+    case 21: return launch_variant<4, 7, 1, 8, 2>(a, s);
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
@@ -821,6 +963,10 @@ int launch_dedisperse_batch(arts_plan_s* const* plans, const DedispJob* jobs, in
     case 15: return launch_batch_variant<2, 7, 3, 8, 1>(q, lds, s);
     case 16: return launch_batch_variant<2, 5, 6, 8, 1>(q, lds, s);
     case 17: return launch_batch_variant<4, 5, 2, 4, 1>(q, lds, s);
+    case 18: return launch_batch_variant<4, 5, 1, 8, 2>(q, lds, s);
+    case 19: return launch_batch_variant<4, 5, 1, 16, 2>(q, lds, s);
+    case 20: return launch_batch_variant<4, 3, 2, 8, 2>(q, lds, s);
+    case 21: return launch_batch_variant<4, 7, 1, 8, 2>(q, lds, s);
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
