@@ -12,7 +12,8 @@ design notes of the repository; each is marked "reading".
 
 Parity status per function:
   channel_freqs, delay_table, tie_audit, downsample, sb_synthesize, dedisperse,
-  dedisperse_at, boxcar, moments, snr, candidates  -- pinned by closed forms / invariants in
+  dedisperse_at, subband_plan, subband_dedisperse, subband_dedisperse_at, boxcar, moments,
+  snr, candidates  -- pinned by closed forms / invariants / hand-worked values in
   tests/test_oracle_pins.py (no function here is "parity unpinned").
 """
 from __future__ import annotations
@@ -126,6 +127,80 @@ def dedisperse_at(data: np.ndarray, delays: np.ndarray, d: int, t: int) -> int:
     where the full table is too slow (same definition as `dedisperse`)."""
     cs = np.arange(data.shape[0])
     return int(np.asarray(data)[cs, t + np.asarray(delays)[d]].astype(np.int64).sum())
+
+
+def subband_plan(nchan, f_lo_mhz, df_mhz, tsamp_s, dm_first, dm_step, ndm, nfine, nsub):
+    """Delay tables of two-step subband dedispersion (Sect. 6b.2 "Dedispersion", the subband
+    dedispersion figure, Table "dedispersion setup": 32 subbands of 48 channels, a coarse
+    subbanding DM step, 32 fine trials per coarse step).
+
+    The band is cut into nsub subbands of nchan / nsub consecutive channels.  Step 1 shifts each
+    channel of a subband by its delay at a coarse DM relative to the subband's own reference
+    frequency; step 2 shifts each subband as a whole by the delay of that reference frequency at
+    the fine DM, relative to the band's reference.
+    Readings: the fine trials are dm_first + k dm_step, k < ndm; trial k belongs to coarse group
+    j = k // nfine, whose coarse DM is the group's centre dm_first + (j nfine + (nfine-1)/2)
+    dm_step; a subband's reference frequency is its highest channel (so both delays are >= 0);
+    both steps use the dispersion law and rounding of delay_table.
+    Returns (fine_dms [ndm], coarse_dms [ncoarse], d1 int64 [ncoarse][nchan],
+    d2 int64 [ndm][nsub]).
+    """
+    if nsub < 1 or nchan % nsub != 0:
+        raise ValueError("nsub must divide nchan")
+    if nfine < 1 or ndm < 1 or not dm_step > 0 or dm_first < 0:
+        raise ValueError("need nfine >= 1, ndm >= 1, dm_step > 0, dm_first >= 0")
+    csub = nchan // nsub
+    ncoarse = (ndm + nfine - 1) // nfine
+    fine = dm_first + dm_step * np.arange(ndm, dtype=np.float64)
+    coarse = dm_first + dm_step * (np.arange(ncoarse, dtype=np.float64) * nfine
+                                   + (nfine - 1) / 2.0)
+    d1 = np.concatenate([delay_table(csub, f_lo_mhz + s * csub * df_mhz, df_mhz, tsamp_s, coarse)
+                         for s in range(nsub)], axis=1)
+    # subband reference frequencies: the highest channel of each subband, spaced csub * df
+    top = csub - 1 if df_mhz > 0 else 0
+    d2 = delay_table(nsub, f_lo_mhz + top * df_mhz, csub * df_mhz, tsamp_s, fine)
+    return fine, coarse, d1, d2
+
+
+def subband_dedisperse(data: np.ndarray, d1: np.ndarray, d2: np.ndarray, nfine: int):
+    """Two-step subband dedispersion of one beam, int64 [ndm][n2] (tables from subband_plan).
+
+    Step 1: Y[j][s][t] = sum over the channels c of subband s of I[c][t + d1[j][c]],
+            t < n1 = nin - max d1.
+    Step 2: X[k][t] = sum over subbands s of Y[k // nfine][s][t + d2[k][s]],
+            t < n2 = n1 - max d2.
+    Both lengths are rectangular over the whole plan, as for dedisperse.
+    """
+    x = np.asarray(data).astype(np.int64)
+    nchan, nin = x.shape
+    ncoarse, nsub = d1.shape[0], d2.shape[1]
+    csub = nchan // nsub
+    n1 = nin - int(d1.max())
+    if n1 <= 0:
+        raise ValueError("input shorter than the step-1 delays")
+    y = np.zeros((ncoarse, nsub, n1), dtype=np.int64)
+    for j in range(ncoarse):
+        for c in range(nchan):
+            y[j, c // csub] += x[c, d1[j, c]: d1[j, c] + n1]
+    n2 = n1 - int(d2.max())
+    if n2 <= 0:
+        raise ValueError("input shorter than the two steps' delays")
+    out = np.zeros((d2.shape[0], n2), dtype=np.int64)
+    for k in range(d2.shape[0]):
+        for s in range(nsub):
+            out[k] += y[k // nfine, s, d2[k, s]: d2[k, s] + n2]
+    return out
+
+
+def subband_dedisperse_at(data: np.ndarray, d1: np.ndarray, d2: np.ndarray, nfine: int,
+                          k: int, t: int) -> int:
+    """One output X[k][t] of subband_dedisperse: every channel c of subband s contributes
+    I[c][t + d2[k][s] + d1[k // nfine][c]] (for sampled checks at full size)."""
+    nchan = data.shape[0]
+    csub = nchan // d2.shape[1]
+    c = np.arange(nchan)
+    idx = t + d2[k][c // csub] + d1[k // nfine][c]
+    return int(np.asarray(data)[c, idx].astype(np.int64).sum())
 
 
 def boxcar(series: np.ndarray, width: int, nrep: int) -> np.ndarray:

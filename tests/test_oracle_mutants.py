@@ -137,6 +137,45 @@ def _sb_transposed(tab, sb_table):
     return out
 
 
+def _subband_plan_variant(kind):
+    def subband_plan(nchan, f_lo_mhz, df_mhz, tsamp_s, dm_first, dm_step, ndm, nfine, nsub):
+        if nsub < 1 or nchan % nsub != 0 or nfine < 1 or ndm < 1 or not dm_step > 0:
+            raise ValueError("bad")
+        csub = nchan // nsub
+        ncoarse = (ndm + nfine - 1) // nfine
+        fine = dm_first + dm_step * np.arange(ndm, dtype=np.float64)
+        off = 0.0 if kind == "group start" else (nfine - 1) / 2.0
+        coarse = dm_first + dm_step * (np.arange(ncoarse) * nfine + off)
+        f = O.channel_freqs(nchan, f_lo_mhz, df_mhz).reshape(nsub, csub)
+        fsub = f.min(axis=1) if kind == "lowest reference" else f.max(axis=1)
+        inv1 = (1 / f**2 - 1 / fsub[:, None] ** 2).reshape(-1)
+        d1 = np.rint(O.K_DM * coarse[:, None] * inv1[None, :] / tsamp_s).astype(np.int64)
+        dm2 = coarse[np.arange(ndm) // nfine] if kind == "coarse in step 2" else fine
+        inv2 = 1 / fsub**2 - 1 / f.max() ** 2
+        d2 = np.rint(O.K_DM * dm2[:, None] * inv2[None, :] / tsamp_s).astype(np.int64)
+        return fine, coarse, d1, d2
+    return subband_plan
+
+
+def _subband_wrong_group(data, d1, d2, nfine):
+    # trial k taken from coarse group k % ncoarse instead of k // nfine
+    x = np.asarray(data).astype(np.int64)
+    nchan, nin = x.shape
+    ncoarse, nsub = d1.shape[0], d2.shape[1]
+    csub = nchan // nsub
+    n1 = nin - int(d1.max())
+    y = np.zeros((ncoarse, nsub, n1), np.int64)
+    for j in range(ncoarse):
+        for c in range(nchan):
+            y[j, c // csub] += x[c, d1[j, c]: d1[j, c] + n1]
+    n2 = n1 - int(d2.max())
+    out = np.zeros((d2.shape[0], n2), np.int64)
+    for k in range(d2.shape[0]):
+        for s in range(nsub):
+            out[k] += y[k % ncoarse, s, d2[k, s]: d2[k, s] + n2]
+    return out
+
+
 MUTANTS = {
     "reference at lowest channel": dict(delay_table=_delay_variant(ref="min")),
     "floor instead of round": dict(delay_table=_delay_variant(rounding=np.floor)),
@@ -150,6 +189,11 @@ MUTANTS = {
     "S/N scaled by w not sqrt(w)": dict(snr=_snr_linear),
     "downsample mean": dict(downsample=_downsample_mean),
     "SB channel index shifted": dict(sb_synthesize=_sb_transposed),
+    "subband coarse DM at group start": dict(subband_plan=_subband_plan_variant("group start")),
+    "subband reference at lowest channel": dict(
+        subband_plan=_subband_plan_variant("lowest reference")),
+    "subband step 2 at the coarse DM": dict(subband_plan=_subband_plan_variant("coarse in step 2")),
+    "subband coarse group k % ncoarse": dict(subband_dedisperse=_subband_wrong_group),
 }
 
 

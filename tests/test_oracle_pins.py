@@ -392,8 +392,91 @@ def test_tophat_snr():
     check_tophat_snr(O)
 
 
+# ------------------------------------------------------------------ subband dedispersion
+def check_subband_golden(o):
+    g = _load("subband_tiny.json")
+    pl = g["plan"]
+    fine, coarse, d1, d2 = o.subband_plan(pl["nchan"], pl["f_lo"], pl["df"], pl["tsamp"],
+                                          pl["dm_first"], pl["dm_step"], pl["ndm"], pl["nfine"],
+                                          pl["nsub"])
+    assert np.allclose(coarse, g["coarse_dms"])
+    assert np.array_equal(d1, np.array(g["d1"]))
+    assert np.array_equal(d2, np.array(g["d2"]))
+    imp = g["impulses"]
+    data = np.zeros((pl["nchan"], imp["nin"]), np.int64)
+    for c, t, v in imp["list"]:
+        data[c, t] = v
+    x = o.subband_dedisperse(data, d1, d2, pl["nfine"])
+    exp = np.zeros((pl["ndm"], imp["n2"]), np.int64)
+    for k, t, v in imp["hits"]:
+        exp[k, t] = v
+    assert np.array_equal(x, exp)
+
+
+def check_subband_reductions(o):
+    rng = np.random.default_rng(11)
+    nchan, f_lo, df, ts = 16, 1220.0, 1.5, 81.92e-6
+    data = rng.integers(0, 256, size=(nchan, 700))
+    # one channel per subband, one fine trial per coarse DM: exactly brute force
+    fine, coarse, d1, d2 = o.subband_plan(nchan, f_lo, df, ts, 3.0, 7.0, 9, 1, nchan)
+    assert np.all(d1 == 0) and np.allclose(coarse, fine)
+    assert np.array_equal(o.subband_dedisperse(data, d1, d2, 1),
+                          o.dedisperse(data, o.delay_table(nchan, f_lo, df, ts, fine)))
+    # one subband: brute force at each trial's coarse DM
+    fine, coarse, d1, d2 = o.subband_plan(nchan, f_lo, df, ts, 3.0, 7.0, 9, 4, 1)
+    assert np.all(d2 == 0)
+    ref = o.dedisperse(data, o.delay_table(nchan, f_lo, df, ts, coarse))
+    got = o.subband_dedisperse(data, d1, d2, 4)
+    for k in range(9):
+        assert np.array_equal(got[k], ref[k // 4, : got.shape[1]])
+    # sampled outputs equal the full evaluation
+    fine, coarse, d1, d2 = o.subband_plan(nchan, f_lo, df, ts, 0.0, 2.0, 10, 4, 4)
+    full = o.subband_dedisperse(data, d1, d2, 4)
+    for k, t in zip(rng.integers(0, 10, 50), rng.integers(0, full.shape[1], 50)):
+        assert o.subband_dedisperse_at(data, d1, d2, 4, int(k), int(t)) == full[k, t]
+
+
+def check_subband_smearing_bound(o):
+    # the composite delay differs from the brute-force delay by the intra-subband delay of the
+    # DM offset from the coarse DM, plus rounding (ALERT GPU 1 plan: DM 0-409.6 step 0.2,
+    # subbanding step 6.4 = 32 fine trials, 32 subbands of 48 channels)
+    nchan, ts = 1536, 81.92e-6
+    df = 300.0 / nchan
+    f_lo = 1220.0 + df / 2
+    fine, coarse, d1, d2 = o.subband_plan(nchan, f_lo, df, ts, 0.0, 0.2, 2048, 32, 32)
+    assert coarse.size == 64 and np.isclose(coarse[0], 3.1) and np.isclose(coarse[1], 9.5)
+    brute = o.delay_table(nchan, f_lo, df, ts, fine)
+    f = o.channel_freqs(nchan, f_lo, df)
+    fs = f.reshape(32, 48).max(axis=1)
+    j = np.arange(2048) // 32
+    comp = d1[j] + np.repeat(d2, 48, axis=1)
+    gap = np.abs(fine - coarse[j])[:, None] * o.K_DM * (1 / f**2 - 1 / np.repeat(fs, 48)**2) / ts
+    assert np.all(np.abs(comp - brute) <= np.ceil(gap) + 1)
+    assert np.abs(comp - brute).max() >= 2        # the method is an approximation
+
+
+def test_subband_golden():
+    check_subband_golden(O)
+
+
+def test_subband_reductions():
+    check_subband_reductions(O)
+
+
+def test_subband_smearing_bound():
+    check_subband_smearing_bound(O)
+
+
+def test_subband_rejects_bad_args():
+    with pytest.raises(ValueError):
+        O.subband_plan(10, 1220.0, 1.0, 1e-4, 0.0, 1.0, 8, 4, 3)   # 3 does not divide 10
+    with pytest.raises(ValueError):
+        O.subband_plan(12, 1220.0, 1.0, 1e-4, 0.0, 0.0, 8, 4, 3)   # zero DM step
+
+
 ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif_span,
               check_zero_dm, check_impulse, check_sum_conservation, check_brute_force,
               check_linearity_shift_permutation, check_chunked_stream, check_tophat_exact,
               check_downsample, check_sb_synth, check_boxcar, check_moments, check_snr_noise,
-              check_candidates_golden, check_injected_recovery, check_tophat_snr]
+              check_candidates_golden, check_injected_recovery, check_tophat_snr,
+              check_subband_golden, check_subband_reductions, check_subband_smearing_bound]
