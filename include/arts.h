@@ -85,6 +85,34 @@ int arts_plan_create(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp
                      const double* dm_list, int32_t ndm, const int32_t* widths, int32_t nwidth,
                      arts_plan_t* out);
 
+/* Two-step subband dedispersion (Sect. 6b.2 "Dedispersion": the module can dedisperse in two
+ * steps with subbanding; the subband dedispersion figure: subbands of 48 channels first
+ * dedispersed to a coarse DM, then aligned over 32 fine trials; Table "dedispersion setup":
+ * fine DM steps 0.2 / 2.5 with subbanding DM steps 6.4 / 40, 32 subbands).  The plan searches
+ * the fine trials dm_first + k dm_step, k < ndm, in nsub subbands of nchan / nsub channels:
+ *   step 1  Y[j][s][t] = sum over channels c of subband s of I[c][t + d1[j][c]], d1 the delay
+ *           at coarse DM j (the centre of fine trials j nfine .. j nfine + nfine - 1) relative
+ *           to the subband's highest channel, t < nin - max d1;
+ *   step 2  X[k][t] = sum over subbands s of Y[k / nfine][s][t + d2[k][s]], d2 the delay of the
+ *           subband's highest channel at fine DM k relative to the band's highest channel.
+ * Both delays use the law and rounding of arts_delay_table.  X approximates brute force
+ * (arts_plan_delays returns the composite delay d1 + d2 per trial and channel); its length is
+ * nin - max d1 - max d2 (= nin - max_delay of arts_plan_info).  The plan is used like any
+ * other (arts_dedisperse, arts_dedisperse_sb with SB formation in step 1, streams, batches,
+ * serving, candidates).  Limits: nfine = 16 or 32, nchan / nsub <= 257 (16-bit step-1 sums),
+ * D = 1.  One-shot calls keep the intermediate (2 bytes x nbeam x nsub x ncoarse x
+ * (nin - max d1)) in the plan, so calls with one plan on different HIP streams must be ordered
+ * by the caller; streams own theirs.  Errors: ARTS_E_INVAL, ARTS_E_NOMEM, ARTS_E_DEVICE.      */
+int arts_plan_create_subband(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp_s,
+                             double dm_first, double dm_step, int32_t ndm, int32_t nfine,
+                             int32_t nsub, const int32_t* widths, int32_t nwidth,
+                             arts_plan_t* out);
+
+/* Subband structure of a plan: subbands, fine trials per coarse DM, coarse DMs and the largest
+ * delay of each step (all 0 for a brute-force plan).                                        */
+int arts_plan_subband_info(arts_plan_t plan, int32_t* nsub, int32_t* nfine, int32_t* ncoarse,
+                           int32_t* max_delay1, int32_t* max_delay2);
+
 /* As arts_plan_create, with time downsampling by an integer factor D >= 1 (Sect. 6b.2,
  * "Downsampling": a lower time resolution for high DMs).  Input stays native-rate uint8; the
  * kernels sum D consecutive samples (dropping a trailing partial group), delays use D*tsamp

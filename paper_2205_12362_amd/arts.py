@@ -50,6 +50,9 @@ _SIGNATURES = {
                                    C.POINTER(_vp)]),
     "arts_plan_create_ds": (C.c_int, [_i32, _f64, _f64, _f64, _pf64, _i32, _pi32, _i32, _i32,
                                       C.POINTER(_vp)]),
+    "arts_plan_create_subband": (C.c_int, [_i32, _f64, _f64, _f64, _f64, _f64, _i32, _i32, _i32,
+                                           _pi32, _i32, C.POINTER(_vp)]),
+    "arts_plan_subband_info": (C.c_int, [_vp, _pi32, _pi32, _pi32, _pi32, _pi32]),
     "arts_plan_destroy": (None, [_vp]),
     "arts_plan_info": (C.c_int, [_vp, _pi32, _pi32, _pi32, _pi32, _pi32, _pi32]),
     "arts_plan_delays": (C.c_int, [_vp, _pi32]),
@@ -207,6 +210,23 @@ def arts_plan_create_ds(nchan, f_lo, df, tsamp, dms, widths, downsample):
     return h
 
 
+def arts_plan_create_subband(nchan, f_lo, df, tsamp, dm_first, dm_step, ndm, nfine, nsub,
+                             widths):
+    w, wp = _i32arr(widths)
+    h = _vp()
+    _check(lib().arts_plan_create_subband(int(nchan), float(f_lo), float(df), float(tsamp),
+                                          float(dm_first), float(dm_step), int(ndm), int(nfine),
+                                          int(nsub), wp, len(w), C.byref(h)))
+    return h
+
+
+def arts_plan_subband_info(plan):
+    v = [C.c_int32() for _ in range(5)]
+    _check(lib().arts_plan_subband_info(plan, *[C.byref(x) for x in v]))
+    return dict(zip(("nsub", "nfine", "ncoarse", "max_delay1", "max_delay2"),
+                    (x.value for x in v)))
+
+
 def arts_plan_destroy(plan):
     lib().arts_plan_destroy(plan)
 
@@ -350,6 +370,20 @@ class Plan:
     @classmethod
     def from_workload(cls, w):
         return cls(w.nchan, w.f_lo, w.df, w.tsamp, w.dms, w.widths, w.downsample)
+
+    @classmethod
+    def subband(cls, nchan, f_lo, df, tsamp, dm_first, dm_step, ndm, nfine, nsub, widths):
+        """Two-step subband plan (arts_plan_create_subband); dms are the fine trials."""
+        self = cls.__new__(cls)
+        self.dms = dm_first + dm_step * np.arange(int(ndm), dtype=np.float64)
+        self.widths = [int(w) for w in widths]
+        self.handle = arts_plan_create_subband(nchan, f_lo, df, tsamp, dm_first, dm_step, ndm,
+                                               nfine, nsub, self.widths)
+        self.info = arts_plan_info(self.handle)
+        return self
+
+    def subband_info(self):
+        return arts_plan_subband_info(self.handle)
 
     def close(self):
         if getattr(self, "handle", None):

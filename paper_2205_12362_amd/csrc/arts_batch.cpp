@@ -99,6 +99,14 @@ int arts_batch_dedisperse(arts_batch_t b, const arts_request* reqs, int32_t n, i
       job.pitch = pitch;
       job.in_bytes = rows * pitch;
     }
+    if (p->nsub > 0) {  // subband plans: their own two-step launches, the plan's workspace
+      if (int e = prepare_plan(p, job.nbeam, job.nin,
+                               static_cast<int>(reinterpret_cast<uintptr_t>(job.in) & 3u), true))
+        return e;
+      if (int e = launch_dedisperse(p, job, s)) return e;
+      ++nok;
+      continue;
+    }
     auto& g = groups[p->tiling.variant];
     g.first.push_back(p);
     g.second.push_back(job);
@@ -167,6 +175,7 @@ int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, f
 // shape and keeps the fastest (the paper's search is auto-tuned per platform and
 // observation setup, Sect. 6b.2).  Results are cached in a text file, one line per shape:
 //   <nchan> <ndm> <downsample> <max_delay> <nbeam> <nin> <variant> <ms>
+// (for subband plans <downsample> is followed by 's' and the subband count)
 #include <cstdio>
 #include <fstream>
 #include <sstream>
@@ -176,8 +185,9 @@ namespace {
 
 std::string tune_key(const arts_plan_s* p, int32_t nbeam, int64_t nin) {
   std::ostringstream k;
-  k << p->nchan << ' ' << p->ndm << ' ' << p->ds << ' ' << p->max_delay << ' ' << nbeam << ' '
-    << nin;
+  k << p->nchan << ' ' << p->ndm << ' ' << p->ds;
+  if (p->nsub > 0) k << 's' << p->nsub;  // subband plans: D then 's' and the subband count
+  k << ' ' << p->max_delay << ' ' << nbeam << ' ' << nin;
   return k.str();
 }
 

@@ -90,9 +90,16 @@ int build_tiling(arts_plan_s* p, int variant) {
   if (variant < 0 || variant >= kNumVariants)
     return fail(ARTS_E_INVAL, "tiling variant %d out of range [0, %d)", variant, kNumVariants);
   const TileVariant& v = kVariants[variant];
-  if ((p->ds == 1) != (v.spd == 4))
+  if (p->nsub > 0) {  // subband plans: the variant of every step-1 plan
+    if (v.spd != 4) return fail(ARTS_E_INVAL, "variant %d is for 16-bit data", variant);
+    for (arts_plan_s* q : p->sb1)
+      if (int st = build_tiling(q, variant)) return st;
+    p->tiling.variant = variant;
+    return ARTS_OK;
+  }
+  if (p->is16() != (v.spd == 2))
     return fail(ARTS_E_INVAL, "variant %d is for %s data", variant,
-                v.spd == 4 ? "native (D = 1)" : "downsampled (D > 1)");
+                v.spd == 4 ? "byte (native)" : "16-bit (downsampled)");
   Tiling t;
   t.variant = variant;
   t.spd = v.spd;
@@ -126,8 +133,10 @@ int build_tiling(arts_plan_s* p, int variant) {
   const int64_t per_buf = (budget - ((nchan + 3) & ~int64_t(3))) / 2 - 16;
   // a chunk's channels must fit the kernels' narrow partial sums: 8-bit counts of each run, and
   // for packed 16-bit samples (sums of D bytes) a 16-bit half per output
-  const int64_t cc_max = (v.pack && v.spd == 2) ? std::min<int64_t>(255, 65535 / (255LL * p->ds))
-                                                : 255;
+  const int64_t cc_max = (v.pack && v.spd == 2) ? std::min<int64_t>(255, 65535 / p->smax) : 255;
+  if (cc_max < 1)
+    return fail(ARTS_E_INVAL, "variant %d: samples up to %d overflow its 16-bit partial sums",
+                variant, p->smax);
   int cc = static_cast<int>(
       std::min<int64_t>({nchan, cc_max, per_buf / (4LL * (t.win_dwords + t.m_blk))}));
   if (cc < 1)
@@ -272,11 +281,18 @@ static int run_dedisperse(arts_plan_s* p, DedispJob job, hipStream_t s) {
     job.pitch = pitch;
     job.in_bytes = rows * pitch;
   }
+  if (p->nsub > 0)
+    if (int st = prepare_plan(p, job.nbeam, job.nin,
+                              static_cast<int>(reinterpret_cast<uintptr_t>(job.in) & 3u), true))
+      return st;
   return launch_dedisperse(p, job, s);
 }
 
 static void plan_free(arts_plan_s* p) {
   if (!p) return;
+  for (arts_plan_s* q : p->sb1) plan_free(q);
+  plan_free(p->sb2);
+  if (p->d_y) (void)hipFree(p->d_y);
   if (p->d_ds16) (void)hipFree(p->d_ds16);
   if (p->d_align) (void)hipFree(p->d_align);
   free_tiling(p->tiling);
@@ -290,12 +306,7 @@ static void plan_free(arts_plan_s* p) {
   delete p;
 }
 
-static int plan_create(int32_t nchan, double f_lo, double df, double tsamp, const double* dms,
-                       int32_t ndm, const int32_t* widths, int32_t nwidth, int32_t ds,
-                       arts_plan_t* out) {
-  if (!out) return fail(ARTS_E_INVAL, "out is NULL");
-  *out = nullptr;
-  if (ds > 257) return fail(ARTS_E_INVAL, "downsample must be <= 257 (16-bit sums)");
+static int check_widths(int32_t nchan, int32_t ds, const int32_t* widths, int32_t nwidth) {
   if (nwidth < 1 || !widths) return fail(ARTS_E_INVAL, "need at least one boxcar width");
   for (int32_t i = 0; i < nwidth; ++i) {
     if (widths[i] < 1 || (i > 0 && widths[i] <= widths[i - 1]))
@@ -306,6 +317,40 @@ static int plan_create(int32_t nchan, double f_lo, double df, double tsamp, cons
     return fail(ARTS_E_INVAL, "widths above %d samples are not supported", kMaxWidth);
   if (static_cast<int64_t>(nchan) * 255 * ds * widths[nwidth - 1] >= (int64_t(1) << 31))
     return fail(ARTS_E_INVAL, "nchan * 255 * D * wmax must stay below 2^31 (exact int32 sums)");
+  return ARTS_OK;
+}
+
+// Device copies of a plan's delay table, widths and DM values.
+static int upload_plan(arts_plan_s* p) {
+  if (hipError_t ge = hipGetDevice(&p->device); ge != hipSuccess)
+    return fail(ARTS_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(ge));
+  hipError_t e = hipMalloc(&p->d_delays, p->delays.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_widths, p->nwidth * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->d_dms, p->ndm * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_delays, p->delays.data(), p->delays.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_widths, p->widths.data(), p->nwidth * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_dms, p->dms.data(), p->ndm * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? ARTS_E_NOMEM : ARTS_E_DEVICE, "plan upload: %s",
+                hipGetErrorString(e));
+  return ARTS_OK;
+}
+
+// in16: the plan reads 16-bit rows of samples up to smax without downsampling (the second step
+// of a subband plan); variant >= 0 forces that tiling.
+static int plan_create(int32_t nchan, double f_lo, double df, double tsamp, const double* dms,
+                       int32_t ndm, const int32_t* widths, int32_t nwidth, int32_t ds,
+                       arts_plan_t* out, bool in16 = false, int32_t smax = 0,
+                       int variant = -1) {
+  if (!out) return fail(ARTS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (ds > 257) return fail(ARTS_E_INVAL, "downsample must be <= 257 (16-bit sums)");
+  if (int st = check_widths(nchan, ds, widths, nwidth)) return st;
   arts_plan_s* p = new (std::nothrow) arts_plan_s;
   if (!p) return fail(ARTS_E_NOMEM, "host allocation failed");
   p->nchan = nchan;
@@ -327,41 +372,133 @@ static int plan_create(int32_t nchan, double f_lo, double df, double tsamp, cons
   p->max_delay = *std::max_element(p->delays.begin(), p->delays.end());
   p->wmax = widths[nwidth - 1];
   p->halo = p->max_delay + p->wmax - 1;
-  if (hipError_t ge = hipGetDevice(&p->device); ge != hipSuccess) {
-    delete p;
-    return fail(ARTS_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(ge));
-  }
-  hipError_t e = hipMalloc(&p->d_delays, p->delays.size() * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc(&p->d_widths, nwidth * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc(&p->d_dms, ndm * sizeof(double));
-  if (e == hipSuccess)
-    e = hipMemcpy(p->d_delays, p->delays.data(), p->delays.size() * sizeof(int32_t),
-                  hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(p->d_widths, widths, nwidth * sizeof(int32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->d_dms, dms, ndm * sizeof(double), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
+  p->in16 = in16;
+  p->smax = smax > 0 ? smax : 255 * ds;
+  if ((st = upload_plan(p)) != ARTS_OK) {
     plan_free(p);
-    return fail(e == hipErrorOutOfMemory ? ARTS_E_NOMEM : ARTS_E_DEVICE, "plan upload: %s",
-                hipGetErrorString(e));
+    return st;
   }
-  st = build_tiling(p, default_variant(ds, ndm));
-  if (st != ARTS_OK) {
+  st = build_tiling(p, variant >= 0 ? variant : default_variant(ds, ndm));
+  if (st != ARTS_OK && variant < 0) {
     // wide DM spacing: fall back to the variant with the fewest DMs per block
     int best = -1;
     for (int v = 0; v < kNumVariants; ++v) {
-      if ((ds == 1) != (kVariants[v].spd == 4)) continue;
+      if (p->is16() != (kVariants[v].spd == 2)) continue;
       if (best < 0 || kVariants[v].acc * kVariants[v].waves <
                           kVariants[best].acc * kVariants[best].waves)
         best = v;
     }
     st = best >= 0 ? build_tiling(p, best) : st;
-    if (st != ARTS_OK) {
-      plan_free(p);
-      return st;
-    }
+  }
+  if (st != ARTS_OK) {
+    plan_free(p);
+    return st;
   }
   *out = p;
+  return ARTS_OK;
+}
+
+// Two-step subband plan (Sect. 6b.2 "Dedispersion"; Table "dedispersion setup").  Delays as in
+// the oracle's reading: coarse DM = centre of each group of nfine fine trials, subband
+// reference = its highest channel, both steps rounded half to even in FP64.
+static int plan_create_subband(int32_t nchan, double f_lo, double df, double tsamp,
+                               double dm_first, double dm_step, int32_t ndm, int32_t nfine,
+                               int32_t nsub, const int32_t* widths, int32_t nwidth,
+                               arts_plan_t* out) {
+  if (!out) return fail(ARTS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (nchan < 1 || nsub < 1 || nchan % nsub != 0)
+    return fail(ARTS_E_INVAL, "nsub must divide nchan");
+  const int32_t csub = nchan / nsub;
+  if (csub > 257) return fail(ARTS_E_INVAL, "at most 257 channels per subband (16-bit sums)");
+  if (nfine != 16 && nfine != 32)
+    return fail(ARTS_E_INVAL, "nfine must be 16 or 32 (the DM trials of a step-2 block)");
+  if (ndm < 1 || !std::isfinite(dm_first) || !std::isfinite(dm_step) || dm_first < 0 ||
+      !(dm_step > 0))
+    return fail(ARTS_E_INVAL, "need ndm >= 1, dm_first >= 0 and dm_step > 0 (finite)");
+  if (int st = check_widths(nchan, 1, widths, nwidth)) return st;
+  const int32_t ncoarse = (ndm + nfine - 1) / nfine;
+  std::vector<double> fine(ndm), coarse(ncoarse);
+  for (int32_t k = 0; k < ndm; ++k) fine[k] = dm_first + dm_step * k;
+  for (int32_t j = 0; j < ncoarse; ++j)
+    coarse[j] = dm_first + dm_step * (static_cast<double>(j) * nfine + (nfine - 1) / 2.0);
+  arts_plan_s* p = new (std::nothrow) arts_plan_s;
+  if (!p) return fail(ARTS_E_NOMEM, "host allocation failed");
+  p->nchan = nchan;
+  p->ndm = ndm;
+  p->nwidth = nwidth;
+  p->f_lo = f_lo;
+  p->df = df;
+  p->tsamp = tsamp;
+  p->dms = fine;
+  p->widths.assign(widths, widths + nwidth);
+  p->nsub = nsub;
+  p->nfine = nfine;
+  p->ncoarse = ncoarse;
+  static const int32_t kOne[1] = {1};
+  int st = ARTS_OK;
+  p->tie_margin = 1e300;
+  for (int32_t s = 0; s < nsub && st == ARTS_OK; ++s) {
+    arts_plan_s* q = nullptr;
+    st = plan_create(csub, f_lo + static_cast<double>(s) * csub * df, df, tsamp, coarse.data(),
+                     ncoarse, kOne, 1, 1, &q);
+    if (st == ARTS_OK) {
+      p->sb1.push_back(q);
+      p->max_d1 = std::max(p->max_d1, q->max_delay);
+      p->tie_margin = std::min(p->tie_margin, q->tie_margin);
+    }
+  }
+  if (st == ARTS_OK) {
+    const double top = df > 0 ? csub - 1 : 0;
+    st = plan_create(nsub, f_lo + top * df, csub * df, tsamp, fine.data(), ndm, kOne, 1, 1,
+                     &p->sb2, true, 255 * csub, nfine == 32 ? 6 : 7);
+  }
+  if (st != ARTS_OK) {
+    plan_free(p);
+    return st;
+  }
+  p->tie_margin = std::min(p->tie_margin, p->sb2->tie_margin);
+  // composite delay of (trial k, channel c): step 1 at k's coarse DM plus step 2 of c's subband
+  p->delays.resize(static_cast<size_t>(ndm) * nchan);
+  for (int32_t k = 0; k < ndm; ++k)
+    for (int32_t c = 0; c < nchan; ++c) {
+      const int32_t sb = c / csub;
+      p->delays[static_cast<size_t>(k) * nchan + c] =
+          p->sb1[sb]->delays[static_cast<size_t>(k / nfine) * csub + c % csub] +
+          p->sb2->delays[static_cast<size_t>(k) * nsub + sb];
+    }
+  p->max_delay = p->max_d1 + p->sb2->max_delay;
+  p->wmax = widths[nwidth - 1];
+  p->halo = p->max_delay + p->wmax - 1;
+  p->tiling.variant = p->sb1[0]->tiling.variant;
+  if ((st = upload_plan(p)) != ARTS_OK) {
+    plan_free(p);
+    return st;
+  }
+  *out = p;
+  return ARTS_OK;
+}
+
+int64_t subband_ws_elems(const arts_plan_s* p, int32_t nbeam, int64_t nin) {
+  if (p->nsub == 0) return 0;
+  const int64_t L1p = (nin - p->max_d1 + 1) & ~int64_t(1);
+  return static_cast<int64_t>(nbeam) * p->nsub * p->ncoarse * std::max<int64_t>(L1p, 0);
+}
+
+int prepare_plan(arts_plan_s* p, int32_t nbeam, int64_t nin, int g0, bool plan_ws) {
+  if (p->nsub == 0) return ensure_tables(p, g0);
+  for (arts_plan_s* q : p->sb1)
+    if (int st = ensure_tables(q, g0)) return st;
+  // step-2 rows start at even element offsets of a 256-byte aligned buffer: class 0
+  if (int st = ensure_tables(p->sb2, 0)) return st;
+  if (!plan_ws) return ARTS_OK;
+  const int64_t need = subband_ws_elems(p, nbeam, nin);
+  if (need <= p->y_cap) return ARTS_OK;
+  if (p->d_y) (void)hipFree(p->d_y);
+  p->d_y = nullptr;
+  p->y_cap = 0;
+  ARTS_HIP(hipMalloc(&p->d_y, need * sizeof(uint16_t)));
+  p->y_cap = need;
   return ARTS_OK;
 }
 
@@ -415,6 +552,25 @@ int arts_plan_create_ds(int32_t nchan, double f_lo_mhz, double df_mhz, double ts
                         int32_t nwidth, int32_t downsample, arts_plan_t* out) {
   return plan_create(nchan, f_lo_mhz, df_mhz, tsamp_s, dm_list, ndm, widths, nwidth,
                      downsample, out);
+}
+
+int arts_plan_create_subband(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp_s,
+                             double dm_first, double dm_step, int32_t ndm, int32_t nfine,
+                             int32_t nsub, const int32_t* widths, int32_t nwidth,
+                             arts_plan_t* out) {
+  return plan_create_subband(nchan, f_lo_mhz, df_mhz, tsamp_s, dm_first, dm_step, ndm, nfine,
+                             nsub, widths, nwidth, out);
+}
+
+int arts_plan_subband_info(arts_plan_t p, int32_t* nsub, int32_t* nfine, int32_t* ncoarse,
+                           int32_t* max_delay1, int32_t* max_delay2) {
+  if (int st = check_plan(p)) return st;
+  if (nsub) *nsub = p->nsub;
+  if (nfine) *nfine = p->nfine;
+  if (ncoarse) *ncoarse = p->ncoarse;
+  if (max_delay1) *max_delay1 = p->max_d1;
+  if (max_delay2) *max_delay2 = p->nsub ? p->sb2->max_delay : 0;
+  return ARTS_OK;
 }
 
 void arts_plan_destroy(arts_plan_t plan) { plan_free(plan); }

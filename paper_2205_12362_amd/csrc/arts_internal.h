@@ -71,6 +71,19 @@ struct arts_plan_s {
   int64_t ds16_cap = 0;        // elements
   uint8_t* d_align = nullptr;  // dword-aligned copy of one-shot inputs with odd row pitch
   int64_t align_cap = 0;       // bytes
+  // input rows are 16-bit: downsampled sums (D > 1) or, for the second step of a subband plan,
+  // step-1 subband sums; smax is the largest sample value (bounds the packed partial sums)
+  bool in16 = false;
+  int32_t smax = 255;
+  // two-step subband plans (arts_plan_create_subband): per-subband step-1 plans over the coarse
+  // DMs, the step-2 plan over the subbands at the fine DMs, and the 16-bit intermediate
+  // [nbeam][nsub][ncoarse][pitch] the two share
+  int32_t nsub = 0, nfine = 0, ncoarse = 0, max_d1 = 0;
+  std::vector<arts_plan_s*> sb1;
+  arts_plan_s* sb2 = nullptr;
+  uint16_t* d_y = nullptr;
+  int64_t y_cap = 0;  // elements
+  bool is16() const { return ds > 1 || in16; }
 };
 
 namespace arts {
@@ -106,9 +119,25 @@ struct DedispJob {
   int32_t nbeam = 0;
   int32_t* out = nullptr;          // [nbeam][ndm][nout]
   int64_t nout = 0;
+  // layout overrides (0 / false: the plain layout above)
+  int32_t src_stride = 0;          // rows between source beams in `in` / `in16` (default nchan)
+  int32_t tbl_stride = 0;          // sb_table entries between beams (default nchan)
+  int64_t out_pitch = 0;           // out elements between DM rows (default nout)
+  int64_t out_bstride = 0;         // out elements between beams (default ndm * out_pitch)
+  bool out16 = false;              // store the sums as uint16 (the caller bounds them)
+  int64_t in16_blk = 0;            // in16 elements added per DM block
+  // subband plans: the caller's 16-bit intermediate (streams own one; null: the plan's)
+  uint16_t* y = nullptr;
+  int64_t y_elems = 0;
 };
 
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s);
+// Subband plans: elements of the 16-bit intermediate for nbeam beams of nin samples.
+int64_t subband_ws_elems(const arts_plan_s* p, int32_t nbeam, int64_t nin);
+// Subband plans: the step plans' offset tables for input alignment class g0 and, if
+// plan_ws, the plan's own intermediate for nbeam x nin, so that a later launch allocates
+// nothing.  Other plans: their tables for g0.
+int prepare_plan(arts_plan_s* p, int32_t nbeam, int64_t nin, int g0, bool plan_ws);
 
 // Device descriptor storage of persistent batch launches (reused across calls).
 struct BatchBuffers {
@@ -161,6 +190,8 @@ struct arts_stream_s {
   std::vector<int64_t> N16;                // per plan: 16-bit samples held per row
   std::vector<int32_t*> series;
   std::vector<int64_t> L, H;
+  std::vector<uint16_t*> y;                // per plan: subband intermediate (subband plans)
+  std::vector<int64_t> y_elems;
   arts_candidate* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
   unsigned long long* h_count = nullptr;  // pinned

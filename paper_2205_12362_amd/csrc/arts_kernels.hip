@@ -79,15 +79,21 @@ struct DedispArgs {
   const uint16_t* in16;     // downsampled 16-bit rows (spd = 2 kernels)
   const uint16_t* in16_end;
   int64_t pitch16;          // elements between downsampled rows
-  const uint8_t* sb_table;  // nullable: row (b, c) reads source beam sb_table[b*nchan + c]
+  const uint8_t* sb_table;  // nullable: row (b, c) reads source beam sb_table[b*tbl_stride + c]
   const int32_t* base;      // [nblk][nchan]
   const int32_t* list;      // [nblk][m_blk][nchan] LDS byte offsets, by chunk then m
   const uint32_t* cnt;      // [nblk][nchunk][m_blk] packed per-m channel counts
-  int32_t* out;
+  int32_t* out;             // out[b*out_bstride + d*out_pitch + t], int32 (or uint16: out16)
   int64_t nout;
+  int64_t out_pitch, out_bstride;
+  int64_t in16_blk;         // in16 elements added per DM block
   int64_t nwg;
   int32_t nchan, ndm, nsrc, ds, nbeam;
   int32_t m_blk, nblk, win, cc, nchunk, ntt;
+  int32_t src_stride;       // rows between source beams (nchan unless the job says otherwise)
+  int32_t tbl_stride;       // SB table entries between beams
+  int32_t out16;
+  int32_t pad_;
 };
 
 // Source beam of channel c of beam b: b itself, or the SB table entry (read from the LDS copy
@@ -99,7 +105,7 @@ __device__ __forceinline__ int src_beam(const DedispArgs& a, const uint8_t* sbro
 
 __device__ __forceinline__ const uint8_t* row_ptr(const DedispArgs& a, int src, int c) {
   if (src >= a.nsrc) return nullptr;
-  return a.in + (static_cast<int64_t>(src) * a.nchan + c) * a.pitch;
+  return a.in + (static_cast<int64_t>(src) * a.src_stride + c) * a.pitch;
 }
 
 // acc += one byte / 16-bit half of w, as a single SDWA add.  Written as (ALU-only) inline asm
@@ -131,9 +137,10 @@ __device__ __forceinline__ void add_half(uint32_t& acc, uint32_t w) {
         : "+v"(acc) : "v"(w));
 }
 
-__device__ __forceinline__ const uint16_t* row_ptr16(const DedispArgs& a, int src, int c) {
+__device__ __forceinline__ const uint16_t* row_ptr16(const DedispArgs& a, int src, int c,
+                                                     int blk) {
   if (src >= a.nsrc) return nullptr;
-  return a.in16 + (static_cast<int64_t>(src) * a.nchan + c) * a.pitch16;
+  return a.in16 + (static_cast<int64_t>(src) * a.src_stride + c) * a.pitch16 + blk * a.in16_blk;
 }
 
 template <int SPD, int J, int MS>
@@ -456,8 +463,9 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 // row's valid range only ever feed output samples that are not stored.
 template <int SPD, int WAVES>
 __device__ __forceinline__ void stage_windows(const DedispArgs& a, const uint8_t* sbrow, int b,
-                                              int64_t t0, const int32_t* base_blk, int c0,
-                                              int ncc, uint32_t* buf, int lane, int wave) {
+                                              int blk, int64_t t0, const int32_t* base_blk,
+                                              int c0, int ncc, uint32_t* buf, int lane,
+                                              int wave) {
   for (int jj = wave; jj < ncc; jj += WAVES) {
     const int c = c0 + jj;
     const int64_t ws = t0 + base_blk[c];
@@ -472,7 +480,7 @@ __device__ __forceinline__ void stage_windows(const DedispArgs& a, const uint8_t
       lo = a.in;
       hi = a.in_end;
     } else {
-      const uint16_t* r16 = row_ptr16(a, src, c);
+      const uint16_t* r16 = row_ptr16(a, src, c, blk);
       if (r16) first = reinterpret_cast<const uint8_t*>(r16 + ws);
       lo = reinterpret_cast<const uint8_t*>(a.in16);
       hi = reinterpret_cast<const uint8_t*>(a.in16_end);
@@ -553,9 +561,10 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
                            (threadIdx.x & 3)] = 0;
   if (a.sb_table)
     for (int c = threadIdx.x; c < a.nchan; c += WAVES * 64)
-      sbrow[c] = a.sb_table[static_cast<int64_t>(b) * a.nchan + c];
+      sbrow[c] = a.sb_table[static_cast<int64_t>(b) * a.tbl_stride + c];
   __syncthreads();
-  stage_windows<SPD, WAVES>(a, sbrow, b, t0, base_blk, 0, min(a.cc, a.nchan), lds, lane, wave);
+  stage_windows<SPD, WAVES>(a, sbrow, b, blk, t0, base_blk, 0, min(a.cc, a.nchan), lds, lane,
+                            wave);
   stage_lists<WAVES>(a, list_blk, 0, min(a.cc, a.nchan),
                      reinterpret_cast<int32_t*>(lds + a.cc * a.win), lane, wave);
   __builtin_amdgcn_s_waitcnt(0);
@@ -569,7 +578,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
       uint32_t* nxt = lds + ((ch + 1) & 1) * buf_words;
       const int c1 = c0 + a.cc;
       const int ncc1 = min(a.cc, a.nchan - c1);
-      stage_windows<SPD, WAVES>(a, sbrow, b, t0, base_blk, c1, ncc1, nxt, lane, wave);
+      stage_windows<SPD, WAVES>(a, sbrow, b, blk, t0, base_blk, c1, ncc1, nxt, lane, wave);
       stage_lists<WAVES>(a, list_blk, c1, ncc1, reinterpret_cast<int32_t*>(nxt + a.cc * a.win),
                          lane, wave);
     }
@@ -655,11 +664,21 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
     for (int x = 0; x < ACC; ++x) {
       const int d = dwave0 + x;
       if (d < a.ndm) {
-        int32_t* o = a.out + (static_cast<int64_t>(b) * a.ndm + d) * a.nout;
+        const int64_t row = static_cast<int64_t>(b) * a.out_bstride + d * a.out_pitch;
+        if (a.out16) {
+          uint16_t* o = reinterpret_cast<uint16_t*>(a.out) + row;
 #pragma unroll
-        for (int i = 0; i < T; ++i) {
-          const int64_t t = t0 + static_cast<int64_t>(lane) * T + i;
-          if (t < a.nout) o[t] = static_cast<int32_t>(acc[x][i]);
+          for (int i = 0; i < T; ++i) {
+            const int64_t t = t0 + static_cast<int64_t>(lane) * T + i;
+            if (t < a.nout) o[t] = static_cast<uint16_t>(acc[x][i]);
+          }
+        } else {
+          int32_t* o = a.out + row;
+#pragma unroll
+          for (int i = 0; i < T; ++i) {
+            const int64_t t = t0 + static_cast<int64_t>(lane) * T + i;
+            if (t < a.nout) o[t] = static_cast<int32_t>(acc[x][i]);
+          }
         }
       }
     }
@@ -803,12 +822,13 @@ static int launch_batch_variant(BatchArgs q, size_t lds, hipStream_t s) {
 static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
   DedispArgs a{};
   int g0 = 0;
-  if (p->ds == 1) {
+  if (!p->is16()) {
     if (job.pitch % 4 != 0) return fail(ARTS_E_INVAL, "internal: row pitch not a multiple of 4");
     g0 = static_cast<int>(reinterpret_cast<uintptr_t>(job.in) & 3u);
   } else {
-    if (!job.in16) return fail(ARTS_E_INVAL, "downsampled plan needs 16-bit rows");
-    if (job.pitch16 % 2 != 0 || (reinterpret_cast<uintptr_t>(job.in16) & 1u))
+    if (!job.in16) return fail(ARTS_E_INVAL, "16-bit plan needs 16-bit rows");
+    if (job.pitch16 % 2 != 0 || job.in16_blk % 2 != 0 ||
+        (reinterpret_cast<uintptr_t>(job.in16) & 1u))
       return fail(ARTS_E_INVAL, "internal: 16-bit row pitch must be even");
     g0 = static_cast<int>((reinterpret_cast<uintptr_t>(job.in16) >> 1) & 1u);
   }
@@ -829,6 +849,12 @@ static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
   a.cnt = t.d_cnt[g0];
   a.out = job.out;
   a.nout = job.nout;
+  a.out_pitch = job.out_pitch > 0 ? job.out_pitch : job.nout;
+  a.out_bstride = job.out_bstride > 0 ? job.out_bstride : p->ndm * a.out_pitch;
+  a.out16 = job.out16 ? 1 : 0;
+  a.in16_blk = job.in16_blk;
+  a.src_stride = job.src_stride > 0 ? job.src_stride : p->nchan;
+  a.tbl_stride = job.tbl_stride > 0 ? job.tbl_stride : p->nchan;
   a.nchan = p->nchan;
   a.ndm = p->ndm;
   a.nsrc = job.nsrc;
@@ -845,7 +871,53 @@ static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
   return ARTS_OK;
 }
 
+// Two-step subband dedispersion.  Step 1: one launch per subband, its step plan summing the
+// subband's channels (rows src_stride = nchan apart in the caller's input, SB table entries
+// likewise) at the coarse DMs into 16-bit rows Y[b][s][j][t], t < L1 = nin - max step-1 delay.
+// Step 2: the step-2 plan sums the subbands at the fine DMs; its DM blocks are the coarse
+// groups (m_blk = nfine), so block j reads rows Y[b][.][j] (in16_blk = one row pitch).
+static int launch_subband(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
+  const int32_t csub = p->nchan / p->nsub;
+  const int64_t L1 = job.nin - p->max_d1;
+  const int64_t L1p = (L1 + 1) & ~int64_t(1);
+  const int64_t need = subband_ws_elems(p, job.nbeam, job.nin);
+  if (L1 < 1 || job.nout > L1 - p->sb2->max_delay)
+    return fail(ARTS_E_INVAL, "internal: subband job shorter than its delays");
+  uint16_t* y = job.y ? job.y : p->d_y;
+  if (need > (job.y ? job.y_elems : p->y_cap))
+    return fail(ARTS_E_INVAL, "internal: subband workspace not prepared");
+  for (int32_t sb = 0; sb < p->nsub; ++sb) {
+    DedispJob j1 = job;
+    const int64_t off = static_cast<int64_t>(sb) * csub * job.pitch;
+    j1.in = job.in + off;
+    j1.in_bytes = job.in_bytes - off;
+    j1.src_stride = p->nchan;
+    j1.sb_table = job.sb_table ? job.sb_table + static_cast<int64_t>(sb) * csub : nullptr;
+    j1.tbl_stride = p->nchan;
+    j1.out = reinterpret_cast<int32_t*>(y + static_cast<int64_t>(sb) * p->ncoarse * L1p);
+    j1.out16 = true;
+    j1.out_pitch = L1p;
+    j1.out_bstride = static_cast<int64_t>(p->nsub) * p->ncoarse * L1p;
+    j1.nout = L1;
+    if (int st = launch_dedisperse(p->sb1[sb], j1, s)) return st;
+  }
+  DedispJob j2;
+  j2.in16 = y;
+  j2.in16_elems = need;
+  j2.pitch16 = static_cast<int64_t>(p->ncoarse) * L1p;
+  j2.in16_blk = L1p;
+  j2.nin = L1;
+  j2.nsrc = job.nbeam;
+  j2.nbeam = job.nbeam;
+  j2.out = job.out;
+  j2.nout = job.nout;
+  j2.out_pitch = job.out_pitch;
+  j2.out_bstride = job.out_bstride;
+  return launch_dedisperse(p->sb2, j2, s);
+}
+
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
+  if (p->nsub > 0) return launch_subband(p, job, s);
   DedispArgs a;
   if (int st = make_args(p, job, &a)) return st;
   switch (p->tiling.variant) {

@@ -112,6 +112,10 @@ int arts_server_tick(arts_server_t v, int32_t* nrun) {
     const int parity = static_cast<int>(s->pushed & 1);
     if (int st = stream_advance(s, parity, v->hs)) return st;
     for (size_t p = 0; p < s->plans.size(); ++p) {
+      if (s->plans[p]->nsub > 0) {  // subband plans: their own two-step launches
+        if (int st = launch_dedisperse(s->plans[p], stream_job(s, parity, p), v->hs)) return st;
+        continue;
+      }
       auto& g = groups[s->plans[p]->tiling.variant];
       g.first.push_back(s->plans[p]);
       g.second.push_back(stream_job(s, parity, p));

@@ -115,6 +115,8 @@ int64_t stream_bytes_needed(const arts_plan_t* plans, int32_t nplan, int32_t nsr
     }
   }
   if (native) total += 2 * rows * ((hmax + chunk + 3) & ~int64_t(3));
+  for (int32_t i = 0; i < nplan; ++i)
+    total += 2 * subband_ws_elems(plans[i], nbeam, static_cast<int64_t>(plans[i]->halo) + chunk);
   return total;
 }
 
@@ -133,6 +135,8 @@ DedispJob stream_job(arts_stream_s* s, int parity, size_t p) {
     job.in_bytes = rows * s->W - off;
     job.nin = s->H[p] + s->chunk;
     job.pitch = s->W;
+    job.y = s->y[p];
+    job.y_elems = s->y_elems[p];
   } else {
     job.in = s->input;  // unused: the kernel reads the 16-bit ring
     job.in_bytes = rows * s->chunk;
@@ -297,7 +301,14 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
     const int g0 = s->plans[p]->ds == 1
                        ? static_cast<int>((reinterpret_cast<uintptr_t>(s->ring[0]) + s->hmax - s->H[p]) & 3u)
                        : static_cast<int>((reinterpret_cast<uintptr_t>(s->ring16[0][p]) >> 1) & 1u);
-    st = ensure_tables(s->plans[p], g0);
+    st = prepare_plan(s->plans[p], nbeam, s->H[p] + chunk, g0, false);
+  }
+  for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
+    uint16_t* y = nullptr;
+    const int64_t e = subband_ws_elems(s->plans[p], nbeam, s->H[p] + chunk);
+    if (e > 0) st = dev_alloc(s, reinterpret_cast<void**>(&y), e * sizeof(uint16_t));
+    s->y.push_back(y);
+    s->y_elems.push_back(e);
   }
   for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
     int32_t* ser = nullptr;

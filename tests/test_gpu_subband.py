@@ -1,0 +1,135 @@
+"""GPU parity of two-step subband dedispersion: bit-exact against the oracle's subband_dedisperse
+for small plans (both fine-trial counts, ragged last coarse group, every step-1 tiling, SB
+formation in step 1), in a stream (zero history, one-shot oracle on the concatenation), in a
+batch, and at the full size of the ALERT plan for one GPU (1536 channels, 32 subbands, DM 0 to
+409.6 in steps of 0.2, subbanding step 6.4) on every output of one beam."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2205_12362_amd import arts, synth
+from tests._parity import compare_candidates, near_threshold_rows, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan_and_oracle(nchan, nsub, nfine, ndm, dm_first=0.0, dm_step=0.5, widths=(1, 2, 4, 8)):
+    f_lo, df = synth.band(nchan)
+    p = arts.Plan.subband(nchan, f_lo, df, synth.TSAMP, dm_first, dm_step, ndm, nfine, nsub,
+                          widths)
+    fine, coarse, d1, d2 = O.subband_plan(nchan, f_lo, df, synth.TSAMP, dm_first, dm_step, ndm,
+                                          nfine, nsub)
+    return p, (fine, coarse, d1, d2)
+
+
+@pytest.mark.parametrize("nfine,ndm", [(32, 64), (16, 64), (32, 50), (16, 37)])
+def test_subband_small_matches_oracle(nfine, ndm):
+    p, (fine, coarse, d1, d2) = _plan_and_oracle(96, 8, nfine, ndm)
+    info = p.subband_info()
+    assert info["nsub"] == 8 and info["nfine"] == nfine and info["ncoarse"] == coarse.size
+    assert info["max_delay1"] == int(d1.max()) and info["max_delay2"] == int(d2.max())
+    comp = d1[np.arange(ndm) // nfine] + np.repeat(d2, 12, axis=1)
+    assert np.array_equal(p.delays(), comp)
+    assert p.max_delay == int(d1.max()) + int(d2.max())
+    rng = np.random.default_rng(nfine + ndm)
+    nin = p.max_delay + 2500 + int(rng.integers(0, 7))
+    data = rng.integers(0, 256, size=(2, 96, nin), dtype=np.uint8)
+    got = p.dedisperse(to_dev(data)).cpu().numpy()
+    for b in range(2):
+        assert np.array_equal(got[b], O.subband_dedisperse(data[b], d1, d2, nfine)), b
+
+
+def test_subband_step1_tilings_agree():
+    p, (fine, coarse, d1, d2) = _plan_and_oracle(144, 12, 32, 96, dm_first=20.0, dm_step=1.0)
+    data = synth.noise((1, 144, p.max_delay + 3001), seed=5)
+    ref = O.subband_dedisperse(data[0], d1, d2, 32)
+    native = [v for v in range(arts.arts_tiling_count())
+              if "SPD=4" in arts.arts_tiling_describe(v)]
+    for v in native:
+        p.set_tiling(v)
+        assert p.tiling() == v
+        assert np.array_equal(p.dedisperse(to_dev(data)).cpu().numpy()[0], ref), v
+    with pytest.raises(arts.ArtsError):
+        p.set_tiling(6)                      # a 16-bit tiling cannot run step 1
+
+
+def test_subband_fused_sb_formation():
+    nchan, nsub = 96, 8
+    p, (fine, coarse, d1, d2) = _plan_and_oracle(nchan, nsub, 32, 64)
+    tab = synth.noise((4, nchan, p.max_delay + 2200), seed=8)
+    table = synth.sb_table_synthetic(9, 4, nchan)
+    got = p.dedisperse_sb(to_dev(tab), to_dev(table)).cpu().numpy()
+    sb = O.sb_synthesize(tab, table)
+    for s in range(9):
+        assert np.array_equal(got[s], O.subband_dedisperse(sb[s], d1, d2, 32)), s
+
+
+def test_subband_candidates_with_burst():
+    nchan, nsub = 128, 8
+    p, (fine, coarse, d1, d2) = _plan_and_oracle(nchan, nsub, 32, 128, dm_step=0.5,
+                                                 widths=(1, 2, 4, 8, 16))
+    brute = O.delay_table(nchan, *synth.band(nchan), synth.TSAMP, fine)
+    data = synth.noise((nchan, p.max_delay + 6000), seed=31)
+    synth.add_tophat(data, 2000 + brute[70], 8, 12)
+    x = O.subband_dedisperse(data, d1, d2, 32)
+    series = p.dedisperse(to_dev(data[None]))
+    assert np.array_equal(series.cpu().numpy()[0], x)
+    nrep = x.shape[1] - 15
+    ora = O.candidates(x, [1, 2, 4, 8, 16], nrep, 8.0)
+    near = near_threshold_rows(x, [1, 2, 4, 8, 16], nrep, 8.0, np.arange(x.shape[0]))
+    got = p.candidates(series, 8.0)
+    assert len(ora) > 0
+    compare_candidates(got, ora, near)
+
+
+def test_subband_in_stream_matches_one_shot():
+    nchan, nsub, chunk = 64, 8, 2400
+    f_lo, df = synth.band(nchan)
+    p = arts.Plan.subband(nchan, f_lo, df, synth.TSAMP, 0.0, 1.0, 64, 32, nsub, [1, 2, 4])
+    _, _, d1, d2 = O.subband_plan(nchan, f_lo, df, synth.TSAMP, 0.0, 1.0, 64, 32, nsub)
+    H = p.halo
+    chunks = [synth.noise((2, nchan, chunk), seed=60 + k) for k in range(4)]
+    full = np.concatenate([np.zeros((2, nchan, H), np.uint8)] + chunks, axis=2)
+    with arts.Stream([p], 2, chunk, 6.0) as st:
+        for k, c in enumerate(chunks):
+            st.push(to_dev(c))
+            st.wait()
+            got = st.series(0).cpu().numpy()
+            for b in range(2):
+                win = full[b][:, k * chunk: H + (k + 1) * chunk]
+                assert np.array_equal(got[b], O.subband_dedisperse(win, d1, d2, 32)), (k, b)
+
+
+def test_subband_in_batch_equals_plan_call():
+    import torch
+    p, _ = _plan_and_oracle(96, 8, 16, 48)
+    q = arts.Plan.from_workload(synth.cfg_small())
+    rng = np.random.default_rng(2)
+    d1 = torch.from_numpy(rng.integers(0, 256, (2, 96, p.max_delay + 1700), dtype=np.uint8)).cuda()
+    d2 = torch.from_numpy(rng.integers(0, 256, (1, 128, 9000), dtype=np.uint8)).cuda()
+    o1 = torch.empty((2, 48, arts.series_length(p, d1.shape[2])), dtype=torch.int32,
+                     device="cuda")
+    o2 = torch.empty((1, q.info["ndm"], arts.series_length(q, 9000)), dtype=torch.int32,
+                     device="cuda")
+    with arts.Batch() as b:
+        st = b.dedisperse([(p, d1, o1), (q, d2, o2)])
+    assert list(st) == [arts.ARTS_OK, arts.ARTS_OK]
+    assert torch.equal(o1, p.dedisperse(d1))
+    assert torch.equal(o2, q.dedisperse(d2))
+
+
+def test_subband_alert_plan_full_size():
+    # ALERT GPU 1 (Table "dedispersion setup"): DM 0-409.6 step 0.2, subbanding step 6.4
+    nchan = 1536
+    f_lo, df = synth.band(nchan)
+    p = arts.Plan.subband(nchan, f_lo, df, synth.TSAMP, 0.0, 0.2, 2048, 32, 32,
+                          [1 << k for k in range(9)])
+    fine, coarse, d1, d2 = O.subband_plan(nchan, f_lo, df, synth.TSAMP, 0.0, 0.2, 2048, 32, 32)
+    assert coarse.size == 64
+    nin = synth.CHUNK + p.halo
+    data = synth.noise((1, nchan, nin), seed=77)
+    print("subband full size: nin", nin, flush=True)
+    got = p.dedisperse(to_dev(data)).cpu().numpy()[0]
+    ref = O.subband_dedisperse(data[0], d1, d2, 32)
+    assert got.shape == ref.shape
+    assert np.array_equal(got, ref)
