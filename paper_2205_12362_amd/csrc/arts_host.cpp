@@ -90,10 +90,10 @@ int build_tiling(arts_plan_s* p, int variant) {
   if (variant < 0 || variant >= kNumVariants)
     return fail(ARTS_E_INVAL, "tiling variant %d out of range [0, %d)", variant, kNumVariants);
   const TileVariant& v = kVariants[variant];
-  if (p->nsub > 0) {  // subband plans: the variant of every step-1 plan
-    if (v.spd != 4) return fail(ARTS_E_INVAL, "variant %d is for 16-bit data", variant);
-    for (arts_plan_s* q : p->sb1)
-      if (int st = build_tiling(q, variant)) return st;
+  if (p->nsub > 0) {  // subband plans: the variant of the step-1 plan
+    if (v.spd != 4 || v.pack == 2)
+      return fail(ARTS_E_INVAL, "variant %d cannot run the first subband step", variant);
+    if (int st = build_tiling(p->sb1, variant)) return st;
     p->tiling.variant = variant;
     return ARTS_OK;
   }
@@ -139,6 +139,9 @@ int build_tiling(arts_plan_s* p, int variant) {
                 variant, p->smax);
   int cc = static_cast<int>(
       std::min<int64_t>({nchan, cc_max, per_buf / (4LL * (t.win_dwords + t.m_blk))}));
+  // split plans: chunks must not straddle channel groups, so cc divides the group size
+  if (p->split > 0)
+    while (cc > 1 && p->split % cc != 0) --cc;
   if (cc < 1)
     return fail(ARTS_E_INVAL,
                 "variant %d: one channel's window (%d B) exceeds the LDS budget (%lld B); the DM "
@@ -290,7 +293,7 @@ static int run_dedisperse(arts_plan_s* p, DedispJob job, hipStream_t s) {
 
 static void plan_free(arts_plan_s* p) {
   if (!p) return;
-  for (arts_plan_s* q : p->sb1) plan_free(q);
+  plan_free(p->sb1);
   plan_free(p->sb2);
   if (p->d_y) (void)hipFree(p->d_y);
   if (p->d_ds16) (void)hipFree(p->d_ds16);
@@ -342,11 +345,12 @@ static int upload_plan(arts_plan_s* p) {
 }
 
 // in16: the plan reads 16-bit rows of samples up to smax without downsampling (the second step
-// of a subband plan); variant >= 0 forces that tiling.
+// of a subband plan); variant >= 0 forces that tiling; delays (host [ndm][nchan], nullable)
+// replaces the computed table and split sets channel groups (the first step of a subband plan).
 static int plan_create(int32_t nchan, double f_lo, double df, double tsamp, const double* dms,
                        int32_t ndm, const int32_t* widths, int32_t nwidth, int32_t ds,
                        arts_plan_t* out, bool in16 = false, int32_t smax = 0,
-                       int variant = -1) {
+                       int variant = -1, const int32_t* delays = nullptr, int32_t split = 0) {
   if (!out) return fail(ARTS_E_INVAL, "out is NULL");
   *out = nullptr;
   if (ds > 257) return fail(ARTS_E_INVAL, "downsample must be <= 257 (16-bit sums)");
@@ -363,12 +367,16 @@ static int plan_create(int32_t nchan, double f_lo, double df, double tsamp, cons
   if (ndm >= 1 && dms) p->dms.assign(dms, dms + ndm);
   p->widths.assign(widths, widths + nwidth);
   p->delays.resize(static_cast<size_t>(std::max(ndm, 1)) * std::max(nchan, 1));
-  int st = compute_delays(nchan, f_lo, df, tsamp, dms, ndm, ds, p->delays.data(),
-                          &p->tie_margin);
+  int st = ARTS_OK;
+  if (delays)
+    std::copy(delays, delays + p->delays.size(), p->delays.begin());
+  else
+    st = compute_delays(nchan, f_lo, df, tsamp, dms, ndm, ds, p->delays.data(), &p->tie_margin);
   if (st != ARTS_OK) {
     delete p;
     return st;
   }
+  p->split = split;
   p->max_delay = *std::max_element(p->delays.begin(), p->delays.end());
   p->wmax = widths[nwidth - 1];
   p->halo = p->max_delay + p->wmax - 1;
@@ -438,17 +446,27 @@ static int plan_create_subband(int32_t nchan, double f_lo, double df, double tsa
   static const int32_t kOne[1] = {1};
   int st = ARTS_OK;
   p->tie_margin = 1e300;
+  // step-1 delays: each subband's channels relative to the subband's own highest channel
+  std::vector<int32_t> d1(static_cast<size_t>(ncoarse) * nchan), dsub(static_cast<size_t>(ncoarse) * csub);
   for (int32_t s = 0; s < nsub && st == ARTS_OK; ++s) {
-    arts_plan_s* q = nullptr;
-    st = plan_create(csub, f_lo + static_cast<double>(s) * csub * df, df, tsamp, coarse.data(),
-                     ncoarse, kOne, 1, 1, &q);
-    if (st == ARTS_OK) {
-      p->sb1.push_back(q);
-      p->max_d1 = std::max(p->max_d1, q->max_delay);
-      p->tie_margin = std::min(p->tie_margin, q->tie_margin);
-    }
+    double margin = 0;
+    st = compute_delays(csub, f_lo + static_cast<double>(s) * csub * df, df, tsamp,
+                        coarse.data(), ncoarse, 1, dsub.data(), &margin);
+    p->tie_margin = std::min(p->tie_margin, margin);
+    for (int32_t j = 0; j < ncoarse && st == ARTS_OK; ++j)
+      for (int32_t c = 0; c < csub; ++c)
+        d1[static_cast<size_t>(j) * nchan + s * csub + c] = dsub[static_cast<size_t>(j) * csub + c];
+  }
+  // the packed tiling with 24 DMs per block, else whichever fits the delay spread
+  if (st == ARTS_OK) {
+    st = plan_create(nchan, f_lo, df, tsamp, coarse.data(), ncoarse, kOne, 1, 1, &p->sb1, false,
+                     0, 10, d1.data(), csub);
+    if (st != ARTS_OK)
+      st = plan_create(nchan, f_lo, df, tsamp, coarse.data(), ncoarse, kOne, 1, 1, &p->sb1,
+                       false, 0, -1, d1.data(), csub);
   }
   if (st == ARTS_OK) {
+    p->max_d1 = p->sb1->max_delay;
     const double top = df > 0 ? csub - 1 : 0;
     st = plan_create(nsub, f_lo + top * df, csub * df, tsamp, fine.data(), ndm, kOne, 1, 1,
                      &p->sb2, true, 255 * csub, nfine == 32 ? 6 : 7);
@@ -461,16 +479,14 @@ static int plan_create_subband(int32_t nchan, double f_lo, double df, double tsa
   // composite delay of (trial k, channel c): step 1 at k's coarse DM plus step 2 of c's subband
   p->delays.resize(static_cast<size_t>(ndm) * nchan);
   for (int32_t k = 0; k < ndm; ++k)
-    for (int32_t c = 0; c < nchan; ++c) {
-      const int32_t sb = c / csub;
+    for (int32_t c = 0; c < nchan; ++c)
       p->delays[static_cast<size_t>(k) * nchan + c] =
-          p->sb1[sb]->delays[static_cast<size_t>(k / nfine) * csub + c % csub] +
-          p->sb2->delays[static_cast<size_t>(k) * nsub + sb];
-    }
+          d1[static_cast<size_t>(k / nfine) * nchan + c] +
+          p->sb2->delays[static_cast<size_t>(k) * nsub + c / csub];
   p->max_delay = p->max_d1 + p->sb2->max_delay;
   p->wmax = widths[nwidth - 1];
   p->halo = p->max_delay + p->wmax - 1;
-  p->tiling.variant = p->sb1[0]->tiling.variant;
+  p->tiling.variant = p->sb1->tiling.variant;
   if ((st = upload_plan(p)) != ARTS_OK) {
     plan_free(p);
     return st;
@@ -481,14 +497,13 @@ static int plan_create_subband(int32_t nchan, double f_lo, double df, double tsa
 
 int64_t subband_ws_elems(const arts_plan_s* p, int32_t nbeam, int64_t nin) {
   if (p->nsub == 0) return 0;
-  const int64_t L1p = (nin - p->max_d1 + 1) & ~int64_t(1);
+  const int64_t L1p = (nin - p->max_d1 + 3) & ~int64_t(3);
   return static_cast<int64_t>(nbeam) * p->nsub * p->ncoarse * std::max<int64_t>(L1p, 0);
 }
 
 int prepare_plan(arts_plan_s* p, int32_t nbeam, int64_t nin, int g0, bool plan_ws) {
   if (p->nsub == 0) return ensure_tables(p, g0);
-  for (arts_plan_s* q : p->sb1)
-    if (int st = ensure_tables(q, g0)) return st;
+  if (int st = ensure_tables(p->sb1, g0)) return st;
   // step-2 rows start at even element offsets of a 256-byte aligned buffer: class 0
   if (int st = ensure_tables(p->sb2, 0)) return st;
   if (!plan_ws) return ARTS_OK;

@@ -79,8 +79,11 @@ struct arts_plan_s {
   // DMs, the step-2 plan over the subbands at the fine DMs, and the 16-bit intermediate
   // [nbeam][nsub][ncoarse][pitch] the two share
   int32_t nsub = 0, nfine = 0, ncoarse = 0, max_d1 = 0;
-  std::vector<arts_plan_s*> sb1;
+  arts_plan_s* sb1 = nullptr;  // step 1: all channels, coarse DMs, outputs split per subband
   arts_plan_s* sb2 = nullptr;
+  // channels per output group (step-1 plans: the subband width; 0: one group).  The kernel
+  // writes each group's sums to its own output rows and starts the next group from zero.
+  int32_t split = 0;
   uint16_t* d_y = nullptr;
   int64_t y_cap = 0;  // elements
   bool is16() const { return ds > 1 || in16; }
@@ -124,6 +127,7 @@ struct DedispJob {
   int32_t tbl_stride = 0;          // sb_table entries between beams (default nchan)
   int64_t out_pitch = 0;           // out elements between DM rows (default nout)
   int64_t out_bstride = 0;         // out elements between beams (default ndm * out_pitch)
+  int64_t out_sstride = 0;         // out elements between channel groups (plans with a split)
   bool out16 = false;              // store the sums as uint16 (the caller bounds them)
   int64_t in16_blk = 0;            // in16 elements added per DM block
   // subband plans: the caller's 16-bit intermediate (streams own one; null: the plan's)

@@ -93,7 +93,8 @@ struct DedispArgs {
   int32_t src_stride;       // rows between source beams (nchan unless the job says otherwise)
   int32_t tbl_stride;       // SB table entries between beams
   int32_t out16;
-  int32_t pad_;
+  int32_t split;            // channels per output group (0: one group); a multiple of cc
+  int64_t out_sstride;      // out elements between channel groups
 };
 
 // Source beam of channel c of beam b: b itself, or the SB table entry (read from the LDS copy
@@ -516,9 +517,93 @@ __device__ __forceinline__ void stage_lists(const DedispArgs& a, const int32_t* 
   }
 }
 
+// Store a lane's sums of ACC DM trials (rows dwave0 + x) for outputs t0 + lane*T + i < nout;
+// off: output elements added (the channel group of split plans).
+// A lane's N consecutive int32 sums to p, where p is M dwords past a 16-byte boundary (VW = 4)
+// or M dwords past an 8-byte boundary (VW = 2): scalar stores up to the boundary, then vector
+// stores, then the remainder.
+template <int N, int VW, int M>
+__device__ __forceinline__ void store_run(int32_t* p, const uint32_t* v) {
+  constexpr int head = (VW - M) % VW;
+  constexpr int nvec = (N - head) / VW;
+#pragma unroll
+  for (int i = 0; i < head; ++i) p[i] = static_cast<int32_t>(v[i]);
+#pragma unroll
+  for (int k = 0; k < nvec; ++k) {
+    const int i = head + VW * k;
+    if constexpr (VW == 4)
+      *reinterpret_cast<uint4*>(p + i) = make_uint4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+    else
+      *reinterpret_cast<uint2*>(p + i) = make_uint2(v[i], v[i + 1]);
+  }
+#pragma unroll
+  for (int i = head + VW * nvec; i < N; ++i) p[i] = static_cast<int32_t>(v[i]);
+}
+
+// OUT16: the sums are stored as uint16 (split plans, whose groups are bounded to 16 bits).
+template <int T, int ACC, bool OUT16>
+__device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (*acc)[T],
+                                           int64_t off, int b, int dwave0, int64_t t0,
+                                           int lane) {
+#pragma unroll
+  for (int x = 0; x < ACC; ++x) {
+    const int d = dwave0 + x;
+    if (d < a.ndm) {
+      const int64_t row = off + static_cast<int64_t>(b) * a.out_bstride + d * a.out_pitch;
+      if constexpr (OUT16) {
+        // rows start 8-byte aligned (pitch a multiple of 4 samples) and a lane's T = 4 J
+        // samples start at a multiple of 4: whole lanes store 16-bit pairs 8 bytes at a time
+        static_assert(T % 4 == 0, "16-bit group stores need T % 4 == 0");
+        uint16_t* o = reinterpret_cast<uint16_t*>(a.out) + row;
+        const int64_t tl = t0 + static_cast<int64_t>(lane) * T;
+        if (tl + T <= a.nout) {
+          uint2* q = reinterpret_cast<uint2*>(o + tl);
+#pragma unroll
+          for (int k = 0; k < T / 4; ++k)
+            q[k] = make_uint2((acc[x][4 * k] & 0xFFFFu) | (acc[x][4 * k + 1] << 16),
+                              (acc[x][4 * k + 2] & 0xFFFFu) | (acc[x][4 * k + 3] << 16));
+        } else {
+#pragma unroll
+          for (int i = 0; i < T; ++i)
+            if (tl + i < a.nout) o[tl + i] = static_cast<uint16_t>(acc[x][i]);
+        }
+      } else {
+        // lanes are T dwords apart, a multiple of 16 bytes for T % 4 == 0 (8 bytes for even
+        // T): the alignment of a lane's run is that of the row's tile start, uniform
+        int32_t* o = a.out + row;
+        const int64_t tl = t0 + static_cast<int64_t>(lane) * T;
+        int32_t* p = o + tl;
+        const int mis = static_cast<int>((reinterpret_cast<uintptr_t>(p) >> 2) & 3);
+        if (tl + T <= a.nout) {
+          if constexpr (T % 4 == 0) {
+            switch (mis) {
+              case 0: store_run<T, 4, 0>(p, acc[x]); break;
+              case 1: store_run<T, 4, 1>(p, acc[x]); break;
+              case 2: store_run<T, 4, 2>(p, acc[x]); break;
+              default: store_run<T, 4, 3>(p, acc[x]); break;
+            }
+          } else if constexpr (T % 2 == 0) {
+            if (mis & 1)
+              store_run<T, 2, 1>(p, acc[x]);
+            else
+              store_run<T, 2, 0>(p, acc[x]);
+          } else {
+#pragma unroll
+            for (int i = 0; i < T; ++i) p[i] = static_cast<int32_t>(acc[x][i]);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < T; ++i)
+            if (tl + i < a.nout) p[i] = static_cast<int32_t>(acc[x][i]);
+        }
+      }
+    }
+  }
+}
+
 // One tile: DM block blk, time tile tt, beam b.  Used by the one-launch-per-job kernel and by
 // the persistent batch kernel; ends after its global stores with no LDS access pending.
-template <int SPD, int J, int ACC, int WAVES, int PK>
+template <int SPD, int J, int ACC, int WAVES, int PK, bool SPLIT = false>
 __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, int tt, int b,
                                                 uint32_t* lds) {
   constexpr int T = SPD * J;
@@ -573,6 +658,18 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   for (int ch = 0; ch < a.nchunk; ++ch) {
     uint32_t* cur = lds + (ch & 1) * buf_words;
     const int c0 = ch * a.cc;
+    // ---- split plans: the previous chunk ended a channel group: store its sums now, so that
+    // the stores have this chunk's work to complete before the wait at its end
+    if constexpr (SPLIT) {
+      if (ch > 0 && (c0 % a.split) == 0 && wave_active) {
+        store_tile<T, ACC, true>(a, acc, (c0 / a.split - 1) * a.out_sstride, b, dwave0, t0,
+                                 lane);
+#pragma unroll
+        for (int x = 0; x < ACC; ++x)
+#pragma unroll
+          for (int i = 0; i < T; ++i) acc[x][i] = 0;
+      }
+    }
     // ---- start fetching the next chunk into the other buffer
     if (ch + 1 < a.nchunk) {
       uint32_t* nxt = lds + ((ch + 1) & 1) * buf_words;
@@ -650,7 +747,12 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
-  if (wave_active) {
+  if constexpr (SPLIT) {  // the last channel group
+    if (wave_active)
+      store_tile<T, ACC, true>(a, acc, (a.nchan / a.split - 1) * a.out_sstride, b, dwave0, t0,
+                               lane);
+  }
+  if (wave_active && !SPLIT) {
     if constexpr (PK == 2) {
 #pragma unroll
       for (int x = 0; x < ACC; ++x) {
@@ -660,44 +762,37 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
         flush_fr<J, 3>(acc[x], fa[x][3], fo[x][3]);
       }
     }
-#pragma unroll
-    for (int x = 0; x < ACC; ++x) {
-      const int d = dwave0 + x;
-      if (d < a.ndm) {
-        const int64_t row = static_cast<int64_t>(b) * a.out_bstride + d * a.out_pitch;
-        if (a.out16) {
-          uint16_t* o = reinterpret_cast<uint16_t*>(a.out) + row;
-#pragma unroll
-          for (int i = 0; i < T; ++i) {
-            const int64_t t = t0 + static_cast<int64_t>(lane) * T + i;
-            if (t < a.nout) o[t] = static_cast<uint16_t>(acc[x][i]);
-          }
-        } else {
-          int32_t* o = a.out + row;
-#pragma unroll
-          for (int i = 0; i < T; ++i) {
-            const int64_t t = t0 + static_cast<int64_t>(lane) * T + i;
-            if (t < a.nout) o[t] = static_cast<int32_t>(acc[x][i]);
-          }
-        }
-      }
-    }
+    store_tile<T, ACC, false>(a, acc, 0, b, dwave0, t0, lane);
   }
 }
 
 // One launch per job: workgroup -> tile, renumbered so that each of the 8 XCDs (to which
 // workgroups are dealt round-robin) runs a contiguous range of (beam, time tile, DM block):
 // neighbouring DM blocks read overlapping input windows and then share that XCD's L2.
-template <int SPD, int J, int ACC, int WAVES, int PK>
-__global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
-  extern __shared__ uint32_t lds[];
+template <int SPD, int J, int ACC, int WAVES, int PK, bool SPLIT>
+__device__ __forceinline__ void dedisperse_grid(const DedispArgs& a, uint32_t* lds) {
   const int64_t bid = blockIdx.x;
   const int64_t q8 = a.nwg >> 3, r8 = a.nwg & 7, xcd = bid & 7, pos = bid >> 3;
   const int64_t lin = xcd < r8 ? xcd * (q8 + 1) + pos : r8 * (q8 + 1) + (xcd - r8) * q8 + pos;
   const int blk = static_cast<int>(lin % a.nblk);
   const int64_t rest = lin / a.nblk;
-  dedisperse_tile<SPD, J, ACC, WAVES, PK>(a, blk, static_cast<int>(rest % a.ntt),
-                                          static_cast<int>(rest / a.ntt), lds);
+  dedisperse_tile<SPD, J, ACC, WAVES, PK, SPLIT>(a, blk, static_cast<int>(rest % a.ntt),
+                                                 static_cast<int>(rest / a.ntt), lds);
+}
+
+template <int SPD, int J, int ACC, int WAVES, int PK, bool SPLIT>
+__global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  dedisperse_grid<SPD, J, ACC, WAVES, PK, SPLIT>(a, lds);
+}
+
+// Split plans (the first subband step): the group stores add live registers; four waves per
+// SIMD keep two 8-wave workgroups on a CU.
+template <int SPD, int J, int ACC, int WAVES, int PK>
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
+void dedisperse_split_kernel(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  dedisperse_grid<SPD, J, ACC, WAVES, PK, true>(a, lds);
 }
 
 // Persistent batch kernel: a grid sized to the machine pulls tiles of several jobs from work
@@ -775,22 +870,37 @@ static int allow_full_lds(K kernel, int static_bytes = 0) {
 // static LDS of the persistent kernel (the work-queue slot), rounded to its allocation unit
 constexpr int kBatchStaticLds = 512;
 
+template <typename K>
+static int launch_kernel(K kernel, int waves, const DedispArgs& a, size_t lds, hipStream_t s,
+                         bool& attr_set) {
+  if (!attr_set) {
+    if (int st = allow_full_lds(kernel)) return st;
+    attr_set = true;
+  }
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(a.nwg)), dim3(waves * 64), lds, s, a);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+// Plans with channel groups (the first step of subband plans) run an instance that stores each
+// group's sums; it exists for the byte-sample variants that are not framed.
 template <int SPD, int J, int ACC, int WAVES, int PK>
 static int launch_variant(DedispArgs a, hipStream_t s) {
   const size_t lds = lds_bytes(a);
   if (lds > 160 * 1024) return fail(ARTS_E_INVAL, "LDS request %zu B exceeds 160 KiB", lds);
   a.nwg = static_cast<int64_t>(a.nbeam) * a.ntt * a.nblk;
   if (a.nwg > INT_MAX) return fail(ARTS_E_INVAL, "grid too large (%lld blocks)", (long long)a.nwg);
-  static bool attr_set = false;  // one flag per template instance
-  if (!attr_set) {
-    if (int st = allow_full_lds(&dedisperse_kernel<SPD, J, ACC, WAVES, PK>)) return st;
-    attr_set = true;
+  static bool attr_plain = false, attr_split = false;  // one pair per template instance
+  if (a.split > 0) {
+    if constexpr (SPD == 4 && PK != 2)
+      return launch_kernel(&dedisperse_split_kernel<SPD, J, ACC, WAVES, PK>, WAVES, a, lds, s,
+                           attr_split);
+    else
+      return fail(ARTS_E_INVAL, "this tiling variant cannot split channel groups");
   }
-  (void)hipGetLastError();
-  hipLaunchKernelGGL((dedisperse_kernel<SPD, J, ACC, WAVES, PK>), dim3(static_cast<unsigned>(a.nwg)),
-                     dim3(WAVES * 64), lds, s, a);
-  ARTS_HIP(hipGetLastError());
-  return ARTS_OK;
+  return launch_kernel(&dedisperse_kernel<SPD, J, ACC, WAVES, PK, false>, WAVES, a, lds, s,
+                       attr_plain);
 }
 
 template <int SPD, int J, int ACC, int WAVES, int PK>
@@ -853,6 +963,10 @@ static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
   a.out_bstride = job.out_bstride > 0 ? job.out_bstride : p->ndm * a.out_pitch;
   a.out16 = job.out16 ? 1 : 0;
   a.in16_blk = job.in16_blk;
+  a.split = p->split;
+  a.out_sstride = job.out_sstride;
+  if ((p->split > 0) != job.out16)
+    return fail(ARTS_E_INVAL, "internal: 16-bit output goes with channel groups");
   a.src_stride = job.src_stride > 0 ? job.src_stride : p->nchan;
   a.tbl_stride = job.tbl_stride > 0 ? job.tbl_stride : p->nchan;
   a.nchan = p->nchan;
@@ -871,36 +985,28 @@ static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
   return ARTS_OK;
 }
 
-// Two-step subband dedispersion.  Step 1: one launch per subband, its step plan summing the
-// subband's channels (rows src_stride = nchan apart in the caller's input, SB table entries
-// likewise) at the coarse DMs into 16-bit rows Y[b][s][j][t], t < L1 = nin - max step-1 delay.
-// Step 2: the step-2 plan sums the subbands at the fine DMs; its DM blocks are the coarse
-// groups (m_blk = nfine), so block j reads rows Y[b][.][j] (in16_blk = one row pitch).
+// Two-step subband dedispersion.  Step 1: one launch of the step-1 plan (all channels at the
+// coarse DMs, each channel's delay relative to its subband's reference) whose sums are split
+// per subband into 16-bit rows Y[b][s][j][t], t < L1 = nin - max step-1 delay.  Step 2: the
+// step-2 plan sums the subbands at the fine DMs; its DM blocks are the coarse groups
+// (m_blk = nfine), so block j reads rows Y[b][.][j] (in16_blk = one row pitch).
 static int launch_subband(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
-  const int32_t csub = p->nchan / p->nsub;
   const int64_t L1 = job.nin - p->max_d1;
-  const int64_t L1p = (L1 + 1) & ~int64_t(1);
+  const int64_t L1p = (L1 + 3) & ~int64_t(3);  // 8-byte aligned rows for the group stores
   const int64_t need = subband_ws_elems(p, job.nbeam, job.nin);
   if (L1 < 1 || job.nout > L1 - p->sb2->max_delay)
     return fail(ARTS_E_INVAL, "internal: subband job shorter than its delays");
   uint16_t* y = job.y ? job.y : p->d_y;
   if (need > (job.y ? job.y_elems : p->y_cap))
     return fail(ARTS_E_INVAL, "internal: subband workspace not prepared");
-  for (int32_t sb = 0; sb < p->nsub; ++sb) {
-    DedispJob j1 = job;
-    const int64_t off = static_cast<int64_t>(sb) * csub * job.pitch;
-    j1.in = job.in + off;
-    j1.in_bytes = job.in_bytes - off;
-    j1.src_stride = p->nchan;
-    j1.sb_table = job.sb_table ? job.sb_table + static_cast<int64_t>(sb) * csub : nullptr;
-    j1.tbl_stride = p->nchan;
-    j1.out = reinterpret_cast<int32_t*>(y + static_cast<int64_t>(sb) * p->ncoarse * L1p);
-    j1.out16 = true;
-    j1.out_pitch = L1p;
-    j1.out_bstride = static_cast<int64_t>(p->nsub) * p->ncoarse * L1p;
-    j1.nout = L1;
-    if (int st = launch_dedisperse(p->sb1[sb], j1, s)) return st;
-  }
+  DedispJob j1 = job;
+  j1.out = reinterpret_cast<int32_t*>(y);
+  j1.out16 = true;
+  j1.out_pitch = L1p;
+  j1.out_sstride = static_cast<int64_t>(p->ncoarse) * L1p;
+  j1.out_bstride = static_cast<int64_t>(p->nsub) * p->ncoarse * L1p;
+  j1.nout = L1;
+  if (int st = launch_dedisperse(p->sb1, j1, s)) return st;
   DedispJob j2;
   j2.in16 = y;
   j2.in16_elems = need;
