@@ -495,18 +495,30 @@ static int plan_create_subband(int32_t nchan, double f_lo, double df, double tsa
   return ARTS_OK;
 }
 
+int64_t subband_pitch(const arts_plan_s* p, int64_t nin, int32_t pad) {
+  return (nin - p->max_d1 + pad + 3) & ~int64_t(3);
+}
+
+// Elements for any front pad 0..3.
 int64_t subband_ws_elems(const arts_plan_s* p, int32_t nbeam, int64_t nin) {
   if (p->nsub == 0) return 0;
-  const int64_t L1p = (nin - p->max_d1 + 3) & ~int64_t(3);
-  return static_cast<int64_t>(nbeam) * p->nsub * p->ncoarse * std::max<int64_t>(L1p, 0);
+  return static_cast<int64_t>(nbeam) * p->nsub * p->ncoarse *
+         std::max<int64_t>(subband_pitch(p, nin, 3), 0);
 }
 
 int prepare_plan(arts_plan_s* p, int32_t nbeam, int64_t nin, int g0, bool plan_ws) {
   if (p->nsub == 0) return ensure_tables(p, g0);
-  if (int st = ensure_tables(p->sb1, g0)) return st;
-  // step-2 rows start at even element offsets of a 256-byte aligned buffer: class 0
-  if (int st = ensure_tables(p->sb2, 0)) return st;
-  if (!plan_ws) return ARTS_OK;
+  if (plan_ws) {
+    if (int st = ensure_tables(p->sb1, g0)) return st;
+    // one-shot rows start at even element offsets of a 256-byte aligned buffer: class 0
+    if (int st = ensure_tables(p->sb2, 0)) return st;
+  } else {  // streams: step 1 also reads shifted windows, step 2 rows after a pad
+    for (int g = 0; g < 4; ++g)
+      if (int st = ensure_tables(p->sb1, g)) return st;
+    for (int g = 0; g < 2; ++g)
+      if (int st = ensure_tables(p->sb2, g)) return st;
+    return ARTS_OK;
+  }
   const int64_t need = subband_ws_elems(p, nbeam, nin);
   if (need <= p->y_cap) return ARTS_OK;
   if (p->d_y) (void)hipFree(p->d_y);

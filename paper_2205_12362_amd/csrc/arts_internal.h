@@ -130,14 +130,23 @@ struct DedispJob {
   int64_t out_sstride = 0;         // out elements between channel groups (plans with a split)
   bool out16 = false;              // store the sums as uint16 (the caller bounds them)
   int64_t in16_blk = 0;            // in16 elements added per DM block
-  // subband plans: the caller's 16-bit intermediate (streams own one; null: the plan's)
+  // subband plans: the caller's 16-bit intermediate (streams own one; null: the plan's).  With
+  // y_prev (the previous chunk's rows, same layout) only the last y_new step-1 samples are
+  // computed and the rest is taken from y_prev shifted by y_new.  Rows start y_pad elements
+  // into their pitch (chosen so that the new samples start 8-byte aligned).
   uint16_t* y = nullptr;
+  const uint16_t* y_prev = nullptr;
   int64_t y_elems = 0;
+  int64_t y_new = 0;
+  int32_t y_pad = 0;
 };
 
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s);
 // Subband plans: elements of the 16-bit intermediate for nbeam beams of nin samples.
 int64_t subband_ws_elems(const arts_plan_s* p, int32_t nbeam, int64_t nin);
+// Row pitch of a subband plan's step-1 rows: L1 = nin - max step-1 delay samples after a front
+// pad of `pad` elements, rounded to 4 (8-byte aligned rows).
+int64_t subband_pitch(const arts_plan_s* p, int64_t nin, int32_t pad);
 // Subband plans: the step plans' offset tables for input alignment class g0 and, if
 // plan_ws, the plan's own intermediate for nbeam x nin, so that a later launch allocates
 // nothing.  Other plans: their tables for g0.
@@ -194,8 +203,10 @@ struct arts_stream_s {
   std::vector<int64_t> N16;                // per plan: 16-bit samples held per row
   std::vector<int32_t*> series;
   std::vector<int64_t> L, H;
-  std::vector<uint16_t*> y;                // per plan: subband intermediate (subband plans)
+  std::vector<uint16_t*> y[2];             // per plan: step-1 rows of subband plans (parity)
   std::vector<int64_t> y_elems;
+  std::vector<int32_t> y_pad;
+  bool y_stale = false;                    // after a restore: the next push recomputes step 1
   arts_candidate* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
   unsigned long long* h_count = nullptr;  // pinned

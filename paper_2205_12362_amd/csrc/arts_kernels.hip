@@ -489,6 +489,11 @@ __device__ __forceinline__ void stage_windows(const DedispArgs& a, const uint8_t
     const uint32_t* P = reinterpret_cast<const uint32_t*>(
         reinterpret_cast<uintptr_t>(first) & ~static_cast<uintptr_t>(3));
     const uint8_t* pb = reinterpret_cast<const uint8_t*>(P);
+    // the dwords that hold at least one byte of the buffer (a buffer need not start or end on
+    // a dword boundary; such a dword lies in the same page as its valid bytes, and the plan's
+    // offsets never use the bytes outside the buffer as samples of a stored output)
+    lo = reinterpret_cast<const uint8_t*>(reinterpret_cast<uintptr_t>(lo) & ~uintptr_t(3));
+    hi = reinterpret_cast<const uint8_t*>((reinterpret_cast<uintptr_t>(hi) + 3) & ~uintptr_t(3));
     if (first && pb >= lo && pb + 4 * static_cast<int64_t>(a.win) <= hi) {
       for (int k4 = 4 * lane; k4 < a.win; k4 += 256)  // 16 bytes per lane, 1 KiB per wave
         __builtin_amdgcn_global_load_lds((global_ptr_t)(P + k4),
@@ -551,12 +556,13 @@ __device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (
     if (d < a.ndm) {
       const int64_t row = off + static_cast<int64_t>(b) * a.out_bstride + d * a.out_pitch;
       if constexpr (OUT16) {
-        // rows start 8-byte aligned (pitch a multiple of 4 samples) and a lane's T = 4 J
-        // samples start at a multiple of 4: whole lanes store 16-bit pairs 8 bytes at a time
+        // rows are 8-byte aligned (pitch a multiple of 4 samples) and a lane's T = 4 J samples
+        // start at a multiple of 4: whole lanes store 16-bit pairs 8 bytes at a time when the
+        // output starts 8-byte aligned (always, except a stream's full recomputation)
         static_assert(T % 4 == 0, "16-bit group stores need T % 4 == 0");
         uint16_t* o = reinterpret_cast<uint16_t*>(a.out) + row;
         const int64_t tl = t0 + static_cast<int64_t>(lane) * T;
-        if (tl + T <= a.nout) {
+        if (tl + T <= a.nout && (reinterpret_cast<uintptr_t>(o + tl) & 7u) == 0) {
           uint2* q = reinterpret_cast<uint2*>(o + tl);
 #pragma unroll
           for (int k = 0; k < T / 4; ++k)
@@ -992,24 +998,41 @@ static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
 // (m_blk = nfine), so block j reads rows Y[b][.][j] (in16_blk = one row pitch).
 static int launch_subband(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   const int64_t L1 = job.nin - p->max_d1;
-  const int64_t L1p = (L1 + 3) & ~int64_t(3);  // 8-byte aligned rows for the group stores
-  const int64_t need = subband_ws_elems(p, job.nbeam, job.nin);
-  if (L1 < 1 || job.nout > L1 - p->sb2->max_delay)
+  const int32_t pad = job.y ? job.y_pad : 0;
+  const int64_t L1p = subband_pitch(p, job.nin, pad);
+  const int64_t rows = static_cast<int64_t>(job.nbeam) * p->nsub * p->ncoarse;
+  const int64_t need = rows * L1p;
+  if (L1 < 1 || job.nout > L1 - p->sb2->max_delay || pad < 0 || pad > 3)
     return fail(ARTS_E_INVAL, "internal: subband job shorter than its delays");
   uint16_t* y = job.y ? job.y : p->d_y;
   if (need > (job.y ? job.y_elems : p->y_cap))
     return fail(ARTS_E_INVAL, "internal: subband workspace not prepared");
   DedispJob j1 = job;
-  j1.out = reinterpret_cast<int32_t*>(y);
+  j1.out = reinterpret_cast<int32_t*>(y + pad);
+  j1.nout = L1;
+  if (job.y && job.y_prev && job.y_new > 0 && job.y_new < L1) {
+    // rows [0, L1 - new) are the previous chunk's rows [new, L1); step 1 computes the rest
+    // from the last new + max_d1 input samples of the window
+    const int64_t keep = L1 - job.y_new;
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(job.y_prev + pad + job.y_new);
+    const uint8_t* prev = reinterpret_cast<const uint8_t*>(job.y_prev);
+    if (int st = launch_copy_rows(reinterpret_cast<uint8_t*>(y + pad), 2 * L1p, src, 2 * L1p,
+                                  rows, 2 * keep, prev, prev + 2 * need, s))
+      return st;
+    j1.in = job.in + keep;
+    j1.in_bytes = job.in_bytes - keep;
+    j1.nin = job.y_new + p->max_d1;
+    j1.out = reinterpret_cast<int32_t*>(y + pad + keep);
+    j1.nout = job.y_new;
+  }
   j1.out16 = true;
   j1.out_pitch = L1p;
   j1.out_sstride = static_cast<int64_t>(p->ncoarse) * L1p;
   j1.out_bstride = static_cast<int64_t>(p->nsub) * p->ncoarse * L1p;
-  j1.nout = L1;
   if (int st = launch_dedisperse(p->sb1, j1, s)) return st;
   DedispJob j2;
-  j2.in16 = y;
-  j2.in16_elems = need;
+  j2.in16 = y + pad;
+  j2.in16_elems = need - pad;
   j2.pitch16 = static_cast<int64_t>(p->ncoarse) * L1p;
   j2.in16_blk = L1p;
   j2.nin = L1;

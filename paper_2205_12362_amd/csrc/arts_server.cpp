@@ -130,6 +130,7 @@ int arts_server_tick(arts_server_t v, int32_t* nrun) {
     if (int st = stream_candidates(s, v->hs)) return st;
     ARTS_HIP(hipEventRecord(s->ev_done, v->hs));
     ++s->pushed;
+    s->y_stale = false;
     e->ready = false;
   }
   return ARTS_OK;

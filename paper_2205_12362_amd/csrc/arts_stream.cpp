@@ -37,6 +37,9 @@ void stream_free(arts_stream_s* s) {
   if (s->input) (void)hipFree(s->input);
   for (auto* p : s->series)
     if (p) (void)hipFree(p);
+  for (auto& v : s->y)
+    for (auto* y : v)
+      if (y) (void)hipFree(y);
   if (s->d_cand) (void)hipFree(s->d_cand);
   if (s->d_count) (void)hipFree(s->d_count);
   if (s->h_count) (void)hipHostFree(s->h_count);
@@ -115,8 +118,8 @@ int64_t stream_bytes_needed(const arts_plan_t* plans, int32_t nplan, int32_t nsr
     }
   }
   if (native) total += 2 * rows * ((hmax + chunk + 3) & ~int64_t(3));
-  for (int32_t i = 0; i < nplan; ++i)
-    total += 2 * subband_ws_elems(plans[i], nbeam, static_cast<int64_t>(plans[i]->halo) + chunk);
+  for (int32_t i = 0; i < nplan; ++i)  // two parities of 16-bit step-1 rows
+    total += 4 * subband_ws_elems(plans[i], nbeam, static_cast<int64_t>(plans[i]->halo) + chunk);
   return total;
 }
 
@@ -135,8 +138,11 @@ DedispJob stream_job(arts_stream_s* s, int parity, size_t p) {
     job.in_bytes = rows * s->W - off;
     job.nin = s->H[p] + s->chunk;
     job.pitch = s->W;
-    job.y = s->y[p];
+    job.y = s->y[parity][p];
+    job.y_prev = s->y_stale ? nullptr : s->y[parity ^ 1][p];
     job.y_elems = s->y_elems[p];
+    job.y_new = s->chunk;
+    job.y_pad = s->y_pad[p];
   } else {
     job.in = s->input;  // unused: the kernel reads the 16-bit ring
     job.in_bytes = rows * s->chunk;
@@ -303,12 +309,23 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
                        : static_cast<int>((reinterpret_cast<uintptr_t>(s->ring16[0][p]) >> 1) & 1u);
     st = prepare_plan(s->plans[p], nbeam, s->H[p] + chunk, g0, false);
   }
+  // subband plans: step-1 rows for both parities, zero like the history they stand for; the
+  // front pad puts each chunk's new rows 8-byte aligned
   for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
-    uint16_t* y = nullptr;
-    const int64_t e = subband_ws_elems(s->plans[p], nbeam, s->H[p] + chunk);
-    if (e > 0) st = dev_alloc(s, reinterpret_cast<void**>(&y), e * sizeof(uint16_t));
-    s->y.push_back(y);
+    const arts_plan_s* pl = s->plans[p];
+    const int64_t e = subband_ws_elems(pl, nbeam, s->H[p] + chunk);
+    const int64_t keep = s->H[p] - pl->max_d1;  // L1 - chunk
     s->y_elems.push_back(e);
+    s->y_pad.push_back(pl->nsub > 0 ? static_cast<int32_t>((4 - keep % 4) % 4) : 0);
+    for (int r = 0; r < 2; ++r) {
+      uint16_t* y = nullptr;
+      if (e > 0 && st == ARTS_OK) {
+        st = dev_alloc(s, reinterpret_cast<void**>(&y), e * sizeof(uint16_t));
+        if (st == ARTS_OK && hipMemset(y, 0, e * sizeof(uint16_t)) != hipSuccess)
+          st = fail(ARTS_E_DEVICE, "subband row clear failed");
+      }
+      s->y[r].push_back(y);
+    }
   }
   for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
     int32_t* ser = nullptr;
@@ -360,7 +377,7 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
   const int parity = static_cast<int>(s->pushed & 1);
   // warm-up chunks search a chunk-dependent part of each series: they run eagerly, and the
   // graphs are captured once every plan searches its whole chunk
-  if ((s->flags & kGraph) && stream_warm(s, s->pushed)) {
+  if ((s->flags & kGraph) && stream_warm(s, s->pushed) && !s->y_stale) {
     if (!s->gexec[parity]) {
       hipGraph_t g = nullptr;
       ARTS_HIP(hipStreamBeginCapture(s->hs, hipStreamCaptureModeThreadLocal));
@@ -383,6 +400,7 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
   }
   ARTS_HIP(hipEventRecord(s->ev_done, s->hs));
   ++s->pushed;
+  s->y_stale = false;
   return ARTS_OK;
 }
 
@@ -488,6 +506,7 @@ int arts_stream_restore(arts_stream_t s, const uint8_t* host, int64_t bytes,
     off += pr.second;
   }
   s->pushed = s->waited = chunks_pushed;
+  s->y_stale = true;  // subband step-1 rows are not part of a snapshot: recompute them once
   return ARTS_OK;
 }
 

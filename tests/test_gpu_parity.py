@@ -342,3 +342,26 @@ def test_candidates_apertif_rows():
     sel = got[np.isin(got["dm_index"], rows)]
     compare_candidates(sel, ora, near)
     assert len(ora) > 0
+
+
+@pytest.mark.parametrize("off", [1, 2, 3])
+def test_dedisperse_misaligned_buffer(off):
+    # an input whose start and end are not dword-aligned: the dwords holding its first and last
+    # samples must be read (DM 0 puts the first samples of channel 0 into output 0, and with
+    # DM 0 alone the last samples of the last row into the last output)
+    import torch
+    f_lo, df = synth.band(64)
+    for dms in (np.arange(0.0, 40.0), np.array([0.0])):
+        w = synth.Workload("mis", 64, f_lo, df, synth.TSAMP, dms, [1])
+        delays = O.delay_table(64, f_lo, df, synth.TSAMP, dms)
+        nin = int(delays.max()) + 1200
+        nin += (-nin) % 4                                  # row pitch stays a multiple of 4
+        data = np.random.default_rng(off).integers(0, 256, (2, 64, nin), dtype=np.uint8)
+        buf = torch.zeros(data.size + 8, dtype=torch.uint8, device="cuda")
+        view = buf[off: off + data.size].view(2, 64, nin)
+        view.copy_(torch.from_numpy(data))
+        assert view.data_ptr() % 4 == off
+        with _plan(w) as p:
+            got = p.dedisperse(view).cpu().numpy()
+        for b in range(2):
+            assert np.array_equal(got[b], O.dedisperse(data[b], delays)), (off, dms.size, b)

@@ -157,3 +157,28 @@ def test_stream_rejects_bad_arguments():
             st.push(to_dev(np.zeros((3, NCHAN, CHUNK), np.uint8)))  # previous not collected
         assert e.value.status == arts.ARTS_E_STATE
         st.wait()
+
+
+def test_stream_two_native_plans_unaligned_offset():
+    # native plans with different halos read the shared ring from different offsets; an offset
+    # that is not a multiple of 4 starts the smaller plan's window inside a dword
+    f_lo, df = synth.band(NCHAN)
+    wa = synth.Workload("a", NCHAN, f_lo, df, synth.TSAMP, np.arange(0.0, 90.0), [1, 2])
+    wb = synth.Workload("b", NCHAN, f_lo, df, synth.TSAMP, np.arange(0.0, 300.0, 3.0), [1, 2, 4])
+    pa, pb = arts.Plan.from_workload(wa), arts.Plan.from_workload(wb)
+    assert (pb.halo - pa.halo) % 4 != 0
+    da = O.delay_table(NCHAN, f_lo, df, synth.TSAMP, wa.dms)
+    db = O.delay_table(NCHAN, f_lo, df, synth.TSAMP, wb.dms)
+    H = [pa.halo, pb.halo]
+    hmax = max(H)
+    chunks = _chunks(2, 4, seed=140)
+    full = np.concatenate([np.zeros((2, NCHAN, hmax), np.uint8)] + chunks, axis=2)
+    with arts.Stream([pa, pb], 2, CHUNK, 6.0) as st:
+        for k, c in enumerate(chunks):
+            st.push(to_dev(c))
+            st.wait()
+            for p, d in enumerate((da, db)):
+                got = st.series(p).cpu().numpy()
+                for b in range(2):
+                    win = full[b][:, hmax - H[p] + k * CHUNK: hmax + (k + 1) * CHUNK]
+                    assert np.array_equal(got[b], O.dedisperse(win, d)), (k, p, b)

@@ -134,3 +134,58 @@ def test_subband_alert_plan_full_size():
     ref = O.subband_dedisperse(data[0], d1, d2, 32)
     assert got.shape == ref.shape
     assert np.array_equal(got, ref)
+
+
+def _sub_stream_setup(chunk, ndm=64, dm_step=5.0):
+    nchan, nsub = 64, 8
+    f_lo, df = synth.band(nchan)
+    p = arts.Plan.subband(nchan, f_lo, df, synth.TSAMP, 0.0, dm_step, ndm, 32, nsub, [1, 2, 4])
+    _, _, d1, d2 = O.subband_plan(nchan, f_lo, df, synth.TSAMP, 0.0, dm_step, ndm, 32, nsub)
+    return nchan, p, d1, d2
+
+
+def test_subband_stream_history_longer_than_chunk():
+    # the step-1 rows carried between chunks span several chunks (halo > 2 chunks)
+    chunk = 1000
+    nchan, p, d1, d2 = _sub_stream_setup(chunk)
+    H = p.halo
+    assert H > 2 * chunk
+    chunks = [synth.noise((1, nchan, chunk), seed=200 + k) for k in range(7)]
+    full = np.concatenate([np.zeros((1, nchan, H), np.uint8)] + chunks, axis=2)
+    with arts.Stream([p], 1, chunk, 6.0) as st:
+        for k, c in enumerate(chunks):
+            st.push(to_dev(c))
+            st.wait()
+            win = full[0][:, k * chunk: H + (k + 1) * chunk]
+            assert np.array_equal(st.series(0).cpu().numpy()[0],
+                                  O.subband_dedisperse(win, d1, d2, 32)), k
+
+
+def test_subband_stream_restore_and_graph():
+    import torch
+    chunk = 1200
+    nchan, p, d1, d2 = _sub_stream_setup(chunk)
+    chunks = [synth.noise((2, nchan, chunk), seed=300 + k) for k in range(8)]
+    ref = []
+    with arts.Stream([p], 2, chunk, 6.0) as st:
+        for k, c in enumerate(chunks):
+            st.push(to_dev(c))
+            st.wait()
+            ref.append(st.series(0).cpu().numpy().copy())
+            if k == 3:
+                snap, n = st.snapshot()
+    # resumed from the snapshot: the step-1 rows are recomputed on the first push
+    with arts.Stream([p], 2, chunk, 6.0) as st2:
+        st2.restore(snap, n)
+        for j, c in enumerate(chunks[4:]):
+            st2.push(to_dev(c))
+            st2.wait()
+            assert np.array_equal(st2.series(0).cpu().numpy(), ref[4 + j]), j
+    # graph replay (graphs from the first warm chunk on), with eager work between replays
+    with arts.Stream([p], 2, chunk, 6.0, graph=True) as st3:
+        for k, c in enumerate(chunks):
+            st3.push(to_dev(c))
+            st3.wait()
+            torch.cuda.synchronize()
+            _ = (torch.ones(1000, device="cuda") * 2).sum().item()
+            assert np.array_equal(st3.series(0).cpu().numpy(), ref[k]), k
