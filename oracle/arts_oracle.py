@@ -13,8 +13,8 @@ design notes of the repository; each is marked "reading".
 Parity status per function:
   channel_freqs, delay_table, tie_audit, downsample, sb_synthesize, dedisperse,
   dedisperse_at, subband_plan, subband_dedisperse, subband_dedisperse_at, boxcar, moments,
-  snr, candidates  -- pinned by closed forms / invariants / hand-worked values in
-  tests/test_oracle_pins.py (no function here is "parity unpinned").
+  snr, candidates, cluster_dm_width  -- pinned by closed forms / invariants / hand-worked
+  values / brute force in tests/test_oracle_pins.py (no function here is "parity unpinned").
 """
 from __future__ import annotations
 
@@ -284,3 +284,83 @@ def search(data: np.ndarray, delays: np.ndarray, widths, threshold: float, beam:
     if nrep is None:
         nrep = x.shape[1] - wmax + 1
     return x, candidates(x, widths, nrep, threshold, beam=beam, t_offset=t_offset)
+
+
+def cluster_dm_width(cands):
+    """AMBER's optional real-time clustering in the DM-width plane (Sect. 6b.2, "Clustering").
+
+    The paper's two steps, in its order: (1) candidates of different widths at the same time and
+    the same DM are grouped and only the highest S/N is kept; (2) groups in neighbouring DM
+    trials are compacted, again keeping the highest S/N; one candidate is reported per
+    resulting DM-width cluster.
+
+    Readings: a candidate (beam, dm_index, width w, sample t, snr) occupies the boxcar window
+    [t, t + w - 1]; "the same time" means overlapping windows, taken transitively, so a step-1
+    group is a maximal chain of overlapping windows in one (beam, DM) row and covers the union of
+    its windows; "neighbouring DM trials" are dm_index and dm_index + 1 of the same beam, and two
+    groups there are compacted when their covered intervals overlap, again transitively.  The
+    reported candidate is the member with the highest S/N, ties to the lowest dm_index, then the
+    earliest sample, then the smallest width.
+
+    cands: sequence of (beam, dm_index, width, sample, snr).  Returns (reps, label): reps is the
+    list of reported candidates sorted by (beam, dm_index, width, sample), label[i] the index in
+    reps of input candidate i's cluster.
+    """
+    n = len(cands)
+    for c in cands:
+        if int(c[2]) < 1:
+            raise ValueError("candidate width must be >= 1")
+    # step 1: per (beam, dm) row, in order of (sample, width); a candidate whose window starts
+    # after everything the current group covers opens a new group
+    rows = {}
+    for i, c in enumerate(cands):
+        rows.setdefault((int(c[0]), int(c[1])), []).append(i)
+    groups = []                      # [beam, dm, first, last, members]
+    for key in sorted(rows):
+        order = sorted(rows[key], key=lambda i: (int(cands[i][3]), int(cands[i][2])))
+        cur = None
+        for i in order:
+            t0 = int(cands[i][3])
+            t1 = t0 + int(cands[i][2]) - 1
+            if cur is None or t0 > cur[3]:
+                cur = [key[0], key[1], t0, t1, []]
+                groups.append(cur)
+            cur[3] = max(cur[3], t1)
+            cur[4].append(i)
+    # step 2: join groups of DM trials d and d + 1 (same beam) whose covered intervals overlap
+    parent = list(range(len(groups)))
+
+    def find(a):
+        while parent[a] != a:
+            a = parent[a]
+        return a
+
+    by_row = {}
+    for g, grp in enumerate(groups):
+        by_row.setdefault((grp[0], grp[1]), []).append(g)
+    for g, grp in enumerate(groups):
+        for h in by_row.get((grp[0], grp[1] + 1), []):
+            other = groups[h]
+            if grp[2] <= other[3] and other[2] <= grp[3]:
+                ra, rb = find(g), find(h)
+                if ra != rb:
+                    parent[max(ra, rb)] = min(ra, rb)
+    # report: the best member of every cluster
+    members = {}
+    for g, grp in enumerate(groups):
+        members.setdefault(find(g), []).extend(grp[4])
+
+    def rank(i):
+        c = cands[i]
+        return (-float(c[4]), int(c[1]), int(c[3]), int(c[2]))
+
+    best = {root: min(m, key=rank) for root, m in members.items()}
+    roots = sorted(best, key=lambda r: (int(cands[best[r]][0]), int(cands[best[r]][1]),
+                                        int(cands[best[r]][2]), int(cands[best[r]][3])))
+    reps = [tuple(cands[best[r]]) for r in roots]
+    index = {r: k for k, r in enumerate(roots)}
+    label = [0] * n
+    for root, m in members.items():
+        for i in m:
+            label[i] = index[root]
+    return reps, label

@@ -176,6 +176,59 @@ def _subband_wrong_group(data, d1, d2, nfine):
     return out
 
 
+def _cluster_variant(kind):
+    # DM-width clustering written out again with one planted change
+    def cluster_dm_width(cands):
+        rows = {}
+        for i, c in enumerate(cands):
+            rows.setdefault((0 if kind == "beam ignored" else c[0], c[1]), []).append(i)
+        groups = []
+        for key in sorted(rows):
+            cur = None
+            for i in sorted(rows[key], key=lambda i: (cands[i][3], cands[i][2])):
+                t0 = cands[i][3]
+                t1 = t0 + cands[i][2] - (0 if kind == "window one longer" else 1)
+                ref = cur and (cur[2] + cands[cur[4][0]][2] - 1 if kind == "first window only"
+                               else cur[3])
+                if cur is None or t0 > ref:
+                    cur = [key[0], key[1], t0, t1, []]
+                    groups.append(cur)
+                cur[3] = max(cur[3], t1)
+                cur[4].append(i)
+        for grp in groups:                    # the kept candidate's own window
+            if kind == "step 2 on kept window":
+                k = min(grp[4], key=lambda i: (-cands[i][4], cands[i][3], cands[i][2]))
+                grp[2], grp[3] = cands[k][3], cands[k][3] + cands[k][2] - 1
+        parent = list(range(len(groups)))
+
+        def find(a):
+            while parent[a] != a:
+                a = parent[a]
+            return a
+        step = 2 if kind == "DM neighbour two apart" else 1
+        for g, a in enumerate(groups):
+            for h, b in enumerate(groups):
+                if b[0] == a[0] and b[1] == a[1] + step and a[2] <= b[3] and b[2] <= a[3]:
+                    ra, rb = find(g), find(h)
+                    parent[max(ra, rb)] = min(ra, rb)
+        members = {}
+        for g, grp in enumerate(groups):
+            members.setdefault(find(g), []).extend(grp[4])
+        sgn = -1 if kind == "ties to highest DM" else 1
+        best = {r: min(m, key=lambda i: (-cands[i][4], sgn * cands[i][1], cands[i][3],
+                                         cands[i][2]))
+                for r, m in members.items()}
+        roots = sorted(best, key=lambda r: tuple(cands[best[r]][:4]))
+        reps = [tuple(cands[best[r]]) for r in roots]
+        idx = {r: k for k, r in enumerate(roots)}
+        label = [0] * len(cands)
+        for r, m in members.items():
+            for i in m:
+                label[i] = idx[r]
+        return reps, label
+    return cluster_dm_width
+
+
 MUTANTS = {
     "reference at lowest channel": dict(delay_table=_delay_variant(ref="min")),
     "floor instead of round": dict(delay_table=_delay_variant(rounding=np.floor)),
@@ -194,6 +247,15 @@ MUTANTS = {
         subband_plan=_subband_plan_variant("lowest reference")),
     "subband step 2 at the coarse DM": dict(subband_plan=_subband_plan_variant("coarse in step 2")),
     "subband coarse group k % ncoarse": dict(subband_dedisperse=_subband_wrong_group),
+    "cluster beams not separated": dict(cluster_dm_width=_cluster_variant("beam ignored")),
+    "cluster window one sample longer": dict(
+        cluster_dm_width=_cluster_variant("window one longer")),
+    "cluster step 1 not transitive": dict(cluster_dm_width=_cluster_variant("first window only")),
+    "cluster step 2 on the kept window": dict(
+        cluster_dm_width=_cluster_variant("step 2 on kept window")),
+    "cluster DM neighbour two apart": dict(
+        cluster_dm_width=_cluster_variant("DM neighbour two apart")),
+    "cluster ties to the highest DM": dict(cluster_dm_width=_cluster_variant("ties to highest DM")),
 }
 
 
@@ -209,6 +271,10 @@ def _run_all(ns):
 
 def test_unmutated_copy_passes():
     assert _run_all(_copy()) == []
+
+
+def test_unmutated_cluster_rewrite_passes():
+    assert _run_all(_copy(cluster_dm_width=_cluster_variant("none"))) == []
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

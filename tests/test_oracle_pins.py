@@ -474,9 +474,127 @@ def test_subband_rejects_bad_args():
         O.subband_plan(12, 1220.0, 1.0, 1e-4, 0.0, 0.0, 8, 4, 3)   # zero DM step
 
 
+# ---------------------------------------------------------------- DM-width clustering
+def check_cluster_golden(o):
+    g = _load("cluster_tiny.json")
+    cands = [tuple(c) for c in g["candidates"]]
+    reps, label = o.cluster_dm_width(cands)
+    assert [tuple(r) for r in reps] == [tuple(r) for r in g["reps"]]
+    parts = {}
+    for i, k in enumerate(label):
+        parts.setdefault(k, []).append(i)
+    assert sorted(parts.values()) == sorted(g["clusters"])
+
+
+def _random_cands(rng, n, nbeam=2, ndm=6, tmax=40, widths=(1, 2, 4, 8)):
+    seen, out = set(), []
+    while len(out) < n:
+        key = (int(rng.integers(nbeam)), int(rng.integers(ndm)), int(rng.choice(widths)),
+               int(rng.integers(tmax)))
+        if key not in seen:
+            seen.add(key)
+            out.append(key + (float(rng.choice([6.0, 6.5, 7.0, 7.5, 9.0])),))
+    return out
+
+
+def _components_brute(cands):
+    # connected components of the graph: same beam, DM indices at most 1 apart, windows
+    # [t, t + w - 1] intersecting (the union of a step-1 group is an interval, so two groups'
+    # extents overlap exactly when two of their windows do)
+    n = len(cands)
+    adj = [[] for _ in range(n)]
+    for i in range(n):
+        bi, di, wi, ti, _ = cands[i]
+        for j in range(i + 1, n):
+            bj, dj, wj, tj, _ = cands[j]
+            if bi == bj and abs(di - dj) <= 1 and ti <= tj + wj - 1 and tj <= ti + wi - 1:
+                adj[i].append(j)
+                adj[j].append(i)
+    comp, out = [-1] * n, []
+    for s in range(n):
+        if comp[s] >= 0:
+            continue
+        comp[s], todo, members = len(out), [s], []
+        while todo:
+            a = todo.pop()
+            members.append(a)
+            for b in adj[a]:
+                if comp[b] < 0:
+                    comp[b] = comp[s]
+                    todo.append(b)
+        out.append(sorted(members))
+    return out
+
+
+def check_cluster_brute_force(o):
+    rng = np.random.default_rng(11)
+    for n in (1, 2, 5, 30, 80, 160):
+        cands = _random_cands(rng, n)
+        reps, label = o.cluster_dm_width(cands)
+        parts = {}
+        for i, k in enumerate(label):
+            parts.setdefault(k, []).append(i)
+        comps = _components_brute(cands)
+        assert sorted(parts.values()) == sorted(comps), n
+        assert len(reps) == len(comps)
+        for k, members in parts.items():
+            top = max(cands[i][4] for i in members)
+            r = reps[k]
+            assert r[4] == top and tuple(r) in [cands[i] for i in members]
+            # the lowest DM, earliest sample, smallest width among the members at that S/N
+            assert tuple(r[:4]) == min(((cands[i][0], cands[i][1], cands[i][2], cands[i][3])
+                                        for i in members if cands[i][4] == top),
+                                       key=lambda c: (c[1], c[3], c[2]))
+
+
+def check_cluster_invariants(o):
+    rng = np.random.default_rng(12)
+    cands = _random_cands(rng, 60)
+    reps, label = o.cluster_dm_width(cands)
+    perm = rng.permutation(len(cands))
+    reps2, label2 = o.cluster_dm_width([cands[i] for i in perm])
+    assert reps2 == reps                                   # input order does not matter
+    assert [label[i] for i in perm] == label2
+    assert o.cluster_dm_width([]) == ([], [])
+    one = (3, 7, 4, 100, 8.25)
+    assert o.cluster_dm_width([one]) == ([one], [0])
+    # disjoint windows in one row, or one DM apart with a one-sample gap, never join
+    apart = [(0, 0, 4, 0, 7.0), (0, 0, 4, 4, 7.0), (0, 1, 2, 8, 7.0), (0, 3, 2, 8, 7.0)]
+    assert len(o.cluster_dm_width(apart)[0]) == 4
+    # a dispersed burst seen over widths and DMs reduces to few clusters and keeps its best S/N
+    w = synth.cfg_small()
+    delays = o.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms[:80])
+    data = synth.noise((w.nchan, int(delays.max()) + 1500), seed=5)
+    synth.add_tophat(data, 600 + delays[40], 6, 14)
+    _, cands = o.search(data, delays, w.widths, 7.0)
+    reps, _ = o.cluster_dm_width(cands)
+    assert 0 < len(reps) < len(cands) / 4
+    assert max(r[4] for r in reps) == max(c[4] for c in cands)
+    best = max(reps, key=lambda r: r[4])
+    assert abs(best[1] - 40) <= 2 and abs(best[3] - 600) <= 16
+
+
+def test_cluster_golden():
+    check_cluster_golden(O)
+
+
+def test_cluster_brute_force():
+    check_cluster_brute_force(O)
+
+
+def test_cluster_invariants():
+    check_cluster_invariants(O)
+
+
+def test_cluster_rejects_bad_width():
+    with pytest.raises(ValueError):
+        O.cluster_dm_width([(0, 0, 0, 5, 7.0)])
+
+
 ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif_span,
               check_zero_dm, check_impulse, check_sum_conservation, check_brute_force,
               check_linearity_shift_permutation, check_chunked_stream, check_tophat_exact,
               check_downsample, check_sb_synth, check_boxcar, check_moments, check_snr_noise,
               check_candidates_golden, check_injected_recovery, check_tophat_snr,
-              check_subband_golden, check_subband_reductions, check_subband_smearing_bound]
+              check_subband_golden, check_subband_reductions, check_subband_smearing_bound,
+              check_cluster_golden, check_cluster_brute_force, check_cluster_invariants]
