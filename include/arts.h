@@ -208,6 +208,36 @@ int arts_candidates(arts_plan_t plan, const int32_t* series, int32_t nbeam, int6
                     float threshold, int64_t t_offset, int32_t beam_offset,
                     arts_candidate* host_out, int64_t capacity, int64_t* count, void* stream);
 
+/* DM-width clustering (Sect. 6b.2, "Clustering", optional in the paper): candidates of
+ * different widths at the same time and DM are reduced to the one with the highest S/N, then
+ * groups in neighbouring DM trials are compacted the same way, and one candidate is reported
+ * per resulting cluster.  Readings taken here: a candidate covers its boxcar window
+ * [sample, sample + width - 1]; step 1 groups the candidates of one (beam, dm_index) whose
+ * windows overlap, transitively, and a group covers the union of its windows; step 2 joins the
+ * groups of dm_index d and d + 1 of one beam whose covered intervals overlap, transitively.  A
+ * cluster reports its member with the highest S/N, ties to the lowest dm_index, then the
+ * earliest sample, then the smallest width.
+ *
+ * arts_plan_set_cluster(plan, 1) makes the candidate searches of this plan report clusters:
+ * arts_candidates, arts_batch_candidates (per request) and the streams created afterwards (a
+ * stream reads the setting in arts_stream_create).  Clustering runs on the device over the
+ * candidates of one call, request or chunk and one plan.  The capacity of those calls must
+ * still hold the unclustered candidates (with ARTS_E_CAPACITY, *count is that number).
+ * enable: 0 (default) or 1; other values give ARTS_E_INVAL.                                 */
+int arts_plan_set_cluster(arts_plan_t plan, int32_t enable);
+int arts_plan_get_cluster(arts_plan_t plan, int32_t* enable);
+
+/* Cluster a device list of this plan's candidates in place (same rule as above).
+ * cand: device arts_candidate [n], n < 2^31, beam in [beam_offset, beam_offset + nbeam),
+ * 0 <= dm_index < the plan's ndm.  On return cand[0, *count) holds one candidate per cluster,
+ * in no particular order.  Records that agree in beam, dm_index, width and sample (never
+ * produced by this library) are kept apart only by S/N: of equal ones, either may be reported.
+ * Uses the plan's workspace (grown on demand); SYNCHRONISES stream.  Errors: ARTS_E_INVAL for
+ * a record outside the beams or DM trials, a width < 1 or a NaN S/N (the list is then left
+ * unchanged), ARTS_E_NOMEM / ARTS_E_DEVICE.                                                  */
+int arts_plan_cluster(arts_plan_t plan, arts_candidate* cand, int64_t n, int32_t nbeam,
+                      int32_t beam_offset, int64_t* count, void* stream);
+
 /* -------------------------------------------------------------------------- batches ---- */
 
 /* One search request of an uneven batch: its own plan (channel count, DM range, widths, D),

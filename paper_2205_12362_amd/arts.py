@@ -58,6 +58,9 @@ _SIGNATURES = {
     "arts_plan_delays": (C.c_int, [_vp, _pi32]),
     "arts_plan_set_tiling": (C.c_int, [_vp, _i32]),
     "arts_plan_get_tiling": (C.c_int, [_vp, _pi32]),
+    "arts_plan_set_cluster": (C.c_int, [_vp, _i32]),
+    "arts_plan_get_cluster": (C.c_int, [_vp, _pi32]),
+    "arts_plan_cluster": (C.c_int, [_vp, _vp, _i64, _i32, _i32, _pi64, _vp]),
     "arts_tiling_count": (_i32, []),
     "arts_plan_autotune": (C.c_int, [_vp, _i32, _i64, _i32, C.c_char_p, _pi32,
                                      C.POINTER(C.c_float)]),
@@ -354,6 +357,35 @@ def arts_candidates(plan, series, threshold, t_offset=0, beam_offset=0, capacity
     _check(st)
 
 
+def arts_plan_set_cluster(plan, enable):
+    _check(lib().arts_plan_set_cluster(plan, int(enable)))
+
+
+def arts_plan_get_cluster(plan):
+    v = C.c_int32(0)
+    _check(lib().arts_plan_get_cluster(plan, C.byref(v)))
+    return bool(v.value)
+
+
+def arts_plan_cluster(plan, cand, nbeam, beam_offset=0, stream=None):
+    """Cluster a device candidate list in place.  `cand` is a device uint8 tensor of n * 32
+    bytes (arts_candidate records) or a numpy CANDIDATE_DTYPE array (copied to the device);
+    returns the clusters as a numpy array sorted by (beam, dm, width, sample)."""
+    import torch
+    if isinstance(cand, np.ndarray):
+        cand = torch.from_numpy(np.ascontiguousarray(cand, dtype=CANDIDATE_DTYPE)
+                                .view(np.uint8)).cuda()
+    if cand.dtype != torch.uint8 or not cand.is_cuda or cand.numel() % 32:
+        raise ValueError("cand must be a device uint8 tensor of whole 32-byte records")
+    n = cand.numel() // 32
+    cnt = C.c_int64(0)
+    _check(lib().arts_plan_cluster(plan, cand.data_ptr() if n else None, n, int(nbeam),
+                                   int(beam_offset), C.byref(cnt), _stream(stream)))
+    out = cand[: cnt.value * 32].cpu().numpy().view(CANDIDATE_DTYPE).copy()
+    out.sort(order=["beam", "dm_index", "width", "sample"])
+    return out
+
+
 class Plan:
     """Owning wrapper around an arts_plan_t."""
 
@@ -433,6 +465,17 @@ class Plan:
 
     def candidates(self, series, threshold, **kw):
         return arts_candidates(self.handle, series, threshold, **kw)
+
+    @property
+    def cluster(self):
+        return arts_plan_get_cluster(self.handle)
+
+    @cluster.setter
+    def cluster(self, enable):
+        arts_plan_set_cluster(self.handle, enable)
+
+    def cluster_candidates(self, cand, nbeam, beam_offset=0, stream=None):
+        return arts_plan_cluster(self.handle, cand, nbeam, beam_offset, stream)
 
 
 # ---------------------------------------------------------------------------- streaming

@@ -18,6 +18,7 @@ struct arts_batch_s {
   arts_candidate* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
   int64_t cand_cap = 0;
+  ClusterWs cl;  // DM-width clustering of requests whose plan asks for it
 };
 
 namespace {
@@ -54,6 +55,7 @@ void arts_batch_destroy(arts_batch_t b) {
     if (p) (void)hipFree(p);
   if (b->d_cand) (void)hipFree(b->d_cand);
   if (b->d_count) (void)hipFree(b->d_count);
+  free_cluster_ws(b->cl);
   delete b;
 }
 
@@ -137,6 +139,13 @@ int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, f
     ARTS_HIP(hipMalloc(&b->d_cand, cap * sizeof(arts_candidate)));
     b->cand_cap = cap;
   }
+  // clustered requests share one workspace, sized before any launch
+  int64_t cl_rows = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (reqs[i].plan && reqs[i].plan->cluster && reqs[i].nbeam >= 1)
+      cl_rows = std::max<int64_t>(cl_rows, static_cast<int64_t>(reqs[i].nbeam) * reqs[i].plan->ndm);
+  if (cl_rows > 0)
+    if (int e = ensure_cluster_ws(b->cl, std::max<int64_t>(capacity, 1), cl_rows)) return e;
   if (int e = launch_zero_u64(b->d_count, 1, s)) return e;
   int32_t beam0 = 0;
   for (int32_t i = 0; i < n; ++i) {
@@ -144,10 +153,17 @@ int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, f
     if (r.plan && r.nbeam >= 1 && r.nin >= 1) {
       const int64_t L = series_len(r.plan, r.nin);
       const int64_t nrep = L - r.plan->wmax + 1;
-      if (L >= 1 && nrep >= 1)
+      if (L >= 1 && nrep >= 1) {
+        if (r.plan->cluster)
+          if (int e = launch_cluster_mark(b->cl, b->d_count, s)) return e;
         if (int e = launch_candidates(r.plan, r.out, r.nbeam, L, nrep, threshold, 0, beam0, nullptr,
                                       nullptr, b->d_cand, b->d_count, capacity, s))
           return e;
+        if (r.plan->cluster)
+          if (int e = launch_cluster(b->cl, b->d_cand, b->d_count, capacity, true, r.nbeam,
+                                     r.plan->ndm, beam0, s))
+            return e;
+      }
     }
     beam0 += std::max(0, r.nbeam);
   }

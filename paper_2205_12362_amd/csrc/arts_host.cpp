@@ -306,6 +306,7 @@ static void plan_free(arts_plan_s* p) {
   if (p->d_musig) (void)hipFree(p->d_musig);
   if (p->d_cand) (void)hipFree(p->d_cand);
   if (p->d_count) (void)hipFree(p->d_count);
+  free_cluster_ws(p->cl);
   delete p;
 }
 
@@ -633,6 +634,45 @@ int arts_plan_get_tiling(arts_plan_t p, int32_t* variant) {
   return ARTS_OK;
 }
 
+int arts_plan_set_cluster(arts_plan_t p, int32_t enable) {
+  if (int st = check_plan(p)) return st;
+  if (enable != 0 && enable != 1) return fail(ARTS_E_INVAL, "enable must be 0 or 1");
+  p->cluster = enable != 0;
+  return ARTS_OK;
+}
+
+int arts_plan_get_cluster(arts_plan_t p, int32_t* enable) {
+  if (int st = check_plan(p)) return st;
+  if (enable) *enable = p->cluster ? 1 : 0;
+  return ARTS_OK;
+}
+
+int arts_plan_cluster(arts_plan_t p, arts_candidate* cand, int64_t n, int32_t nbeam,
+                      int32_t beam_offset, int64_t* count, void* stream) {
+  if (int st = check_plan(p)) return st;
+  if (!count || n < 0 || (n > 0 && !cand) || nbeam < 1)
+    return fail(ARTS_E_INVAL, "bad pointer or size");
+  *count = 0;
+  if (n == 0) return ARTS_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t rows = static_cast<int64_t>(nbeam) * p->ndm;
+  if (int st = ensure_cand(p, 0)) return st;
+  if (int st = ensure_cluster_ws(p->cl, n, rows)) return st;
+  unsigned long long n0 = static_cast<unsigned long long>(n), n1 = 0;
+  ARTS_HIP(hipMemcpyAsync(p->d_count, &n0, sizeof n0, hipMemcpyHostToDevice, s));
+  if (int st = launch_cluster(p->cl, cand, p->d_count, n, false, nbeam, p->ndm, beam_offset, s))
+    return st;
+  ARTS_HIP(hipMemcpyAsync(&n1, p->d_count, sizeof n1, hipMemcpyDeviceToHost, s));
+  int skipped = 0, bad = 0;
+  if (int st = read_cluster_status(p->cl, &skipped, &bad, s)) return st;  // synchronises
+  if (bad)
+    return fail(ARTS_E_INVAL, "a candidate lies outside the plan's beams or DM trials, has "
+                              "width < 1 or a NaN S/N");
+  if (skipped) return fail(ARTS_E_DEVICE, "internal: clustering skipped");
+  *count = static_cast<int64_t>(n1);
+  return ARTS_OK;
+}
+
 int32_t arts_tiling_count(void) { return kNumVariants; }
 
 int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
@@ -726,9 +766,15 @@ int arts_candidates(arts_plan_t p, const int32_t* series, int32_t nbeam, int64_t
   if (int st = ensure_stats(p, rows)) return st;
   if (int st = ensure_cand(p, capacity)) return st;
   if (int st = launch_zero_u64(p->d_count, 1, s)) return st;
+  if (p->cluster)
+    if (int st = ensure_cluster_ws(p->cl, std::max<int64_t>(capacity, 1), rows)) return st;
   if (int st = launch_candidates(p, series, nbeam, L, nrep, threshold, t_offset, beam_offset,
                                  p->d_s1, p->d_musig, p->d_cand, p->d_count, capacity, s))
     return st;
+  if (p->cluster)
+    if (int st = launch_cluster(p->cl, p->d_cand, p->d_count, capacity, false, nbeam, p->ndm,
+                                beam_offset, s))
+      return st;
   unsigned long long n = 0;
   ARTS_HIP(hipMemcpyAsync(&n, p->d_count, sizeof n, hipMemcpyDeviceToHost, s));
   ARTS_HIP(hipStreamSynchronize(s));

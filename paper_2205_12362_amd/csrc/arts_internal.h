@@ -44,6 +44,13 @@ struct Tiling {
   uint32_t* d_cnt[4] = {};     // per g0: [nblk][nchunk][m_blk] 4 x 8-bit channel counts per m
 };
 
+// Device workspace of the DM-width clustering (arts_cluster.hip): per-row counters and
+// offsets for `rows` (beam, DM) rows and per-candidate scratch for lists of up to `cap`.
+struct ClusterWs {
+  void* d_mem = nullptr;
+  int64_t cap = 0, rows = 0, bytes = 0;
+};
+
 }  // namespace arts
 
 struct arts_plan_s {
@@ -86,6 +93,10 @@ struct arts_plan_s {
   int32_t split = 0;
   uint16_t* d_y = nullptr;
   int64_t y_cap = 0;  // elements
+  // DM-width clustering of this plan's candidates (arts_plan_set_cluster) and the workspace of
+  // one-shot calls
+  bool cluster = false;
+  arts::ClusterWs cl;
   bool is16() const { return ds > 1 || in16; }
 };
 
@@ -179,6 +190,19 @@ int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam
 int launch_sb_gather(const uint8_t* tab, int32_t ntab, const uint8_t* sb_table, int32_t nsb,
                      int32_t nchan, int64_t nsamp, uint8_t* out, hipStream_t s);
 int launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+// DM-width clustering.  launch_cluster replaces the candidates cand[beg, *count) by one per
+// cluster (cand[beg, beg + clusters), *count updated on the device), where beg is 0 or, with
+// from_mark, the value of *count that launch_cluster_mark saved before the plan's candidates
+// were appended.  `cap` is the list capacity: a larger *count (dropped appends) or an invalid
+// record leaves the list unchanged (read_cluster_status tells which).
+int64_t cluster_ws_bytes(int64_t cap, int64_t rows);
+int ensure_cluster_ws(ClusterWs& w, int64_t cap, int64_t rows);
+void free_cluster_ws(ClusterWs& w);
+int launch_cluster_mark(ClusterWs& w, const unsigned long long* count, hipStream_t s);
+int launch_cluster(ClusterWs& w, arts_candidate* cand, unsigned long long* count, int64_t cap,
+                   bool from_mark, int32_t nbeam, int32_t ndm, int32_t beam_offset,
+                   hipStream_t s);
+int read_cluster_status(ClusterWs& w, int* skipped, int* bad, hipStream_t s);
 // dst[r][s] = sum of D consecutive src bytes, s < nout (16-bit rows, pitches in elements/bytes)
 int launch_downsample(uint16_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch,
                       int64_t nrows, int64_t nout, int32_t D, hipStream_t s);
@@ -210,6 +234,8 @@ struct arts_stream_s {
   arts_candidate* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
   unsigned long long* h_count = nullptr;  // pinned
+  std::vector<char> cluster;               // per plan: cluster its candidates (set at creation)
+  arts::ClusterWs cl;
   int64_t cap = 0;
   hipStream_t hs = nullptr;
   hipEvent_t ev_in = nullptr, ev_done = nullptr;

@@ -43,6 +43,7 @@ void stream_free(arts_stream_s* s) {
   if (s->d_cand) (void)hipFree(s->d_cand);
   if (s->d_count) (void)hipFree(s->d_count);
   if (s->h_count) (void)hipHostFree(s->h_count);
+  free_cluster_ws(s->cl);
   for (auto e : s->pev)
     if (e) (void)hipEventDestroy(e);
   if (s->ev_in) (void)hipEventDestroy(s->ev_in);
@@ -120,6 +121,10 @@ int64_t stream_bytes_needed(const arts_plan_t* plans, int32_t nplan, int32_t nsr
   if (native) total += 2 * rows * ((hmax + chunk + 3) & ~int64_t(3));
   for (int32_t i = 0; i < nplan; ++i)  // two parities of 16-bit step-1 rows
     total += 4 * subband_ws_elems(plans[i], nbeam, static_cast<int64_t>(plans[i]->halo) + chunk);
+  int64_t cl_rows = 0;  // clustering workspace
+  for (int32_t i = 0; i < nplan; ++i)
+    if (plans[i]->cluster) cl_rows = std::max<int64_t>(cl_rows, static_cast<int64_t>(nbeam) * plans[i]->ndm);
+  if (cl_rows > 0) total += cluster_ws_bytes(cand_capacity, cl_rows);
   return total;
 }
 
@@ -176,11 +181,18 @@ int stream_candidates(arts_stream_s* s, hipStream_t hs) {
     const int64_t nrep = s->chunk / pl->ds;
     const int64_t t0 = stream_warmup(s, p, s->pushed);
     if (t0 >= nrep) continue;
+    const bool clu = s->cluster[p] != 0;
+    if (clu)
+      if (int st = launch_cluster_mark(s->cl, s->d_count, hs)) return st;
     // sample numbers are made absolute on the host: chunk-relative start minus the halo
     if (int st = launch_candidates(pl, s->series[p], s->nbeam, s->L[p], nrep, s->thr,
                                    -s->H[p] / pl->ds, 0, nullptr, nullptr, s->d_cand,
                                    s->d_count, s->cap, hs, t0))
       return st;
+    if (clu)
+      if (int st = launch_cluster(s->cl, s->d_cand, s->d_count, s->cap, true, s->nbeam, pl->ndm,
+                                  0, hs))
+        return st;
   }
   ARTS_HIP(hipMemcpyAsync(s->h_count, s->d_count, sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, hs));
@@ -336,6 +348,16 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
   if (st == ARTS_OK)
     st = dev_alloc(s, reinterpret_cast<void**>(&s->d_cand), cand_capacity * sizeof(arts_candidate));
   if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&s->d_count), 64);
+  // DM-width clustering, for the plans that ask for it when the stream is created
+  int64_t cl_rows = 0;
+  for (auto* pl : s->plans) {
+    s->cluster.push_back(pl->cluster ? 1 : 0);
+    if (pl->cluster) cl_rows = std::max<int64_t>(cl_rows, static_cast<int64_t>(nbeam) * pl->ndm);
+  }
+  if (st == ARTS_OK && cl_rows > 0) {
+    st = ensure_cluster_ws(s->cl, cand_capacity, cl_rows);
+    if (st == ARTS_OK) s->device_bytes += s->cl.bytes;
+  }
   if (st == ARTS_OK && hipHostMalloc(reinterpret_cast<void**>(&s->h_count), 64) != hipSuccess)
     st = fail(ARTS_E_NOMEM, "pinned allocation failed");
   if (st == ARTS_OK && hipStreamCreateWithFlags(&s->hs, hipStreamNonBlocking) != hipSuccess)
