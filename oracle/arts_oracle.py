@@ -13,7 +13,7 @@ design notes of the repository; each is marked "reading".
 Parity status per function:
   channel_freqs, delay_table, tie_audit, downsample, sb_synthesize, dedisperse,
   dedisperse_at, subband_plan, subband_dedisperse, subband_dedisperse_at, boxcar, moments,
-  snr, candidates, cluster_dm_width  -- pinned by closed forms / invariants / hand-worked
+  snr, candidates, cluster_dm_width, cluster_offline  -- pinned by closed forms / invariants / hand-worked
   values / brute force in tests/test_oracle_pins.py (no function here is "parity unpinned").
 """
 from __future__ import annotations
@@ -364,3 +364,39 @@ def cluster_dm_width(cands):
         for i in m:
             label[i] = index[root]
     return reps, label
+
+
+def cluster_offline(cands, t_window: int, dm_edges, min_snr: float):
+    """Offline clustering of an observation's candidates over time (Sect. 6b.1, "Offline
+    analysis"): candidates below a DM or an S/N limit are discarded (the paper: DM below 20,
+    S/N below 10), and within each time window (0.5 s in the paper) and each DM window (windows
+    that widen as the DM grows) only the candidate with the highest S/N is kept.
+
+    Readings: a candidate's time is its start in native samples, sample * downsample; the time
+    windows are [k t_window, (k + 1) t_window) for integer k (floor division, also for negative
+    starts); the DM windows are [e_j, e_{j+1}) over the increasing edges dm_edges, the last one
+    open-ended, and a DM below e_0 is discarded (e_0 is the DM limit); S/N below min_snr is
+    discarded (S/N equal to it is kept); windows are shared by all beams; ties in S/N go to the
+    candidate that comes first in the input.
+
+    cands: sequence of (beam, dm_index, width, sample, snr, downsample, dm).  Returns the kept
+    candidates sorted by (native start, dm, beam, width).
+    """
+    edges = [float(e) for e in dm_edges]
+    if t_window < 1 or not edges or any(b <= a for a, b in zip(edges, edges[1:])):
+        raise ValueError("t_window >= 1 and strictly increasing DM edges are required")
+    best = {}
+    for i, c in enumerate(cands):
+        snr, ds, dm = float(c[4]), int(c[5]), float(c[6])
+        if int(c[2]) < 1 or ds < 1 or snr != snr or dm != dm:
+            raise ValueError("candidate width and downsample must be >= 1, S/N and DM numbers")
+        if dm < edges[0] or snr < min_snr:
+            continue
+        start = int(c[3]) * ds
+        j = max(k for k, e in enumerate(edges) if e <= dm)
+        key = (start // t_window, j)
+        if key not in best or snr > float(cands[best[key]][4]):
+            best[key] = i
+    kept = [tuple(cands[i]) for i in best.values()]
+    kept.sort(key=lambda c: (int(c[3]) * int(c[5]), float(c[6]), int(c[0]), int(c[2])))
+    return kept

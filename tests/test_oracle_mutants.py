@@ -229,6 +229,33 @@ def _cluster_variant(kind):
     return cluster_dm_width
 
 
+def _offline_variant(kind):
+    # offline clustering written out again with one planted change
+    def cluster_offline(cands, t_window, dm_edges, min_snr):
+        edges = [float(e) for e in dm_edges]
+        if t_window < 1 or not edges or any(b <= a for a, b in zip(edges, edges[1:])):
+            raise ValueError("bad")
+        best = {}
+        for i, c in enumerate(cands):
+            snr, ds, dm = float(c[4]), int(c[5]), float(c[6])
+            if dm < edges[0] or (snr <= min_snr if kind == "strict S/N limit" else snr < min_snr):
+                continue
+            start = int(c[3]) * (1 if kind == "downsample ignored" else ds)
+            tw = int(start / t_window) if kind == "truncating division" else start // t_window
+            if kind == "upper-closed DM windows":
+                j = max([k for k, e in enumerate(edges) if e < dm] or [0])
+            else:
+                j = max(k for k, e in enumerate(edges) if e <= dm)
+            key = (tw, j, c[0]) if kind == "windows per beam" else (tw, j)
+            if key not in best or snr > float(cands[best[key]][4]) or (
+                    kind == "ties to the last" and snr == float(cands[best[key]][4])):
+                best[key] = i
+        kept = [tuple(cands[i]) for i in best.values()]
+        kept.sort(key=lambda c: (int(c[3]) * int(c[5]), float(c[6]), int(c[0]), int(c[2])))
+        return kept
+    return cluster_offline
+
+
 MUTANTS = {
     "reference at lowest channel": dict(delay_table=_delay_variant(ref="min")),
     "floor instead of round": dict(delay_table=_delay_variant(rounding=np.floor)),
@@ -256,6 +283,15 @@ MUTANTS = {
     "cluster DM neighbour two apart": dict(
         cluster_dm_width=_cluster_variant("DM neighbour two apart")),
     "cluster ties to the highest DM": dict(cluster_dm_width=_cluster_variant("ties to highest DM")),
+    "offline time in downsampled samples": dict(
+        cluster_offline=_offline_variant("downsample ignored")),
+    "offline truncating time division": dict(
+        cluster_offline=_offline_variant("truncating division")),
+    "offline strict S/N limit": dict(cluster_offline=_offline_variant("strict S/N limit")),
+    "offline upper-closed DM windows": dict(
+        cluster_offline=_offline_variant("upper-closed DM windows")),
+    "offline windows per beam": dict(cluster_offline=_offline_variant("windows per beam")),
+    "offline ties to the last": dict(cluster_offline=_offline_variant("ties to the last")),
 }
 
 
@@ -275,6 +311,10 @@ def test_unmutated_copy_passes():
 
 def test_unmutated_cluster_rewrite_passes():
     assert _run_all(_copy(cluster_dm_width=_cluster_variant("none"))) == []
+
+
+def test_unmutated_offline_rewrite_passes():
+    assert _run_all(_copy(cluster_offline=_offline_variant("none"))) == []
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

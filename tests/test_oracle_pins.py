@@ -591,10 +591,99 @@ def test_cluster_rejects_bad_width():
         O.cluster_dm_width([(0, 0, 0, 5, 7.0)])
 
 
+# ---------------------------------------------------------------- offline clustering
+def check_offline_golden(o):
+    g = _load("cluster_offline_tiny.json")
+    cands = [tuple(c) for c in g["candidates"]]
+    kept = o.cluster_offline(cands, g["t_window"], g["dm_edges"], g["min_snr"])
+    assert [tuple(c) for c in kept] == [cands[i] for i in g["kept"]]
+
+
+def _random_offline(rng, n):
+    out = []
+    for _ in range(n):
+        ds = int(rng.choice([1, 2, 4]))
+        out.append((int(rng.integers(3)), int(rng.integers(50)), int(rng.choice([1, 2, 4, 8])),
+                    int(rng.integers(-400, 3000)) // ds, float(rng.choice([9.5, 10.0, 11.0, 14.0])),
+                    ds, float(rng.choice([15.0, 20.0, 33.0, 60.0, 61.5, 130.0, 400.0]))))
+    return out
+
+
+def check_offline_brute_force(o):
+    rng = np.random.default_rng(21)
+    edges, tw, smin = [20.0, 40.0, 60.0, 61.5, 200.0], 250, 10.0
+    for n in (0, 1, 7, 60, 400):
+        cands = _random_offline(rng, n)
+        kept = o.cluster_offline(cands, tw, edges, smin)
+        # the windows, computed independently: every passing candidate's window, by scanning
+        passing = [i for i, c in enumerate(cands) if c[6] >= edges[0] and c[4] >= smin]
+        win = {}
+        for i in passing:
+            c = cands[i]
+            start = c[3] * c[5]
+            k = 0
+            while (k + 1) * tw <= start:
+                k += 1
+            while k * tw > start:
+                k -= 1
+            j = sum(1 for e in edges if e <= c[6]) - 1
+            win.setdefault((k, j), []).append(i)
+        assert len(kept) == len(win), n
+        chosen = set()
+        for members in win.values():
+            top = max(cands[i][4] for i in members)
+            first = min(i for i in members if cands[i][4] == top)
+            chosen.add(first)
+        assert sorted(kept) == sorted(cands[i] for i in chosen)
+        starts = [c[3] * c[5] for c in kept]
+        assert starts == sorted(starts)
+
+
+def check_offline_invariants(o):
+    rng = np.random.default_rng(22)
+    cands = [c for c in _random_offline(rng, 200) if c[3] >= 0]
+    # one window holding everything keeps only the global best (first on ties)
+    big = o.cluster_offline(cands, 10 ** 9, [-1.0], -1e9)
+    assert len(big) == 1 and big[0][4] == max(c[4] for c in cands)
+    assert big[0] == next(c for c in cands if c[4] == big[0][4])
+    # the limits: a candidate exactly at both limits stays, just below either goes
+    base = (0, 0, 1, 7, 10.0, 1, 20.0)
+    assert o.cluster_offline([base], 100, [20.0], 10.0) == [base]
+    assert o.cluster_offline([base[:4] + (np.nextafter(10.0, 0.0),) + base[5:]], 100,
+                             [20.0], 10.0) == []
+    assert o.cluster_offline([base[:6] + (np.nextafter(20.0, 0.0),)], 100, [20.0], 10.0) == []
+    # the same native start from different downsampling lands in the same window
+    a, b = (0, 0, 1, 40, 11.0, 1, 30.0), (1, 0, 1, 10, 12.0, 4, 30.0)
+    assert o.cluster_offline([a, b], 41, [20.0], 10.0) == [b]
+    assert o.cluster_offline([], 100, [20.0], 10.0) == []
+
+
+def test_offline_golden():
+    check_offline_golden(O)
+
+
+def test_offline_brute_force():
+    check_offline_brute_force(O)
+
+
+def test_offline_invariants():
+    check_offline_invariants(O)
+
+
+def test_offline_rejects_bad_args():
+    with pytest.raises(ValueError):
+        O.cluster_offline([], 0, [20.0], 10.0)
+    with pytest.raises(ValueError):
+        O.cluster_offline([], 10, [20.0, 20.0], 10.0)
+    with pytest.raises(ValueError):
+        O.cluster_offline([(0, 0, 1, 5, 11.0, 0, 30.0)], 10, [20.0], 10.0)
+
+
 ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif_span,
               check_zero_dm, check_impulse, check_sum_conservation, check_brute_force,
               check_linearity_shift_permutation, check_chunked_stream, check_tophat_exact,
               check_downsample, check_sb_synth, check_boxcar, check_moments, check_snr_noise,
               check_candidates_golden, check_injected_recovery, check_tophat_snr,
               check_subband_golden, check_subband_reductions, check_subband_smearing_bound,
-              check_cluster_golden, check_cluster_brute_force, check_cluster_invariants]
+              check_cluster_golden, check_cluster_brute_force, check_cluster_invariants,
+              check_offline_golden, check_offline_brute_force, check_offline_invariants]
