@@ -338,6 +338,8 @@ def alert_bench(args):
     f_lo, df = synth.band(NCHAN)
     plans = [arts.Plan.subband(NCHAN, f_lo, df, synth.TSAMP, a, st, n, nf, 32, ALERT_WIDTHS)
              for a, st, n, nf in ALERT_PLANS]
+    for p in plans:
+        p.cluster = bool(args.cluster)
     table = torch.from_numpy(synth.sb_table_synthetic(NSB, NTAB, NCHAN)).cuda()
     pool = [torch.from_numpy(synth.noise((NTAB, NCHAN, CHUNK), seed=900 + k)).cuda()
             for k in range(2)]
@@ -392,7 +394,7 @@ def alert_bench(args):
                                "819.2-3379.2/2.5 (40): 5120 trials; widths 1,5,10,25,50,100,"
                                "250; 12500 new samples per step",
                    "ntrial": ntrial, "nsb": NSB, "chunk": CHUNK, "threshold": THRESHOLD,
-                   "device_bytes": info["device_bytes"]},
+                   "cluster": bool(args.cluster), "device_bytes": info["device_bytes"]},
         "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
         "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                              "p99": float(np.percentile(lat_ms, 99)),
@@ -405,6 +407,80 @@ def alert_bench(args):
         "brute_force_adds_per_step": NSB * ntrial * NCHAN * (CHUNK + 249),
         "candidates_per_step": ncand / args.steps,
         "sensitivity_vs_brute_force": sens}))
+
+
+def cluster_bench(args):
+    """DM-width clustering of a serving-scale burst storm: 71 SBs x 2048 DM trials, widths
+    1..256, 1500 events over up to 81 trials and every width plus 100 000 isolated candidates
+    (about 660 000 candidates), clustered in place on the device (arts_plan_cluster).  Each step
+    restores the list from a device copy (a 21 MB device copy) and clusters it."""
+    import torch
+
+    import paper_2205_12362_amd.arts as arts
+    from paper_2205_12362_amd import synth
+
+    widths = [1 << k for k in range(9)]
+    b, d, w, t, s = synth.candidate_tracks(NSB, 2048, widths, CHUNK, 1500, 100000, seed=3)
+    n = b.size
+    rec = np.zeros(n, dtype=arts.CANDIDATE_DTYPE)
+    rec["beam"], rec["dm_index"], rec["width"], rec["sample"], rec["snr"] = b, d, w, t, s
+    rec["downsample"] = 1
+    rec["dm"] = d.astype(np.float32)
+    f_lo, df = synth.band(NCHAN)
+    plan = arts.Plan(NCHAN, f_lo, df, synth.TSAMP, np.arange(2048, dtype=np.float64), widths)
+    pristine = torch.from_numpy(rec.view(np.uint8)).cuda()
+    work = torch.empty_like(pristine)
+    ncl = 0
+    for k in range(args.warmup):
+        work.copy_(pristine)
+        ncl = len(plan.cluster_candidates(work, NSB))
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    lat = []
+    for k in range(args.steps):
+        t1 = time.perf_counter()
+        work.copy_(pristine)
+        cnt = ctypes_cluster(arts, plan, work, n)
+        lat.append(time.perf_counter() - t1)
+    elapsed = time.perf_counter() - t_start
+    assert cnt == ncl or args.warmup == 0
+    ms = 1e3 * elapsed / args.steps
+    # algorithmic bytes: every candidate record read once, every cluster record written once
+    algo = 32 * n + 32 * cnt
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        cands = list(zip(b.tolist(), d.tolist(), w.tolist(), t.tolist(),
+                         s.astype(float).tolist()))
+        t0 = time.perf_counter()
+        reps, _ = O.cluster_dm_width(cands)
+        dt = time.perf_counter() - t0
+        assert len(reps) == cnt, (len(reps), cnt)
+        cpu = {"value": n / dt, "unit": "candidates/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole list ({n} candidates), once"}
+    lat_ms = np.array(lat) * 1e3
+    print(json.dumps({
+        "metric": "candidates clustered/s", "value": n * args.steps / elapsed,
+        "unit": "candidates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "DM-width clustering of a burst storm: 71 SBs x 2048 DMs, widths "
+                               "1-256, 1500 events + 100000 isolated candidates",
+                   "candidates": int(n), "clusters": int(cnt)},
+        "call_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                            "p99": float(np.percentile(lat_ms, 99))},
+        "roofline": {"bound": "hbm", "achieved": algo / (ms * 1e-3) / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": algo / (ms * 1e-3) / 8e12, "traffic": None,
+                     "note": "whole call: every clustering launch and the host synchronisation"},
+        "cpu_baseline": cpu}))
+
+
+def ctypes_cluster(arts, plan, work, n):
+    import ctypes as C
+    cnt = C.c_int64(0)
+    arts._check(arts.lib().arts_plan_cluster(plan.handle, work.data_ptr(), n, NSB, 0,
+                                             C.byref(cnt), None))
+    return cnt.value
 
 
 def main():
@@ -420,20 +496,25 @@ def main():
     ap.add_argument("--variant", type=int, default=None, help="native dedispersion tiling")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 1 GiB twice (counter calibration)")
-    ap.add_argument("--workload", choices=["serving", "uneven", "alert"], default="serving",
+    ap.add_argument("--workload", choices=["serving", "uneven", "alert", "cluster"],
+                    default="serving",
                     help="serving: the 71-SB stream step (default); uneven: 64 uneven requests, "
                          "persistent batch vs per-request calls; alert: the paper's subband "
-                         "dedispersion setup for one compound beam")
+                         "dedispersion setup for one compound beam; cluster: DM-width "
+                         "clustering of a serving-scale candidate list")
+    ap.add_argument("--cluster", action="store_true",
+                    help="serving / alert: cluster each chunk's candidates (DM-width)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
               "design note, not built", file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("uneven", "alert"):
+    if args.workload in ("uneven", "alert", "cluster"):
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         torch.cuda.set_device(0)
-        (uneven_bench if args.workload == "uneven" else alert_bench)(args)
+        {"uneven": uneven_bench, "alert": alert_bench, "cluster": cluster_bench}[args.workload](
+            args)
         return
 
     import torch
@@ -449,6 +530,8 @@ def main():
     p_ds = arts.Plan.from_workload(w_ds)
     if args.variant is not None:
         p_nat.set_tiling(args.variant)
+    if args.cluster:
+        p_nat.cluster = p_ds.cluster = True
     table = synth.sb_table_synthetic(NSB, NTAB, NCHAN)
 
     log("generating inputs ...")
@@ -541,7 +624,7 @@ def main():
                    "nchan": NCHAN, "nsb": NSB, "ntab": NTAB, "chunk": CHUNK,
                    "ndm_native": int(w_nat.dms.size), "ndm_ds4": int(w_ds.dms.size),
                    "graph": bool(args.graph), "threshold": THRESHOLD,
-                   "device_bytes": info["device_bytes"]},
+                   "cluster": bool(args.cluster), "device_bytes": info["device_bytes"]},
         "adds_per_s": (units_nat + units_ds) * NCHAN * args.steps / elapsed,
         "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
         "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),

@@ -238,6 +238,28 @@ int arts_plan_get_cluster(arts_plan_t plan, int32_t* enable);
 int arts_plan_cluster(arts_plan_t plan, arts_candidate* cand, int64_t n, int32_t nbeam,
                       int32_t beam_offset, int64_t* count, void* stream);
 
+/* Offline clustering of an observation's candidates over time (Sect. 6b.1, "Offline
+ * analysis": candidates below DM 20 or S/N 10 are discarded, and within a 0.5 s time window and
+ * DM windows that widen with DM only the highest-S/N candidate is kept).  Readings taken here:
+ * a candidate's time is its native start sample * downsample; time window k is
+ * [k t_window, (k + 1) t_window) native samples (floor division; 0.5 s is t_window = 6104 at
+ * 81.92 us); DM window j is [dm_edges[j], dm_edges[j + 1]), the last one open-ended, and a DM
+ * below dm_edges[0] is discarded (the DM limit; the widening edges are the caller's choice);
+ * S/N below min_snr (compared in FP32) is discarded; the windows are shared by all beams of the
+ * list; ties in S/N go to the candidate earlier in the list.
+ * cand: device arts_candidate [n] (e.g. the clustered candidates of every chunk, uploaded),
+ * n < 2^31, not modified.  dm_edges: host double [nedge], finite, strictly increasing,
+ * 1 <= nedge < 2^20.  The kept candidates go to host_out [capacity], sorted by (native start,
+ * dm, beam, width); *count receives their number (ARTS_E_CAPACITY if above capacity).
+ * Allocates and frees a device workspace of about 32 n + 32 max(2n, 1024) bytes per call
+ * (offline use); SYNCHRONISES stream.  Errors: ARTS_E_INVAL for bad arguments or a record
+ * with width < 1, downsample outside [1, 2^20), a NaN S/N or DM, or a native start beyond
+ * +-2^42; ARTS_E_NOMEM, ARTS_E_DEVICE.                                                      */
+int arts_cluster_offline(const arts_candidate* cand, int64_t n, int64_t t_window,
+                         const double* dm_edges, int32_t nedge, float min_snr,
+                         arts_candidate* host_out, int64_t capacity, int64_t* count,
+                         void* stream);
+
 /* -------------------------------------------------------------------------- batches ---- */
 
 /* One search request of an uneven batch: its own plan (channel count, DM range, widths, D),

@@ -61,6 +61,8 @@ _SIGNATURES = {
     "arts_plan_set_cluster": (C.c_int, [_vp, _i32]),
     "arts_plan_get_cluster": (C.c_int, [_vp, _pi32]),
     "arts_plan_cluster": (C.c_int, [_vp, _vp, _i64, _i32, _i32, _pi64, _vp]),
+    "arts_cluster_offline": (C.c_int, [_vp, _i64, _i64, _pf64, _i32, _f32, _vp, _i64, _pi64,
+                                       _vp]),
     "arts_tiling_count": (_i32, []),
     "arts_plan_autotune": (C.c_int, [_vp, _i32, _i64, _i32, C.c_char_p, _pi32,
                                      C.POINTER(C.c_float)]),
@@ -371,12 +373,7 @@ def arts_plan_cluster(plan, cand, nbeam, beam_offset=0, stream=None):
     """Cluster a device candidate list in place.  `cand` is a device uint8 tensor of n * 32
     bytes (arts_candidate records) or a numpy CANDIDATE_DTYPE array (copied to the device);
     returns the clusters as a numpy array sorted by (beam, dm, width, sample)."""
-    import torch
-    if isinstance(cand, np.ndarray):
-        cand = torch.from_numpy(np.ascontiguousarray(cand, dtype=CANDIDATE_DTYPE)
-                                .view(np.uint8)).cuda()
-    if cand.dtype != torch.uint8 or not cand.is_cuda or cand.numel() % 32:
-        raise ValueError("cand must be a device uint8 tensor of whole 32-byte records")
+    cand = _device_records(cand)
     n = cand.numel() // 32
     cnt = C.c_int64(0)
     _check(lib().arts_plan_cluster(plan, cand.data_ptr() if n else None, n, int(nbeam),
@@ -384,6 +381,40 @@ def arts_plan_cluster(plan, cand, nbeam, beam_offset=0, stream=None):
     out = cand[: cnt.value * 32].cpu().numpy().view(CANDIDATE_DTYPE).copy()
     out.sort(order=["beam", "dm_index", "width", "sample"])
     return out
+
+
+def _device_records(cand):
+    import torch
+    if isinstance(cand, np.ndarray):
+        cand = torch.from_numpy(np.ascontiguousarray(cand, dtype=CANDIDATE_DTYPE)
+                                .view(np.uint8)).cuda()
+    if cand.dtype != torch.uint8 or not cand.is_cuda or cand.numel() % 32:
+        raise ValueError("cand must be a device uint8 tensor of whole 32-byte records")
+    return cand
+
+
+def arts_cluster_offline(cand, t_window, dm_edges, min_snr, capacity=None, stream=None):
+    """Offline time/DM-window clustering of a candidate list (numpy CANDIDATE_DTYPE array or
+    device uint8 tensor of records); returns the kept candidates as a numpy array."""
+    cand = _device_records(cand)
+    n = cand.numel() // 32
+    edges = np.ascontiguousarray(dm_edges, dtype=np.float64)
+    capacity = max(1, n) if capacity is None else int(capacity)
+    buf = np.zeros(max(capacity, 1), dtype=CANDIDATE_DTYPE)
+    cnt = C.c_int64(0)
+    _check(lib().arts_cluster_offline(cand.data_ptr() if n else None, n, int(t_window),
+                                      edges.ctypes.data_as(_pf64), edges.size, float(min_snr),
+                                      buf.ctypes.data, capacity, C.byref(cnt), _stream(stream)))
+    return buf[: cnt.value].copy()
+
+
+def offline_dm_edges(dm_lo=20.0, dm_hi=5000.0, ratio=1.1):
+    """DM window edges that widen with DM: dm_lo, dm_lo * ratio, ... up to dm_hi (the paper's
+    DM limit is 20; it does not give the widths, so the 10 % growth is this helper's choice)."""
+    e = [float(dm_lo)]
+    while e[-1] * ratio < dm_hi:
+        e.append(e[-1] * ratio)
+    return np.array(e)
 
 
 class Plan:

@@ -3,6 +3,7 @@
 // plain (one call per step) path.
 #include <algorithm>
 #include <cfenv>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -644,6 +645,63 @@ int arts_plan_set_cluster(arts_plan_t p, int32_t enable) {
 int arts_plan_get_cluster(arts_plan_t p, int32_t* enable) {
   if (int st = check_plan(p)) return st;
   if (enable) *enable = p->cluster ? 1 : 0;
+  return ARTS_OK;
+}
+
+int arts_cluster_offline(const arts_candidate* cand, int64_t n, int64_t t_window,
+                         const double* dm_edges, int32_t nedge, float min_snr,
+                         arts_candidate* host_out, int64_t capacity, int64_t* count,
+                         void* stream) {
+  if (!count || n < 0 || (n > 0 && !cand) || capacity < 0 || (capacity > 0 && !host_out))
+    return fail(ARTS_E_INVAL, "bad pointer or size");
+  if (n >= INT_MAX) return fail(ARTS_E_INVAL, "at most 2^31 - 1 candidates");
+  if (t_window < 1) return fail(ARTS_E_INVAL, "t_window must be >= 1");
+  if (!dm_edges || nedge < 1 || nedge >= (1 << 20))
+    return fail(ARTS_E_INVAL, "1 <= nedge < 2^20 DM window edges required");
+  for (int32_t i = 0; i < nedge; ++i)
+    if (!std::isfinite(dm_edges[i]) || (i > 0 && !(dm_edges[i] > dm_edges[i - 1])))
+      return fail(ARTS_E_INVAL, "DM window edges must be finite and strictly increasing");
+  if (std::isnan(min_snr)) return fail(ARTS_E_INVAL, "min_snr is NaN");
+  *count = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  const int64_t bytes = offline_ws_bytes(n, nedge);
+  if (hipMalloc(&ws, bytes) != hipSuccess)
+    return fail(ARTS_E_NOMEM, "offline clustering workspace of %lld bytes", (long long)bytes);
+  struct Free {
+    void* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{ws};
+  ARTS_HIP(hipMemcpyAsync(offline_edges(ws, n), dm_edges, sizeof(double) * nedge,
+                          hipMemcpyHostToDevice, s));
+  arts_candidate* d_out = nullptr;
+  unsigned long long* d_count = nullptr;
+  int* d_bad = nullptr;
+  if (int st = launch_cluster_offline(cand, n, t_window, offline_edges(ws, n), nedge, min_snr, ws,
+                                      &d_out, &d_count, &d_bad, s))
+    return st;
+  unsigned long long nk = 0;
+  int bad = 0;
+  ARTS_HIP(hipMemcpyAsync(&nk, d_count, sizeof nk, hipMemcpyDeviceToHost, s));
+  ARTS_HIP(hipMemcpyAsync(&bad, d_bad, sizeof bad, hipMemcpyDeviceToHost, s));
+  ARTS_HIP(hipStreamSynchronize(s));
+  if (bad)
+    return fail(ARTS_E_INVAL, "a candidate has width < 1, downsample outside [1, 2^20), a NaN "
+                              "S/N or DM, or a native start beyond +-2^42 samples");
+  *count = static_cast<int64_t>(nk);
+  if (*count > capacity)
+    return fail(ARTS_E_CAPACITY, "%llu kept candidates, capacity %lld", nk, (long long)capacity);
+  if (nk == 0) return ARTS_OK;
+  ARTS_HIP(hipMemcpyAsync(host_out, d_out, nk * sizeof(arts_candidate), hipMemcpyDeviceToHost,
+                          s));
+  ARTS_HIP(hipStreamSynchronize(s));
+  std::sort(host_out, host_out + nk, [](const arts_candidate& a, const arts_candidate& b) {
+    const int64_t ta = a.sample * a.downsample, tb = b.sample * b.downsample;
+    if (ta != tb) return ta < tb;
+    if (a.dm != b.dm) return a.dm < b.dm;
+    if (a.beam != b.beam) return a.beam < b.beam;
+    return a.width < b.width;
+  });
   return ARTS_OK;
 }
 

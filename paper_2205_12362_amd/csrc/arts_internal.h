@@ -203,6 +203,15 @@ int launch_cluster(ClusterWs& w, arts_candidate* cand, unsigned long long* count
                    bool from_mark, int32_t nbeam, int32_t ndm, int32_t beam_offset,
                    hipStream_t s);
 int read_cluster_status(ClusterWs& w, int* skipped, int* bad, hipStream_t s);
+// Offline clustering over time / DM windows (arts_cluster_offline).  The workspace of
+// offline_ws_bytes(n, nedge) bytes holds a counter, the hash table, the DM edges (copy them to
+// offline_edges(ws, n) first) and the output records; *out, *d_count and *d_bad point into it.
+int64_t offline_ws_bytes(int64_t n, int32_t nedge);
+double* offline_edges(void* ws, int64_t n);
+int launch_cluster_offline(const arts_candidate* cand, int64_t n, int64_t t_window,
+                           const double* d_edges, int32_t nedge, float min_snr, void* ws,
+                           arts_candidate** out, unsigned long long** d_count, int** d_bad,
+                           hipStream_t s);
 // dst[r][s] = sum of D consecutive src bytes, s < nout (16-bit rows, pitches in elements/bytes)
 int launch_downsample(uint16_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch,
                       int64_t nrows, int64_t nout, int32_t D, hipStream_t s);

@@ -195,3 +195,46 @@ def random_bursts(delays: np.ndarray, nrep: int, seed: int, n: int = 20, dm_rang
         bursts.append(Burst(t0 + delays[d].astype(np.int64), fwhm, amp))
         meta.append((d, t0, fwhm, target))
     return bursts, meta
+
+
+def candidate_tracks(nbeam: int, ndm: int, widths, nsamp: int, ntrack: int, nnoise: int,
+                     seed: int, halfspan: int = 40):
+    """Synthetic candidate list shaped like a search's output around bright events, for the
+    clustering path.  Each track is one event in one beam, seen at DM trials d0 - h .. d0 + h
+    (h drawn up to `halfspan`) and at every width, with a start sample that drifts linearly
+    with the DM offset (a trial DM away from the true one shifts the arrival) and an S/N that
+    falls off away from the track's centre DM and width; `nnoise` isolated candidates are
+    spread uniformly over beams, DM trials, widths and samples with S/N just above 8.
+    Returns int64 columns (beam, dm_index, width, sample) and float32 snr, with every
+    (beam, dm_index, width, sample) distinct, in random order."""
+    rng = np.random.default_rng(seed)
+    widths = np.asarray(list(widths), dtype=np.int64)
+    cols = [[], [], [], [], []]
+    for _ in range(ntrack):
+        b = int(rng.integers(nbeam))
+        d0 = int(rng.integers(ndm))
+        h = int(rng.integers(1, halfspan + 1))
+        t0 = int(rng.integers(0, nsamp))
+        drift = float(rng.uniform(-3.0, 3.0))
+        wc = int(rng.integers(widths.size))
+        peak = float(rng.uniform(10.0, 60.0))
+        d = np.arange(max(0, d0 - h), min(ndm, d0 + h + 1), dtype=np.int64)
+        for k, w in enumerate(widths):
+            t = t0 + np.rint(drift * (d - d0)).astype(np.int64) - w // 2
+            s = peak / (1.0 + np.abs(d - d0) / 4.0) / (1.0 + abs(k - wc) * 0.3)
+            cols[0].append(np.full(d.size, b))
+            cols[1].append(d)
+            cols[2].append(np.full(d.size, w))
+            cols[3].append(t)
+            cols[4].append(s)
+    cols[0].append(rng.integers(0, nbeam, nnoise))
+    cols[1].append(rng.integers(0, ndm, nnoise))
+    cols[2].append(rng.choice(widths, nnoise))
+    cols[3].append(rng.integers(0, nsamp, nnoise))
+    cols[4].append(rng.uniform(8.0, 9.0, nnoise))
+    b, d, w, t = (np.concatenate(c).astype(np.int64) for c in cols[:4])
+    s = np.concatenate(cols[4]).astype(np.float32)
+    key = ((b * ndm + d) * (widths.max() + 1) + w) * (4 * nsamp + 1) + (t + 2 * nsamp)
+    _, first = np.unique(key, return_index=True)
+    order = rng.permutation(first)
+    return b[order], d[order], w[order], t[order], s[order]

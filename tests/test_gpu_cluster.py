@@ -222,3 +222,99 @@ def test_clustered_capacity_counts_unclustered():
                                     buf.ctypes.data, 4, C.byref(n), None)
     assert st == arts.ARTS_E_CAPACITY and n.value == nraw
     assert 0 < len(p.candidates(series, 7.0, capacity=4)) < nraw  # retried with the raw count
+
+
+def test_cluster_serving_scale_list():
+    # a burst storm at the serving shape: 71 SBs x 2048 DM trials, AMBER-like widths 1..256,
+    # 1500 events spread over up to 81 DM trials and every width, 100 000 isolated candidates
+    widths = [1 << k for k in range(9)]
+    b, d, w, t, s = synth.candidate_tracks(71, 2048, widths, 12500, 1500, 100000, seed=3)
+    cands = list(zip(b.tolist(), d.tolist(), w.tolist(), t.tolist(), s.astype(float).tolist()))
+    assert len(cands) > 600000
+    print("cluster serving scale: candidates", len(cands), flush=True)
+    f_lo, df = synth.band(64)
+    p = arts.Plan(64, f_lo, df, synth.TSAMP, np.arange(2048) * 1.0, widths)
+    got = p.cluster_candidates(_records(cands), 71)
+    reps, _ = O.cluster_dm_width(cands)
+    assert _tuples(got) == sorted(reps, key=lambda r: (r[0], r[1], r[2], r[3]))
+
+
+# ------------------------------------------------------------------ offline (time, DM windows)
+def _records7(cands):
+    a = np.zeros(len(cands), dtype=arts.CANDIDATE_DTYPE)
+    for i, (b, d, w, t, s, ds, dm) in enumerate(cands):
+        a[i] = (t, b, d, w, ds, s, dm)
+    return a
+
+
+def _tuples7(arr):
+    return [(int(c["beam"]), int(c["dm_index"]), int(c["width"]), int(c["sample"]),
+             float(c["snr"]), int(c["downsample"]), float(c["dm"])) for c in arr]
+
+
+def _check_offline(cands, t_window, edges, min_snr):
+    rec = _records7(cands)
+    got = arts.arts_cluster_offline(rec, t_window, edges, min_snr)
+    ref = O.cluster_offline(_tuples7(rec), t_window, edges, float(np.float32(min_snr)))
+    assert _tuples7(got) == ref
+    return got
+
+
+def test_offline_golden_fixture():
+    with open(os.path.join(GOLDEN, "cluster_offline_tiny.json")) as f:
+        g = json.load(f)
+    got = _check_offline([tuple(c) for c in g["candidates"]], g["t_window"], g["dm_edges"],
+                         g["min_snr"])
+    want = [g["candidates"][i] for i in g["kept"]]
+    assert [(c[0], c[1], c[3]) for c in _tuples7(got)] == [(c[0], c[1], c[3]) for c in want]
+
+
+@pytest.mark.parametrize("n", [0, 1, 100, 50000])
+def test_offline_random_lists_match_oracle(n):
+    rng = np.random.default_rng(40 + n)
+    cands = []
+    for _ in range(n):
+        ds = int(rng.choice([1, 2, 4, 8]))
+        cands.append((int(rng.integers(71)), int(rng.integers(2048)), int(rng.choice([1, 4, 16])),
+                      int(rng.integers(-20000, 600000)) // ds,
+                      float(rng.choice([9.5, 10.0, 10.5, 12.0, 20.0])), ds,
+                      float(rng.choice([10.0, 20.0, 21.5, 50.0, 300.0, 1200.0, 4000.0]))))
+    got = _check_offline(cands, 6104, arts.offline_dm_edges(), 10.0)
+    assert len(got) <= n
+
+
+def test_offline_rejects_bad_input_and_reports_capacity():
+    base = [(0, 0, 1, 7, 11.0, 1, 30.0), (0, 1, 1, 9000, 12.0, 1, 30.0)]
+    for bad in [(0, 2, 0, 7, 11.0, 1, 30.0), (0, 2, 1, 7, 11.0, 0, 30.0),
+                (0, 2, 1, 7, float("nan"), 1, 30.0), (0, 2, 1, 1 << 43, 11.0, 1, 30.0)]:
+        with pytest.raises(arts.ArtsError) as e:
+            arts.arts_cluster_offline(_records7(base + [bad]), 6104, [20.0], 10.0)
+        assert e.value.status == arts.ARTS_E_INVAL
+    for edges in ([20.0, 20.0], [30.0, 20.0], []):
+        with pytest.raises(arts.ArtsError):
+            arts.arts_cluster_offline(_records7(base), 6104, edges, 10.0)
+    with pytest.raises(arts.ArtsError) as e:
+        arts.arts_cluster_offline(_records7(base), 6104, [20.0], 10.0, capacity=1)
+    assert e.value.status == arts.ARTS_E_CAPACITY
+
+
+def test_offline_after_streamed_dm_width_clusters():
+    # the paper's chain: per-chunk DM-width clusters from the stream, then the whole observation
+    # clustered over 0.5 s windows and widening DM windows, DM >= 20 and S/N >= 10
+    nsrc = 3
+    table = synth.sb_table_synthetic(4, nsrc, 64)
+    chunks = [synth.noise((nsrc, 64, 2400), seed=700 + k) for k in range(8)]
+    for k in (3, 5, 6):
+        hot = chunks[k][k % nsrc, :, 500:540].astype(int) + 70
+        chunks[k][k % nsrc, :, 500:540] = np.minimum(255, hot).astype(np.uint8)
+    _, b = _stream_pair(nsrc, 4, table, graph=False)
+    allc = []
+    with b:
+        for c in chunks:
+            b.push(to_dev(c))
+            allc.append(b.wait()[0])
+    allc = np.concatenate(allc)
+    assert len(allc) > 0
+    got = arts.arts_cluster_offline(allc, 6104, arts.offline_dm_edges(), 10.0)
+    ref = O.cluster_offline(_tuples7(allc), 6104, list(arts.offline_dm_edges()), 10.0)
+    assert _tuples7(got) == ref
