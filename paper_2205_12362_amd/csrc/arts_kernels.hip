@@ -1383,6 +1383,8 @@ constexpr int kCandResLds = 64 * 1024;
 // row of that length fills 2 workgroups per CU), else 4
 constexpr int kCandLong = 8192;
 constexpr int kMaxWidthsCand = 64;
+// plans with up to this many widths take the whole-row maxima of all widths in one pass
+constexpr int kCandRegW = 16;
 
 struct CandOut {
   arts_candidate* cand;
@@ -1435,6 +1437,7 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
   __shared__ int32_t t_prearg[NT], t_suf[NT];
   __shared__ double s_musig[2];
   __shared__ int s_hit[kMaxWidthsCand];
+  __shared__ unsigned long long s_hitmask;
 
   const int64_t row = blockIdx.x;
   const int32_t* x = series + row * pitch;
@@ -1495,6 +1498,7 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
         (static_cast<double>(S2c) - static_cast<double>(r) * static_cast<double>(r) / dn) / dn;
     s_musig[0] = static_cast<double>(m0) + static_cast<double>(r) / dn;
     s_musig[1] = var > 0.0 ? sqrt(var) : 0.0;
+    s_hitmask = 0;
   }
   __syncthreads();
   const double mu = s_musig[0], sigma = s_musig[1];
@@ -1520,9 +1524,54 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
   if constexpr (RES) {
     // exclusive prefix over x[-1 .. nres) with x[-1] = 0: B_w(t) = P[t + 1 + w] - P[t + 1]
     scan_inplace<NT>(P, nres + 1, wsum);
+    const int nr = static_cast<int>(nrep);
+    if (nw <= kCandRegW) {
+      // whole-row maximum of B_w for every width at once: each start's P[t + 1] is read once
+      // and reused by all widths (maxima in registers), then one workgroup-wide OR of the
+      // per-width hit bits
+      int wreg[kCandRegW];
+      int32_t bm[kCandRegW];
+#pragma unroll
+      for (int wi = 0; wi < kCandRegW; ++wi) {
+        wreg[wi] = wi < nw ? __builtin_amdgcn_readfirstlane(s_wid[wi]) : 0;
+        bm[wi] = INT_MIN;
+      }
+      int t0 = tid;
+      for (; t0 + 3 * NT < nr; t0 += 4 * NT) {
+        const uint32_t* q = P + t0 + 1;
+        uint32_t a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = q[u * NT];
+#pragma unroll
+        for (int wi = 0; wi < kCandRegW; ++wi) {
+          if (wi < nw) {
+            const uint32_t* qw = q + wreg[wi];
+            uint32_t b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) b[u] = qw[u * NT];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bm[wi] = max(bm[wi], static_cast<int32_t>(b[u] - a[u]));
+          }
+        }
+      }
+      for (; t0 < nr; t0 += NT) {
+        const uint32_t a0 = P[t0 + 1];
+#pragma unroll
+        for (int wi = 0; wi < kCandRegW; ++wi)
+          if (wi < nw) bm[wi] = max(bm[wi], static_cast<int32_t>(P[t0 + 1 + wreg[wi]] - a0));
+      }
+      unsigned long long hits = 0;
+#pragma unroll
+      for (int wi = 0; wi < kCandRegW; ++wi)
+        if (wi < nw && static_cast<long long>(bm[wi]) > s_thr[wi]) hits |= 1ULL << wi;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) hits |= __shfl_xor(hits, off, 64);
+      if ((tid & 63) == 0 && hits) atomicOr(&s_hitmask, hits);
+      __syncthreads();
+      if (tid < nw) s_hit[tid] = static_cast<int>((s_hitmask >> tid) & 1ULL);
+    } else {
     // whole-row maximum of B_w per width: groups of 8 starts 256 apart, whose 16 reads share
     // one base address (immediate offsets) and are in flight together; then the last starts
-    const int nr = static_cast<int>(nrep);
     for (int wi = 0; wi < nw; ++wi) {
       const int w = s_wid[wi];
       int32_t bmax = INT_MIN;
@@ -1543,6 +1592,7 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
         bmax = max(bmax, static_cast<int32_t>(P[t0 + 1 + w] - P[t0 + 1]));
       const int hit = __syncthreads_or(static_cast<long long>(bmax) > s_thr[wi] ? 1 : 0);
       if (tid == 0) s_hit[wi] = hit;
+    }
     }
   }
   int cin = 0;  // carry buffer holding runs open at the previous segment's end
