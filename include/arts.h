@@ -310,10 +310,13 @@ int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, f
  *   nsrc          source rows per chunk (beams, or TABs when sb_table is given)
  *   sb_table      device uint8 [nbeam][nchan] forming nbeam SBs from the nsrc TABs on the fly,
  *                 or NULL (then nbeam == nsrc)
- *   chunk         new native samples per push (a multiple of every plan's D)
+ *   chunk         new native samples per push (a multiple of every plan's D, and of 4 if a
+ *                 plan is a subband plan: its step-1 rows move by whole 8-byte groups)
  *   threshold     candidate S/N threshold;  cand_capacity: device candidate buffer entries
- *   flags         ARTS_STREAM_GRAPH: each push replays a captured hipGraph (two graphs, one per
- *                 ring parity);  ARTS_STREAM_PROFILE: time each phase with HIP events (phase 0
+ *   flags         ARTS_STREAM_GRAPH: each push replays a captured hipGraph (one per ring parity
+ *                 and position of the subband plans' step-1 windows, which move by one chunk per
+ *                 push inside their buffer and are copied back to its front when they reach
+ *                 its end);  ARTS_STREAM_PROFILE: time each phase with HIP events (phase 0
  *                 ring advance, 1..nplan dedispersion of plan i-1, nplan+1 statistics +
  *                 candidates of all plans).  The two flags are exclusive.
  * The stream owns its rings, series, workspace and a HIP stream of default priority.  Errors:

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -141,15 +142,20 @@ struct DedispJob {
   int64_t out_sstride = 0;         // out elements between channel groups (plans with a split)
   bool out16 = false;              // store the sums as uint16 (the caller bounds them)
   int64_t in16_blk = 0;            // in16 elements added per DM block
-  // subband plans: the caller's 16-bit intermediate (streams own one; null: the plan's).  With
-  // y_prev (the previous chunk's rows, same layout) only the last y_new step-1 samples are
-  // computed and the rest is taken from y_prev shifted by y_new.  Rows start y_pad elements
-  // into their pitch (chosen so that the new samples start 8-byte aligned).
+  // subband plans: the caller's 16-bit intermediate (streams own one; null: the plan's).  Row r
+  // of the window starts at y + r * y_pitch + y_pad (y_pitch 0: the plan's own pitch), chosen
+  // so that the new samples start 8-byte aligned.  With y_prev (the previous chunk's window,
+  // same pitch) only the last y_new step-1 samples are computed; the rest are the previous
+  // window's samples [y_new, L1), copied unless y_prev + y_new == y (already in place).
+  // y_elems: elements from y to the end of its buffer; [y_lo, y_hi): the buffer y_prev lies in.
   uint16_t* y = nullptr;
   const uint16_t* y_prev = nullptr;
   int64_t y_elems = 0;
   int64_t y_new = 0;
   int32_t y_pad = 0;
+  int64_t y_pitch = 0;
+  const uint16_t* y_lo = nullptr;
+  const uint16_t* y_hi = nullptr;
 };
 
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s);
@@ -236,9 +242,12 @@ struct arts_stream_s {
   std::vector<int64_t> N16;                // per plan: 16-bit samples held per row
   std::vector<int32_t*> series;
   std::vector<int64_t> L, H;
-  std::vector<uint16_t*> y[2];             // per plan: step-1 rows of subband plans (parity)
-  std::vector<int64_t> y_elems;
-  std::vector<int32_t> y_pad;
+  // per plan, subband plans only: one buffer of step-1 rows whose window origin moves by one
+  // chunk per push (y_at chunks in, at most y_m) and is compacted back to 0 after that
+  std::vector<uint16_t*> ybuf;
+  std::vector<int64_t> y_elems;            // buffer elements
+  std::vector<int64_t> y_pitch;            // row pitch (elements)
+  std::vector<int32_t> y_pad, y_m, y_at, y_from;  // y_from: previous origin, -1: none
   bool y_stale = false;                    // after a restore: the next push recomputes step 1
   arts_candidate* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
@@ -248,7 +257,8 @@ struct arts_stream_s {
   int64_t cap = 0;
   hipStream_t hs = nullptr;
   hipEvent_t ev_in = nullptr, ev_done = nullptr;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // captured pushes, keyed by the ring parity and each subband plan's window origin
+  std::map<std::vector<int>, hipGraphExec_t> graphs;
   int64_t pushed = 0, waited = 0;
   int64_t device_bytes = 0;
   // profiling: events bracketing each phase of the last push
@@ -262,6 +272,8 @@ namespace arts {
 
 // Stream internals (arts_stream.cpp), shared with the serving engine (arts_server.cpp).
 int stream_advance(arts_stream_s* s, int parity, hipStream_t hs);
+// Moves each subband plan's step-1 window for the next push (once per push, before its jobs).
+void stream_y_step(arts_stream_s* s);
 DedispJob stream_job(arts_stream_s* s, int parity, size_t plan_index);
 // Output samples of chunk k whose dedispersion window starts before the stream's first input
 // sample (they read the zero history) are left out of the statistics and the search: plan p

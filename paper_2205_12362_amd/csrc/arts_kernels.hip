@@ -999,26 +999,34 @@ static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
 static int launch_subband(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   const int64_t L1 = job.nin - p->max_d1;
   const int32_t pad = job.y ? job.y_pad : 0;
-  const int64_t L1p = subband_pitch(p, job.nin, pad);
+  const int64_t L1p = job.y && job.y_pitch > 0 ? job.y_pitch : subband_pitch(p, job.nin, pad);
   const int64_t rows = static_cast<int64_t>(job.nbeam) * p->nsub * p->ncoarse;
-  const int64_t need = rows * L1p;
-  if (L1 < 1 || job.nout > L1 - p->sb2->max_delay || pad < 0 || pad > 3)
+  const int64_t need = (rows - 1) * L1p + pad + L1;  // through the last row's window
+  if (L1 < 1 || job.nout > L1 - p->sb2->max_delay || pad < 0 || pad > 3 || L1p < pad + L1 ||
+      (L1p & 3) != 0)
     return fail(ARTS_E_INVAL, "internal: subband job shorter than its delays");
   uint16_t* y = job.y ? job.y : p->d_y;
-  if (need > (job.y ? job.y_elems : p->y_cap))
-    return fail(ARTS_E_INVAL, "internal: subband workspace not prepared");
+  const int64_t have = job.y ? job.y_elems : p->y_cap;
+  if (need > have) return fail(ARTS_E_INVAL, "internal: subband workspace not prepared");
   DedispJob j1 = job;
   j1.out = reinterpret_cast<int32_t*>(y + pad);
   j1.nout = L1;
   if (job.y && job.y_prev && job.y_new > 0 && job.y_new < L1) {
-    // rows [0, L1 - new) are the previous chunk's rows [new, L1); step 1 computes the rest
-    // from the last new + max_d1 input samples of the window
+    // rows [0, L1 - new) are the previous window's rows [new, L1): already in place when the
+    // window moved by `new` inside its buffer, else copied; step 1 computes the rest from the
+    // last new + max_d1 input samples of the window
     const int64_t keep = L1 - job.y_new;
-    const uint8_t* src = reinterpret_cast<const uint8_t*>(job.y_prev + pad + job.y_new);
-    const uint8_t* prev = reinterpret_cast<const uint8_t*>(job.y_prev);
-    if (int st = launch_copy_rows(reinterpret_cast<uint8_t*>(y + pad), 2 * L1p, src, 2 * L1p,
-                                  rows, 2 * keep, prev, prev + 2 * need, s))
-      return st;
+    const uint16_t* src = job.y_prev + pad + job.y_new;
+    if (src != y + pad) {
+      if (!job.y_lo || !job.y_hi || src < job.y_lo || src + (rows - 1) * L1p + keep > job.y_hi)
+        return fail(ARTS_E_INVAL, "internal: subband history outside its buffer");
+      const uint8_t* lo = reinterpret_cast<const uint8_t*>(job.y_lo);
+      const uint8_t* hi = reinterpret_cast<const uint8_t*>(job.y_hi);
+      if (int st = launch_copy_rows(reinterpret_cast<uint8_t*>(y + pad), 2 * L1p,
+                                    reinterpret_cast<const uint8_t*>(src), 2 * L1p, rows, 2 * keep,
+                                    lo, hi, s))
+        return st;
+    }
     j1.in = job.in + keep;
     j1.in_bytes = job.in_bytes - keep;
     j1.nin = job.y_new + p->max_d1;
@@ -1032,7 +1040,7 @@ static int launch_subband(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   if (int st = launch_dedisperse(p->sb1, j1, s)) return st;
   DedispJob j2;
   j2.in16 = y + pad;
-  j2.in16_elems = need - pad;
+  j2.in16_elems = have - pad;
   j2.pitch16 = static_cast<int64_t>(p->ncoarse) * L1p;
   j2.in16_blk = L1p;
   j2.nin = L1;

@@ -110,6 +110,7 @@ int arts_server_tick(arts_server_t v, int32_t* nrun) {
   for (auto* e : run) {
     arts_stream_s* s = e->s;
     const int parity = static_cast<int>(s->pushed & 1);
+    stream_y_step(s);
     if (int st = stream_advance(s, parity, v->hs)) return st;
     for (size_t p = 0; p < s->plans.size(); ++p) {
       if (s->plans[p]->nsub > 0) {  // subband plans: their own two-step launches

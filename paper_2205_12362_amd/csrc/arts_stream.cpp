@@ -27,8 +27,8 @@ int nphases(const arts_stream_s* s) { return static_cast<int>(s->plans.size()) +
 void stream_free(arts_stream_s* s) {
   if (!s) return;
   if (s->hs) (void)hipStreamSynchronize(s->hs);
-  for (auto& g : s->gexec)
-    if (g) (void)hipGraphExecDestroy(g);
+  for (auto& kv : s->graphs)
+    if (kv.second) (void)hipGraphExecDestroy(kv.second);
   for (auto* r : s->ring)
     if (r) (void)hipFree(r);
   for (auto& v : s->ring16)
@@ -37,9 +37,8 @@ void stream_free(arts_stream_s* s) {
   if (s->input) (void)hipFree(s->input);
   for (auto* p : s->series)
     if (p) (void)hipFree(p);
-  for (auto& v : s->y)
-    for (auto* y : v)
-      if (y) (void)hipFree(y);
+  for (auto* y : s->ybuf)
+    if (y) (void)hipFree(y);
   if (s->d_cand) (void)hipFree(s->d_cand);
   if (s->d_count) (void)hipFree(s->d_count);
   if (s->h_count) (void)hipHostFree(s->h_count);
@@ -61,8 +60,27 @@ int dev_alloc(arts_stream_s* s, void** p, size_t bytes) {
   return ARTS_OK;
 }
 
-// The device work of one push (ring advance, dedispersion per plan, statistics and
-// candidates); enqueued on s->hs, possibly under graph capture.
+// Step-1 row layout of a subband plan in a stream: L1 = halo + chunk - max step-1 delay samples
+// per window, a front pad that puts each chunk's new rows 8-byte aligned, and room for the
+// window to move m = floor(L1 / chunk) chunks before it is compacted back to the front (the
+// copy then never overlaps: it starts (m + 1) chunks in, past the L1 - chunk samples kept).
+struct YLayout {
+  int64_t l1 = 0, pitch = 0, rows = 0;
+  int32_t pad = 0, m = 0;
+};
+
+YLayout y_layout(const arts_plan_s* pl, int32_t nbeam, int64_t chunk) {
+  YLayout y;
+  if (pl->nsub == 0) return y;
+  const int64_t H = static_cast<int64_t>(pl->ds) * pl->halo;
+  y.l1 = H + chunk - pl->max_d1;
+  const int64_t keep = y.l1 - chunk;
+  y.pad = static_cast<int32_t>((4 - keep % 4) % 4);
+  y.m = static_cast<int32_t>(std::max<int64_t>(1, y.l1 / chunk));
+  y.pitch = (y.pad + y.l1 + y.m * chunk + 3) & ~int64_t(3);
+  y.rows = static_cast<int64_t>(nbeam) * pl->nsub * pl->ncoarse;
+  return y;
+}
 }  // namespace
 
 // Phases of one push, reused by the serving engine (which batches the dedispersion of many
@@ -119,8 +137,10 @@ int64_t stream_bytes_needed(const arts_plan_t* plans, int32_t nplan, int32_t nsr
     }
   }
   if (native) total += 2 * rows * ((hmax + chunk + 3) & ~int64_t(3));
-  for (int32_t i = 0; i < nplan; ++i)  // two parities of 16-bit step-1 rows
-    total += 4 * subband_ws_elems(plans[i], nbeam, static_cast<int64_t>(plans[i]->halo) + chunk);
+  for (int32_t i = 0; i < nplan; ++i) {  // 16-bit step-1 rows
+    const YLayout y = y_layout(plans[i], nbeam, chunk);
+    total += 2 * y.rows * y.pitch;
+  }
   int64_t cl_rows = 0;  // clustering workspace
   for (int32_t i = 0; i < nplan; ++i)
     if (plans[i]->cluster) cl_rows = std::max<int64_t>(cl_rows, static_cast<int64_t>(nbeam) * plans[i]->ndm);
@@ -143,11 +163,18 @@ DedispJob stream_job(arts_stream_s* s, int parity, size_t p) {
     job.in_bytes = rows * s->W - off;
     job.nin = s->H[p] + s->chunk;
     job.pitch = s->W;
-    job.y = s->y[parity][p];
-    job.y_prev = s->y_stale ? nullptr : s->y[parity ^ 1][p];
-    job.y_elems = s->y_elems[p];
-    job.y_new = s->chunk;
-    job.y_pad = s->y_pad[p];
+    if (pl->nsub > 0) {
+      uint16_t* b = s->ybuf[p];
+      const int64_t at = s->y_at[p] * s->chunk;
+      job.y = b + at;
+      job.y_prev = s->y_from[p] < 0 ? nullptr : b + s->y_from[p] * s->chunk;
+      job.y_elems = s->y_elems[p] - at;
+      job.y_new = s->chunk;
+      job.y_pad = s->y_pad[p];
+      job.y_pitch = s->y_pitch[p];
+      job.y_lo = b;
+      job.y_hi = b + s->y_elems[p];
+    }
   } else {
     job.in = s->input;  // unused: the kernel reads the 16-bit ring
     job.in_bytes = rows * s->chunk;
@@ -158,6 +185,19 @@ DedispJob stream_job(arts_stream_s* s, int parity, size_t p) {
     job.pitch16 = s->W16[p];
   }
   return job;
+}
+
+void stream_y_step(arts_stream_s* s) {
+  for (size_t p = 0; p < s->plans.size(); ++p) {
+    if (!s->ybuf[p]) continue;
+    if (s->y_stale) {  // recompute the whole window at the front
+      s->y_from[p] = -1;
+      s->y_at[p] = 0;
+    } else {
+      s->y_from[p] = s->y_at[p];
+      s->y_at[p] = s->y_at[p] < s->y_m[p] ? s->y_at[p] + 1 : 0;
+    }
+  }
 }
 
 int64_t stream_warmup(const arts_stream_s* s, size_t p, int64_t k) {
@@ -280,6 +320,11 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
       return fail(ARTS_E_INVAL, "chunk %lld is not a multiple of plan %d's downsampling %d",
                   (long long)chunk, i, p->ds);
     }
+    if (p->nsub > 0 && chunk % 4 != 0) {  // the step-1 window moves by whole 8-byte groups
+      stream_free(s);
+      return fail(ARTS_E_INVAL, "plan %d is a subband plan: the chunk must be a multiple of 4",
+                  i);
+    }
     s->plans.push_back(p);
     s->H.push_back(static_cast<int64_t>(p->ds) * p->halo);
     s->L.push_back(chunk / p->ds + p->wmax - 1);
@@ -321,23 +366,24 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
                        : static_cast<int>((reinterpret_cast<uintptr_t>(s->ring16[0][p]) >> 1) & 1u);
     st = prepare_plan(s->plans[p], nbeam, s->H[p] + chunk, g0, false);
   }
-  // subband plans: step-1 rows for both parities, zero like the history they stand for; the
-  // front pad puts each chunk's new rows 8-byte aligned
+  // subband plans: one buffer of step-1 rows, zero like the history they stand for (the first
+  // window sits at the front; every push moves it by one chunk)
   for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
-    const arts_plan_s* pl = s->plans[p];
-    const int64_t e = subband_ws_elems(pl, nbeam, s->H[p] + chunk);
-    const int64_t keep = s->H[p] - pl->max_d1;  // L1 - chunk
+    const YLayout y = y_layout(s->plans[p], nbeam, chunk);
+    const int64_t e = y.rows * y.pitch;
     s->y_elems.push_back(e);
-    s->y_pad.push_back(pl->nsub > 0 ? static_cast<int32_t>((4 - keep % 4) % 4) : 0);
-    for (int r = 0; r < 2; ++r) {
-      uint16_t* y = nullptr;
-      if (e > 0 && st == ARTS_OK) {
-        st = dev_alloc(s, reinterpret_cast<void**>(&y), e * sizeof(uint16_t));
-        if (st == ARTS_OK && hipMemset(y, 0, e * sizeof(uint16_t)) != hipSuccess)
-          st = fail(ARTS_E_DEVICE, "subband row clear failed");
-      }
-      s->y[r].push_back(y);
+    s->y_pitch.push_back(y.pitch);
+    s->y_pad.push_back(y.pad);
+    s->y_m.push_back(y.m);
+    s->y_at.push_back(0);
+    s->y_from.push_back(-1);
+    uint16_t* b = nullptr;
+    if (e > 0) {
+      st = dev_alloc(s, reinterpret_cast<void**>(&b), e * sizeof(uint16_t));
+      if (st == ARTS_OK && hipMemset(b, 0, e * sizeof(uint16_t)) != hipSuccess)
+        st = fail(ARTS_E_DEVICE, "subband row clear failed");
     }
+    s->ybuf.push_back(b);
   }
   for (size_t p = 0; p < s->plans.size() && st == ARTS_OK; ++p) {
     int32_t* ser = nullptr;
@@ -397,10 +443,15 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
   if (chunk && chunk != s->input)
     ARTS_HIP(hipMemcpyAsync(s->input, chunk, rows * s->chunk, hipMemcpyDeviceToDevice, s->hs));
   const int parity = static_cast<int>(s->pushed & 1);
+  stream_y_step(s);
   // warm-up chunks search a chunk-dependent part of each series: they run eagerly, and the
-  // graphs are captured once every plan searches its whole chunk
+  // graphs are captured once every plan searches its whole chunk, one per ring parity and
+  // step-1 window position
   if ((s->flags & kGraph) && stream_warm(s, s->pushed) && !s->y_stale) {
-    if (!s->gexec[parity]) {
+    std::vector<int> key{parity};
+    for (size_t p = 0; p < s->plans.size(); ++p) key.push_back(s->ybuf[p] ? s->y_at[p] : 0);
+    hipGraphExec_t& ge = s->graphs[key];
+    if (!ge) {
       hipGraph_t g = nullptr;
       ARTS_HIP(hipStreamBeginCapture(s->hs, hipStreamCaptureModeThreadLocal));
       const int st = enqueue_push(s, parity, false);
@@ -410,12 +461,14 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
         return st;
       }
       if (ce != hipSuccess) return fail(ARTS_E_DEVICE, "graph capture: %s", hipGetErrorString(ce));
-      const hipError_t ie = hipGraphInstantiate(&s->gexec[parity], g, nullptr, nullptr, 0);
+      const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
-      if (ie != hipSuccess)
+      if (ie != hipSuccess) {
+        ge = nullptr;
         return fail(ARTS_E_DEVICE, "graph instantiate: %s", hipGetErrorString(ie));
+      }
     }
-    ARTS_HIP(hipGraphLaunch(s->gexec[parity], s->hs));
+    ARTS_HIP(hipGraphLaunch(ge, s->hs));
   } else {
     if (int st = enqueue_push(s, parity, (s->flags & kProfile) != 0)) return st;
     s->pending_profile = (s->flags & kProfile) != 0;

@@ -189,3 +189,43 @@ def test_subband_stream_restore_and_graph():
             torch.cuda.synchronize()
             _ = (torch.ones(1000, device="cuda") * 2).sum().item()
             assert np.array_equal(st3.series(0).cpu().numpy(), ref[k]), k
+
+
+def test_subband_stream_in_server_equals_standalone():
+    # the serving engine advances the step-1 window of a subband stream like arts_stream_push,
+    # also while a native stream shares its ticks; compaction happens every m + 1 chunks
+    chunk = 1000
+    nchan, p, d1, d2 = _sub_stream_setup(chunk)
+    f_lo, df = synth.band(nchan)
+    q = arts.Plan(nchan, f_lo, df, synth.TSAMP, np.arange(0, 100, 2.0), [1, 2, 4])
+    chunks = [synth.noise((2, nchan, chunk), seed=400 + k) for k in range(9)]
+    with arts.Server(8 << 30) as srv:
+        a = srv.open([p], 2, chunk, 6.0)
+        b = srv.open([q], 1, chunk, 6.0)
+        served = []
+        for k, c in enumerate(chunks):
+            srv.submit(a, to_dev(c))
+            srv.submit(b, to_dev(c[:1]))
+            assert srv.tick() == 2
+            ca, _ = srv.collect(a)
+            srv.collect(b)
+            served.append((srv.series(a, 0).cpu().numpy().copy(), ca))
+    p2, _ = _plan_and_oracle(nchan, 8, 32, 64, dm_step=5.0, widths=(1, 2, 4))
+    H = p2.halo
+    full = np.concatenate([np.zeros((2, nchan, H), np.uint8)] + chunks, axis=2)
+    with arts.Stream([p2], 2, chunk, 6.0) as st:
+        for k, c in enumerate(chunks):
+            st.push(to_dev(c))
+            cands, _ = st.wait()
+            got = st.series(0).cpu().numpy()
+            assert np.array_equal(got, served[k][0]), k
+            assert np.array_equal(cands, served[k][1]), k
+            win = full[0][:, k * chunk: H + (k + 1) * chunk]
+            assert np.array_equal(got[0], O.subband_dedisperse(win, d1, d2, 32)), k
+
+
+def test_subband_stream_chunk_multiple_of_four():
+    nchan, p, _, _ = _sub_stream_setup(1000)
+    with pytest.raises(arts.ArtsError) as e:
+        arts.Stream([p], 1, 1002, 6.0)
+    assert e.value.status == arts.ARTS_E_INVAL
