@@ -373,11 +373,10 @@ def alert_bench(args):
     ntrial = sum(n for _, _, n, _ in ALERT_PLANS)
     units = NSB * ntrial * CHUNK
     ms_step = 1e3 * elapsed / args.steps
-    adds = 0
+    adds = 0  # per push once warm: step 1 on the new samples, step 2 on the series
     for p, (a, st, n, nf) in zip(plans, ALERT_PLANS):
         sbi = p.subband_info()
-        L1 = p.halo + CHUNK - sbi["max_delay1"]
-        adds += NSB * sbi["ncoarse"] * NCHAN * L1 + NSB * n * 32 * (CHUNK + 249)
+        adds += NSB * sbi["ncoarse"] * NCHAN * CHUNK + NSB * n * 32 * (CHUNK + 249)
     del pool
     torch.cuda.empty_cache()
     log("sensitivity against brute force ...")
