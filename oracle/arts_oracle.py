@@ -13,7 +13,8 @@ design notes of the repository; each is marked "reading".
 Parity status per function:
   channel_freqs, delay_table, tie_audit, downsample, sb_synthesize, dedisperse,
   dedisperse_at, subband_plan, subband_dedisperse, subband_dedisperse_at, boxcar, moments,
-  snr, candidates, cluster_dm_width, cluster_offline  -- pinned by closed forms / invariants / hand-worked
+  snr, candidates, cluster_dm_width, cluster_offline, rfi_time_domain, rfi_freq_domain,
+  rfi_clean  -- pinned by closed forms / invariants / hand-worked
   values / brute force in tests/test_oracle_pins.py (no function here is "parity unpinned").
 """
 from __future__ import annotations
@@ -400,3 +401,78 @@ def cluster_offline(cands, t_window: int, dm_edges, min_snr: float):
     kept = [tuple(cands[i]) for i in best.values()]
     kept.sort(key=lambda c: (int(c[3]) * int(c[5]), float(c[6]), int(c[0]), int(c[2])))
     return kept
+
+
+def _round_half_even_div(s: int, n: int) -> int:
+    """round_half_even(s / n) for integers s >= 0, n >= 1, exactly."""
+    q, r = divmod(s, n)
+    if 2 * r > n or (2 * r == n and q % 2 == 1):
+        q += 1
+    return q
+
+
+def _cut(values: np.ndarray, k: float) -> int:
+    """Largest value that is not an outlier: floor(mu + k sigma) with the population mean and
+    standard deviation of `values` (FP64 from exact integer sums); values above it are cut."""
+    v = np.asarray(values, dtype=np.int64)
+    n = v.size
+    s1 = int(v.sum())
+    s2 = int((v * v).sum())
+    mu = s1 / n
+    var = max(0.0, (s2 - s1 * s1 / n) / n)
+    return int(np.floor(mu + k * np.sqrt(var)))
+
+
+def rfi_time_domain(data: np.ndarray, k: float, niter: int = 3) -> np.ndarray:
+    """Time-domain RFI mitigation of one source row [nchan][nsamp] (Sect. 6b.2 "RFI mitigation",
+    Sect. 9 on the fraction of data lost: bright, wide-band, low-DM RFI, three iterations on
+    ever cleaner data, local statistics).
+
+    Readings: the statistic is the zero-DM series z(t) = sum_c x[c][t] over the chunk; in each
+    iteration the samples with z(t) > mean(z) + k std(z) (population, over the chunk's current
+    data) are replaced, in every channel, by that channel's mean over the other samples rounded
+    half to even.  A dispersed burst spreads over many samples of z and is left alone.
+    Returns a cleaned uint8 copy."""
+    x = np.array(data, dtype=np.int64)
+    for _ in range(niter):
+        z = x.sum(axis=0)
+        bad = z > _cut(z, k)
+        if not bad.any():
+            break
+        good = ~bad
+        n = int(good.sum())
+        for c in range(x.shape[0]):
+            x[c, bad] = _round_half_even_div(int(x[c, good].sum()), n)
+    return x.astype(np.uint8)
+
+
+def rfi_freq_domain(data: np.ndarray, k: float, niter: int = 3) -> np.ndarray:
+    """Frequency-domain RFI mitigation of one source row [nchan][nsamp] (narrow-band RFI, three
+    iterations, local statistics; same passages).
+
+    Readings: each spectrum (one sample, all channels) is cleaned on its own: in each iteration
+    the channels with x[c] > mean + k std (population, over the spectrum's current values) are
+    replaced by the mean of the other channels rounded half to even.  A broad-band signal
+    raises the whole spectrum and is left alone.  Returns a cleaned uint8 copy."""
+    x = np.array(data, dtype=np.int64)
+    for t in range(x.shape[1]):
+        col = x[:, t]
+        for _ in range(niter):
+            bad = col > _cut(col, k)
+            if not bad.any():
+                break
+            good = ~bad
+            col[bad] = _round_half_even_div(int(col[good].sum()), int(good.sum()))
+        x[:, t] = col
+    return x.astype(np.uint8)
+
+
+def rfi_clean(data: np.ndarray, k_time: float, k_freq: float, niter: int = 3) -> np.ndarray:
+    """Both filters on one chunk of source rows [nsrc][nchan][nsamp] (or one row
+    [nchan][nsamp]): the time-domain filter, then the frequency-domain filter, per row.
+    Reading: that order (the paper names the time-domain method first)."""
+    a = np.asarray(data)
+    rows = a[None] if a.ndim == 2 else a
+    out = np.stack([rfi_freq_domain(rfi_time_domain(r, k_time, niter), k_freq, niter)
+                    for r in rows])
+    return out[0] if a.ndim == 2 else out

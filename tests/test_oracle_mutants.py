@@ -256,6 +256,60 @@ def _offline_variant(kind):
     return cluster_offline
 
 
+def _rfi_variant(kind):
+    # the two RFI filters written out again with one planted change
+    def rhe(s, n):
+        if kind == "round half up":
+            return (2 * s + n) // (2 * n)
+        q, r = divmod(s, n)
+        return q + 1 if 2 * r > n or (2 * r == n and q % 2 == 1) else q
+
+    def outliers(v, k):
+        v = np.asarray(v, np.float64)
+        sd = v.std(ddof=1 if kind == "sample sigma" else 0)
+        if kind == "two-sided cut":
+            return np.abs(v - v.mean()) > k * sd
+        return v > np.floor(v.mean() + k * sd)
+
+    def rfi_time_domain(data, k, niter=3):
+        x = np.array(data, dtype=np.int64)
+        for _ in range(1 if kind == "one iteration" else niter):
+            if kind == "per-channel time cut":
+                for c in range(x.shape[0]):
+                    bad = outliers(x[c], k)
+                    if bad.any():
+                        x[c, bad] = rhe(int(x[c, ~bad].sum()), int((~bad).sum()))
+                continue
+            bad = outliers(x.sum(axis=0), k)
+            if not bad.any():
+                break
+            keep = np.ones_like(bad) if kind == "means include cut samples" else ~bad
+            for c in range(x.shape[0]):
+                x[c, bad] = rhe(int(x[c, keep].sum()), int(keep.sum()))
+        return x.astype(np.uint8)
+
+    def rfi_freq_domain(data, k, niter=3):
+        x = np.array(data, dtype=np.int64)
+        for t in range(x.shape[1]):
+            col = x[:, t]
+            for _ in range(1 if kind == "one iteration" else niter):
+                bad = outliers(col, k)
+                if not bad.any():
+                    break
+                col[bad] = rhe(int(col[~bad].sum()), int((~bad).sum()))
+            x[:, t] = col
+        return x.astype(np.uint8)
+
+    def rfi_clean(data, k_time, k_freq, niter=3):
+        a = np.asarray(data)
+        rows = a[None] if a.ndim == 2 else a
+        out = np.stack([rfi_freq_domain(rfi_time_domain(r, k_time, niter), k_freq, niter)
+                        for r in rows])
+        return out[0] if a.ndim == 2 else out
+    return dict(rfi_time_domain=rfi_time_domain, rfi_freq_domain=rfi_freq_domain,
+                rfi_clean=rfi_clean)
+
+
 MUTANTS = {
     "reference at lowest channel": dict(delay_table=_delay_variant(ref="min")),
     "floor instead of round": dict(delay_table=_delay_variant(rounding=np.floor)),
@@ -292,6 +346,12 @@ MUTANTS = {
         cluster_offline=_offline_variant("upper-closed DM windows")),
     "offline windows per beam": dict(cluster_offline=_offline_variant("windows per beam")),
     "offline ties to the last": dict(cluster_offline=_offline_variant("ties to the last")),
+    "rfi round half up": _rfi_variant("round half up"),
+    "rfi sample sigma": _rfi_variant("sample sigma"),
+    "rfi two-sided cut": _rfi_variant("two-sided cut"),
+    "rfi one iteration": _rfi_variant("one iteration"),
+    "rfi per-channel time cut": _rfi_variant("per-channel time cut"),
+    "rfi means include cut samples": _rfi_variant("means include cut samples"),
 }
 
 
@@ -315,6 +375,10 @@ def test_unmutated_cluster_rewrite_passes():
 
 def test_unmutated_offline_rewrite_passes():
     assert _run_all(_copy(cluster_offline=_offline_variant("none"))) == []
+
+
+def test_unmutated_rfi_rewrite_passes():
+    assert _run_all(_copy(**_rfi_variant("none"))) == []
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

@@ -679,6 +679,80 @@ def test_offline_rejects_bad_args():
         O.cluster_offline([(0, 0, 1, 5, 11.0, 0, 30.0)], 10, [20.0], 10.0)
 
 
+# ---------------------------------------------------------------- RFI mitigation
+def check_rfi_golden(o):
+    g = _load("rfi_tiny.json")
+    t = np.array(g["time"]["data"], np.uint8)
+    assert np.array_equal(o.rfi_time_domain(t, g["time"]["k"]), np.array(g["time"]["clean"]))
+    f = np.array(g["freq"]["data"], np.uint8)
+    assert np.array_equal(o.rfi_freq_domain(f, g["freq"]["k"]), np.array(g["freq"]["clean"]))
+    # both filters: the frequency-domain fixture has no time-domain outlier at k = 3
+    assert np.array_equal(o.rfi_clean(f, 3.0, g["freq"]["k"]), np.array(g["freq"]["clean"]))
+
+
+def check_rfi_targets(o):
+    nchan, nsamp = 96, 3000
+    base = synth.noise((nchan, nsamp), seed=41)
+    # quiet data: nothing moves at 6 sigma
+    assert np.array_equal(o.rfi_time_domain(base, 6.0), base)
+    assert np.array_equal(o.rfi_freq_domain(base, 6.0), base)
+    # a bright broad-band zero-DM spike: the time domain replaces the whole column by the
+    # channel means of the other samples, the frequency domain leaves it (the spectrum is flat)
+    x = base.copy()
+    x[:, 1200] = np.minimum(255, x[:, 1200].astype(int) + 60).astype(np.uint8)
+    t = o.rfi_time_domain(x, 6.0)
+    others = np.delete(np.arange(nsamp), 1200)
+    means = np.rint(base[:, others].astype(np.float64).mean(axis=1))
+    assert np.all(np.abs(t[:, 1200].astype(int) - means) <= 1)
+    assert np.array_equal(np.delete(t, 1200, axis=1), np.delete(x, 1200, axis=1))
+    assert np.array_equal(o.rfi_freq_domain(x, 6.0), x)
+    # only bright samples are cut: a dropout (a column of zeros) stays
+    w = base.copy()
+    w[:, 700] = 0
+    assert np.array_equal(o.rfi_time_domain(w, 6.0), w)
+    # a dispersed burst of the same energy spread over 500 samples passes the time domain
+    f_lo, df = synth.band(nchan)
+    d = o.delay_table(nchan, f_lo, df, synth.TSAMP, np.array([500.0]))[0]
+    y = base.copy()
+    synth.add_tophat(y, 1000 + d, 4, 30)
+    assert np.array_equal(o.rfi_time_domain(y, 6.0), y)
+    # narrow-band spikes in two channels at one sample: the frequency domain replaces them
+    assert np.array_equal(o.rfi_freq_domain(base, 5.0), base)
+    z = base.copy()
+    z[[10, 50], 2000] = 255
+    f = o.rfi_freq_domain(z, 5.0)
+    assert np.all(f[[10, 50], 2000] < 200)
+    assert np.array_equal(np.delete(f, 2000, axis=1), np.delete(z, 2000, axis=1))
+
+
+def check_rfi_iterations(o):
+    # every iteration cleans what the previous one exposed: two spikes of different height
+    # (zero-DM excess 400, 60 and 4 over a flat 400: each hides the next from the 3-sigma cut)
+    x = np.full((4, 200), 100, np.uint8)
+    x[:, 50] = 200
+    x[:, 120] = 115
+    x[:, 7] = 101
+    cols = [50, 120, 7]
+    for n in range(4):
+        y = o.rfi_time_domain(x, 3.0, niter=n)
+        assert [int(y[0, c]) for c in cols] == [100] * min(n, 3) + [200, 115, 101][min(n, 3):], n
+    # constant data are a fixed point of both filters
+    c = np.full((5, 40), 77, np.uint8)
+    assert np.array_equal(o.rfi_clean(c, 0.5, 0.5), c)
+
+
+def test_rfi_golden():
+    check_rfi_golden(O)
+
+
+def test_rfi_targets():
+    check_rfi_targets(O)
+
+
+def test_rfi_iterations():
+    check_rfi_iterations(O)
+
+
 ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif_span,
               check_zero_dm, check_impulse, check_sum_conservation, check_brute_force,
               check_linearity_shift_permutation, check_chunked_stream, check_tophat_exact,
@@ -686,4 +760,5 @@ ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif
               check_candidates_golden, check_injected_recovery, check_tophat_snr,
               check_subband_golden, check_subband_reductions, check_subband_smearing_bound,
               check_cluster_golden, check_cluster_brute_force, check_cluster_invariants,
-              check_offline_golden, check_offline_brute_force, check_offline_invariants]
+              check_offline_golden, check_offline_brute_force, check_offline_invariants,
+              check_rfi_golden, check_rfi_targets, check_rfi_iterations]
