@@ -33,6 +33,8 @@ THRESHOLD = 8.0
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  Exact integer adds: one 32-bit add per lane
 # per clock (v_add_u32), two with packed 16-bit adds (v_pk_add_u16).
 PEAK_INT32_ADDS = 256 * 64 * 2.4e9
+# RFI mitigation thresholds of --rfi (standard deviations; the paper does not give AMBER's)
+RFI_K_TIME, RFI_K_FREQ = 6.0, 5.0
 PEAK_PK16_ADDS = 2 * PEAK_INT32_ADDS
 
 
@@ -345,6 +347,8 @@ def alert_bench(args):
             for k in range(2)]
     stream = arts.Stream(plans, NTAB, CHUNK, THRESHOLD, sb_table=table, nbeam=NSB,
                          cand_capacity=1 << 20, profile=True)
+    if args.rfi:
+        stream.set_rfi(RFI_K_TIME, RFI_K_FREQ)
     cur = torch.cuda.current_stream()
     nwarm = max(args.warmup, stream.warm_chunks())
     for k in range(nwarm):
@@ -393,7 +397,8 @@ def alert_bench(args):
                                "819.2-3379.2/2.5 (40): 5120 trials; widths 1,5,10,25,50,100,"
                                "250; 12500 new samples per step",
                    "ntrial": ntrial, "nsb": NSB, "chunk": CHUNK, "threshold": THRESHOLD,
-                   "cluster": bool(args.cluster), "device_bytes": info["device_bytes"]},
+                   "cluster": bool(args.cluster), "rfi": bool(args.rfi),
+                   "device_bytes": info["device_bytes"]},
         "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
         "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                              "p99": float(np.percentile(lat_ms, 99)),
@@ -503,6 +508,9 @@ def main():
                          "clustering of a serving-scale candidate list")
     ap.add_argument("--cluster", action="store_true",
                     help="serving / alert: cluster each chunk's candidates (DM-width)")
+    ap.add_argument("--rfi", action="store_true",
+                    help="serving / alert: RFI mitigation of each chunk's TABs (time domain at "
+                         "6 sigma, frequency domain at 5 sigma, 3 iterations each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
@@ -551,6 +559,8 @@ def main():
 
     stream = arts.Stream([p_nat, p_ds], NTAB, CHUNK, THRESHOLD, sb_table=tbl, nbeam=NSB,
                          cand_capacity=1 << 20, graph=args.graph, profile=not args.graph)
+    if args.rfi:
+        stream.set_rfi(RFI_K_TIME, RFI_K_FREQ)
     info = stream.info()
     cur = torch.cuda.current_stream()
 
@@ -623,7 +633,8 @@ def main():
                    "nchan": NCHAN, "nsb": NSB, "ntab": NTAB, "chunk": CHUNK,
                    "ndm_native": int(w_nat.dms.size), "ndm_ds4": int(w_ds.dms.size),
                    "graph": bool(args.graph), "threshold": THRESHOLD,
-                   "cluster": bool(args.cluster), "device_bytes": info["device_bytes"]},
+                   "cluster": bool(args.cluster), "rfi": bool(args.rfi),
+                   "device_bytes": info["device_bytes"]},
         "adds_per_s": (units_nat + units_ds) * NCHAN * args.steps / elapsed,
         "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
         "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),

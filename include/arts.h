@@ -60,6 +60,32 @@ typedef struct arts_candidate {
   float dm;
 } arts_candidate;
 
+/* --------------------------------------------------------------------- RFI mitigation ---- */
+
+/* RFI mitigation of filterbank rows, in place (Sect. 6b.2 "RFI mitigation", optional in the
+ * paper: one filter for bright wide-band low-DM RFI and one for narrow-band RFI; Sect. 9 on the
+ * data lost to RFI: a time-domain and a frequency-domain method, each applied three times, every
+ * pass to the data the previous one cleaned, on local statistics).  Readings taken here:
+ *  - time domain, per row [nchan][nsamp]: the zero-DM series z(t) = sum_c x[c][t]; in each
+ *    iteration the samples with z(t) > floor(mean + k_time sigma) (population statistics of z
+ *    over the rows' nsamp samples) are replaced, in every channel, by that channel's mean over
+ *    the other samples, rounded half to even.  A dispersed burst is spread out in z and stays;
+ *  - frequency domain, per spectrum (one row, one sample): channels with
+ *    x[c] > floor(mean + k_freq sigma) over the spectrum are replaced by the mean of the other
+ *    channels, rounded half to even;
+ *  - the time domain runs first; an iteration that flags nothing ends its filter.
+ * The cuts floor(mean + k sigma) are exact: integer tests on the exact sums (an integer u is
+ * above mean + k sigma when D = n u - sum > 0 and D^2 > k^2 (n sum_sq - sum^2)).
+ * data: device uint8 [nrow][nchan] rows of `pitch` bytes, of which the first nsamp are used
+ * (e.g. the TABs of one chunk); nsamp * nchan <= 2^32.  k_time, k_freq: thresholds in standard
+ * deviations, 0 or within [2^-6, 1024].  niter_time, niter_freq: iterations (the paper: 3; 0
+ * turns a filter off).  nchan <= 4096 when niter_freq > 0.  Allocates a device workspace of about
+ * nrow * (8 nsamp + 12 nchan) bytes for the call; SYNCHRONISES stream.  Errors: ARTS_E_INVAL,
+ * ARTS_E_NOMEM, ARTS_E_DEVICE.                                                               */
+int arts_rfi_clean(uint8_t* data, int32_t nrow, int32_t nchan, int64_t nsamp, int64_t pitch,
+                   float k_time, int32_t niter_time, float k_freq, int32_t niter_freq,
+                   void* stream);
+
 /* ------------------------------------------------------------------------------ plans ---- */
 
 /* Host only (no device call): the plan's delay table.
@@ -327,6 +353,14 @@ typedef struct arts_stream_s* arts_stream_t;
 int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
                        const uint8_t* sb_table, int32_t nbeam, int64_t chunk, float threshold,
                        int64_t cand_capacity, uint32_t flags, arts_stream_t* out);
+
+/* Clean every chunk pushed from now on before it is searched: its nsrc source rows (the TABs
+ * of a stream with an SB table) go through the filters of arts_rfi_clean with these arguments
+ * (statistics over the chunk).  Call between pushes (ARTS_E_STATE while a chunk is in flight);
+ * the stream allocates its workspace here, and captured graphs are captured again.  niter_time
+ * = niter_freq = 0 turns cleaning off.  Errors: ARTS_E_INVAL, ARTS_E_STATE, ARTS_E_NOMEM.   */
+int arts_stream_set_rfi(arts_stream_t s, float k_time, int32_t niter_time, float k_freq,
+                        int32_t niter_freq);
 
 /* Device staging buffer [nsrc][nchan][chunk] owned by the stream: a producer may copy the next
  * chunk straight into it and push with chunk = that pointer (or NULL), avoiding a copy.        */

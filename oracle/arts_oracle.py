@@ -412,15 +412,28 @@ def _round_half_even_div(s: int, n: int) -> int:
 
 
 def _cut(values: np.ndarray, k: float) -> int:
-    """Largest value that is not an outlier: floor(mu + k sigma) with the population mean and
-    standard deviation of `values` (FP64 from exact integer sums); values above it are cut."""
+    """Largest value that is not an outlier: floor(mu + k sigma), exactly, with the population
+    mean and standard deviation of `values`; values above it are cut.  An integer u exceeds
+    mu + k sigma exactly when D = n u - s1 > 0 and D^2 > k^2 (n s2 - s1^2) (k >= 0, sums
+    exact); the FP64 value of mu + k sigma only gives the starting guess."""
+    from fractions import Fraction
     v = np.asarray(values, dtype=np.int64)
     n = v.size
     s1 = int(v.sum())
     s2 = int((v * v).sum())
-    mu = s1 / n
-    var = max(0.0, (s2 - s1 * s1 / n) / n)
-    return int(np.floor(mu + k * np.sqrt(var)))
+    var_n2 = n * s2 - s1 * s1
+    kk = Fraction(k) ** 2
+
+    def above(u):
+        d = n * u - s1
+        return d > 0 and d * d > kk * var_n2
+
+    c = int(np.floor(s1 / n + k * np.sqrt(max(0, var_n2)) / n))
+    while above(c):
+        c -= 1
+    while not above(c + 1):
+        c += 1
+    return c
 
 
 def rfi_time_domain(data: np.ndarray, k: float, niter: int = 3) -> np.ndarray:
@@ -430,9 +443,11 @@ def rfi_time_domain(data: np.ndarray, k: float, niter: int = 3) -> np.ndarray:
 
     Readings: the statistic is the zero-DM series z(t) = sum_c x[c][t] over the chunk; in each
     iteration the samples with z(t) > mean(z) + k std(z) (population, over the chunk's current
-    data) are replaced, in every channel, by that channel's mean over the other samples rounded
+    data; decided exactly) are replaced, in every channel, by that channel's mean over the other samples rounded
     half to even.  A dispersed burst spreads over many samples of z and is left alone.
     Returns a cleaned uint8 copy."""
+    if not k >= 0:
+        raise ValueError("k must be >= 0")
     x = np.array(data, dtype=np.int64)
     for _ in range(niter):
         z = x.sum(axis=0)
@@ -454,6 +469,8 @@ def rfi_freq_domain(data: np.ndarray, k: float, niter: int = 3) -> np.ndarray:
     the channels with x[c] > mean + k std (population, over the spectrum's current values) are
     replaced by the mean of the other channels rounded half to even.  A broad-band signal
     raises the whole spectrum and is left alone.  Returns a cleaned uint8 copy."""
+    if not k >= 0:
+        raise ValueError("k must be >= 0")
     x = np.array(data, dtype=np.int64)
     for t in range(x.shape[1]):
         col = x[:, t]

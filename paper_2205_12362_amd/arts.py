@@ -63,6 +63,8 @@ _SIGNATURES = {
     "arts_plan_cluster": (C.c_int, [_vp, _vp, _i64, _i32, _i32, _pi64, _vp]),
     "arts_cluster_offline": (C.c_int, [_vp, _i64, _i64, _pf64, _i32, _f32, _vp, _i64, _pi64,
                                        _vp]),
+    "arts_rfi_clean": (C.c_int, [_vp, _i32, _i32, _i64, _i64, _f32, _i32, _f32, _i32, _vp]),
+    "arts_stream_set_rfi": (C.c_int, [_vp, _f32, _i32, _f32, _i32]),
     "arts_tiling_count": (_i32, []),
     "arts_plan_autotune": (C.c_int, [_vp, _i32, _i64, _i32, C.c_char_p, _pi32,
                                      C.POINTER(C.c_float)]),
@@ -408,6 +410,21 @@ def arts_cluster_offline(cand, t_window, dm_edges, min_snr, capacity=None, strea
     return buf[: cnt.value].copy()
 
 
+def arts_rfi_clean(data, k_time, k_freq, niter_time=3, niter_freq=3, nsamp=None, stream=None):
+    """Clean a device uint8 tensor [nrow][nchan][pitch] in place (the first nsamp samples of
+    each row, default all)."""
+    import torch
+    if data.dtype != torch.uint8 or not data.is_cuda or data.dim() != 3 or not \
+            data.is_contiguous():
+        raise ValueError("data must be a contiguous device uint8 tensor [nrow][nchan][pitch]")
+    nrow, nchan, pitch = data.shape
+    _check(lib().arts_rfi_clean(data.data_ptr(), nrow, nchan,
+                                pitch if nsamp is None else int(nsamp), pitch, float(k_time),
+                                int(niter_time), float(k_freq), int(niter_freq),
+                                _stream(stream)))
+    return data
+
+
 def offline_dm_edges(dm_lo=20.0, dm_hi=5000.0, ratio=1.1):
     """DM window edges that widen with DM: dm_lo, dm_lo * ratio, ... up to dm_hi (the paper's
     DM limit is 20; it does not give the widths, so the 10 % growth is this helper's choice)."""
@@ -624,6 +641,10 @@ class Stream:
 
     def info(self):
         return arts_stream_info(self.handle)
+
+    def set_rfi(self, k_time, k_freq, niter_time=3, niter_freq=3):
+        _check(lib().arts_stream_set_rfi(self.handle, float(k_time), int(niter_time),
+                                         float(k_freq), int(niter_freq)))
 
     def timing(self, phase):
         return arts_stream_timing(self.handle, phase)

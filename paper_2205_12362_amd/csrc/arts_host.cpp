@@ -648,6 +648,28 @@ int arts_plan_get_cluster(arts_plan_t p, int32_t* enable) {
   return ARTS_OK;
 }
 
+int arts_rfi_clean(uint8_t* data, int32_t nrow, int32_t nchan, int64_t nsamp, int64_t pitch,
+                   float k_time, int32_t niter_time, float k_freq, int32_t niter_freq,
+                   void* stream) {
+  if (!data) return fail(ARTS_E_INVAL, "data is NULL");
+  if (nrow < 1 || nchan < 1 || nsamp < 1 || pitch < nsamp)
+    return fail(ARTS_E_INVAL, "nrow, nchan, nsamp >= 1 and pitch >= nsamp required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  const int64_t bytes = rfi_ws_bytes(nrow, nchan, nsamp);
+  if (hipMalloc(&ws, bytes) != hipSuccess)
+    return fail(ARTS_E_NOMEM, "RFI workspace of %lld bytes", (long long)bytes);
+  struct Free {
+    void* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{ws};
+  if (int st = launch_rfi(data, nrow, nchan, nsamp, pitch, k_time, niter_time, k_freq,
+                          niter_freq, ws, s))
+    return st;
+  ARTS_HIP(hipStreamSynchronize(s));
+  return ARTS_OK;
+}
+
 int arts_cluster_offline(const arts_candidate* cand, int64_t n, int64_t t_window,
                          const double* dm_edges, int32_t nedge, float min_snr,
                          arts_candidate* host_out, int64_t capacity, int64_t* count,

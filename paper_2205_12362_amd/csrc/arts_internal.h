@@ -209,6 +209,12 @@ int launch_cluster(ClusterWs& w, arts_candidate* cand, unsigned long long* count
                    bool from_mark, int32_t nbeam, int32_t ndm, int32_t beam_offset,
                    hipStream_t s);
 int read_cluster_status(ClusterWs& w, int* skipped, int* bad, hipStream_t s);
+// RFI mitigation of [nrow][nchan] rows of `pitch` bytes (nsamp used), in place; the workspace
+// has rfi_ws_bytes(nrow, nchan, nsamp) bytes.
+int64_t rfi_ws_bytes(int32_t nrow, int32_t nchan, int64_t nsamp);
+int launch_rfi(uint8_t* x, int32_t nrow, int32_t nchan, int64_t nsamp, int64_t pitch,
+               float k_time, int32_t niter_time, float k_freq, int32_t niter_freq, void* ws,
+               hipStream_t s);
 // Offline clustering over time / DM windows (arts_cluster_offline).  The workspace of
 // offline_ws_bytes(n, nedge) bytes holds a counter, the hash table, the DM edges (copy them to
 // offline_edges(ws, n) first) and the output records; *out, *d_count and *d_bad point into it.
@@ -254,6 +260,10 @@ struct arts_stream_s {
   unsigned long long* h_count = nullptr;  // pinned
   std::vector<char> cluster;               // per plan: cluster its candidates (set at creation)
   arts::ClusterWs cl;
+  // RFI mitigation of each pushed chunk (arts_stream_set_rfi): thresholds, iterations, workspace
+  float rfi_kt = 0, rfi_kf = 0;
+  int32_t rfi_nt = 0, rfi_nf = 0;
+  void* rfi_ws = nullptr;
   int64_t cap = 0;
   hipStream_t hs = nullptr;
   hipEvent_t ev_in = nullptr, ev_done = nullptr;

@@ -43,6 +43,7 @@ void stream_free(arts_stream_s* s) {
   if (s->d_count) (void)hipFree(s->d_count);
   if (s->h_count) (void)hipHostFree(s->h_count);
   free_cluster_ws(s->cl);
+  if (s->rfi_ws) (void)hipFree(s->rfi_ws);
   for (auto e : s->pev)
     if (e) (void)hipEventDestroy(e);
   if (s->ev_in) (void)hipEventDestroy(s->ev_in);
@@ -88,6 +89,10 @@ YLayout y_layout(const arts_plan_s* pl, int32_t nbeam, int64_t chunk) {
 namespace arts {
 
 int stream_advance(arts_stream_s* s, int parity, hipStream_t hs) {
+  if (s->rfi_ws && (s->rfi_nt > 0 || s->rfi_nf > 0))  // clean the new chunk before it is used
+    if (int st = launch_rfi(s->input, s->nsrc, s->nchan, s->chunk, s->chunk, s->rfi_kt,
+                            s->rfi_nt, s->rfi_kf, s->rfi_nf, s->rfi_ws, hs))
+      return st;
   uint8_t* dst = s->ring[parity];
   const uint8_t* src = s->ring[parity ^ 1];
   const int64_t rows = static_cast<int64_t>(s->nsrc) * s->nchan;
@@ -588,6 +593,29 @@ int arts_stream_restore(arts_stream_t s, const uint8_t* host, int64_t bytes,
 int arts_stream_snapshot_bytes(arts_stream_t s, int64_t* bytes) {
   if (!s || !bytes) return fail(ARTS_E_INVAL, "NULL argument");
   *bytes = ring_bytes_total(s);
+  return ARTS_OK;
+}
+
+int arts_stream_set_rfi(arts_stream_t s, float k_time, int32_t niter_time, float k_freq,
+                        int32_t niter_freq) {
+  if (!s) return fail(ARTS_E_INVAL, "stream is NULL");
+  const auto k_ok = [](float k) { return k == 0.0f || (k >= 0.015625f && k <= 1024.0f); };
+  if (niter_time < 0 || niter_freq < 0 || !k_ok(k_time) || !k_ok(k_freq))
+    return fail(ARTS_E_INVAL, "RFI: iterations >= 0, thresholds 0 or within [2^-6, 1024]");
+  if (niter_freq > 0 && s->nchan > 4096)
+    return fail(ARTS_E_INVAL, "RFI: at most 4096 channels for the frequency-domain filter");
+  if (s->pushed != s->waited) return fail(ARTS_E_STATE, "a chunk is in flight");
+  if (!s->rfi_ws && (niter_time > 0 || niter_freq > 0)) {
+    const int64_t bytes = rfi_ws_bytes(s->nsrc, s->nchan, s->chunk);
+    if (int st = dev_alloc(s, &s->rfi_ws, bytes)) return st;
+  }
+  s->rfi_kt = k_time;
+  s->rfi_nt = niter_time;
+  s->rfi_kf = k_freq;
+  s->rfi_nf = niter_freq;
+  for (auto& kv : s->graphs)  // captured pushes do not clean: capture again
+    if (kv.second) (void)hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
   return ARTS_OK;
 }
 
