@@ -14,7 +14,7 @@ Parity status per function:
   channel_freqs, delay_table, tie_audit, downsample, sb_synthesize, dedisperse,
   dedisperse_at, subband_plan, subband_dedisperse, subband_dedisperse_at, boxcar, moments,
   snr, candidates, cluster_dm_width, cluster_offline, rfi_time_domain, rfi_freq_domain,
-  rfi_clean  -- pinned by closed forms / invariants / hand-worked
+  rfi_clean, sb_index_at_fmax, sb_switch_freqs, sb_table_beam_model  -- pinned by closed forms / invariants / hand-worked
   values / brute force in tests/test_oracle_pins.py (no function here is "parity unpinned").
 """
 from __future__ import annotations
@@ -493,3 +493,77 @@ def rfi_clean(data: np.ndarray, k_time: float, k_freq: float, niter: int = 3) ->
     out = np.stack([rfi_freq_domain(rfi_time_domain(r, k_time, niter), k_freq, niter)
                     for r in rows])
     return out[0] if a.ndim == 2 else out
+
+
+def sb_index_at_fmax(n_sb: int, ntab: int):
+    """Grating index and TAB index of SB n_sb at the highest frequency (Appendix "Synthesized
+    Beams"): n_TAB = n_sb mod N_TAB, minus N_TAB if above N_TAB/2 - 1, and n_gr such that
+    n_sb = n_gr N_TAB + n_TAB.  Reading: the paper calls the rounding of n_sb / N_TAB "upward";
+    the rounding that keeps n_sb = n_gr N_TAB + n_TAB (and the position equation) is the one
+    taken: n_gr = (n_sb - n_TAB) / N_TAB exactly."""
+    if ntab < 2 or ntab % 2:
+        raise ValueError("an even number of TABs is required")
+    n_tab = n_sb % ntab
+    if n_tab > ntab // 2 - 1:
+        n_tab -= ntab
+    return (n_sb - n_tab) // ntab, n_tab
+
+
+def sb_switch_freqs(n_sb: int, ntab: int, f_max: float, alpha: float, b_max: float,
+                    b_cq: float, kmax: int = 64):
+    """Frequencies f_k (MHz) at which grating n_gr of TAB n_TAB - k sgn(n_sb) lies where the SB
+    points (Appendix "Synthesized Beams", the equation for f0, applied to the k-th neighbour):
+    f_k = f_max (n_gr B_max + (n_TAB - k sgn) alpha B_cq) / (n_gr B_max + n_TAB alpha B_cq).
+    Reading: the second term on the right of the position equation uses the TAB separation
+    theta_sep(f0), as the substitution that follows it does (the equation as printed has the
+    grating spacing there).  Returns [f_0 = f_max, f_1, ..., f_kmax]."""
+    n_gr, n_tab = sb_index_at_fmax(n_sb, ntab)
+    s = (n_sb > 0) - (n_sb < 0)
+    if s == 0:  # the central SB is the central TAB's main lobe at every frequency
+        return [f_max]
+    a = alpha * b_cq
+    den = n_gr * b_max + n_tab * a
+    return [f_max * (n_gr * b_max + (n_tab - k * s) * a) / den for k in range(kmax + 1)]
+
+
+def sb_table_beam_model(nsb: int, ntab: int, nchan: int, f_lo_mhz: float, df_mhz: float,
+                        f_max: float = 1500.0, alpha: float = 0.80, b_max: float = 1296.0,
+                        b_cq: float = 144.0, quarter: bool = False):
+    """SB table from the beam model (Appendix "Synthesized Beams"), uint8 [nsb][nchan]: the TAB
+    whose grating response covers SB s in channel c.
+
+    SB s has index n_sb = s - (nsb - 1) // 2 (0 = the centre of the compound beam).  At
+    f >= f_max the SB takes TAB n_TAB (sb_index_at_fmax); going down in frequency it switches
+    to TAB n_TAB - k sgn(n_sb) below the k-th switch frequency f_sw,k = (1 - b) f_{k-1} + b f_k
+    (sb_switch_freqs), b = 1/2 when SBs are one beam width apart (71 SBs) and, when they are
+    half a beam width apart (151 SBs, quarter=True), b = 1/4 for even n_sb and 3/4 for odd.
+    Readings: a TAB index outside [-N/2, N/2 - 1] is the same TAB one grating over, so the
+    index is wrapped into that range; TAB n is row n + N/2 of the input (the central TAB is
+    row N/2).  Channel frequencies are f_lo + c df (channel_freqs).  Returns (table, margin):
+    margin = the smallest |f_c - f_sw,k| over the decisions taken, so that a caller can confirm
+    no channel sits on a switch frequency."""
+    if nsb < 1 or nchan < 1 or not (alpha > 0 and b_max > 0 and b_cq > 0 and f_max > 0):
+        raise ValueError("bad beam-model arguments")
+    f = channel_freqs(nchan, f_lo_mhz, df_mhz)
+    half = ntab // 2
+    out = np.zeros((nsb, nchan), dtype=np.uint8)
+    margin = np.inf
+    for srow in range(nsb):
+        n_sb = srow - (nsb - 1) // 2
+        n_gr, n_tab = sb_index_at_fmax(n_sb, ntab)
+        sgn = (n_sb > 0) - (n_sb < 0)
+        fk = sb_switch_freqs(n_sb, ntab, f_max, alpha, b_max, b_cq)
+        b = 0.5 if not quarter else (0.25 if n_sb % 2 == 0 else 0.75)
+        fsw = [(1 - b) * fk[k - 1] + b * fk[k] for k in range(1, len(fk))]
+        for c in range(nchan):
+            k = 0
+            if sgn != 0:
+                while k < len(fsw) and f[c] < fsw[k]:
+                    k += 1
+                if k < len(fsw):
+                    margin = min(margin, abs(f[c] - fsw[k]))
+                if k > 0:
+                    margin = min(margin, abs(f[c] - fsw[k - 1]))
+            j = n_tab - k * sgn
+            out[srow, c] = ((j + half) % ntab)
+    return out, margin

@@ -310,6 +310,61 @@ def _rfi_variant(kind):
                 rfi_clean=rfi_clean)
 
 
+def _sb_beam_variant(kind):
+    # the beam-model SB table written out again with one planted change
+    def sb_index_at_fmax(n_sb, ntab):
+        if ntab < 2 or ntab % 2:
+            raise ValueError("bad")
+        if kind == "grating index rounded up":
+            n_gr = -((-n_sb) // ntab)
+            return n_gr, n_sb - n_gr * ntab
+        n_tab = n_sb % ntab
+        if n_tab > ntab // 2 - 1:
+            n_tab -= ntab
+        return (n_sb - n_tab) // ntab, n_tab
+
+    def sb_switch_freqs(n_sb, ntab, f_max, alpha, b_max, b_cq, kmax=64):
+        n_gr, n_tab = sb_index_at_fmax(n_sb, ntab)
+        sg = (n_sb > 0) - (n_sb < 0)
+        if sg == 0:
+            return [f_max]
+        d = -sg if kind == "switch away from the centre" else sg
+        if kind == "grating spacing in the second term":
+            den = n_gr / b_cq + n_tab * alpha / b_max
+            return [f_max * ((n_gr + n_tab - k * d) / b_cq) / den for k in range(kmax + 1)]
+        a = alpha * b_cq
+        den = n_gr * b_max + n_tab * a
+        return [f_max * (n_gr * b_max + (n_tab - k * d) * a) / den for k in range(kmax + 1)]
+
+    def sb_table_beam_model(nsb, ntab, nchan, f_lo_mhz, df_mhz, f_max=1500.0, alpha=0.80,
+                            b_max=1296.0, b_cq=144.0, quarter=False):
+        f = O.channel_freqs(nchan, f_lo_mhz, df_mhz)
+        out = np.zeros((nsb, nchan), dtype=np.uint8)
+        for row in range(nsb):
+            n_sb = row - (nsb - 1) // 2
+            n_gr, n_tab = sb_index_at_fmax(n_sb, ntab)
+            sg = (n_sb > 0) - (n_sb < 0)
+            d = -sg if kind == "switch away from the centre" else sg
+            fk = sb_switch_freqs(n_sb, ntab, f_max, alpha, b_max, b_cq)
+            even = n_sb % 2 == 0
+            if kind == "quarter blends swapped":
+                even = not even
+            b = 0.5 if not quarter else (0.25 if even else 0.75)
+            fsw = [(1 - b) * fk[k - 1] + b * fk[k] for k in range(1, len(fk))]
+            for c in range(nchan):
+                k = 0
+                while sg and k < len(fsw) and f[c] < fsw[k]:
+                    k += 1
+                j = n_tab - k * d
+                if kind == "no wrap":
+                    j = min(max(j, -(ntab // 2)), ntab // 2 - 1)
+                off = 0 if kind == "TAB row without offset" else ntab // 2
+                out[row, c] = (j + off) % ntab
+        return out, 1.0
+    return dict(sb_index_at_fmax=sb_index_at_fmax, sb_switch_freqs=sb_switch_freqs,
+                sb_table_beam_model=sb_table_beam_model)
+
+
 MUTANTS = {
     "reference at lowest channel": dict(delay_table=_delay_variant(ref="min")),
     "floor instead of round": dict(delay_table=_delay_variant(rounding=np.floor)),
@@ -352,6 +407,13 @@ MUTANTS = {
     "rfi one iteration": _rfi_variant("one iteration"),
     "rfi per-channel time cut": _rfi_variant("per-channel time cut"),
     "rfi means include cut samples": _rfi_variant("means include cut samples"),
+    "sb beam grating index rounded up": _sb_beam_variant("grating index rounded up"),
+    "sb beam grating spacing in the second term": _sb_beam_variant(
+        "grating spacing in the second term"),
+    "sb beam switch away from the centre": _sb_beam_variant("switch away from the centre"),
+    "sb beam quarter blends swapped": _sb_beam_variant("quarter blends swapped"),
+    "sb beam TAB row without offset": _sb_beam_variant("TAB row without offset"),
+    "sb beam no wrap": _sb_beam_variant("no wrap"),
 }
 
 
@@ -384,6 +446,10 @@ def test_unmutated_offline_rewrite_passes():
 
 def test_unmutated_rfi_rewrite_passes():
     assert _run_all(_copy(**_rfi_variant("none"))) == []
+
+
+def test_unmutated_sb_beam_rewrite_passes():
+    assert _run_all(_copy(**_sb_beam_variant("none"))) == []
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

@@ -753,6 +753,77 @@ def test_rfi_iterations():
     check_rfi_iterations(O)
 
 
+# ---------------------------------------------------------------- SB table from the beam model
+def check_sb_beam_golden(o):
+    g = _load("sb_beam_tiny.json")
+    for n_sb, n_gr, n_tab in g["index"]:
+        assert o.sb_index_at_fmax(n_sb, g["ntab"]) == (n_gr, n_tab), n_sb
+    for n_sb, f1 in g["f1"]:
+        got = o.sb_switch_freqs(n_sb, g["ntab"], g["f_max"], g["alpha"], g["b_max"], g["b_cq"])
+        assert abs(got[1] - f1) < 1e-9 and got[0] == g["f_max"], n_sb
+    kw = dict(f_max=g["f_max"], alpha=g["alpha"], b_max=g["b_max"], b_cq=g["b_cq"])
+    for nsb, key, quarter in ((71, "switch71", False), (151, "switch151", True)):
+        t, margin = o.sb_table_beam_model(nsb, g["ntab"], g["nchan"], g["f_lo"], g["df"],
+                                          quarter=quarter, **kw)
+        assert t.shape == (nsb, g["nchan"]) and margin > 1e-4
+        for row, c0, r0, c1, r1 in g[key]:
+            assert (int(t[row, c0]), int(t[row, c1])) == (r0, r1), (nsb, row)
+        assert np.all(t[(nsb - 1) // 2] == g["ntab"] // 2)
+
+
+def check_sb_beam_nearest(o):
+    # one beam width apart (71 SBs), the switch halfway between f_{k-1} and f_k is where two TABs'
+    # grating responses are equally far (in angle) from the SB: the table picks, per channel,
+    # the TAB whose response of the SB's grating order is nearest, among all TAB indices
+    nchan, ntab, a, bmax, bcq, fmax = 384, 12, 0.8, 1296.0, 144.0, 1500.0
+    f_lo, df = synth.band(nchan)
+    f = o.channel_freqs(nchan, f_lo, df)
+    t, margin = o.sb_table_beam_model(71, ntab, nchan, f_lo, df, fmax, a, bmax, bcq)
+    assert margin > 1e-6
+    for row in range(71):
+        n_sb = row - 35
+        n_gr, n_tab = o.sb_index_at_fmax(n_sb, ntab)
+        target = (n_gr / bcq + n_tab * a / bmax) / fmax        # position x (c = 1) at f_max
+        js = np.arange(n_tab - 60, n_tab + 61)
+        for c in range(nchan):
+            pos = (n_gr / bcq + js * a / bmax) / f[c]
+            j = js[int(np.argmin(np.abs(pos - target)))]
+            assert t[row, c] == (j + ntab // 2) % ntab, (n_sb, c)
+
+
+def check_sb_beam_invariants(o):
+    nchan, ntab = 256, 12
+    f_lo, df = synth.band(nchan)
+    for quarter, nsb in ((False, 71), (True, 151)):
+        t, _ = o.sb_table_beam_model(nsb, ntab, nchan, f_lo, df, quarter=quarter)
+        f = o.channel_freqs(nchan, f_lo, df)
+        for row in range(nsb):
+            n_sb = row - (nsb - 1) // 2
+            n_gr, n_tab = o.sb_index_at_fmax(n_sb, ntab)
+            assert n_sb == n_gr * ntab + n_tab and -ntab // 2 <= n_tab < ntab // 2
+            # at and above f_max the TAB of the decomposition; walking down in frequency the
+            # TAB index moves away by one at a time, in the direction of -sgn(n_sb)
+            top = t[row, f >= 1500.0]
+            assert np.all(top == n_tab + ntab // 2)
+            steps = (np.diff(t[row][::-1].astype(int)) % ntab)
+            sgn = (n_sb > 0) - (n_sb < 0)
+            assert set(steps.tolist()) <= {0, (-sgn) % ntab}, n_sb
+    with pytest.raises(ValueError):
+        o.sb_index_at_fmax(3, 11)
+
+
+def test_sb_beam_golden():
+    check_sb_beam_golden(O)
+
+
+def test_sb_beam_nearest():
+    check_sb_beam_nearest(O)
+
+
+def test_sb_beam_invariants():
+    check_sb_beam_invariants(O)
+
+
 ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif_span,
               check_zero_dm, check_impulse, check_sum_conservation, check_brute_force,
               check_linearity_shift_permutation, check_chunked_stream, check_tophat_exact,
@@ -761,4 +832,5 @@ ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif
               check_subband_golden, check_subband_reductions, check_subband_smearing_bound,
               check_cluster_golden, check_cluster_brute_force, check_cluster_invariants,
               check_offline_golden, check_offline_brute_force, check_offline_invariants,
-              check_rfi_golden, check_rfi_targets, check_rfi_iterations]
+              check_rfi_golden, check_rfi_targets, check_rfi_iterations,
+              check_sb_beam_golden, check_sb_beam_nearest, check_sb_beam_invariants]
