@@ -508,6 +508,9 @@ def main():
                          "clustering of a serving-scale candidate list")
     ap.add_argument("--cluster", action="store_true",
                     help="serving / alert: cluster each chunk's candidates (DM-width)")
+    ap.add_argument("--sb-table", choices=["synthetic", "model"], default="synthetic",
+                    help="serving: the SB table of the 71 SBs: the synthetic stand-in or the "
+                         "beam model's (arts_sb_table_beam_model)")
     ap.add_argument("--rfi", action="store_true",
                     help="serving / alert: RFI mitigation of each chunk's TABs (time domain at "
                          "6 sigma, frequency domain at 5 sigma, 3 iterations each)")
@@ -539,7 +542,10 @@ def main():
         p_nat.set_tiling(args.variant)
     if args.cluster:
         p_nat.cluster = p_ds.cluster = True
-    table = synth.sb_table_synthetic(NSB, NTAB, NCHAN)
+    if args.sb_table == "model":
+        table, _ = arts.arts_sb_table_beam_model(NSB, NTAB, NCHAN, w_nat.f_lo, w_nat.df)
+    else:
+        table = synth.sb_table_synthetic(NSB, NTAB, NCHAN)
 
     log("generating inputs ...")
     t0 = time.perf_counter()
@@ -634,7 +640,7 @@ def main():
                    "ndm_native": int(w_nat.dms.size), "ndm_ds4": int(w_ds.dms.size),
                    "graph": bool(args.graph), "threshold": THRESHOLD,
                    "cluster": bool(args.cluster), "rfi": bool(args.rfi),
-                   "device_bytes": info["device_bytes"]},
+                   "sb_table": args.sb_table, "device_bytes": info["device_bytes"]},
         "adds_per_s": (units_nat + units_ds) * NCHAN * args.steps / elapsed,
         "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
         "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),

@@ -101,6 +101,31 @@ int arts_delay_table(int32_t nchan, double f_lo_mhz, double df_mhz, double tsamp
                      const double* dm_list, int32_t ndm, int32_t downsample,
                      int32_t* delays_out, double* tie_margin_out);
 
+/* Host only (no device call): the SB table from the beam model (Appendix "Synthesized Beams"):
+ * table_out[s][c] = the TAB row whose grating response covers SB s in channel c.
+ *  - SB s has index n_SB = s - (nsb - 1) / 2 (0 is the centre of the compound beam).  At f_max
+ *    it takes TAB n_TAB = n_SB mod ntab (minus ntab if above ntab/2 - 1) of grating order n_gr,
+ *    n_SB = n_gr ntab + n_TAB (the paper's "rounding upward" of n_SB / ntab is read as the
+ *    rounding that keeps this identity).
+ *  - Going down in frequency it switches to TAB n_TAB - k sgn(n_SB) below the k-th switch
+ *    frequency f_sw,k = (1 - b) f_{k-1} + b f_k, where f_0 = f_max and
+ *    f_k = f_max (n_gr B_max + (n_TAB - k sgn) alpha B_cq) / (n_gr B_max + n_TAB alpha B_cq)
+ *    (the paper's equation for f0 applied to the k-th neighbour, with the TAB separation in its
+ *    second term as in the substitution that follows it); b = 1/2 for SBs one beam width apart
+ *    (quarter = 0, the 71 SBs of ARTS), and for half a beam width (quarter = 1, 151 SBs)
+ *    b = 1/4 for even n_SB and 3/4 for odd.  64 neighbours are followed.
+ *  - A TAB index outside [-ntab/2, ntab/2 - 1] is the same TAB one grating order over and is
+ *    wrapped into that range; TAB n is row n + ntab/2 of the TAB input.
+ * Channel c is at f_lo + c df MHz.  ARTS: ntab = 12, alpha = 0.80, B_max = 1296 m, B_cq = 144 m,
+ * f_max = 1500 MHz.  table_out: host uint8 [nsb][nchan].  margin_out (nullable): the smallest
+ * distance (MHz) of a channel frequency from a switch frequency it was compared with.
+ * Errors: ARTS_E_INVAL (odd or out-of-range ntab, non-positive model constants, a channel
+ * frequency <= 0, NULL table).                                                             */
+int arts_sb_table_beam_model(int32_t nsb, int32_t ntab, int32_t nchan, double f_lo_mhz,
+                             double df_mhz, double f_max_mhz, double alpha, double b_max_m,
+                             double b_cq_m, int32_t quarter, uint8_t* table_out,
+                             double* margin_out);
+
 /* Create a search plan on the current HIP device: validates the arguments (as above; widths
  * must be strictly increasing and >= 1), computes the FP64 delay table, and uploads it with the
  * tiling tables of the dedispersion kernel.  dm_list [ndm] and widths [nwidth] are host arrays,

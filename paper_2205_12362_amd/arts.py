@@ -64,6 +64,8 @@ _SIGNATURES = {
     "arts_cluster_offline": (C.c_int, [_vp, _i64, _i64, _pf64, _i32, _f32, _vp, _i64, _pi64,
                                        _vp]),
     "arts_rfi_clean": (C.c_int, [_vp, _i32, _i32, _i64, _i64, _f32, _i32, _f32, _i32, _vp]),
+    "arts_sb_table_beam_model": (C.c_int, [_i32, _i32, _i32, _f64, _f64, _f64, _f64, _f64, _f64,
+                                           _i32, _vp, _pf64]),
     "arts_stream_set_rfi": (C.c_int, [_vp, _f32, _i32, _f32, _i32]),
     "arts_tiling_count": (_i32, []),
     "arts_plan_autotune": (C.c_int, [_vp, _i32, _i64, _i32, C.c_char_p, _pi32,
@@ -423,6 +425,17 @@ def arts_rfi_clean(data, k_time, k_freq, niter_time=3, niter_freq=3, nsamp=None,
                                 int(niter_time), float(k_freq), int(niter_freq),
                                 _stream(stream)))
     return data
+
+
+def arts_sb_table_beam_model(nsb, ntab, nchan, f_lo, df, f_max=1500.0, alpha=0.80,
+                             b_max=1296.0, b_cq=144.0, quarter=False):
+    """SB table [nsb][nchan] (numpy uint8) from the beam model, and its switch margin (MHz)."""
+    out = np.zeros((int(nsb), int(nchan)), dtype=np.uint8)
+    m = C.c_double()
+    _check(lib().arts_sb_table_beam_model(int(nsb), int(ntab), int(nchan), float(f_lo), float(df),
+                                          float(f_max), float(alpha), float(b_max), float(b_cq),
+                                          int(bool(quarter)), out.ctypes.data, C.byref(m)))
+    return out, m.value
 
 
 def offline_dm_edges(dm_lo=20.0, dm_hi=5000.0, ratio=1.1):

@@ -648,6 +648,54 @@ int arts_plan_get_cluster(arts_plan_t p, int32_t* enable) {
   return ARTS_OK;
 }
 
+int arts_sb_table_beam_model(int32_t nsb, int32_t ntab, int32_t nchan, double f_lo_mhz,
+                             double df_mhz, double f_max_mhz, double alpha, double b_max_m,
+                             double b_cq_m, int32_t quarter, uint8_t* table_out,
+                             double* margin_out) {
+  if (!table_out) return fail(ARTS_E_INVAL, "table_out is NULL");
+  if (nsb < 1 || nchan < 1 || ntab < 2 || ntab > 256 || ntab % 2 != 0)
+    return fail(ARTS_E_INVAL, "nsb, nchan >= 1 and an even ntab in [2, 256] required");
+  if (!(f_max_mhz > 0) || !(alpha > 0) || !(b_max_m > 0) || !(b_cq_m > 0) ||
+      !std::isfinite(f_lo_mhz) || !std::isfinite(df_mhz) || df_mhz == 0 ||
+      (quarter != 0 && quarter != 1))
+    return fail(ARTS_E_INVAL, "bad beam-model arguments");
+  constexpr int kSwitches = 64;  // neighbours followed down in frequency
+  const int32_t half = ntab / 2;
+  const double a = alpha * b_cq_m;
+  double margin = std::numeric_limits<double>::infinity();
+  for (int32_t row = 0; row < nsb; ++row) {
+    const int32_t n_sb = row - (nsb - 1) / 2;
+    int32_t n_tab = ((n_sb % ntab) + ntab) % ntab;  // index at f_max in [-N/2, N/2 - 1]
+    if (n_tab > half - 1) n_tab -= ntab;
+    const int32_t n_gr = (n_sb - n_tab) / ntab;       // exact: n_sb = n_gr N + n_tab
+    const int32_t sg = (n_sb > 0) - (n_sb < 0);
+    uint8_t* out = table_out + static_cast<int64_t>(row) * nchan;
+    if (sg == 0) {
+      std::memset(out, half, nchan);
+      continue;
+    }
+    // f_k: frequency where grating n_gr of TAB n_tab - k sg points where the SB does
+    const double den = n_gr * b_max_m + n_tab * a;
+    double fk[kSwitches + 1], fsw[kSwitches];
+    for (int k = 0; k <= kSwitches; ++k)
+      fk[k] = f_max_mhz * (n_gr * b_max_m + (n_tab - k * sg) * a) / den;
+    const double b = quarter ? (n_sb % 2 == 0 ? 0.25 : 0.75) : 0.5;
+    for (int k = 1; k <= kSwitches; ++k) fsw[k - 1] = (1 - b) * fk[k - 1] + b * fk[k];
+    for (int32_t c = 0; c < nchan; ++c) {
+      const double f = f_lo_mhz + c * df_mhz;
+      if (!(f > 0)) return fail(ARTS_E_INVAL, "channel %d has frequency %g MHz", c, f);
+      int k = 0;
+      while (k < kSwitches && f < fsw[k]) ++k;
+      if (k < kSwitches) margin = std::min(margin, std::fabs(f - fsw[k]));
+      if (k > 0) margin = std::min(margin, std::fabs(f - fsw[k - 1]));
+      const int32_t j = n_tab - k * sg;
+      out[c] = static_cast<uint8_t>((((j + half) % ntab) + ntab) % ntab);
+    }
+  }
+  if (margin_out) *margin_out = margin;
+  return ARTS_OK;
+}
+
 int arts_rfi_clean(uint8_t* data, int32_t nrow, int32_t nchan, int64_t nsamp, int64_t pitch,
                    float k_time, int32_t niter_time, float k_freq, int32_t niter_freq,
                    void* stream) {

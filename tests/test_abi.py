@@ -88,3 +88,21 @@ def test_strerror():
     for st in range(-7, 1):
         assert L.arts_strerror(st)
     assert ctypes.sizeof(arts.Candidate) == 32
+
+
+@pytest.mark.parametrize("nsb,nchan,quarter", [(71, 1536, False), (151, 1536, True),
+                                               (71, 384, False), (9, 100, True), (1, 16, False)])
+def test_sb_table_beam_model_matches_oracle(nsb, nchan, quarter):
+    # host-only call: the library's beam-model SB table equals the oracle's, switch margins too
+    f_lo, df = synth.band(nchan)
+    got, margin = arts.arts_sb_table_beam_model(nsb, 12, nchan, f_lo, df, quarter=quarter)
+    ref, rmargin = O.sb_table_beam_model(nsb, 12, nchan, f_lo, df, quarter=quarter)
+    assert np.array_equal(got, ref)
+    assert margin == rmargin
+
+
+@pytest.mark.parametrize("args", [(71, 11, 64), (71, 0, 64), (0, 12, 64), (71, 12, 0)])
+def test_sb_table_beam_model_rejects(args):
+    nsb, ntab, nchan = args
+    with pytest.raises(arts.ArtsError):
+        arts.arts_sb_table_beam_model(nsb, ntab, max(nchan, 1) if nchan else 0, 1220.0, 0.2)
