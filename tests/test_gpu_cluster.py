@@ -318,3 +318,32 @@ def test_offline_after_streamed_dm_width_clusters():
     got = arts.arts_cluster_offline(allc, 6104, arts.offline_dm_edges(), 10.0)
     ref = O.cluster_offline(_tuples7(allc), 6104, list(arts.offline_dm_edges()), 10.0)
     assert _tuples7(got) == ref
+
+
+def test_server_stream_with_clustered_plan_equals_standalone():
+    # a clustered plan served beside another stream reports what a standalone stream reports
+    nsrc, chunk = 3, 2400
+    table = synth.sb_table_synthetic(4, nsrc, 64)
+    chunks = [synth.noise((nsrc, 64, chunk), seed=800 + k) for k in range(5)]
+    for k in (2, 3):
+        hot = chunks[k][0, :, 700:740].astype(int) + 60
+        chunks[k][0, :, 700:740] = np.minimum(255, hot).astype(np.uint8)
+    _, st = _stream_pair(nsrc, 4, table, graph=False)
+    f_lo, df = synth.band(64)
+    served_plans = [arts.Plan(64, f_lo, df, synth.TSAMP, np.arange(0, 300, 3.0), [1, 2, 4, 8]),
+                    arts.Plan(64, f_lo, df, synth.TSAMP, np.arange(300, 900, 6.0), [1, 2, 4], 4)]
+    served_plans[0].cluster = True
+    other = arts.Plan(64, f_lo, df, synth.TSAMP, np.arange(0, 100, 1.0), [1, 2])
+    with st, arts.Server(8 << 30) as srv:
+        a = srv.open(served_plans, nsrc, chunk, 5.5, sb_table=to_dev(table), nbeam=4,
+                     cand_capacity=1 << 18)
+        b = srv.open([other], 1, chunk, 6.0)
+        for k, c in enumerate(chunks):
+            srv.submit(a, to_dev(c))
+            srv.submit(b, to_dev(c[:1]))
+            assert srv.tick() == 2
+            got, _ = srv.collect(a)
+            srv.collect(b)
+            st.push(to_dev(c))
+            ref, _ = st.wait()
+            assert sorted(_tuples(got)) == sorted(_tuples(ref)), k

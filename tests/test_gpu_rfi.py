@@ -125,3 +125,28 @@ def test_stream_cleans_each_chunk(graph):
                 clean[3] = chunks[3]
                 clean[4] = chunks[4]
                 full = np.concatenate([np.zeros((nsrc, nchan, H), np.uint8)] + clean, axis=2)
+
+
+def test_server_stream_cleans_like_a_standalone_stream():
+    # RFI mitigation set on a served stream (through its stream handle) acts as on its own
+    import ctypes as C
+    nchan, chunk, nsrc = 64, 2400, 2
+    f_lo, df = synth.band(nchan)
+    mk = lambda: arts.Plan(nchan, f_lo, df, synth.TSAMP, np.arange(0, 200, 2.0), [1, 2, 4])
+    p1, p2 = mk(), mk()
+    chunks = [_inject(synth.noise((nsrc, nchan, chunk), seed=160 + k), seed=170 + k)
+              for k in range(4)]
+    with arts.Server(8 << 30) as srv, arts.Stream([p2], nsrc, chunk, 6.0) as st:
+        a = srv.open([p1], nsrc, chunk, 6.0)
+        h = C.c_void_p()
+        arts._check(arts.lib().arts_server_stream(srv.handle, a, C.byref(h)))
+        arts._check(arts.lib().arts_stream_set_rfi(h, 5.0, 3, 4.5, 3))
+        st.set_rfi(5.0, 4.5)
+        for c in chunks:
+            srv.submit(a, to_dev(c))
+            srv.tick()
+            got, _ = srv.collect(a)
+            st.push(to_dev(c))
+            ref, _ = st.wait()
+            assert np.array_equal(srv.series(a, 0).cpu().numpy(), st.series(0).cpu().numpy())
+            assert np.array_equal(got, ref)
