@@ -19,6 +19,8 @@ struct arts_batch_s {
   unsigned long long* d_count = nullptr;
   int64_t cand_cap = 0;
   ClusterWs cl;  // DM-width clustering of requests whose plan asks for it
+  uint8_t* d_flags = nullptr;  // candidate pre-pass rows (max over requests)
+  int64_t flags_cap = 0;
 };
 
 namespace {
@@ -55,6 +57,7 @@ void arts_batch_destroy(arts_batch_t b) {
     if (p) (void)hipFree(p);
   if (b->d_cand) (void)hipFree(b->d_cand);
   if (b->d_count) (void)hipFree(b->d_count);
+  if (b->d_flags) (void)hipFree(b->d_flags);
   free_cluster_ws(b->cl);
   delete b;
 }
@@ -146,6 +149,17 @@ int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, f
       cl_rows = std::max<int64_t>(cl_rows, static_cast<int64_t>(reqs[i].nbeam) * reqs[i].plan->ndm);
   if (cl_rows > 0)
     if (int e = ensure_cluster_ws(b->cl, std::max<int64_t>(capacity, 1), cl_rows)) return e;
+  int64_t all_rows = 0;  // candidate pre-pass flags, sized before any launch
+  for (int32_t i = 0; i < n; ++i)
+    if (reqs[i].plan && reqs[i].nbeam >= 1)
+      all_rows = std::max<int64_t>(all_rows, static_cast<int64_t>(reqs[i].nbeam) * reqs[i].plan->ndm);
+  if (all_rows > b->flags_cap) {
+    if (b->d_flags) (void)hipFree(b->d_flags);
+    b->d_flags = nullptr;
+    b->flags_cap = 0;
+    ARTS_HIP(hipMalloc(&b->d_flags, all_rows));
+    b->flags_cap = all_rows;
+  }
   if (int e = launch_zero_u64(b->d_count, 1, s)) return e;
   int32_t beam0 = 0;
   for (int32_t i = 0; i < n; ++i) {
@@ -157,7 +171,7 @@ int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, f
         if (r.plan->cluster)
           if (int e = launch_cluster_mark(b->cl, b->d_count, s)) return e;
         if (int e = launch_candidates(r.plan, r.out, r.nbeam, L, nrep, threshold, 0, beam0, nullptr,
-                                      nullptr, b->d_cand, b->d_count, capacity, s))
+                                      nullptr, b->d_cand, b->d_count, capacity, s, 0, b->d_flags))
           return e;
         if (r.plan->cluster)
           if (int e = launch_cluster(b->cl, b->d_cand, b->d_count, capacity, true, r.nbeam,

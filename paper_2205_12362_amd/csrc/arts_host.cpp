@@ -241,6 +241,16 @@ int ensure_cand(arts_plan_s* p, int64_t cap) {
   return ARTS_OK;
 }
 
+int ensure_flags(arts_plan_s* p, int64_t rows) {
+  if (rows <= p->flags_cap && p->d_flags) return ARTS_OK;
+  if (p->d_flags) (void)hipFree(p->d_flags);
+  p->d_flags = nullptr;
+  p->flags_cap = 0;
+  ARTS_HIP(hipMalloc(&p->d_flags, rows));
+  p->flags_cap = rows;
+  return ARTS_OK;
+}
+
 int ensure_ds16(arts_plan_s* p, int64_t elems) {
   if (elems <= p->ds16_cap) return ARTS_OK;
   if (p->d_ds16) (void)hipFree(p->d_ds16);
@@ -307,6 +317,7 @@ static void plan_free(arts_plan_s* p) {
   if (p->d_musig) (void)hipFree(p->d_musig);
   if (p->d_cand) (void)hipFree(p->d_cand);
   if (p->d_count) (void)hipFree(p->d_count);
+  if (p->d_flags) (void)hipFree(p->d_flags);
   free_cluster_ws(p->cl);
   delete p;
 }
@@ -896,8 +907,10 @@ int arts_candidates(arts_plan_t p, const int32_t* series, int32_t nbeam, int64_t
   if (int st = launch_zero_u64(p->d_count, 1, s)) return st;
   if (p->cluster)
     if (int st = ensure_cluster_ws(p->cl, std::max<int64_t>(capacity, 1), rows)) return st;
+  if (int st = ensure_flags(p, rows)) return st;
   if (int st = launch_candidates(p, series, nbeam, L, nrep, threshold, t_offset, beam_offset,
-                                 p->d_s1, p->d_musig, p->d_cand, p->d_count, capacity, s))
+                                 p->d_s1, p->d_musig, p->d_cand, p->d_count, capacity, s, 0,
+                                 p->d_flags))
     return st;
   if (p->cluster)
     if (int st = launch_cluster(p->cl, p->d_cand, p->d_count, capacity, false, nbeam, p->ndm,

@@ -75,6 +75,8 @@ struct arts_plan_s {
   arts_candidate* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
   int64_t cand_cap = 0;
+  uint8_t* d_flags = nullptr;  // per (beam, DM) row: may hold a candidate (candidate pre-pass)
+  int64_t flags_cap = 0;
   uint16_t* d_ds16 = nullptr;  // downsampled rows of one-shot calls with D > 1
   int64_t ds16_cap = 0;        // elements
   uint8_t* d_align = nullptr;  // dword-aligned copy of one-shot inputs with odd row pitch
@@ -117,6 +119,7 @@ int ensure_tables(arts_plan_s* p, int g0);
 void free_tiling(Tiling& t);
 int ensure_stats(arts_plan_s* p, int64_t rows);
 int ensure_cand(arts_plan_s* p, int64_t cap);
+int ensure_flags(arts_plan_s* p, int64_t rows);
 int ensure_ds16(arts_plan_s* p, int64_t elems);
 int ensure_align(arts_plan_s* p, int64_t bytes);
 
@@ -189,7 +192,7 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
                       int64_t nrep, float thr, int64_t t_offset, int32_t beam_offset,
                       const int64_t* s1, const double* musig, arts_candidate* cand,
                       unsigned long long* count, int64_t cap, hipStream_t s,
-                      int64_t t_begin = 0);
+                      int64_t t_begin = 0, uint8_t* flags = nullptr);
 int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
                       int64_t nrep, const int64_t* s1, const double* musig, int32_t* sums,
                       float* snr, hipStream_t s);
@@ -258,6 +261,7 @@ struct arts_stream_s {
   arts_candidate* d_cand = nullptr;
   unsigned long long* d_count = nullptr;
   unsigned long long* h_count = nullptr;  // pinned
+  uint8_t* d_flags = nullptr;              // candidate pre-pass: nbeam x max ndm rows
   std::vector<char> cluster;               // per plan: cluster its candidates (set at creation)
   arts::ClusterWs cl;
   // RFI mitigation of each pushed chunk (arts_stream_set_rfi): thresholds, iterations, workspace

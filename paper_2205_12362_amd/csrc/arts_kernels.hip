@@ -1322,6 +1322,19 @@ __device__ __forceinline__ WidthParams width_params(int w, int64_t N, double mu,
   return wp;
 }
 
+// Mean and population sigma of a series from its exact sums over N samples (shifted by the
+// integer part of the mean, so that the variance comes from small numbers).
+__device__ __forceinline__ void row_musig(long long S1, long long S2, long long N, double* mu,
+                                          double* sigma) {
+  const long long m0 = S1 / N, r = S1 - N * m0;
+  const long long S2c = S2 - 2 * m0 * S1 + N * m0 * m0;
+  const double dn = static_cast<double>(N);
+  const double var =
+      (static_cast<double>(S2c) - static_cast<double>(r) * static_cast<double>(r) / dn) / dn;
+  *mu = static_cast<double>(m0) + static_cast<double>(r) / dn;
+  *sigma = var > 0.0 ? sqrt(var) : 0.0;
+}
+
 __global__ __launch_bounds__(kBoxThreads) void boxcar_snr_kernel(
     const int32_t* __restrict__ series, int64_t L, int64_t nrep, int32_t ndm, int64_t nseg,
     const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, const int64_t* __restrict__ s1,
@@ -1432,7 +1445,10 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
     const int32_t* __restrict__ series, int64_t pitch, int64_t L, int64_t nrep, int32_t ndm,
     const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, const double* __restrict__ dms,
     double thr, int64_t t_offset, int32_t beam_offset, int32_t ds,
-    arts_candidate* __restrict__ cand, unsigned long long* __restrict__ count, int64_t cap) {
+    arts_candidate* __restrict__ cand, unsigned long long* __restrict__ count, int64_t cap,
+    const uint8_t* __restrict__ flags) {
+  // rows the pre-pass found below the threshold at every width give no candidate
+  if (flags != nullptr && flags[blockIdx.x] == 0) return;
   extern __shared__ uint32_t P[];
   __shared__ uint32_t wsum[NT / 64];
   __shared__ long long red[2][NT / 64];
@@ -1499,13 +1515,7 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
     long long S2 = 0;
 #pragma unroll
     for (int v = 0; v < NT / 64; ++v) S2 += red[1][v];
-    const long long N = nrep, m0 = S1 / N, r = S1 - N * m0;
-    const long long S2c = S2 - 2 * m0 * S1 + N * m0 * m0;
-    const double dn = static_cast<double>(N);
-    const double var =
-        (static_cast<double>(S2c) - static_cast<double>(r) * static_cast<double>(r) / dn) / dn;
-    s_musig[0] = static_cast<double>(m0) + static_cast<double>(r) / dn;
-    s_musig[1] = var > 0.0 ? sqrt(var) : 0.0;
+    row_musig(S1, S2, nrep, &s_musig[0], &s_musig[1]);
     s_hitmask = 0;
   }
   __syncthreads();
@@ -1734,10 +1744,134 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
                                               s_scale[tid]);
 }
 
+// Pre-pass of the candidate search, one wave per row and no workgroup barrier: the row is read
+// once, in chunks of kPreC samples (coalesced, one chunk ahead), for the exact moments over its
+// nrep searched starts and the inclusive prefix S[i] = x[0] + ... + x[i] (mod 2^32), which goes
+// into a ring of kPreR entries in LDS (the raw chunk is staged there first, so that each lane
+// scans four consecutive samples).  Starts are evaluated D = ceil(wmax / kPreC) chunks behind
+// the newest prefix, B_w(t) = S[t + w - 1] - S[t - 1] (S[-1] = 0 in the ring's last slot), and
+// the whole-row maximum of B_w per width is kept in registers.  A row is flagged if some width's
+// maximum exceeds its threshold (the same moments and width_params as the main kernel, so the
+// main kernel finds no candidate in a row left unflagged).  Needs nw <= kCandRegW and
+// wmax <= kPreMaxW, so that the ring holds D + 2 chunks.
+constexpr int kPreC = 256;
+constexpr int kPreR = 2048;
+constexpr int kPreMaxW = 6 * kPreC;
+
+__global__ __launch_bounds__(256) void cand_pre_kernel(
+    const int32_t* __restrict__ series, int64_t pitch, int64_t nrep, int64_t nrows,
+    const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, double thr,
+    uint8_t* __restrict__ flags) {
+  __shared__ uint32_t ring[4][kPreR];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + wv;
+  if (row >= nrows) return;  // the whole wave: nothing below synchronises across waves
+  uint32_t* rg = ring[wv];
+  const int32_t* x = series + row * pitch;
+  const int64_t lw = nrep + wmax - 1;  // samples the searched starts reach
+  int wreg[kCandRegW];
+  int32_t bm[kCandRegW];
+#pragma unroll
+  for (int wi = 0; wi < kCandRegW; ++wi) {
+    wreg[wi] = wi < nw ? widths[wi] : 0;
+    bm[wi] = INT_MIN;
+  }
+  if (lane == 0) rg[kPreR - 1] = 0u;  // S[-1]
+  long long s1 = 0, s2 = 0;
+  uint32_t carry = 0;
+  const int64_t D = (wmax + kPreC - 1) / kPreC;
+  const int64_t nchunk = (lw + kPreC - 1) / kPreC;
+  // coalesced loads (lane l holds samples l, l + 64, l + 128, l + 192 of a chunk), issued one
+  // chunk ahead of their use
+  int32_t nx[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) nx[u] = lane + 64 * u < lw ? x[lane + 64 * u] : 0;
+  for (int64_t k = 0; k < nchunk + D; ++k) {
+    if (k < nchunk) {
+      const int64_t c0 = k * kPreC;
+      int32_t cx[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cx[u] = nx[u];
+      if (k + 1 < nchunk) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t i = c0 + kPreC + lane + 64 * u;
+          nx[u] = i < lw ? x[i] : 0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (c0 + lane + 64 * u < nrep) {
+          s1 += cx[u];
+          s2 += static_cast<long long>(cx[u]) * cx[u];
+        }
+        rg[(c0 + lane + 64 * u) & (kPreR - 1)] = static_cast<uint32_t>(cx[u]);  // raw, for now
+      }
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes are done
+      __builtin_amdgcn_wave_barrier();
+      // four consecutive samples per lane for the scan
+      uint32_t* slot = rg + ((c0 + 4 * lane) & (kPreR - 1));
+      const uint4 raw = *reinterpret_cast<const uint4*>(slot);
+      const uint32_t q[4] = {raw.x, raw.x + raw.y, raw.x + raw.y + raw.z,
+                             raw.x + raw.y + raw.z + raw.w};
+      uint32_t inc = q[3];  // inclusive scan of the lanes' totals
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
+      }
+      const uint32_t base = carry + inc - q[3];
+      uint4 wq;
+      wq.x = base + q[0];
+      wq.y = base + q[1];
+      wq.z = base + q[2];
+      wq.w = base + q[3];
+      *reinterpret_cast<uint4*>(slot) = wq;
+      carry += __shfl(inc, 63, 64);
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    const int64_t kk = k - D;
+    if (kk >= 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t t = kk * kPreC + lane + 64 * u;
+        if (t < nrep) {
+          const uint32_t a = rg[(t - 1) & (kPreR - 1)];
+#pragma unroll
+          for (int wi = 0; wi < kCandRegW; ++wi)
+            if (wi < nw)
+              bm[wi] = max(bm[wi], static_cast<int32_t>(rg[(t + wreg[wi] - 1) & (kPreR - 1)] - a));
+        }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_xor(s1, off, 64);
+    s2 += __shfl_xor(s2, off, 64);
+#pragma unroll
+    for (int wi = 0; wi < kCandRegW; ++wi) bm[wi] = max(bm[wi], __shfl_xor(bm[wi], off, 64));
+  }
+  if (lane == 0) {
+    double mu, sigma;
+    row_musig(s1, s2, nrep, &mu, &sigma);
+    int hit = 0;
+    if (sigma > 0.0)
+      for (int wi = 0; wi < nw; ++wi)
+        if (static_cast<long long>(bm[wi]) > width_params(wreg[wi], nrep, mu, sigma, thr).thr_int)
+          hit = 1;
+    flags[row] = static_cast<uint8_t>(hit);
+  }
+}
+
 int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
                       int64_t nrep, float thr, int64_t t_offset, int32_t beam_offset,
                       const int64_t*, const double*, arts_candidate* cand,
-                      unsigned long long* count, int64_t cap, hipStream_t s, int64_t t_begin) {
+                      unsigned long long* count, int64_t cap, hipStream_t s, int64_t t_begin,
+                      uint8_t* flags) {
   if (t_begin < 0 || t_begin >= nrep) return fail(ARTS_E_INVAL, "t_begin outside [0, nrep)");
   const int64_t nrows = static_cast<int64_t>(nbeam) * p->ndm;
   if (nrows > INT_MAX) return fail(ARTS_E_INVAL, "candidate grid too large");
@@ -1765,10 +1899,18 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
   const int nt = wide ? 512 : 256;
   auto kern = res ? (wide ? candidates_kernel<true, 512> : candidates_kernel<true, 256>)
                   : (wide ? candidates_kernel<false, 512> : candidates_kernel<false, 256>);
+  // rows that cannot hold a candidate are sorted out first when the pre-pass applies
+  const bool pre = flags != nullptr && p->nwidth <= kCandRegW && p->wmax <= kPreMaxW &&
+                   nrows >= 1024;
+  if (pre)
+    hipLaunchKernelGGL(cand_pre_kernel, dim3(static_cast<unsigned>((nrows + 3) / 4)), dim3(256),
+                       0, s, series + t_begin, L, nrep - t_begin, nrows, p->d_widths,
+                       p->nwidth, p->wmax, static_cast<double>(thr), flags);
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(nrows)), dim3(nt), lds, s,
                      series + t_begin, L, L - t_begin, nrep - t_begin, p->ndm, p->d_widths,
                      p->nwidth, p->wmax, p->d_dms, static_cast<double>(thr),
-                     t_offset + t_begin, beam_offset, p->ds, cand, count, cap);
+                     t_offset + t_begin, beam_offset, p->ds, cand, count, cap,
+                     pre ? flags : nullptr);
   ARTS_HIP(hipGetLastError());
   return ARTS_OK;
 }

@@ -42,6 +42,7 @@ void stream_free(arts_stream_s* s) {
   if (s->d_cand) (void)hipFree(s->d_cand);
   if (s->d_count) (void)hipFree(s->d_count);
   if (s->h_count) (void)hipHostFree(s->h_count);
+  if (s->d_flags) (void)hipFree(s->d_flags);
   free_cluster_ws(s->cl);
   if (s->rfi_ws) (void)hipFree(s->rfi_ws);
   for (auto e : s->pev)
@@ -146,6 +147,10 @@ int64_t stream_bytes_needed(const arts_plan_t* plans, int32_t nplan, int32_t nsr
     const YLayout y = y_layout(plans[i], nbeam, chunk);
     total += 2 * y.rows * y.pitch;
   }
+  int64_t max_rows = 0;  // candidate pre-pass flags
+  for (int32_t i = 0; i < nplan; ++i)
+    max_rows = std::max<int64_t>(max_rows, static_cast<int64_t>(nbeam) * plans[i]->ndm);
+  total += max_rows;
   int64_t cl_rows = 0;  // clustering workspace
   for (int32_t i = 0; i < nplan; ++i)
     if (plans[i]->cluster) cl_rows = std::max<int64_t>(cl_rows, static_cast<int64_t>(nbeam) * plans[i]->ndm);
@@ -232,7 +237,7 @@ int stream_candidates(arts_stream_s* s, hipStream_t hs) {
     // sample numbers are made absolute on the host: chunk-relative start minus the halo
     if (int st = launch_candidates(pl, s->series[p], s->nbeam, s->L[p], nrep, s->thr,
                                    -s->H[p] / pl->ds, 0, nullptr, nullptr, s->d_cand,
-                                   s->d_count, s->cap, hs, t0))
+                                   s->d_count, s->cap, hs, t0, s->d_flags))
       return st;
     if (clu)
       if (int st = launch_cluster(s->cl, s->d_cand, s->d_count, s->cap, true, s->nbeam, pl->ndm,
@@ -399,6 +404,9 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
   if (st == ARTS_OK)
     st = dev_alloc(s, reinterpret_cast<void**>(&s->d_cand), cand_capacity * sizeof(arts_candidate));
   if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&s->d_count), 64);
+  int64_t max_rows = 0;  // candidate pre-pass flags
+  for (auto* pl : s->plans) max_rows = std::max<int64_t>(max_rows, static_cast<int64_t>(nbeam) * pl->ndm);
+  if (st == ARTS_OK) st = dev_alloc(s, reinterpret_cast<void**>(&s->d_flags), max_rows);
   // DM-width clustering, for the plans that ask for it when the stream is created
   int64_t cl_rows = 0;
   for (auto* pl : s->plans) {
