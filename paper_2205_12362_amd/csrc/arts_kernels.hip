@@ -1758,6 +1758,21 @@ constexpr int kPreC = 256;
 constexpr int kPreR = 2048;
 constexpr int kPreMaxW = 6 * kPreC;
 
+// Inclusive prefix sum across a wave64 with DPP moves (no LDS round trip): shifts by 1, 2, 4
+// and 8 lanes within each row of 16, then row 0's total to row 1 and row 2's to row 3
+// (row_bcast:15), then row 1's to rows 2 and 3 (row_bcast:31).  Lanes without a source add 0.
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+  const int x = static_cast<int>(v);
+  int s = x;
+  s += __builtin_amdgcn_update_dpp(0, s, 0x111, 0xf, 0xf, false);  // row_shr:1
+  s += __builtin_amdgcn_update_dpp(0, s, 0x112, 0xf, 0xf, false);  // row_shr:2
+  s += __builtin_amdgcn_update_dpp(0, s, 0x114, 0xf, 0xf, false);  // row_shr:4
+  s += __builtin_amdgcn_update_dpp(0, s, 0x118, 0xf, 0xf, false);  // row_shr:8
+  s += __builtin_amdgcn_update_dpp(0, s, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  s += __builtin_amdgcn_update_dpp(0, s, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return static_cast<uint32_t>(s);
+}
+
 __global__ __launch_bounds__(256) void cand_pre_kernel(
     const int32_t* __restrict__ series, int64_t pitch, int64_t nrep, int64_t nrows,
     const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, double thr,
@@ -1814,12 +1829,7 @@ __global__ __launch_bounds__(256) void cand_pre_kernel(
       const uint4 raw = *reinterpret_cast<const uint4*>(slot);
       const uint32_t q[4] = {raw.x, raw.x + raw.y, raw.x + raw.y + raw.z,
                              raw.x + raw.y + raw.z + raw.w};
-      uint32_t inc = q[3];  // inclusive scan of the lanes' totals
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += t;
-      }
+      const uint32_t inc = wave_scan_incl(q[3]);  // inclusive scan of the lanes' totals
       const uint32_t base = carry + inc - q[3];
       uint4 wq;
       wq.x = base + q[0];
@@ -1827,7 +1837,7 @@ __global__ __launch_bounds__(256) void cand_pre_kernel(
       wq.z = base + q[2];
       wq.w = base + q[3];
       *reinterpret_cast<uint4*>(slot) = wq;
-      carry += __shfl(inc, 63, 64);
+      carry += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(inc), 63));
     }
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_wave_barrier();
