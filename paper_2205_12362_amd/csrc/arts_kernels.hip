@@ -1745,18 +1745,25 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
 }
 
 // Pre-pass of the candidate search, one wave per row and no workgroup barrier: the row is read
-// once, in chunks of kPreC samples (coalesced, one chunk ahead), for the exact moments over its
-// nrep searched starts and the inclusive prefix S[i] = x[0] + ... + x[i] (mod 2^32), which goes
-// into a ring of kPreR entries in LDS (the raw chunk is staged there first, so that each lane
-// scans four consecutive samples).  Starts are evaluated D = ceil(wmax / kPreC) chunks behind
-// the newest prefix, B_w(t) = S[t + w - 1] - S[t - 1] (S[-1] = 0 in the ring's last slot), and
-// the whole-row maximum of B_w per width is kept in registers.  A row is flagged if some width's
-// maximum exceeds its threshold (the same moments and width_params as the main kernel, so the
-// main kernel finds no candidate in a row left unflagged).  Needs nw <= kCandRegW and
-// wmax <= kPreMaxW, so that the ring holds D + 2 chunks.
+// once, in chunks of kPreC samples (lane l loads samples 4l .. 4l + 3 of a chunk with one
+// 16-byte load, issued one chunk ahead), for the exact moments over its nrep searched starts
+// and the inclusive prefix S[i] = x[0] + ... + x[i] (mod 2^32), which goes into a ring of RB
+// entries in LDS.  Starts are evaluated D = ceil(wmax / kPreC) chunks behind the newest
+// prefix, B_w(t) = S[t + w - 1] - S[t - 1] (S[-1] = 0 in the ring's last slot), and the
+// whole-row maximum of B_w per width is kept in registers.  Lane l evaluates starts l, l + 64,
+// l + 128 and l + 192 of a chunk, so that one address per width serves all four (immediate
+// offsets) and the reads are free of bank conflicts.  A read range that passes the ring's end
+// continues into a guard of kPreC entries that mirrors the ring's first chunk slot (written
+// together with it), so no read address is wrapped.  A row is flagged if some width's maximum
+// exceeds its threshold (the same moments and width_params as the main kernel, so the main
+// kernel finds no candidate in a row left unflagged).  NW is the width count rounded up to an
+// even number, the extra widths repeating the last; the ring holds D + 2 chunks.
 constexpr int kPreC = 256;
-constexpr int kPreR = 2048;
 constexpr int kPreMaxW = 6 * kPreC;
+
+struct PreWidths {
+  int32_t w[kCandRegW];
+};
 
 // Inclusive prefix sum across a wave64 with DPP moves (no LDS round trip): shifts by 1, 2, 4
 // and 8 lanes within each row of 16, then row 0's total to row 1 and row 2's to row 3
@@ -1773,107 +1780,143 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
   return static_cast<uint32_t>(s);
 }
 
+// samples c0 + 4 lane + u (u < 4) of a row of lw samples, 0 beyond it
+__device__ __forceinline__ void pre_load4(const int32_t* x, int64_t c0, int64_t lw, int lane,
+                                          int32_t* v) {
+  const int64_t i = c0 + 4 * lane;
+  if (c0 + kPreC <= lw) {
+    int4 q;
+    __builtin_memcpy(&q, x + i, sizeof(q));
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = i + u < lw ? x[i + u] : 0;
+  }
+}
+
+template <int NW, int RB>
 __global__ __launch_bounds__(256) void cand_pre_kernel(
     const int32_t* __restrict__ series, int64_t pitch, int64_t nrep, int64_t nrows,
-    const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, double thr,
-    uint8_t* __restrict__ flags) {
-  __shared__ uint32_t ring[4][kPreR];
+    PreWidths wd, int32_t wmax, double thr, uint8_t* __restrict__ flags) {
+  static_assert(NW <= kCandRegW && RB % kPreC == 0 && (RB & (RB - 1)) == 0, "pre-pass shape");
+  __shared__ uint32_t ring[4][RB + kPreC];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + wv;
   if (row >= nrows) return;  // the whole wave: nothing below synchronises across waves
   uint32_t* rg = ring[wv];
   const int32_t* x = series + row * pitch;
   const int64_t lw = nrep + wmax - 1;  // samples the searched starts reach
-  int wreg[kCandRegW];
-  int32_t bm[kCandRegW];
+  int32_t bm[NW];
 #pragma unroll
-  for (int wi = 0; wi < kCandRegW; ++wi) {
-    wreg[wi] = wi < nw ? widths[wi] : 0;
-    bm[wi] = INT_MIN;
-  }
-  if (lane == 0) rg[kPreR - 1] = 0u;  // S[-1]
+  for (int wi = 0; wi < NW; ++wi) bm[wi] = INT_MIN;
+  if (lane == 0) rg[RB - 1] = 0u;  // S[-1]
   long long s1 = 0, s2 = 0;
   uint32_t carry = 0;
   const int64_t D = (wmax + kPreC - 1) / kPreC;
   const int64_t nchunk = (lw + kPreC - 1) / kPreC;
-  // coalesced loads (lane l holds samples l, l + 64, l + 128, l + 192 of a chunk), issued one
-  // chunk ahead of their use
   int32_t nx[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) nx[u] = lane + 64 * u < lw ? x[lane + 64 * u] : 0;
+  pre_load4(x, 0, lw, lane, nx);
   for (int64_t k = 0; k < nchunk + D; ++k) {
     if (k < nchunk) {
       const int64_t c0 = k * kPreC;
       int32_t cx[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) cx[u] = nx[u];
-      if (k + 1 < nchunk) {
+      if (k + 1 < nchunk) pre_load4(x, c0 + kPreC, lw, lane, nx);
+      if (c0 + kPreC <= nrep) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int64_t i = c0 + kPreC + lane + 64 * u;
-          nx[u] = i < lw ? x[i] : 0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (c0 + lane + 64 * u < nrep) {
           s1 += cx[u];
           s2 += static_cast<long long>(cx[u]) * cx[u];
         }
-        rg[(c0 + lane + 64 * u) & (kPreR - 1)] = static_cast<uint32_t>(cx[u]);  // raw, for now
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (c0 + 4 * lane + u < nrep) {
+            s1 += cx[u];
+            s2 += static_cast<long long>(cx[u]) * cx[u];
+          }
       }
+      const uint32_t q0 = static_cast<uint32_t>(cx[0]), q1 = q0 + static_cast<uint32_t>(cx[1]),
+                     q2 = q1 + static_cast<uint32_t>(cx[2]), q3 = q2 + static_cast<uint32_t>(cx[3]);
+      const uint32_t inc = wave_scan_incl(q3);  // inclusive scan of the lanes' totals
+      const uint32_t base = carry + inc - q3;
+      uint4 wq;
+      wq.x = base + q0;
+      wq.y = base + q1;
+      wq.z = base + q2;
+      wq.w = base + q3;
+      const int slot = static_cast<int>(c0 & (RB - 1));
+      *reinterpret_cast<uint4*>(rg + slot + 4 * lane) = wq;
+      if (slot == 0) *reinterpret_cast<uint4*>(rg + RB + 4 * lane) = wq;  // the guard
+      carry += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(inc), 63));
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes are done
       __builtin_amdgcn_wave_barrier();
-      // four consecutive samples per lane for the scan
-      uint32_t* slot = rg + ((c0 + 4 * lane) & (kPreR - 1));
-      const uint4 raw = *reinterpret_cast<const uint4*>(slot);
-      const uint32_t q[4] = {raw.x, raw.x + raw.y, raw.x + raw.y + raw.z,
-                             raw.x + raw.y + raw.z + raw.w};
-      const uint32_t inc = wave_scan_incl(q[3]);  // inclusive scan of the lanes' totals
-      const uint32_t base = carry + inc - q[3];
-      uint4 wq;
-      wq.x = base + q[0];
-      wq.y = base + q[1];
-      wq.z = base + q[2];
-      wq.w = base + q[3];
-      *reinterpret_cast<uint4*>(slot) = wq;
-      carry += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(inc), 63));
     }
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_wave_barrier();
     const int64_t kk = k - D;
     if (kk >= 0) {
+      const int64_t t0 = kk * kPreC;
+      const uint32_t* pa = rg + ((t0 - 1) & (RB - 1)) + lane;
+      uint32_t av[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t t = kk * kPreC + lane + 64 * u;
-        if (t < nrep) {
-          const uint32_t a = rg[(t - 1) & (kPreR - 1)];
+      for (int u = 0; u < 4; ++u) av[u] = pa[64 * u];
+      if (t0 + kPreC <= nrep) {
 #pragma unroll
-          for (int wi = 0; wi < kCandRegW; ++wi)
-            if (wi < nw)
-              bm[wi] = max(bm[wi], static_cast<int32_t>(rg[(t + wreg[wi] - 1) & (kPreR - 1)] - a));
+        for (int wi = 0; wi < NW; ++wi) {
+          const uint32_t* pw = rg + ((t0 + wd.w[wi] - 1) & (RB - 1)) + lane;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            bm[wi] = max(bm[wi], static_cast<int32_t>(pw[64 * u] - av[u]));
+        }
+      } else {
+#pragma unroll
+        for (int wi = 0; wi < NW; ++wi) {
+          const uint32_t* pw = rg + ((t0 + wd.w[wi] - 1) & (RB - 1)) + lane;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (t0 + lane + 64 * u < nrep)
+              bm[wi] = max(bm[wi], static_cast<int32_t>(pw[64 * u] - av[u]));
         }
       }
     }
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_wave_barrier();
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     s1 += __shfl_xor(s1, off, 64);
     s2 += __shfl_xor(s2, off, 64);
 #pragma unroll
-    for (int wi = 0; wi < kCandRegW; ++wi) bm[wi] = max(bm[wi], __shfl_xor(bm[wi], off, 64));
+    for (int wi = 0; wi < NW; ++wi) bm[wi] = max(bm[wi], __shfl_xor(bm[wi], off, 64));
   }
   if (lane == 0) {
     double mu, sigma;
     row_musig(s1, s2, nrep, &mu, &sigma);
     int hit = 0;
     if (sigma > 0.0)
-      for (int wi = 0; wi < nw; ++wi)
-        if (static_cast<long long>(bm[wi]) > width_params(wreg[wi], nrep, mu, sigma, thr).thr_int)
+#pragma unroll
+      for (int wi = 0; wi < NW; ++wi)
+        if (static_cast<long long>(bm[wi]) > width_params(wd.w[wi], nrep, mu, sigma, thr).thr_int)
           hit = 1;
     flags[row] = static_cast<uint8_t>(hit);
+  }
+}
+
+typedef void (*PreKernel)(const int32_t*, int64_t, int64_t, int64_t, PreWidths, int32_t, double,
+                          uint8_t*);
+
+template <int RB>
+PreKernel pre_kernel_nw(int nwp) {
+  switch (nwp) {
+    case 2: return cand_pre_kernel<2, RB>;
+    case 4: return cand_pre_kernel<4, RB>;
+    case 6: return cand_pre_kernel<6, RB>;
+    case 8: return cand_pre_kernel<8, RB>;
+    case 10: return cand_pre_kernel<10, RB>;
+    case 12: return cand_pre_kernel<12, RB>;
+    case 14: return cand_pre_kernel<14, RB>;
+    default: return cand_pre_kernel<16, RB>;
   }
 }
 
@@ -1912,10 +1955,17 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
   // rows that cannot hold a candidate are sorted out first when the pre-pass applies
   const bool pre = flags != nullptr && p->nwidth <= kCandRegW && p->wmax <= kPreMaxW &&
                    nrows >= 1024;
-  if (pre)
-    hipLaunchKernelGGL(cand_pre_kernel, dim3(static_cast<unsigned>((nrows + 3) / 4)), dim3(256),
-                       0, s, series + t_begin, L, nrep - t_begin, nrows, p->d_widths,
-                       p->nwidth, p->wmax, static_cast<double>(thr), flags);
+  if (pre) {
+    PreWidths wd;
+    const int nwp = (p->nwidth + 1) & ~1;
+    for (int wi = 0; wi < kCandRegW; ++wi) wd.w[wi] = p->widths[min(wi, p->nwidth - 1)];
+    // the ring holds D + 2 chunks: 4 of them up to wmax = 2 kPreC, else 8
+    const PreKernel kp = p->wmax <= 2 * kPreC ? pre_kernel_nw<4 * kPreC>(nwp)
+                                              : pre_kernel_nw<8 * kPreC>(nwp);
+    hipLaunchKernelGGL(kp, dim3(static_cast<unsigned>((nrows + 3) / 4)), dim3(256), 0, s,
+                       series + t_begin, L, nrep - t_begin, nrows, wd, p->wmax,
+                       static_cast<double>(thr), flags);
+  }
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(nrows)), dim3(nt), lds, s,
                      series + t_begin, L, L - t_begin, nrep - t_begin, p->ndm, p->d_widths,
                      p->nwidth, p->wmax, p->d_dms, static_cast<double>(thr),

@@ -316,6 +316,35 @@ def test_candidates_pure_noise_empty():
     assert len(got) == 0
 
 
+@pytest.mark.parametrize("widths", [[1, 2, 4, 8, 16, 32, 64, 128, 256],
+                                    [1, 3, 7, 20, 100, 600, 1000], [5], list(range(1, 17))])
+def test_candidates_many_rows_match_oracle(widths):
+    # 1030 DM rows of a synthetic series: enough rows that a row-level pre-pass decides which
+    # rows the exact search visits.  A ragged last chunk of starts, odd and even width counts,
+    # a widest width above 512 samples, a level whose prefix sums wrap mod 2^32, and top-hats of
+    # S/N 6 to 24 at random widths in 40 rows (pure noise elsewhere); all rows against the oracle
+    ndm, nrep, thr = 1030, 3001, 8.0
+    wmax = max(widths)
+    L = nrep + wmax - 1
+    rng = np.random.default_rng(500 + len(widths) + wmax)
+    x = np.rint(rng.normal(1.5e6, 600.0, (ndm, L))).astype(np.int64)
+    rows = rng.choice(ndm, 40, replace=False)
+    for i, r in enumerate(rows):
+        w = int(rng.integers(1, wmax + 1))
+        t = int(rng.integers(0, L - w))
+        x[r, t:t + w] += int(round(600.0 * (6.0 + 6.0 * (i % 4)) / math.sqrt(w)))
+    x = x.astype(np.int32)
+    f_lo, df = synth.band(64)
+    _say("candidates many rows", len(widths), "widths, wmax", wmax)
+    with arts.Plan(64, f_lo, df, synth.TSAMP, np.arange(ndm) * 0.01, widths) as p:
+        got = p.candidates(to_dev(x[None]), thr)
+    ora = O.candidates(x, widths, nrep, thr)
+    near = near_threshold_rows(x, widths, nrep, thr, np.arange(ndm))
+    assert len(ora) >= 20
+    n = compare_candidates(got, ora, near)
+    assert n >= len(ora) - 4
+
+
 def test_candidates_apertif_rows():
     # full-size Apertif chunk with 20 bursts: candidates of 48 DM rows (around the bursts and
     # random) against the oracle on those rows; the moments use the reported window only
