@@ -470,10 +470,10 @@ static int plan_create_subband(int32_t nchan, double f_lo, double df, double tsa
       for (int32_t c = 0; c < csub; ++c)
         d1[static_cast<size_t>(j) * nchan + s * csub + c] = dsub[static_cast<size_t>(j) * csub + c];
   }
-  // the packed tiling with 24 DMs per block, else whichever fits the delay spread
+  // the packed tiling with 24 or 32 DMs per block, else whichever fits the delay spread
   if (st == ARTS_OK) {
     st = plan_create(nchan, f_lo, df, tsamp, coarse.data(), ncoarse, kOne, 1, 1, &p->sb1, false,
-                     0, 10, d1.data(), csub);
+                     0, packed_variant(ncoarse), d1.data(), csub);
     if (st != ARTS_OK)
       st = plan_create(nchan, f_lo, df, tsamp, coarse.data(), ncoarse, kOne, 1, 1, &p->sb1,
                        false, 0, -1, d1.data(), csub);
