@@ -127,8 +127,13 @@ int build_tiling(arts_plan_s* p, int variant) {
   t.rmax = rmax;
   // lane 63 reads dwords 63 j + ((r + g) >> shift) .. + j, with g < spd the window's alignment
   t.win_dwords = (64 * v.j + ((rmax + v.spd - 1) >> shift) + 1 + 3) & ~3;
-  const int64_t budget = p->lds_budget > 0 ? p->lds_budget
-                                          : std::max<int64_t>(16 * 1024, 160 * 1024 * v.waves / 16 - 1024);
+  // LDS per workgroup: a CU's 160 KiB shared by the workgroups that its registers and waves
+  // allow, assuming at least 16 waves per CU
+  int64_t budget = p->lds_budget;
+  if (budget <= 0) {
+    const int nwg = std::max(variant_blocks_per_cu(variant, p->split > 0), 16 / v.waves);
+    budget = std::max<int64_t>(16 * 1024, 160 * 1024 / nwg - 1024);
+  }
   // two buffers (each with 4 pad words) and an SB-table row; per channel its window plus one
   // offset-list entry per DM of the block
   const int64_t per_buf = (budget - ((nchan + 3) & ~int64_t(3))) / 2 - 16;

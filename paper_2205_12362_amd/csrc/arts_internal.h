@@ -163,6 +163,7 @@ struct DedispJob {
 };
 
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s);
+int variant_blocks_per_cu(int variant, bool split);
 // Subband plans: elements of the 16-bit intermediate for nbeam beams of nin samples.
 int64_t subband_ws_elems(const arts_plan_s* p, int32_t nbeam, int64_t nin);
 // Row pitch of a subband plan's step-1 rows: L1 = nin - max step-1 delay samples after a front

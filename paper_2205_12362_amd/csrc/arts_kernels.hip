@@ -1060,6 +1060,52 @@ static int launch_subband(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   return launch_dedisperse(p->sb2, j2, s);
 }
 
+// Workgroups of a variant's one-launch kernel that registers and waves allow per CU (LDS
+// aside); 0 if the runtime cannot tell.
+template <int SPD, int J, int ACC, int WAVES, int PK>
+static int occupancy_variant(bool split) {
+  int n = 0;
+  hipError_t e;
+  if constexpr (SPD == 4 && PK != 2) {
+    if (split) {
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, dedisperse_split_kernel<SPD, J, ACC, WAVES, PK>, WAVES * 64, 0);
+      return e == hipSuccess ? n : 0;
+    }
+  }
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &n, dedisperse_kernel<SPD, J, ACC, WAVES, PK, false>, WAVES * 64, 0);
+  return e == hipSuccess ? n : 0;
+}
+
+int variant_blocks_per_cu(int variant, bool split) {
+  switch (variant) {
+    case 0: return occupancy_variant<4, 5, 4, 8, 0>(split);
+    case 1: return occupancy_variant<4, 7, 3, 8, 0>(split);
+    case 2: return occupancy_variant<4, 5, 4, 16, 0>(split);
+    case 3: return occupancy_variant<4, 3, 6, 8, 0>(split);
+    case 4: return occupancy_variant<4, 5, 2, 4, 0>(split);
+    case 5: return occupancy_variant<4, 7, 4, 8, 0>(split);
+    case 6: return occupancy_variant<2, 5, 4, 8, 0>(split);
+    case 7: return occupancy_variant<2, 9, 2, 8, 0>(split);
+    case 8: return occupancy_variant<2, 7, 3, 8, 0>(split);
+    case 9: return occupancy_variant<4, 5, 4, 8, 1>(split);
+    case 10: return occupancy_variant<4, 5, 3, 8, 1>(split);
+    case 11: return occupancy_variant<4, 3, 6, 8, 1>(split);
+    case 12: return occupancy_variant<4, 5, 4, 16, 1>(split);
+    case 13: return occupancy_variant<2, 5, 4, 8, 1>(split);
+    case 14: return occupancy_variant<2, 9, 2, 8, 1>(split);
+    case 15: return occupancy_variant<2, 7, 3, 8, 1>(split);
+    case 16: return occupancy_variant<2, 5, 6, 8, 1>(split);
+    case 17: return occupancy_variant<4, 5, 2, 4, 1>(split);
+    case 18: return occupancy_variant<4, 5, 1, 8, 2>(split);
+    case 19: return occupancy_variant<4, 5, 1, 16, 2>(split);
+    case 20: return occupancy_variant<4, 3, 2, 8, 2>(split);
+    case 21: return occupancy_variant<4, 7, 1, 8, 2>(split);
+    default: return 0;
+  }
+}
+
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   if (p->nsub > 0) return launch_subband(p, job, s);
   DedispArgs a;
