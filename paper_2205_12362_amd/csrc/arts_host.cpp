@@ -475,10 +475,10 @@ static int plan_create_subband(int32_t nchan, double f_lo, double df, double tsa
       for (int32_t c = 0; c < csub; ++c)
         d1[static_cast<size_t>(j) * nchan + s * csub + c] = dsub[static_cast<size_t>(j) * csub + c];
   }
-  // the packed tiling with 24 or 32 DMs per block, else whichever fits the delay spread
+  // the packed tiling that suits the coarse trial count, else whichever fits the delay spread
   if (st == ARTS_OK) {
     st = plan_create(nchan, f_lo, df, tsamp, coarse.data(), ncoarse, kOne, 1, 1, &p->sb1, false,
-                     0, packed_variant(ncoarse), d1.data(), csub);
+                     0, split_variant(ncoarse), d1.data(), csub);
     if (st != ARTS_OK)
       st = plan_create(nchan, f_lo, df, tsamp, coarse.data(), ncoarse, kOne, 1, 1, &p->sb1,
                        false, 0, -1, d1.data(), csub);
@@ -824,7 +824,7 @@ int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
     return fail(ARTS_E_INVAL, "bad variant or buffer");
   const TileVariant& v = kVariants[variant];
   snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d%s", v.j, v.acc, v.waves, v.spd,
-           v.pack == 2 ? " framed" : v.pack ? " packed" : "");
+           v.pack == 3 ? " packed held" : v.pack == 2 ? " framed" : v.pack ? " packed" : "");
   return ARTS_OK;
 }
 

@@ -24,6 +24,7 @@ extern const TileVariant kVariants[];
 extern const int kNumVariants;
 int default_variant(int downsample, int64_t ndm);
 int packed_variant(int64_t ndm);
+int split_variant(int64_t ncoarse);
 
 // Widest supported boxcar (the candidate kernels stage a segment plus wmax samples in LDS).
 constexpr int kMaxWidth = 16384;

@@ -37,15 +37,20 @@ const TileVariant kVariants[] = {
     {4, 5, 1, 16, 2},  // 19: framed: 16 DMs x 1280, one block per CU
     {4, 3, 2, 8, 2},   // 20: framed: 16 DMs x 768
     {4, 7, 1, 8, 2},   // 21: framed:  8 DMs x 1792
+    {4, 5, 2, 8, 3},   // 22: 16 DMs x 1280, packed halves held across chunks
 };
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-// Byte samples: the packed tiling with 24 DMs per block (10) unless 32 per block (9) leaves
-// fewer idle DM slots in the last block; a slot of 9 costs about 2% more than one of 10.
+// Byte samples: the packed tiling with 32 DMs per block (9) unless 24 per block (10) leaves
+// fewer idle DM slots in the last block; a slot of 10 costs about 2% more than one of 9.
 int packed_variant(int64_t ndm) {
   const int64_t s24 = (ndm + 23) / 24 * 24, s32 = (ndm + 31) / 32 * 32;
-  return s32 * 102 < s24 * 100 ? 9 : 10;
+  return s24 * 102 < s32 * 100 ? 10 : 9;
 }
+
+// The first step of subband plans: the held tiling with 16 DMs per block when the coarse
+// trials fill its blocks (its channel-group stores need no spill space), else as above.
+int split_variant(int64_t ncoarse) { return ncoarse % 16 == 0 ? 22 : packed_variant(ncoarse); }
 
 int default_variant(int downsample, int64_t ndm) {
   if (downsample > 1) return 16;
@@ -648,7 +653,17 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
 #pragma unroll
         for (int k = 0; k < NFW; ++k) fa[x][m][k] = fo[x][m][k] = 0;
   }
-  int since = 0;  // channels in the frames since they were last widened (uniform)
+  // held packed variants: per DM, packed halves that persist across chunks (unused otherwise)
+  constexpr int NH = (PK == 3) ? ACC : 1;
+  constexpr int NHW = (PK == 3) ? J : 1;
+  uint32_t he[NH][NHW], ho[NH][NHW];
+  if constexpr (PK == 3) {
+#pragma unroll
+    for (int x = 0; x < NH; ++x)
+#pragma unroll
+      for (int k = 0; k < NHW; ++k) he[x][k] = ho[x][k] = 0;
+  }
+  int since = 0;  // channels in the frames or held halves since they were last widened
 
   const int32_t* base_blk = a.base + static_cast<int64_t>(blk) * a.nchan;
   const int32_t* list_blk = a.list + static_cast<int64_t>(blk) * a.m_blk * a.nchan;
@@ -675,6 +690,10 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
     // the stores have this chunk's work to complete before the wait at its end
     if constexpr (SPLIT) {
       if (ch > 0 && (c0 % a.split) == 0 && wave_active) {
+        if constexpr (PK == 3) {
+#pragma unroll
+          for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
+        }
         store_tile<T, ACC, true>(a, acc, (c0 / a.split - 1) * a.out_sstride, b, dwave0, t0,
                                  lane);
 #pragma unroll
@@ -691,6 +710,22 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
       stage_windows<SPD, WAVES>(a, sbrow, b, blk, t0, base_blk, c1, ncc1, nxt, lane, wave);
       stage_lists<WAVES>(a, list_blk, c1, ncc1, reinterpret_cast<int32_t*>(nxt + a.cc * a.win),
                          lane, wave);
+    }
+    // ---- held variants: a channel group's store has just widened the halves
+    if constexpr (SPLIT && PK == 3) {
+      if (ch > 0 && (c0 % a.split) == 0) since = 0;
+    }
+    // ---- held variants: widen the halves before they could exceed 257 channels
+    if constexpr (PK == 3) {
+      const int ncc = min(a.cc, a.nchan - c0);
+      if (since + ncc > 257) {
+        if (wave_active) {
+#pragma unroll
+          for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
+        }
+        since = 0;
+      }
+      since += ncc;
     }
     // ---- framed variants: widen the frames before they could exceed 257 channels
     if constexpr (PK == 2) {
@@ -726,6 +761,14 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
           accum_run_fr<J, 1, PF>(fa[x][1], fo[x][1], ent + n0, n1, lane_base);
           accum_run_fr<J, 2, PF>(fa[x][2], fo[x][2], ent + n0 + n1, n2, lane_base);
           accum_run_fr<J, 3, PF>(fa[x][3], fo[x][3], ent + n0 + n1 + n2, n3, lane_base);
+        } else if constexpr (PK == 3) {
+          static_assert(SPD == 4, "held halves are for byte samples");
+          const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
+          constexpr bool PF = ACC * T + 2 * ACC * J <= 90;
+          accum_run_pk<J, 0, PF>(he[x], ho[x], ent, n0, lane_base);
+          accum_run_pk<J, 1, PF>(he[x], ho[x], ent + n0, n1, lane_base);
+          accum_run_pk<J, 2, PF>(he[x], ho[x], ent + n0 + n1, n2, lane_base);
+          accum_run_pk<J, 3, PF>(he[x], ho[x], ent + n0 + n1 + n2, n3, lane_base);
         } else if constexpr (PK && SPD == 2) {
           uint32_t pk[J];
 #pragma unroll
@@ -761,11 +804,20 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
     __syncthreads();
   }
   if constexpr (SPLIT) {  // the last channel group
-    if (wave_active)
+    if (wave_active) {
+      if constexpr (PK == 3) {
+#pragma unroll
+        for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
+      }
       store_tile<T, ACC, true>(a, acc, (a.nchan / a.split - 1) * a.out_sstride, b, dwave0, t0,
                                lane);
+    }
   }
   if (wave_active && !SPLIT) {
+    if constexpr (PK == 3) {
+#pragma unroll
+      for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
+    }
     if constexpr (PK == 2) {
 #pragma unroll
       for (int x = 0; x < ACC; ++x) {
@@ -1102,6 +1154,7 @@ int variant_blocks_per_cu(int variant, bool split) {
     case 19: return occupancy_variant<4, 5, 1, 16, 2>(split);
     case 20: return occupancy_variant<4, 3, 2, 8, 2>(split);
     case 21: return occupancy_variant<4, 7, 1, 8, 2>(split);
+    case 22: return occupancy_variant<4, 5, 2, 8, 3>(split);
     default: return 0;
   }
 }
@@ -1133,6 +1186,7 @@ int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
     case 19: return launch_variant<4, 5, 1, 16, 2>(a, s);
     case 20: return launch_variant<4, 3, 2, 8, 2>(a, s);
     case 21: return launch_variant<4, 7, 1, 8, 2>(a, s);
+    case 22: return launch_variant<4, 5, 2, 8, 3>(a, s);
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
@@ -1229,6 +1283,7 @@ int launch_dedisperse_batch(arts_plan_s* const* plans, const DedispJob* jobs, in
     case 19: return launch_batch_variant<4, 5, 1, 16, 2>(q, lds, s);
     case 20: return launch_batch_variant<4, 3, 2, 8, 2>(q, lds, s);
     case 21: return launch_batch_variant<4, 7, 1, 8, 2>(q, lds, s);
+    case 22: return launch_batch_variant<4, 5, 2, 8, 3>(q, lds, s);
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
