@@ -64,8 +64,9 @@ int dev_alloc(arts_stream_s* s, void** p, size_t bytes) {
 
 // Step-1 row layout of a subband plan in a stream: L1 = halo + chunk - max step-1 delay samples
 // per window, a front pad that puts each chunk's new rows 8-byte aligned, and room for the
-// window to move m = floor(L1 / chunk) chunks before it is compacted back to the front (the
-// copy then never overlaps: it starts (m + 1) chunks in, past the L1 - chunk samples kept).
+// window to move m = 2 floor(L1 / chunk) chunks (at least 1) before it is compacted back to
+// the front (the copy then never overlaps: it starts (m + 1) chunks in, past the L1 - chunk
+// samples kept).
 struct YLayout {
   int64_t l1 = 0, pitch = 0, rows = 0;
   int32_t pad = 0, m = 0;
@@ -78,7 +79,9 @@ YLayout y_layout(const arts_plan_s* pl, int32_t nbeam, int64_t chunk) {
   y.l1 = H + chunk - pl->max_d1;
   const int64_t keep = y.l1 - chunk;
   y.pad = static_cast<int32_t>((4 - keep % 4) % 4);
-  y.m = static_cast<int32_t>(std::max<int64_t>(1, y.l1 / chunk));
+  // m moves between copies: twice the fewest that keep the copy from overlapping itself, so
+  // that the copy runs half as often for the memory of m - l1 / chunk more chunks
+  y.m = static_cast<int32_t>(std::max<int64_t>(1, 2 * (y.l1 / chunk)));
   y.pitch = (y.pad + y.l1 + y.m * chunk + 3) & ~int64_t(3);
   y.rows = static_cast<int64_t>(nbeam) * pl->nsub * pl->ncoarse;
   return y;
