@@ -75,6 +75,28 @@ def test_dedisperse_variants_ragged(variant):
         assert np.array_equal(got[b], O.dedisperse(data[b], delays)), b
 
 
+@pytest.mark.parametrize("variant", [v for v in _native_variants()
+                                     if "packed" in arts.arts_tiling_describe(v)])
+def test_packed_variants_many_channels(variant):
+    # 600 channels: the 16-bit partial sums are widened more than once per tile (every staged
+    # chunk, or every 257 channels when they are held across chunks); saturated input puts
+    # every half at its largest value, random input is checked against the oracle
+    _say("packed variant, 600 channels", variant, arts.arts_tiling_describe(variant))
+    nchan = 600
+    f_lo, df = synth.band(nchan)
+    dms = np.arange(45) * 2.3
+    delays = O.delay_table(nchan, f_lo, df, synth.TSAMP, dms)
+    nin = int(delays.max()) + 1500 + 13
+    w = synth.Workload("wide", nchan, f_lo, df, synth.TSAMP, dms, [1])
+    rng = np.random.default_rng(variant + 600)
+    data = rng.integers(0, 256, size=(nchan, nin), dtype=np.uint8)
+    with _plan(w, variant) as p:
+        got = p.dedisperse(to_dev(data)).cpu().numpy()[0]
+        full = p.dedisperse(to_dev(np.full((nchan, nin), 255, np.uint8))).cpu().numpy()[0]
+    assert np.array_equal(got, O.dedisperse(data, delays))
+    assert np.all(full == 255 * nchan)
+
+
 @pytest.mark.parametrize("nchan,ndm,extra", [(1, 1, 1), (3, 5, 2), (37, 33, 1000), (7, 70, 5),
                                              (255, 9, 300), (256, 40, 64), (300, 3, 33)])
 def test_dedisperse_edge_shapes(nchan, ndm, extra):
