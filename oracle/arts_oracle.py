@@ -13,9 +13,10 @@ design notes of the repository; each is marked "reading".
 Parity status per function:
   channel_freqs, delay_table, tie_audit, downsample, sb_synthesize, dedisperse,
   dedisperse_at, subband_plan, subband_dedisperse, subband_dedisperse_at, boxcar, moments,
-  snr, candidates, cluster_dm_width, cluster_offline, rfi_time_domain, rfi_freq_domain,
-  rfi_clean, sb_index_at_fmax, sb_switch_freqs, sb_table_beam_model  -- pinned by closed forms / invariants / hand-worked
-  values / brute force in tests/test_oracle_pins.py (no function here is "parity unpinned").
+  snr, candidates, candidates_integrated, cluster_dm_width, cluster_offline,
+  rfi_time_domain, rfi_freq_domain, rfi_clean, sb_index_at_fmax, sb_switch_freqs,
+  sb_table_beam_model -- pinned by closed forms / invariants / hand-worked values / brute
+  force in tests/test_oracle_pins.py (no function here is "parity unpinned").
 """
 from __future__ import annotations
 
@@ -272,6 +273,44 @@ def candidates(series: np.ndarray, widths, nrep: int, threshold: float, beam: in
                 k = t + int(np.argmax(b[d, t:e]))
                 out.append((beam, d, int(w), k + t_offset, float(s[d, k])))
                 t = e
+    out.sort(key=lambda r: (r[0], r[1], r[2], r[3]))
+    return out
+
+
+def candidates_integrated(series: np.ndarray, widths, nrep: int, threshold: float,
+                          beam: int = 0, t_offset: int = 0):
+    """Threshold candidates with decimated integration (Sect. 6b.2, "Integration": the
+    dedispersed series is downsampled by each trial pulse width).
+
+    Reading: for width w the integrated series holds one sample per w consecutive input samples,
+    the sum over [g, g + w - 1] for g on the absolute grid g + t_offset = 0 (mod w), so that
+    consecutive chunks of a stream share the grid.  Only starts t < nrep on that grid are
+    searched; S/N and threshold are those of `candidates` (the noise of a w-sample sum is
+    sigma * sqrt(w)); a run is a maximal sequence of consecutive grid starts (g, g + w, ...)
+    above the threshold, reported at its largest sum, the earliest on ties.  For w = 1 this is
+    `candidates`.  Returns (beam, dm_index, width, g + t_offset, snr) sorted like `candidates`.
+    """
+    x = np.asarray(series).astype(np.int64)
+    mu, sigma = moments(x, nrep)
+    out = []
+    for w in widths:
+        w = int(w)
+        b = boxcar(x, w, nrep)
+        s = snr(b, w, mu, sigma)
+        grid = np.array([t for t in range(nrep) if (t + t_offset) % w == 0], dtype=np.int64)
+        for d in range(x.shape[0]):
+            above = s[d, grid] > threshold
+            i = 0
+            while i < len(grid):
+                if not above[i]:
+                    i += 1
+                    continue
+                e = i
+                while e < len(grid) and above[e]:
+                    e += 1
+                k = grid[i + int(np.argmax(b[d, grid[i:e]]))]
+                out.append((beam, d, w, int(k) + t_offset, float(s[d, k])))
+                i = e
     out.sort(key=lambda r: (r[0], r[1], r[2], r[3]))
     return out
 

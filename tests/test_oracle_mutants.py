@@ -365,6 +365,43 @@ def _sb_beam_variant(kind):
                 sb_table_beam_model=sb_table_beam_model)
 
 
+def _integrated_variant(kind):
+    def candidates_integrated(series, widths, nrep, threshold, beam=0, t_offset=0):
+        x = np.asarray(series).astype(np.int64)
+        mu, sigma = O.moments(x, nrep)
+        out = []
+        for w in widths:
+            w = int(w)
+            b = O.boxcar(x, w, nrep)
+            if kind == "sums end at the start" and w > 1:
+                b = np.full_like(b, -10**9)
+                b[:, w - 1:] = O.boxcar(x, w, nrep - w + 1)
+            s = O.snr(b, w, mu, sigma)
+            phase = {"grid ignores the offset": 0,
+                     "grid offset sign flipped": -t_offset}.get(kind, t_offset)
+            grid = [t for t in range(nrep) if (t + phase) % w == 0]
+            for d in range(x.shape[0]):
+                above = [s[d, t] > threshold for t in grid]
+                i = 0
+                while i < len(grid):
+                    if not above[i]:
+                        i += 1
+                        continue
+                    e = i
+                    while e < len(grid) and (above[e] or kind == "runs not broken"):
+                        e += 1
+                    vals = [b[d, grid[j]] for j in range(i, e) if above[j]]
+                    idx = [j for j in range(i, e) if above[j]]
+                    m = max(vals)
+                    pick = [j for j, v in zip(idx, vals) if v == m]
+                    k = grid[pick[-1] if kind == "ties to the latest" else pick[0]]
+                    out.append((beam, d, w, int(k) + t_offset, float(s[d, k])))
+                    i = e
+        out.sort(key=lambda r: (r[0], r[1], r[2], r[3]))
+        return out
+    return candidates_integrated
+
+
 MUTANTS = {
     "reference at lowest channel": dict(delay_table=_delay_variant(ref="min")),
     "floor instead of round": dict(delay_table=_delay_variant(rounding=np.floor)),
@@ -414,6 +451,16 @@ MUTANTS = {
     "sb beam quarter blends swapped": _sb_beam_variant("quarter blends swapped"),
     "sb beam TAB row without offset": _sb_beam_variant("TAB row without offset"),
     "sb beam no wrap": _sb_beam_variant("no wrap"),
+    "integrated grid ignores the offset": dict(
+        candidates_integrated=_integrated_variant("grid ignores the offset")),
+    "integrated grid offset sign flipped": dict(
+        candidates_integrated=_integrated_variant("grid offset sign flipped")),
+    "integrated runs not broken": dict(
+        candidates_integrated=_integrated_variant("runs not broken")),
+    "integrated ties to the latest": dict(
+        candidates_integrated=_integrated_variant("ties to the latest")),
+    "integrated sums end at the start": dict(
+        candidates_integrated=_integrated_variant("sums end at the start")),
 }
 
 
@@ -446,6 +493,10 @@ def test_unmutated_offline_rewrite_passes():
 
 def test_unmutated_rfi_rewrite_passes():
     assert _run_all(_copy(**_rfi_variant("none"))) == []
+
+
+def test_unmutated_integrated_rewrite_passes():
+    assert _run_all(_copy(candidates_integrated=_integrated_variant("none"))) == []
 
 
 def test_unmutated_sb_beam_rewrite_passes():

@@ -392,6 +392,101 @@ def test_tophat_snr():
     check_tophat_snr(O)
 
 
+# ------------------------------------------------------------------ decimated integration
+def check_integrated_golden(o):
+    g = _load("integrated_tiny.json")
+    x = np.array(g["series"])
+    got = o.candidates_integrated(x, g["widths"], g["nrep"], g["threshold"],
+                                  t_offset=g["t_offset"])
+    assert [c[:4] for c in got] == [tuple(c[:4]) for c in g["candidates"]]
+    for c, e in zip(got, g["candidates"]):
+        assert abs(c[4] - e[4]) < 1e-9
+
+
+def _integrated_brute(x, widths, nrep, thr, t_offset):
+    # explicit loops: mean and population sigma, the integrated samples of each width on the
+    # absolute grid, their S/N, runs over consecutive integrated samples, first maximum
+    out = []
+    for d, row in enumerate(x.tolist()):
+        n = nrep
+        mu = sum(row[:n]) / n
+        sig = math.sqrt(sum((v - mu) ** 2 for v in row[:n]) / n)
+        for w in widths:
+            ks = [t for t in range(n) if (t + t_offset) % w == 0]
+            vals = [sum(row[t:t + w]) for t in ks]
+            snrs = [(v - w * mu) / (sig * math.sqrt(w)) if sig > 0 else 0.0 for v in vals]
+            i = 0
+            while i < len(ks):
+                if not snrs[i] > thr:
+                    i += 1
+                    continue
+                best = i
+                e = i
+                while e < len(ks) and snrs[e] > thr:
+                    if vals[e] > vals[best]:
+                        best = e
+                    e += 1
+                out.append((0, d, w, ks[best] + t_offset, snrs[best]))
+                i = e
+    return sorted(out, key=lambda r: r[:4])
+
+
+def check_integrated_brute_force(o):
+    rng = np.random.default_rng(77)
+    for trial in range(6):
+        ndm, nrep = 4, int(rng.integers(30, 70))
+        widths = sorted(set(int(v) for v in rng.choice([1, 2, 3, 4, 5, 7, 8], 3)))
+        L = nrep + max(widths) - 1
+        x = rng.integers(0, 20, size=(ndm, L))
+        for r in range(ndm):                      # a few pulses, some straddling grid cells
+            t = int(rng.integers(0, L - 6))
+            x[r, t:t + int(rng.integers(1, 6))] += int(rng.integers(10, 40))
+        t_off = int(rng.integers(-50, 50))
+        thr = float(rng.choice([1.5, 2.0, 2.5]))
+        got = o.candidates_integrated(x, widths, nrep, thr, t_offset=t_off)
+        ref = _integrated_brute(x, widths, nrep, thr, t_off)
+        assert [c[:4] for c in got] == [c[:4] for c in ref], trial
+        for a, b in zip(got, ref):
+            assert abs(a[4] - b[4]) < 1e-9
+
+
+def check_integrated_invariants(o):
+    rng = np.random.default_rng(78)
+    x = rng.integers(0, 30, size=(5, 90))
+    x[1, 40:44] += 60
+    x[3, 10:13] += 50
+    widths, nrep, thr = [1, 2, 4, 5], 80, 2.0
+    # width 1 is the sliding search
+    one = o.candidates_integrated(x, [1], nrep, thr, t_offset=17)
+    assert one == o.candidates(x, [1], nrep, thr, t_offset=17)
+    got = o.candidates_integrated(x, widths, nrep, thr, t_offset=-13)
+    assert got
+    for b, d, w, t, s in got:
+        assert t % w == 0 and -13 <= t < nrep - 13      # on the absolute grid, searched starts
+    # moving the series' origin by a multiple of every width keeps the grid: same candidates,
+    # shifted
+    lcm = 20
+    moved = o.candidates_integrated(x, widths, nrep, thr, t_offset=-13 + lcm)
+    assert [c[:3] + (c[3] - lcm,) for c in moved] == [c[:4] for c in got]
+    # each integrated candidate is a sliding boxcar value: its S/N is at most the sliding
+    # maximum of that row and width
+    for b, d, w, t, s in got:
+        sl = [c[4] for c in o.candidates(x, [w], nrep, thr, t_offset=-13) if c[1] == d]
+        assert sl and s <= max(sl) + 1e-12
+
+
+def test_integrated_golden():
+    check_integrated_golden(O)
+
+
+def test_integrated_brute_force():
+    check_integrated_brute_force(O)
+
+
+def test_integrated_invariants():
+    check_integrated_invariants(O)
+
+
 # ------------------------------------------------------------------ subband dedispersion
 def check_subband_golden(o):
     g = _load("subband_tiny.json")
@@ -829,6 +924,7 @@ ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif
               check_linearity_shift_permutation, check_chunked_stream, check_tophat_exact,
               check_downsample, check_sb_synth, check_boxcar, check_moments, check_snr_noise,
               check_candidates_golden, check_injected_recovery, check_tophat_snr,
+              check_integrated_golden, check_integrated_brute_force, check_integrated_invariants,
               check_subband_golden, check_subband_reductions, check_subband_smearing_bound,
               check_cluster_golden, check_cluster_brute_force, check_cluster_invariants,
               check_offline_golden, check_offline_brute_force, check_offline_invariants,
