@@ -342,6 +342,7 @@ def alert_bench(args):
              for a, st, n, nf in ALERT_PLANS]
     for p in plans:
         p.cluster = bool(args.cluster)
+        p.integration = args.integration
     table = torch.from_numpy(synth.sb_table_synthetic(NSB, NTAB, NCHAN)).cuda()
     pool = [torch.from_numpy(synth.noise((NTAB, NCHAN, CHUNK), seed=900 + k)).cuda()
             for k in range(2)]
@@ -398,7 +399,7 @@ def alert_bench(args):
                                "250; 12500 new samples per step",
                    "ntrial": ntrial, "nsb": NSB, "chunk": CHUNK, "threshold": THRESHOLD,
                    "cluster": bool(args.cluster), "rfi": bool(args.rfi),
-                   "device_bytes": info["device_bytes"]},
+                   "integration": args.integration, "device_bytes": info["device_bytes"]},
         "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
         "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                              "p99": float(np.percentile(lat_ms, 99)),
@@ -511,6 +512,10 @@ def main():
     ap.add_argument("--sb-table", choices=["synthetic", "model"], default="synthetic",
                     help="serving: the SB table of the 71 SBs: the synthetic stand-in or the "
                          "beam model's (arts_sb_table_beam_model)")
+    ap.add_argument("--integration", choices=["sliding", "decimated"], default="sliding",
+                    help="alert: candidate search with sliding boxcars (default) or decimated "
+                         "integration on each width's grid (AMBER's downsampling by the trial "
+                         "widths; they divide the 12 500-sample chunk)")
     ap.add_argument("--rfi", action="store_true",
                     help="serving / alert: RFI mitigation of each chunk's TABs (time domain at "
                          "6 sigma, frequency domain at 5 sigma, 3 iterations each)")

@@ -278,6 +278,23 @@ int arts_candidates(arts_plan_t plan, const int32_t* series, int32_t nbeam, int6
 int arts_plan_set_cluster(arts_plan_t plan, int32_t enable);
 int arts_plan_get_cluster(arts_plan_t plan, int32_t* enable);
 
+/* Integration mode of the candidate search (Sect. 6b.2, "Integration": the dedispersed series
+ * is downsampled by each trial pulse width).  mode 0 (default): sliding boxcars, every start
+ * t < nrep is searched.  mode 1: decimated, as AMBER's downsampling: for width w only starts on
+ * the absolute grid (t + t_offset) % w == 0 are searched, i.e. the series summed over
+ * non-overlapping windows of w samples aligned to absolute sample 0 (streams: to the stream's
+ * first sample, so consecutive chunks share the grid); a run is a maximal sequence of
+ * consecutive grid starts above the threshold, reported at its largest sum (the earliest on
+ * ties).  Moments, S/N and threshold are those of mode 0; width 1 gives identical results.
+ * Applies to arts_candidates, arts_batch_candidates and streams (read at each search).  Mode 1
+ * needs rows held whole in LDS, nrep - t_begin + wmax <= 16383 (chunks of a stream, plan calls
+ * on rows of up to about 16 000 samples); longer rows give ARTS_E_INVAL at the search.  In a
+ * stream every width must divide chunk / downsampling, so that each chunk starts on every
+ * grid (ARTS_E_INVAL at arts_stream_create, or at the push if the mode is set later).
+ * arts_boxcar_snr is not affected.  Other mode values give ARTS_E_INVAL.                      */
+int arts_plan_set_integration(arts_plan_t plan, int32_t mode);
+int arts_plan_get_integration(arts_plan_t plan, int32_t* mode);
+
 /* Cluster a device list of this plan's candidates in place (same rule as above).
  * cand: device arts_candidate [n], n < 2^31, beam in [beam_offset, beam_offset + nbeam),
  * 0 <= dm_index < the plan's ndm.  On return cand[0, *count) holds one candidate per cluster,

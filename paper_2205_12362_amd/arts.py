@@ -60,6 +60,8 @@ _SIGNATURES = {
     "arts_plan_get_tiling": (C.c_int, [_vp, _pi32]),
     "arts_plan_set_cluster": (C.c_int, [_vp, _i32]),
     "arts_plan_get_cluster": (C.c_int, [_vp, _pi32]),
+    "arts_plan_set_integration": (C.c_int, [_vp, _i32]),
+    "arts_plan_get_integration": (C.c_int, [_vp, _pi32]),
     "arts_plan_cluster": (C.c_int, [_vp, _vp, _i64, _i32, _i32, _pi64, _vp]),
     "arts_cluster_offline": (C.c_int, [_vp, _i64, _i64, _pf64, _i32, _f32, _vp, _i64, _pi64,
                                        _vp]),
@@ -367,6 +369,18 @@ def arts_plan_set_cluster(plan, enable):
     _check(lib().arts_plan_set_cluster(plan, int(enable)))
 
 
+def arts_plan_set_integration(plan, mode):
+    """mode 0 / "sliding" (default) or 1 / "decimated" (each width's absolute grid)."""
+    mode = {"sliding": 0, "decimated": 1}.get(mode, mode)
+    _check(lib().arts_plan_set_integration(plan, int(mode)))
+
+
+def arts_plan_get_integration(plan):
+    v = C.c_int32(0)
+    _check(lib().arts_plan_get_integration(plan, C.byref(v)))
+    return ("sliding", "decimated")[v.value]
+
+
 def arts_plan_get_cluster(plan):
     v = C.c_int32(0)
     _check(lib().arts_plan_get_cluster(plan, C.byref(v)))
@@ -534,6 +548,14 @@ class Plan:
     @cluster.setter
     def cluster(self, enable):
         arts_plan_set_cluster(self.handle, enable)
+
+    @property
+    def integration(self):
+        return arts_plan_get_integration(self.handle)
+
+    @integration.setter
+    def integration(self, mode):
+        arts_plan_set_integration(self.handle, mode)
 
     def cluster_candidates(self, cand, nbeam, beam_offset=0, stream=None):
         return arts_plan_cluster(self.handle, cand, nbeam, beam_offset, stream)

@@ -664,6 +664,19 @@ int arts_plan_get_cluster(arts_plan_t p, int32_t* enable) {
   return ARTS_OK;
 }
 
+int arts_plan_set_integration(arts_plan_t p, int32_t mode) {
+  if (int st = check_plan(p)) return st;
+  if (mode != 0 && mode != 1) return fail(ARTS_E_INVAL, "mode must be 0 or 1");
+  p->integration = mode;
+  return ARTS_OK;
+}
+
+int arts_plan_get_integration(arts_plan_t p, int32_t* mode) {
+  if (int st = check_plan(p)) return st;
+  if (mode) *mode = p->integration;
+  return ARTS_OK;
+}
+
 int arts_sb_table_beam_model(int32_t nsb, int32_t ntab, int32_t nchan, double f_lo_mhz,
                              double df_mhz, double f_max_mhz, double alpha, double b_max_m,
                              double b_cq_m, int32_t quarter, uint8_t* table_out,

@@ -101,6 +101,8 @@ struct arts_plan_s {
   // DM-width clustering of this plan's candidates (arts_plan_set_cluster) and the workspace of
   // one-shot calls
   bool cluster = false;
+  // candidate search: 0 sliding boxcars, 1 decimated integration (each width's absolute grid)
+  int32_t integration = 0;
   arts::ClusterWs cl;
   bool is16() const { return ds > 1 || in16; }
 };
@@ -165,6 +167,8 @@ struct DedispJob {
 
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s);
 int variant_blocks_per_cu(int variant, bool split);
+// false for a plan in decimated integration whose widths do not all divide nrep
+bool integration_grid_ok(const arts_plan_s* p, int64_t nrep);
 // Subband plans: elements of the 16-bit intermediate for nbeam beams of nin samples.
 int64_t subband_ws_elems(const arts_plan_s* p, int32_t nbeam, int64_t nin);
 // Row pitch of a subband plan's step-1 rows: L1 = nin - max step-1 delay samples after a front

@@ -1554,7 +1554,7 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
     const int32_t* __restrict__ widths, int32_t nw, int32_t wmax, const double* __restrict__ dms,
     double thr, int64_t t_offset, int32_t beam_offset, int32_t ds,
     arts_candidate* __restrict__ cand, unsigned long long* __restrict__ count, int64_t cap,
-    const uint8_t* __restrict__ flags) {
+    const uint8_t* __restrict__ flags, int32_t decim) {
   // rows the pre-pass found below the threshold at every width give no candidate
   if (flags != nullptr && flags[blockIdx.x] == 0) return;
   extern __shared__ uint32_t P[];
@@ -1750,16 +1750,27 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
         const bool any = static_cast<long long>(bmax) > T;
         if (!__syncthreads_or(any ? 1 : 0) && !c_open[cin][wi]) continue;
       }
-      // ---- classify this thread's starts
+      // ---- classify this thread's starts.  Decimated integration (resident rows only): start
+      // k holds the sum of its grid cell, B_w(g) with g = k - r, r = (s0 + k + t_offset) mod w,
+      // so that a run over consecutive grid starts is a run over consecutive k, and its first
+      // largest value sits at a grid start; cells that begin before the row are below threshold
       bool in_pre = true, open = false;
       int pre_len = 0;
       int32_t pre_max = 0, best = 0;
       int pre_arg = 0, arg = 0;
+      const bool dec = RES && decim != 0 && w > 1;
+      int r = 0;
+      if (dec) {
+        const int64_t m = (s0 + k0 + t_offset) % w;
+        r = static_cast<int>(m < 0 ? m + w : m);
+      }
 #pragma unroll
       for (int i = 0; i < (kCandSeg / NT); ++i) {
         const int k = k0 + i;
-        const bool valid = k < n;
-        const int32_t B = valid ? static_cast<int32_t>(Pseg[k + 1 + w] - Pseg[k + 1]) : 0;
+        const int g = dec ? k - r : k;
+        const bool valid = k < n && (!dec || s0 + g >= 0);
+        const int32_t B = valid ? static_cast<int32_t>(Pseg[g + 1 + w] - Pseg[g + 1]) : 0;
+        if (dec && ++r == w) r = 0;
         const bool a = valid && static_cast<long long>(B) > T;
         if (in_pre) {
           if (a) {
@@ -2054,6 +2065,10 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
   // resident rows: P[0 .. n] and one spare word, n = searched starts + wmax - 1
   const size_t res_lds = (static_cast<size_t>(nrep - t_begin) + p->wmax + 1) * sizeof(uint32_t);
   const bool res = res_lds <= static_cast<size_t>(kCandResLds);
+  if (p->integration != 0 && !res)
+    return fail(ARTS_E_INVAL,
+                "decimated integration needs resident rows: %lld searched starts + wmax %d "
+                "exceed %d", (long long)(nrep - t_begin), p->wmax, kCandResLds / 4 - 1);
   const size_t lds = res ? res_lds : (kCandSeg + p->wmax + 1) * sizeof(uint32_t);
   (void)hipGetLastError();
   const bool wide = nrep - t_begin >= kCandLong;
@@ -2078,7 +2093,7 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
                      series + t_begin, L, L - t_begin, nrep - t_begin, p->ndm, p->d_widths,
                      p->nwidth, p->wmax, p->d_dms, static_cast<double>(thr),
                      t_offset + t_begin, beam_offset, p->ds, cand, count, cap,
-                     pre ? flags : nullptr);
+                     pre ? flags : nullptr, p->integration);
   ARTS_HIP(hipGetLastError());
   return ARTS_OK;
 }

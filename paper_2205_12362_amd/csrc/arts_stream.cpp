@@ -227,7 +227,20 @@ bool stream_warm(const arts_stream_s* s, int64_t k) {
   return true;
 }
 
+// Decimated integration in a stream: chunk samples are numbered relative to the chunk, so each
+// width's grid is the absolute one only if every width divides the chunk's searched length.
+bool integration_grid_ok(const arts_plan_s* p, int64_t nrep) {
+  if (p->integration == 0) return true;
+  for (int32_t w : p->widths)
+    if (nrep % w != 0) return false;
+  return true;
+}
+
 int stream_candidates(arts_stream_s* s, hipStream_t hs) {
+  for (size_t p = 0; p < s->plans.size(); ++p)
+    if (!integration_grid_ok(s->plans[p], s->chunk / s->plans[p]->ds))
+      return fail(ARTS_E_INVAL, "plan %zu searches with decimated integration: every width must "
+                  "divide chunk / downsampling (%lld)", p, (long long)(s->chunk / s->plans[p]->ds));
   if (int st = launch_zero_u64(s->d_count, 1, hs)) return st;
   for (size_t p = 0; p < s->plans.size(); ++p) {
     const arts_plan_s* pl = s->plans[p];
@@ -332,6 +345,11 @@ int arts_stream_create(const arts_plan_t* plans, int32_t nplan, int32_t nsrc,
       stream_free(s);
       return fail(ARTS_E_INVAL, "chunk %lld is not a multiple of plan %d's downsampling %d",
                   (long long)chunk, i, p->ds);
+    }
+    if (!integration_grid_ok(p, chunk / p->ds)) {
+      stream_free(s);
+      return fail(ARTS_E_INVAL, "plan %d searches with decimated integration: every width must "
+                  "divide chunk / downsampling (%lld)", i, (long long)(chunk / p->ds));
     }
     if (p->nsub > 0 && chunk % 4 != 0) {  // the step-1 window moves by whole 8-byte groups
       stream_free(s);
