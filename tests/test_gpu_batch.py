@@ -54,6 +54,32 @@ def test_batch_matches_oracle():
             assert np.array_equal(got[bm], O.dedisperse(x, delays)), (i, bm)
 
 
+def _native_variants():
+    return [v for v in range(arts.arts_tiling_count()) if "SPD=4" in arts.arts_tiling_describe(v)]
+
+
+@pytest.mark.parametrize("variant", _native_variants())
+def test_batch_tilings_match_oracle(variant):
+    # the persistent kernel of every byte-sample tiling (the native requests are set to it)
+    reqs = [r for i, r in enumerate(_small_requests()) if r[0].downsample == 1 and i != 4]
+    plans = [arts.Plan.from_workload(w) for w, _, _ in reqs]
+    for p in plans:
+        p.set_tiling(variant)
+    items, outs = [], []
+    for (w, delays, data), p in zip(reqs, plans):
+        out = to_dev(np.zeros((data.shape[0], w.dms.size, arts.series_length(p, data.shape[2])),
+                              np.int32))
+        items.append((p, to_dev(data), out))
+        outs.append(out)
+    with arts.Batch() as b:
+        st = b.dedisperse(items)
+    for (w, delays, data), s, out in zip(reqs, st, outs):
+        assert s == arts.ARTS_OK
+        got = out.cpu().numpy()
+        for bm in range(data.shape[0]):
+            assert np.array_equal(got[bm], O.dedisperse(data[bm], delays)), (variant, bm)
+
+
 def _uneven(n, seed):
     import torch
     reqs = synth.uneven_requests(n, seed=seed)
