@@ -289,9 +289,7 @@ int arts_plan_get_cluster(arts_plan_t plan, int32_t* enable);
  * first sample, so consecutive chunks share the grid); a run is a maximal sequence of
  * consecutive grid starts above the threshold, reported at its largest sum (the earliest on
  * ties).  Moments, S/N and threshold are those of mode 0; width 1 gives identical results.
- * Applies to arts_candidates, arts_batch_candidates and streams (read at each search).  Mode 1
- * needs rows held whole in LDS, nrep - t_begin + wmax <= 16383 (chunks of a stream, plan calls
- * on rows of up to about 16 000 samples); longer rows give ARTS_E_INVAL at the search.  In a
+ * Applies to arts_candidates, arts_batch_candidates and streams (read at each search).  In a
  * stream every width must divide chunk / downsampling, so that each chunk starts on every
  * grid (ARTS_E_INVAL at arts_stream_create, or at the push if the mode is set later).
  * arts_boxcar_snr is not affected.  Other mode values give ARTS_E_INVAL.                      */

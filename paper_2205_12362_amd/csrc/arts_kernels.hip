@@ -1730,7 +1730,11 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
       Pseg = P + s0;
       __syncthreads();  // every read of the carry slot cleared below has happened
     } else {
-      load_prefix<NT>(x, L, s0, n + wmax, P, wsum);  // ends with a barrier
+      // decimated integration reads a start's grid cell, up to wmax - 1 starts back: the
+      // segment's prefix then begins that much earlier
+      const int lb = decim != 0 ? wmax - 1 : 0;
+      load_prefix<NT>(x, L, s0 - lb, n + wmax + lb, P, wsum);  // ends with a barrier
+      Pseg = P + lb;
     }
     if (tid < nw) c_open[cin ^ 1][tid] = 0;
     if constexpr (RES) __syncthreads();
@@ -1750,15 +1754,15 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
         const bool any = static_cast<long long>(bmax) > T;
         if (!__syncthreads_or(any ? 1 : 0) && !c_open[cin][wi]) continue;
       }
-      // ---- classify this thread's starts.  Decimated integration (resident rows only): start
-      // k holds the sum of its grid cell, B_w(g) with g = k - r, r = (s0 + k + t_offset) mod w,
-      // so that a run over consecutive grid starts is a run over consecutive k, and its first
-      // largest value sits at a grid start; cells that begin before the row are below threshold
+      // ---- classify this thread's starts.  Decimated integration: start k holds the sum of
+      // its grid cell, B_w(g) with g = k - r, r = (s0 + k + t_offset) mod w, so that a run over
+      // consecutive grid starts is a run over consecutive k, and its first largest value sits
+      // at a grid start; cells that begin before the row are below threshold
       bool in_pre = true, open = false;
       int pre_len = 0;
       int32_t pre_max = 0, best = 0;
       int pre_arg = 0, arg = 0;
-      const bool dec = RES && decim != 0 && w > 1;
+      const bool dec = decim != 0 && w > 1;
       int r = 0;
       if (dec) {
         const int64_t m = (s0 + k0 + t_offset) % w;
@@ -2052,10 +2056,10 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
   if (!attr) {
     ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel<false, 256>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (kCandSeg + kMaxWidth + 1) * 4));
+                                 (kCandSeg + 2 * kMaxWidth) * 4));
     ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel<false, 512>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (kCandSeg + kMaxWidth + 1) * 4));
+                                 (kCandSeg + 2 * kMaxWidth) * 4));
     ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel<true, 256>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, kCandResLds));
     ARTS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&candidates_kernel<true, 512>),
@@ -2065,11 +2069,11 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
   // resident rows: P[0 .. n] and one spare word, n = searched starts + wmax - 1
   const size_t res_lds = (static_cast<size_t>(nrep - t_begin) + p->wmax + 1) * sizeof(uint32_t);
   const bool res = res_lds <= static_cast<size_t>(kCandResLds);
-  if (p->integration != 0 && !res)
-    return fail(ARTS_E_INVAL,
-                "decimated integration needs resident rows: %lld searched starts + wmax %d "
-                "exceed %d", (long long)(nrep - t_begin), p->wmax, kCandResLds / 4 - 1);
-  const size_t lds = res ? res_lds : (kCandSeg + p->wmax + 1) * sizeof(uint32_t);
+  // segments of longer rows: kCandSeg starts plus wmax samples (and wmax - 1 before them for
+  // decimated integration)
+  const size_t lds = res ? res_lds
+                         : (kCandSeg + p->wmax + 1 + (p->integration ? p->wmax - 1 : 0)) *
+                               sizeof(uint32_t);
   (void)hipGetLastError();
   const bool wide = nrep - t_begin >= kCandLong;
   const int nt = wide ? 512 : 256;
