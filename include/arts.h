@@ -202,9 +202,10 @@ int arts_plan_autotune(arts_plan_t plan, int32_t nbeam, int64_t nin, int32_t rep
                        const char* cache_path, int32_t* variant_out, float* ms_out);
 /* Writes "J=<dwords per lane> ACC=<DMs per wave> WAVES=<waves per block> SPD=<samples per
  * dword>" and the partial-sum form (" packed": 16-bit halves widened once per staged chunk;
- * " packed held": widened every 257 channels; " framed": raw-dword frames per sub-dword
- * offset; none: single-sample adds) for a variant into buf (NUL-terminated, at most len
- * bytes).                                                                                    */
+ * " packed held": widened every 257 channels; " group sums": the halves are the channel
+ * group sums of the first subband step, the only plans these variants run; " framed":
+ * raw-dword frames per sub-dword offset; none: single-sample adds) for a variant into buf
+ * (NUL-terminated, at most len bytes).                                                       */
 int arts_tiling_describe(int32_t variant, char* buf, int32_t len);
 
 /* ------------------------------------------------------------------------ hot path ---- */

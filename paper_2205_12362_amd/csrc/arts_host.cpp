@@ -101,6 +101,11 @@ int build_tiling(arts_plan_s* p, int variant) {
   if (p->is16() != (v.spd == 2))
     return fail(ARTS_E_INVAL, "variant %d is for %s data", variant,
                 v.spd == 4 ? "byte (native)" : "16-bit (downsampled)");
+  // group-sum tilings keep a channel group's sums in 16-bit halves: split plans with groups of
+  // at most 257 byte channels
+  if (v.pack == 4 && (p->split <= 0 || p->split > 257))
+    return fail(ARTS_E_INVAL, "variant %d runs the first subband step only (groups of at most "
+                "257 channels)", variant);
   Tiling t;
   t.variant = variant;
   t.spd = v.spd;
@@ -837,7 +842,11 @@ int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
     return fail(ARTS_E_INVAL, "bad variant or buffer");
   const TileVariant& v = kVariants[variant];
   snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d%s", v.j, v.acc, v.waves, v.spd,
-           v.pack == 3 ? " packed held" : v.pack == 2 ? " framed" : v.pack ? " packed" : "");
+           v.pack == 4   ? " group sums"
+           : v.pack == 3 ? " packed held"
+           : v.pack == 2 ? " framed"
+           : v.pack      ? " packed"
+                         : "");
   return ARTS_OK;
 }
 

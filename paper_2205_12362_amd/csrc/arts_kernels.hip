@@ -38,6 +38,7 @@ const TileVariant kVariants[] = {
     {4, 3, 2, 8, 2},   // 20: framed: 16 DMs x 768
     {4, 7, 1, 8, 2},   // 21: framed:  8 DMs x 1792
     {4, 5, 2, 8, 3},   // 22: 16 DMs x 1280, packed halves held across chunks
+    {4, 5, 4, 8, 4},   // 23: 32 DMs x 1280, group sums in packed halves (split plans only)
 };
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -48,9 +49,14 @@ int packed_variant(int64_t ndm) {
   return s24 * 102 < s32 * 100 ? 10 : 9;
 }
 
-// The first step of subband plans: the held tiling with 16 DMs per block when the coarse
-// trials fill its blocks (its channel-group stores need no spill space), else as above.
-int split_variant(int64_t ncoarse) { return ncoarse % 16 == 0 ? 22 : packed_variant(ncoarse); }
+// The first step of subband plans: the group-sum tiling (32 DMs per block) when the coarse
+// trials fill its blocks, else the held one (16 per block), else as above.  Plan creation
+// falls back to the default if the choice does not fit (for instance groups of more than 257
+// channels).
+int split_variant(int64_t ncoarse) {
+  if (ncoarse % 32 == 0) return 23;
+  return ncoarse % 16 == 0 ? 22 : packed_variant(ncoarse);
+}
 
 int default_variant(int downsample, int64_t ndm) {
   if (downsample > 1) return 16;
@@ -619,6 +625,43 @@ __device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (
   }
 }
 
+// Group-sum variants: the packed halves of a channel group are its sums (at most 257 channels
+// of bytes fit a half), stored as 16-bit samples.  Half words: e[k] holds outputs 4k and 4k+2,
+// o[k] outputs 4k+1 and 4k+3; two v_perm_b32 put each four in natural order.  Clears e, o.
+template <int J, int ACC>
+__device__ __forceinline__ void store_group_pk(const DedispArgs& a, uint32_t (*e)[J],
+                                               uint32_t (*o)[J], int64_t off, int b,
+                                               int dwave0, int64_t t0, int lane) {
+  constexpr int T = 4 * J;
+#pragma unroll
+  for (int x = 0; x < ACC; ++x) {
+    const int d = dwave0 + x;
+    if (d < a.ndm) {
+      const int64_t row = off + static_cast<int64_t>(b) * a.out_bstride + d * a.out_pitch;
+      uint16_t* op = reinterpret_cast<uint16_t*>(a.out) + row;
+      const int64_t tl = t0 + static_cast<int64_t>(lane) * T;
+      if (tl + T <= a.nout && (reinterpret_cast<uintptr_t>(op + tl) & 7u) == 0) {
+        uint2* q = reinterpret_cast<uint2*>(op + tl);
+#pragma unroll
+        for (int k = 0; k < J; ++k)
+          q[k] = make_uint2(__builtin_amdgcn_perm(o[x][k], e[x][k], 0x05040100u),
+                            __builtin_amdgcn_perm(o[x][k], e[x][k], 0x07060302u));
+      } else {
+#pragma unroll
+        for (int k = 0; k < J; ++k) {
+          const uint32_t v[4] = {e[x][k] & 0xFFFFu, o[x][k] & 0xFFFFu, e[x][k] >> 16,
+                                 o[x][k] >> 16};
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            if (tl + 4 * k + m < a.nout) op[tl + 4 * k + m] = static_cast<uint16_t>(v[m]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < J; ++k) e[x][k] = o[x][k] = 0;
+  }
+}
+
 // One tile: DM block blk, time tile tt, beam b.  Used by the one-launch-per-job kernel and by
 // the persistent batch kernel; ends after its global stores with no LDS access pending.
 template <int SPD, int J, int ACC, int WAVES, int PK, bool SPLIT = false>
@@ -636,11 +679,13 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   const int dwave0 = blk * a.m_blk + wave * ACC;
   const bool wave_active = dwave0 < a.ndm;
 
-  uint32_t acc[ACC][T];
+  // int32 totals (unused by the group-sum variants, whose groups fit the packed halves)
+  constexpr int TA = (PK == 4) ? 1 : T;
+  uint32_t acc[ACC][TA];
 #pragma unroll
   for (int x = 0; x < ACC; ++x)
 #pragma unroll
-    for (int i = 0; i < T; ++i) acc[x][i] = 0;
+    for (int i = 0; i < TA; ++i) acc[x][i] = 0;
   // framed variants: per DM, four frames of J + 1 dword pairs (unused otherwise)
   constexpr int NF = (PK == 2) ? ACC : 1;
   constexpr int NFW = (PK == 2) ? J + 1 : 1;
@@ -653,11 +698,12 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
 #pragma unroll
         for (int k = 0; k < NFW; ++k) fa[x][m][k] = fo[x][m][k] = 0;
   }
-  // held packed variants: per DM, packed halves that persist across chunks (unused otherwise)
-  constexpr int NH = (PK == 3) ? ACC : 1;
-  constexpr int NHW = (PK == 3) ? J : 1;
+  // held and group-sum variants: per DM, packed halves that persist across chunks (unused
+  // otherwise)
+  constexpr int NH = (PK == 3 || PK == 4) ? ACC : 1;
+  constexpr int NHW = (PK == 3 || PK == 4) ? J : 1;
   uint32_t he[NH][NHW], ho[NH][NHW];
-  if constexpr (PK == 3) {
+  if constexpr (PK == 3 || PK == 4) {
 #pragma unroll
     for (int x = 0; x < NH; ++x)
 #pragma unroll
@@ -690,16 +736,21 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
     // the stores have this chunk's work to complete before the wait at its end
     if constexpr (SPLIT) {
       if (ch > 0 && (c0 % a.split) == 0 && wave_active) {
-        if constexpr (PK == 3) {
-#pragma unroll
-          for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
-        }
-        store_tile<T, ACC, true>(a, acc, (c0 / a.split - 1) * a.out_sstride, b, dwave0, t0,
+        if constexpr (PK == 4) {
+          store_group_pk<J, ACC>(a, he, ho, (c0 / a.split - 1) * a.out_sstride, b, dwave0, t0,
                                  lane);
+        } else {
+          if constexpr (PK == 3) {
 #pragma unroll
-        for (int x = 0; x < ACC; ++x)
+            for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
+          }
+          store_tile<T, ACC, true>(a, acc, (c0 / a.split - 1) * a.out_sstride, b, dwave0, t0,
+                                   lane);
 #pragma unroll
-          for (int i = 0; i < T; ++i) acc[x][i] = 0;
+          for (int x = 0; x < ACC; ++x)
+#pragma unroll
+            for (int i = 0; i < T; ++i) acc[x][i] = 0;
+        }
       }
     }
     // ---- start fetching the next chunk into the other buffer
@@ -761,10 +812,11 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
           accum_run_fr<J, 1, PF>(fa[x][1], fo[x][1], ent + n0, n1, lane_base);
           accum_run_fr<J, 2, PF>(fa[x][2], fo[x][2], ent + n0 + n1, n2, lane_base);
           accum_run_fr<J, 3, PF>(fa[x][3], fo[x][3], ent + n0 + n1 + n2, n3, lane_base);
-        } else if constexpr (PK == 3) {
+        } else if constexpr (PK == 3 || PK == 4) {
           static_assert(SPD == 4, "held halves are for byte samples");
           const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
-          constexpr bool PF = ACC * T + 2 * ACC * J <= 90;
+          // registers: the held halves, plus the int32 totals unless the halves are the sums
+          constexpr bool PF = (PK == 4 ? 0 : ACC * T) + 2 * ACC * J <= 90;
           accum_run_pk<J, 0, PF>(he[x], ho[x], ent, n0, lane_base);
           accum_run_pk<J, 1, PF>(he[x], ho[x], ent + n0, n1, lane_base);
           accum_run_pk<J, 2, PF>(he[x], ho[x], ent + n0 + n1, n2, lane_base);
@@ -805,12 +857,17 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   }
   if constexpr (SPLIT) {  // the last channel group
     if (wave_active) {
-      if constexpr (PK == 3) {
+      if constexpr (PK == 4) {
+        store_group_pk<J, ACC>(a, he, ho, (a.nchan / a.split - 1) * a.out_sstride, b, dwave0,
+                               t0, lane);
+      } else {
+        if constexpr (PK == 3) {
 #pragma unroll
-        for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
+          for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
+        }
+        store_tile<T, ACC, true>(a, acc, (a.nchan / a.split - 1) * a.out_sstride, b, dwave0,
+                                 t0, lane);
       }
-      store_tile<T, ACC, true>(a, acc, (a.nchan / a.split - 1) * a.out_sstride, b, dwave0, t0,
-                               lane);
     }
   }
   if (wave_active && !SPLIT) {
@@ -827,7 +884,8 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
         flush_fr<J, 3>(acc[x], fa[x][3], fo[x][3]);
       }
     }
-    store_tile<T, ACC, false>(a, acc, 0, b, dwave0, t0, lane);
+    if constexpr (PK != 4)  // group-sum variants run split plans only
+      store_tile<T, ACC, false>(a, acc, 0, b, dwave0, t0, lane);
   }
 }
 
@@ -849,6 +907,14 @@ template <int SPD, int J, int ACC, int WAVES, int PK, bool SPLIT>
 __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
   extern __shared__ uint32_t lds[];
   dedisperse_grid<SPD, J, ACC, WAVES, PK, SPLIT>(a, lds);
+}
+
+// Group-sum split plans (the first subband step): four waves per SIMD, two 8-wave workgroups.
+template <int SPD, int J, int ACC, int WAVES, int PK>
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
+void dedisperse_group_kernel(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  dedisperse_grid<SPD, J, ACC, WAVES, PK, true>(a, lds);
 }
 
 // Split plans (the first subband step): the group stores add live registers; four waves per
@@ -958,38 +1024,50 @@ static int launch_variant(DedispArgs a, hipStream_t s) {
   if (a.nwg > INT_MAX) return fail(ARTS_E_INVAL, "grid too large (%lld blocks)", (long long)a.nwg);
   static bool attr_plain = false, attr_split = false;  // one pair per template instance
   if (a.split > 0) {
-    if constexpr (SPD == 4 && PK != 2)
+    if constexpr (PK == 4)
+      return launch_kernel(&dedisperse_group_kernel<SPD, J, ACC, WAVES, PK>, WAVES, a, lds, s,
+                           attr_split);
+    else if constexpr (SPD == 4 && PK != 2)
       return launch_kernel(&dedisperse_split_kernel<SPD, J, ACC, WAVES, PK>, WAVES, a, lds, s,
                            attr_split);
     else
       return fail(ARTS_E_INVAL, "this tiling variant cannot split channel groups");
   }
-  return launch_kernel(&dedisperse_kernel<SPD, J, ACC, WAVES, PK, false>, WAVES, a, lds, s,
-                       attr_plain);
+  if constexpr (PK == 4)
+    return fail(ARTS_E_INVAL, "group-sum tilings run the first subband step only");
+  else
+    return launch_kernel(&dedisperse_kernel<SPD, J, ACC, WAVES, PK, false>, WAVES, a, lds, s,
+                         attr_plain);
 }
 
 template <int SPD, int J, int ACC, int WAVES, int PK>
 static int launch_batch_variant(BatchArgs q, size_t lds, hipStream_t s) {
-  if (lds + kBatchStaticLds > 160 * 1024)
-    return fail(ARTS_E_INVAL, "LDS request %zu B too large for a persistent launch", lds);
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (int st = allow_full_lds(&dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>, kBatchStaticLds))
-      return st;
-    attr_set = true;
+  if constexpr (PK == 4) {
+    return fail(ARTS_E_INVAL, "group-sum tilings run the first subband step only");
+  } else {
+    if (lds + kBatchStaticLds > 160 * 1024)
+      return fail(ARTS_E_INVAL, "LDS request %zu B too large for a persistent launch", lds);
+    static bool attr_set = false;
+    if (!attr_set) {
+      if (int st = allow_full_lds(&dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>,
+                                  kBatchStaticLds))
+        return st;
+      attr_set = true;
+    }
+    int per_cu = 0, dev = 0, ncu = 0;
+    ARTS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>),
+        WAVES * 64, lds));
+    ARTS_HIP(hipGetDevice(&dev));
+    ARTS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t grid =
+        std::max<int64_t>(1, std::min<int64_t>(q.part[8], int64_t(std::max(1, per_cu)) * ncu));
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>),
+                       dim3(static_cast<unsigned>(grid)), dim3(WAVES * 64), lds, s, q);
+    ARTS_HIP(hipGetLastError());
+    return ARTS_OK;
   }
-  int per_cu = 0, dev = 0, ncu = 0;
-  ARTS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(&dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>),
-      WAVES * 64, lds));
-  ARTS_HIP(hipGetDevice(&dev));
-  ARTS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(q.part[8], int64_t(std::max(1, per_cu)) * ncu));
-  (void)hipGetLastError();
-  hipLaunchKernelGGL((dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>), dim3(static_cast<unsigned>(grid)),
-                     dim3(WAVES * 64), lds, s, q);
-  ARTS_HIP(hipGetLastError());
-  return ARTS_OK;
 }
 
 // Kernel arguments of one job.  Rows must start on dword boundaries (pitch and pointer); the
@@ -1118,15 +1196,20 @@ template <int SPD, int J, int ACC, int WAVES, int PK>
 static int occupancy_variant(bool split) {
   int n = 0;
   hipError_t e;
-  if constexpr (SPD == 4 && PK != 2) {
-    if (split) {
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &n, dedisperse_split_kernel<SPD, J, ACC, WAVES, PK>, WAVES * 64, 0);
-      return e == hipSuccess ? n : 0;
+  if constexpr (PK == 4) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, dedisperse_group_kernel<SPD, J, ACC, WAVES, PK>, WAVES * 64, 0);
+  } else {
+    if constexpr (SPD == 4 && PK != 2) {
+      if (split) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, dedisperse_split_kernel<SPD, J, ACC, WAVES, PK>, WAVES * 64, 0);
+        return e == hipSuccess ? n : 0;
+      }
     }
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, dedisperse_kernel<SPD, J, ACC, WAVES, PK, false>, WAVES * 64, 0);
   }
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &n, dedisperse_kernel<SPD, J, ACC, WAVES, PK, false>, WAVES * 64, 0);
   return e == hipSuccess ? n : 0;
 }
 
@@ -1155,6 +1238,7 @@ int variant_blocks_per_cu(int variant, bool split) {
     case 20: return occupancy_variant<4, 3, 2, 8, 2>(split);
     case 21: return occupancy_variant<4, 7, 1, 8, 2>(split);
     case 22: return occupancy_variant<4, 5, 2, 8, 3>(split);
+    case 23: return occupancy_variant<4, 5, 4, 8, 4>(split);
     default: return 0;
   }
 }
@@ -1187,6 +1271,7 @@ int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
     case 20: return launch_variant<4, 3, 2, 8, 2>(a, s);
     case 21: return launch_variant<4, 7, 1, 8, 2>(a, s);
     case 22: return launch_variant<4, 5, 2, 8, 3>(a, s);
+    case 23: return launch_variant<4, 5, 4, 8, 4>(a, s);
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
@@ -1284,6 +1369,7 @@ int launch_dedisperse_batch(arts_plan_s* const* plans, const DedispJob* jobs, in
     case 20: return launch_batch_variant<4, 3, 2, 8, 2>(q, lds, s);
     case 21: return launch_batch_variant<4, 7, 1, 8, 2>(q, lds, s);
     case 22: return launch_batch_variant<4, 5, 2, 8, 3>(q, lds, s);
+    case 23: return launch_batch_variant<4, 5, 4, 8, 4>(q, lds, s);
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
