@@ -2315,10 +2315,64 @@ __global__ __launch_bounds__(kGatherThreads) void copy_rows_kernel(
   }
 }
 
+// Rows whose starts have the same offset within a V word and whose pitches are whole words:
+// the first `head` bytes of a row (up to the first word boundary) and the last `tail` bytes
+// are copied bytewise by the row's first and last block, the nv words between them one V per
+// thread and pass, consecutive threads on consecutive words (kGatherDw passes per block).
+template <typename V>
+__global__ __launch_bounds__(kGatherThreads) void copy_rows_vec_kernel(
+    uint8_t* __restrict__ dst, int64_t dpitch, const uint8_t* __restrict__ src, int64_t spitch,
+    int head, int64_t nv, int tail, int64_t nchunk) {
+  const int64_t row = blockIdx.x / nchunk;
+  const int64_t chunk = blockIdx.x % nchunk;
+  uint8_t* drow = dst + row * dpitch;
+  const uint8_t* srow = src + row * spitch;
+  if (chunk == 0 && static_cast<int>(threadIdx.x) < head) drow[threadIdx.x] = srow[threadIdx.x];
+  if (chunk == nchunk - 1 && static_cast<int>(threadIdx.x) < tail) {
+    const int64_t o = head + nv * static_cast<int64_t>(sizeof(V)) + threadIdx.x;
+    drow[o] = srow[o];
+  }
+  V* dv = reinterpret_cast<V*>(drow + head);
+  const V* sv = reinterpret_cast<const V*>(srow + head);
+  const int64_t k0 = chunk * kGatherThreads * kGatherDw + threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < kGatherDw; ++i) {
+    const int64_t k = k0 + static_cast<int64_t>(i) * kGatherThreads;
+    if (k < nv) dv[k] = sv[k];
+  }
+}
+
+template <typename V>
+static int launch_copy_rows_vec(uint8_t* dst, int64_t dpitch, const uint8_t* src,
+                                int64_t spitch, int64_t nrows, int64_t n, hipStream_t s) {
+  constexpr int64_t w = sizeof(V);
+  const int head = static_cast<int>(
+      std::min<int64_t>(n, (w - static_cast<int64_t>(reinterpret_cast<uintptr_t>(dst) % w)) % w));
+  const int64_t nv = (n - head) / w;
+  const int tail = static_cast<int>(n - head - nv * w);
+  const int64_t per_block = static_cast<int64_t>(kGatherThreads) * kGatherDw;
+  const int64_t nchunk = std::max<int64_t>(1, (nv + per_block - 1) / per_block);
+  if (nrows * nchunk > INT_MAX) return fail(ARTS_E_INVAL, "copy grid too large");
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(copy_rows_vec_kernel<V>, dim3(static_cast<unsigned>(nrows * nchunk)),
+                     dim3(kGatherThreads), 0, s, dst, dpitch, src, spitch, head, nv, tail,
+                     nchunk);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
 int launch_copy_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t spitch,
                      int64_t nrows, int64_t n, const uint8_t* src_begin, const uint8_t* src_end,
                      hipStream_t s) {
   if (nrows <= 0 || n <= 0) return ARTS_OK;
+  // both starts at the same offset within a 16- or 8-byte word and whole-word pitches: words
+  // between a bytewise head and tail
+  const uint64_t al = (reinterpret_cast<uintptr_t>(dst) ^ reinterpret_cast<uintptr_t>(src)) |
+                      static_cast<uint64_t>(dpitch) | static_cast<uint64_t>(spitch);
+  if (n >= 64 && (al & 15u) == 0)
+    return launch_copy_rows_vec<uint4>(dst, dpitch, src, spitch, nrows, n, s);
+  if (n >= 64 && (al & 7u) == 0)
+    return launch_copy_rows_vec<uint2>(dst, dpitch, src, spitch, nrows, n, s);
   const int64_t per_block = static_cast<int64_t>(kGatherThreads) * kGatherDw * 4;
   const int64_t nchunk = (n + 3 + per_block) / per_block;
   if (nrows * nchunk > INT_MAX) return fail(ARTS_E_INVAL, "copy grid too large");
