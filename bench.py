@@ -480,6 +480,58 @@ def cluster_bench(args):
         "cpu_baseline": cpu}))
 
 
+def tilings_bench(args):
+    """Every compiled tiling that runs the serving launches, timed on them: the fused-SB
+    dedispersion of 71 SBs from 12 TABs x 1536 channels over the 2048 native trials (byte
+    tilings) and over the 1476 D=4 trials (16-bit tilings), `args.steps` timed launches after
+    one warm-up launch each (HIP events on the current stream).  One JSON line: per variant its
+    description, ms per launch and Tadd/s (null where the tiling does not fit the plan)."""
+    import torch
+
+    import paper_2205_12362_amd.arts as arts
+    from paper_2205_12362_amd import synth
+
+    table = torch.from_numpy(synth.sb_table_synthetic(NSB, NTAB, NCHAN)).cuda()
+    res = {}
+    for w in (synth.cfg_apertif(), synth.cfg_apertif_ds()):
+        p = arts.Plan.from_workload(w)
+        nin = CHUNK + p.halo * w.downsample
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        tab = torch.randint(0, 256, (NTAB, NCHAN, nin), dtype=torch.uint8, device="cuda",
+                            generator=g)
+        default = p.tiling()
+        spd = "SPD=4" if w.downsample == 1 else "SPD=2"
+        out = None
+        for v in range(arts.arts_tiling_count()):
+            d = arts.arts_tiling_describe(v)
+            if spd not in d or "group" in d:
+                continue
+            try:
+                p.set_tiling(v)
+            except arts.ArtsError:
+                res[v] = {"tiling": d, "plan": w.name, "ms": None, "tadd_s": None}
+                continue
+            log(f"tiling {v}: {d}")
+            out = p.dedisperse_sb(tab, table, out=out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                p.dedisperse_sb(tab, table, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            adds = NSB * w.dms.size * out.shape[2] * NCHAN
+            res[v] = {"tiling": d, "plan": w.name, "default": v == default, "ms": ms,
+                      "tadd_s": adds / ms / 1e9}
+        del tab, out, p
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "dedispersion tilings on the serving launches (71 SBs fused "
+                                  "from 12 TABs x 1536 ch; 2048 native / 1476 D=4 trials)",
+                      "steps": args.steps, "tilings": res}), flush=True)
+
+
 def ctypes_cluster(arts, plan, work, n):
     import ctypes as C
     cnt = C.c_int64(0)
@@ -501,12 +553,13 @@ def main():
     ap.add_argument("--variant", type=int, default=None, help="native dedispersion tiling")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 1 GiB twice (counter calibration)")
-    ap.add_argument("--workload", choices=["serving", "uneven", "alert", "cluster"],
+    ap.add_argument("--workload", choices=["serving", "uneven", "alert", "cluster", "tilings"],
                     default="serving",
                     help="serving: the 71-SB stream step (default); uneven: 64 uneven requests, "
                          "persistent batch vs per-request calls; alert: the paper's subband "
                          "dedispersion setup for one compound beam; cluster: DM-width "
-                         "clustering of a serving-scale candidate list")
+                         "clustering of a serving-scale candidate list; tilings: every "
+                         "dedispersion tiling timed on the serving launches")
     ap.add_argument("--cluster", action="store_true",
                     help="serving / alert: cluster each chunk's candidates (DM-width)")
     ap.add_argument("--sb-table", choices=["synthetic", "model"], default="synthetic",
@@ -524,12 +577,12 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
               "design note, not built", file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("uneven", "alert", "cluster"):
+    if args.workload in ("uneven", "alert", "cluster", "tilings"):
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         torch.cuda.set_device(0)
-        {"uneven": uneven_bench, "alert": alert_bench, "cluster": cluster_bench}[args.workload](
-            args)
+        {"uneven": uneven_bench, "alert": alert_bench, "cluster": cluster_bench,
+         "tilings": tilings_bench}[args.workload](args)
         return
 
     import torch
