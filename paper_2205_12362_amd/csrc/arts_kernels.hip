@@ -59,7 +59,7 @@ int split_variant(int64_t ncoarse) {
 }
 
 int default_variant(int downsample, int64_t ndm) {
-  if (downsample > 1) return 16;
+  if (downsample > 1) return 6;
   return ndm <= 64 ? 17 : packed_variant(ndm);
 }
 
