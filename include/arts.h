@@ -480,7 +480,9 @@ int arts_server_close(arts_server_t server, int32_t stream_id);
 int arts_server_submit(arts_server_t server, int32_t stream_id, const uint8_t* chunk,
                        int32_t from_host);
 /* Enqueue one step for every stream with a submitted chunk; returns at once.  *nrun
- * (nullable) = number of streams stepped.                                                    */
+ * (nullable) = number of streams stepped.  Errors: ARTS_E_DEVICE (a failed launch or copy),
+ * ARTS_E_INVAL (a plan switched to decimated integration that no longer fits the stream's
+ * chunk); the streams of that tick are then left part-way through their step: close them.    */
 int arts_server_tick(arts_server_t server, int32_t* nrun);
 /* Wait for a stream's last step and return its candidates (as arts_stream_wait).             */
 int arts_server_collect(arts_server_t server, int32_t stream_id, arts_candidate* host_out,

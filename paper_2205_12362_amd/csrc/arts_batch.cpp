@@ -67,7 +67,6 @@ int arts_batch_dedisperse(arts_batch_t b, const arts_request* reqs, int32_t n, i
   if (!b || (!reqs && n > 0) || n < 0) return fail(ARTS_E_INVAL, "bad batch arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::map<int, std::pair<std::vector<arts_plan_s*>, std::vector<DedispJob>>> groups;
-  int nok = 0;
   for (int32_t i = 0; i < n; ++i) {
     const arts_request& r = reqs[i];
     int st = ARTS_OK;
@@ -109,13 +108,11 @@ int arts_batch_dedisperse(arts_batch_t b, const arts_request* reqs, int32_t n, i
                                static_cast<int>(reinterpret_cast<uintptr_t>(job.in) & 3u), true))
         return e;
       if (int e = launch_dedisperse(p, job, s)) return e;
-      ++nok;
       continue;
     }
     auto& g = groups[p->tiling.variant];
     g.first.push_back(p);
     g.second.push_back(job);
-    ++nok;
   }
   for (auto& kv : groups) {
     auto& g = kv.second;
@@ -123,7 +120,6 @@ int arts_batch_dedisperse(arts_batch_t b, const arts_request* reqs, int32_t n, i
                                         static_cast<int>(g.first.size()), b->bb, s))
       return e;
   }
-  (void)nok;
   return ARTS_OK;
 }
 
