@@ -939,10 +939,18 @@ struct BatchArgs {
   int32_t njobs;
 };
 
-// Four waves per SIMD (<= 128 VGPRs) so that two 8-wave workgroups share a CU, as in the
-// one-launch-per-job kernel.
+// Waves per SIMD of the persistent kernel: as many as the one-launch-per-job kernel of the
+// same tiling reaches, since the plan sizes its LDS chunks for that many workgroups per CU.
+// Four (<= 128 VGPRs: two 8-wave workgroups per CU), except six (<= 80 VGPRs: three) for the
+// plain 16-bit tiling with 32 DMs per block, whose one-launch kernel needs 76 registers.
 template <int SPD, int J, int ACC, int WAVES, int PK>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
+constexpr int batch_waves_per_eu() {
+  return (SPD == 2 && J == 5 && ACC == 4 && WAVES == 8 && PK == 0) ? 6 : 4;
+}
+
+template <int SPD, int J, int ACC, int WAVES, int PK>
+__global__ __launch_bounds__(WAVES * 64)
+__attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<SPD, J, ACC, WAVES, PK>())))
 void dedisperse_batch_kernel(BatchArgs q) {
   extern __shared__ uint32_t lds[];
   __shared__ long long s_item;
