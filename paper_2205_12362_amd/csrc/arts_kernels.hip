@@ -941,11 +941,15 @@ struct BatchArgs {
 
 // Waves per SIMD of the persistent kernel: as many as the one-launch-per-job kernel of the
 // same tiling reaches, since the plan sizes its LDS chunks for that many workgroups per CU.
-// Four (<= 128 VGPRs: two 8-wave workgroups per CU), except six (<= 80 VGPRs: three) for the
-// plain 16-bit tiling with 32 DMs per block, whose one-launch kernel needs 76 registers.
+// Four (<= 128 VGPRs: two 8-wave workgroups per CU), except six (<= 80 VGPRs) for the two
+// plain tilings whose one-launch kernels need 76 registers: 16-bit samples with 32 DMs per
+// block (three 8-wave workgroups per CU) and byte samples with 8 DMs per 4-wave block (six).
 template <int SPD, int J, int ACC, int WAVES, int PK>
 constexpr int batch_waves_per_eu() {
-  return (SPD == 2 && J == 5 && ACC == 4 && WAVES == 8 && PK == 0) ? 6 : 4;
+  return (PK == 0 && J == 5 && ((SPD == 2 && ACC == 4 && WAVES == 8) ||
+                                (SPD == 4 && ACC == 2 && WAVES == 4)))
+             ? 6
+             : 4;
 }
 
 template <int SPD, int J, int ACC, int WAVES, int PK>
