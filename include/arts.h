@@ -207,6 +207,12 @@ int arts_plan_autotune(arts_plan_t plan, int32_t nbeam, int64_t nin, int32_t rep
  * raw-dword frames per sub-dword offset; none: single-sample adds) for a variant into buf
  * (NUL-terminated, at most len bytes).                                                       */
 int arts_tiling_describe(int32_t variant, char* buf, int32_t len);
+/* Workgroups per CU that registers and waves allow (LDS aside) on the current device for a
+ * variant's one-launch kernel (*per_job; for group-sum variants the split-plan kernel) and its
+ * persistent batch kernel (*persistent; 0 for group-sum variants, which have none).  A plan
+ * sizes its LDS chunks for *per_job workgroups per CU; batches and the serving engine run the
+ * persistent kernel on the same chunks.  Errors: ARTS_E_INVAL, ARTS_E_DEVICE.                 */
+int arts_tiling_occupancy(int32_t variant, int32_t* per_job, int32_t* persistent);
 
 /* ------------------------------------------------------------------------ hot path ---- */
 

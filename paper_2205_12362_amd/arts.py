@@ -73,6 +73,7 @@ _SIGNATURES = {
     "arts_plan_autotune": (C.c_int, [_vp, _i32, _i64, _i32, C.c_char_p, _pi32,
                                      C.POINTER(C.c_float)]),
     "arts_tiling_describe": (C.c_int, [_i32, C.c_char_p, _i32]),
+    "arts_tiling_occupancy": (C.c_int, [_i32, _pi32, _pi32]),
     "arts_sb_synthesize": (C.c_int, [_vp, _i32, _vp, _i32, _i32, _i64, _vp, _vp]),
     "arts_dedisperse": (C.c_int, [_vp, _vp, _i32, _i64, _vp, _vp]),
     "arts_dedisperse_sb": (C.c_int, [_vp, _vp, _i32, _vp, _i32, _i64, _vp, _vp]),
@@ -196,6 +197,14 @@ def arts_tiling_describe(variant):
     buf = C.create_string_buffer(128)
     _check(lib().arts_tiling_describe(int(variant), buf, 128))
     return buf.value.decode()
+
+
+def arts_tiling_occupancy(variant):
+    """(per_job, persistent): workgroups per CU that registers and waves allow for the
+    variant's one-launch kernel and for its persistent batch kernel (0: none)."""
+    a, b = C.c_int32(), C.c_int32()
+    _check(lib().arts_tiling_occupancy(int(variant), C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def arts_version():

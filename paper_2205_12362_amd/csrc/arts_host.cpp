@@ -837,6 +837,17 @@ int arts_plan_cluster(arts_plan_t p, arts_candidate* cand, int64_t n, int32_t nb
 
 int32_t arts_tiling_count(void) { return kNumVariants; }
 
+int arts_tiling_occupancy(int32_t variant, int32_t* per_job, int32_t* persistent) {
+  if (variant < 0 || variant >= kNumVariants || !per_job || !persistent)
+    return fail(ARTS_E_INVAL, "bad variant or NULL output");
+  const bool group = kVariants[variant].pack == 4;
+  *per_job = variant_occupancy(variant, group ? kOccSplit : kOccPlain);
+  *persistent = variant_occupancy(variant, kOccBatch);
+  if (*per_job < 1 || (!group && *persistent < 1))
+    return fail(ARTS_E_DEVICE, "occupancy query failed for variant %d", variant);
+  return ARTS_OK;
+}
+
 int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
   if (variant < 0 || variant >= kNumVariants || !buf || len < 1)
     return fail(ARTS_E_INVAL, "bad variant or buffer");

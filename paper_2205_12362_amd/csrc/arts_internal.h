@@ -166,6 +166,10 @@ struct DedispJob {
 };
 
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s);
+// Workgroups per CU that registers and waves allow (LDS aside) for a tiling variant's kernel
+// of one kind; 0 if the runtime cannot tell or the variant has no kernel of that kind.
+constexpr int kOccPlain = 0, kOccSplit = 1, kOccBatch = 2;
+int variant_occupancy(int variant, int kind);
 int variant_blocks_per_cu(int variant, bool split);
 // false for a plan in decimated integration whose widths do not all divide nrep
 bool integration_grid_ok(const arts_plan_s* p, int64_t nrep);

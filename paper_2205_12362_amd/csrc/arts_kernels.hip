@@ -1202,18 +1202,25 @@ static int launch_subband(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   return launch_dedisperse(p->sb2, j2, s);
 }
 
-// Workgroups of a variant's one-launch kernel that registers and waves allow per CU (LDS
-// aside); 0 if the runtime cannot tell.
+// Workgroups per CU that registers and waves allow (LDS aside) for a variant's kernel of one
+// kind (kOccPlain / kOccSplit: the one-launch kernel of plain or split plans; kOccBatch: the
+// persistent batch kernel); 0 if the runtime cannot tell or the kind does not exist.
 template <int SPD, int J, int ACC, int WAVES, int PK>
-static int occupancy_variant(bool split) {
+static int occupancy_variant(int kind) {
   int n = 0;
-  hipError_t e;
-  if constexpr (PK == 4) {
+  hipError_t e = hipErrorInvalidValue;
+  if constexpr (PK == 4) {  // group sums: split plans only, no persistent instance
+    if (kind == kOccBatch) return 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &n, dedisperse_group_kernel<SPD, J, ACC, WAVES, PK>, WAVES * 64, 0);
   } else {
+    if (kind == kOccBatch) {
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, dedisperse_batch_kernel<SPD, J, ACC, WAVES, PK>, WAVES * 64, 0);
+      return e == hipSuccess ? n : 0;
+    }
     if constexpr (SPD == 4 && PK != 2) {
-      if (split) {
+      if (kind == kOccSplit) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &n, dedisperse_split_kernel<SPD, J, ACC, WAVES, PK>, WAVES * 64, 0);
         return e == hipSuccess ? n : 0;
@@ -1225,34 +1232,38 @@ static int occupancy_variant(bool split) {
   return e == hipSuccess ? n : 0;
 }
 
-int variant_blocks_per_cu(int variant, bool split) {
+int variant_occupancy(int variant, int kind) {
   switch (variant) {
-    case 0: return occupancy_variant<4, 5, 4, 8, 0>(split);
-    case 1: return occupancy_variant<4, 7, 3, 8, 0>(split);
-    case 2: return occupancy_variant<4, 5, 4, 16, 0>(split);
-    case 3: return occupancy_variant<4, 3, 6, 8, 0>(split);
-    case 4: return occupancy_variant<4, 5, 2, 4, 0>(split);
-    case 5: return occupancy_variant<4, 7, 4, 8, 0>(split);
-    case 6: return occupancy_variant<2, 5, 4, 8, 0>(split);
-    case 7: return occupancy_variant<2, 9, 2, 8, 0>(split);
-    case 8: return occupancy_variant<2, 7, 3, 8, 0>(split);
-    case 9: return occupancy_variant<4, 5, 4, 8, 1>(split);
-    case 10: return occupancy_variant<4, 5, 3, 8, 1>(split);
-    case 11: return occupancy_variant<4, 3, 6, 8, 1>(split);
-    case 12: return occupancy_variant<4, 5, 4, 16, 1>(split);
-    case 13: return occupancy_variant<2, 5, 4, 8, 1>(split);
-    case 14: return occupancy_variant<2, 9, 2, 8, 1>(split);
-    case 15: return occupancy_variant<2, 7, 3, 8, 1>(split);
-    case 16: return occupancy_variant<2, 5, 6, 8, 1>(split);
-    case 17: return occupancy_variant<4, 5, 2, 4, 1>(split);
-    case 18: return occupancy_variant<4, 5, 1, 8, 2>(split);
-    case 19: return occupancy_variant<4, 5, 1, 16, 2>(split);
-    case 20: return occupancy_variant<4, 3, 2, 8, 2>(split);
-    case 21: return occupancy_variant<4, 7, 1, 8, 2>(split);
-    case 22: return occupancy_variant<4, 5, 2, 8, 3>(split);
-    case 23: return occupancy_variant<4, 5, 4, 8, 4>(split);
+    case 0: return occupancy_variant<4, 5, 4, 8, 0>(kind);
+    case 1: return occupancy_variant<4, 7, 3, 8, 0>(kind);
+    case 2: return occupancy_variant<4, 5, 4, 16, 0>(kind);
+    case 3: return occupancy_variant<4, 3, 6, 8, 0>(kind);
+    case 4: return occupancy_variant<4, 5, 2, 4, 0>(kind);
+    case 5: return occupancy_variant<4, 7, 4, 8, 0>(kind);
+    case 6: return occupancy_variant<2, 5, 4, 8, 0>(kind);
+    case 7: return occupancy_variant<2, 9, 2, 8, 0>(kind);
+    case 8: return occupancy_variant<2, 7, 3, 8, 0>(kind);
+    case 9: return occupancy_variant<4, 5, 4, 8, 1>(kind);
+    case 10: return occupancy_variant<4, 5, 3, 8, 1>(kind);
+    case 11: return occupancy_variant<4, 3, 6, 8, 1>(kind);
+    case 12: return occupancy_variant<4, 5, 4, 16, 1>(kind);
+    case 13: return occupancy_variant<2, 5, 4, 8, 1>(kind);
+    case 14: return occupancy_variant<2, 9, 2, 8, 1>(kind);
+    case 15: return occupancy_variant<2, 7, 3, 8, 1>(kind);
+    case 16: return occupancy_variant<2, 5, 6, 8, 1>(kind);
+    case 17: return occupancy_variant<4, 5, 2, 4, 1>(kind);
+    case 18: return occupancy_variant<4, 5, 1, 8, 2>(kind);
+    case 19: return occupancy_variant<4, 5, 1, 16, 2>(kind);
+    case 20: return occupancy_variant<4, 3, 2, 8, 2>(kind);
+    case 21: return occupancy_variant<4, 7, 1, 8, 2>(kind);
+    case 22: return occupancy_variant<4, 5, 2, 8, 3>(kind);
+    case 23: return occupancy_variant<4, 5, 4, 8, 4>(kind);
     default: return 0;
   }
+}
+
+int variant_blocks_per_cu(int variant, bool split) {
+  return variant_occupancy(variant, split ? kOccSplit : kOccPlain);
 }
 
 int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {

@@ -41,6 +41,9 @@ def test_version_and_tilings():
         assert s.startswith("J=") and "SPD=" in s
     with pytest.raises(arts.ArtsError):
         arts.arts_tiling_describe(n)
+    for bad in (-1, n):  # rejected before any device query
+        with pytest.raises(arts.ArtsError):
+            arts.arts_tiling_occupancy(bad)
 
 
 @pytest.mark.parametrize("make", [synth.cfg_small, synth.cfg_apertif, synth.cfg_apertif_ds])

@@ -148,3 +148,16 @@ def test_batch_sampled_against_oracle():
             assert got[d, t] == O.dedisperse_at(x, delays, d, t)
         done += 1
     assert done == 2
+
+
+def test_persistent_kernel_keeps_the_per_job_occupancy():
+    # a plan sizes its LDS chunks for the workgroups per CU of its tiling's one-launch kernel;
+    # the persistent kernel that batches and the serving engine run on the same chunks must
+    # reach as many, or the batched launches lose a workgroup per CU
+    for v in range(arts.arts_tiling_count()):
+        per_job, persistent = arts.arts_tiling_occupancy(v)
+        assert per_job >= 1, v
+        if "group" in arts.arts_tiling_describe(v):
+            assert persistent == 0, v
+        else:
+            assert persistent >= per_job, (v, arts.arts_tiling_describe(v), per_job, persistent)
