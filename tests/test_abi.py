@@ -109,3 +109,13 @@ def test_sb_table_beam_model_rejects(args):
     nsb, ntab, nchan = args
     with pytest.raises(arts.ArtsError):
         arts.arts_sb_table_beam_model(nsb, ntab, max(nchan, 1) if nchan else 0, 1220.0, 0.2)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    # no fallback: with libarts.so absent every call raises instead of computing elsewhere
+    monkeypatch.setattr(arts, "_lib", None)
+    monkeypatch.setattr(arts, "LIB_PATH", str(tmp_path / "libarts.so"))
+    with pytest.raises(RuntimeError, match="is missing"):
+        arts.lib()
+    with pytest.raises(RuntimeError, match="is missing"):
+        arts.arts_tiling_count()
