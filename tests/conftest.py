@@ -14,8 +14,9 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests are skipped when no GPU is visible, so "-m gpu" on a CPU machine reports skips, not
-    # failures; on a GPU machine they run against the built library and fail loudly if it is absent.
+    # GPU tests are skipped when no GPU is visible, so "-m gpu" on a CPU-only machine reports
+    # skips, not failures; with a GPU they run against the built library and fail loudly if it
+    # is absent.
     try:
         import torch
         has_gpu = torch.cuda.is_available()
