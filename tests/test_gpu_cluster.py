@@ -13,7 +13,7 @@ import pytest
 
 import oracle as O
 from paper_2205_12362_amd import arts, synth
-from tests._parity import near_threshold_rows, to_dev
+from tests._parity import near_threshold_runs, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -121,7 +121,7 @@ def test_clustered_candidates_match_oracle_from_data():
     nrep = x.shape[1] - max(w.widths) + 1
     thr = 7.0
     ora = O.candidates(x, w.widths, nrep, thr)
-    assert not near_threshold_rows(x, w.widths, nrep, thr, np.arange(x.shape[0]))
+    assert not near_threshold_runs(x, w.widths, nrep, thr, np.arange(x.shape[0]))
     raw = p.candidates(series, thr)
     assert sorted(r[:4] for r in _tuples(raw)) == sorted(c[:4] for c in ora)
     p.cluster = True

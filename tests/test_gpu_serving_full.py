@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 from paper_2205_12362_amd import arts, synth
-from tests._parity import (compare_candidates, near_threshold_rows, oracle_rows_candidates,
+from tests._parity import (compare_candidates, near_threshold_runs, oracle_rows_candidates,
                            to_dev)
 
 pytestmark = pytest.mark.gpu
@@ -110,7 +110,8 @@ def test_serving_configuration_full_size():
                     xs = x_rows[:, t0:]
                     ora = oracle_rows_candidates(xs, ws[p].widths, nrep[p] - t0, THR, rows,
                                                  beam=s, t_offset=off + t0)
-                    near = near_threshold_rows(xs, ws[p].widths, nrep[p] - t0, THR, rows)
+                    near = near_threshold_runs(xs, ws[p].widths, nrep[p] - t0, THR, rows,
+                                               beam=s, t_offset=off + t0)
                     sel = cands[(cands["beam"] == s) & (cands["downsample"] == (1, 4)[p]) &
                                 np.isin(cands["dm_index"], rows)]
                     compare_candidates(sel, ora, near)

@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 from paper_2205_12362_amd import arts, synth
-from tests._parity import compare_candidates, near_threshold_rows, to_dev
+from tests._parity import NearRuns, compare_candidates, near_threshold_runs, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_stream_matches_one_shot(use_table):
             for p, (w, pl) in enumerate(zip(ws, plans)):
                 got = st.series(p).cpu().numpy()
                 oc = []
-                near = set()
+                near = NearRuns()
                 for b in range(nbeam):
                     rows_in = full[b][:, hmax - H[p] + k * CHUNK: hmax + (k + 1) * CHUNK]
                     if w.downsample > 1:
@@ -83,9 +83,9 @@ def test_stream_matches_one_shot(use_table):
                     for c_ in O.candidates(xs, w.widths, nrep - t0, thr, beam=b,
                                            t_offset=off + t0):
                         oc.append(c_)
-                    for (d, wd) in near_threshold_rows(xs, w.widths, nrep - t0, thr,
-                                                       np.arange(x.shape[0])):
-                        near.add((d, wd))
+                    near |= near_threshold_runs(xs, w.widths, nrep - t0, thr,
+                                                np.arange(x.shape[0]), beam=b,
+                                                t_offset=off + t0)
                 sel = cands[cands["downsample"] == w.downsample]
                 compare_candidates(sel, oc, near)
                 found[p] += len(sel)

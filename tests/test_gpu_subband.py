@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 from paper_2205_12362_amd import arts, synth
-from tests._parity import compare_candidates, near_threshold_rows, to_dev
+from tests._parity import compare_candidates, near_threshold_runs, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -77,7 +77,7 @@ def test_subband_candidates_with_burst():
     assert np.array_equal(series.cpu().numpy()[0], x)
     nrep = x.shape[1] - 15
     ora = O.candidates(x, [1, 2, 4, 8, 16], nrep, 8.0)
-    near = near_threshold_rows(x, [1, 2, 4, 8, 16], nrep, 8.0, np.arange(x.shape[0]))
+    near = near_threshold_runs(x, [1, 2, 4, 8, 16], nrep, 8.0, np.arange(x.shape[0]))
     got = p.candidates(series, 8.0)
     assert len(ora) > 0
     compare_candidates(got, ora, near)

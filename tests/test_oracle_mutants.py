@@ -265,11 +265,21 @@ def _rfi_variant(kind):
         return q + 1 if 2 * r > n or (2 * r == n and q % 2 == 1) else q
 
     def outliers(v, k):
-        v = np.asarray(v, np.float64)
-        sd = v.std(ddof=1 if kind == "sample sigma" else 0)
-        if kind == "two-sided cut":
-            return np.abs(v - v.mean()) > k * sd
-        return v > np.floor(v.mean() + k * sd)
+        if kind == "fp64 cut":
+            f = np.asarray(v, np.float64)
+            return f > np.floor(f.mean() + k * f.std())
+        if kind in ("sample sigma", "two-sided cut"):
+            f = np.asarray(v, np.float64)
+            sd = f.std(ddof=1 if kind == "sample sigma" else 0)
+            if kind == "two-sided cut":
+                return np.abs(f - f.mean()) > k * sd
+            return f > np.floor(f.mean() + k * sd)
+        # exact: u > mean + k sigma  <=>  n u - s1 > 0 and (n u - s1)^2 > k^2 (n s2 - s1^2)
+        from fractions import Fraction
+        iv = [int(a) for a in np.asarray(v).ravel()]
+        n, s1, s2 = len(iv), sum(iv), sum(a * a for a in iv)
+        lim = Fraction(k) ** 2 * (n * s2 - s1 * s1)
+        return np.array([n * a - s1 > 0 and (n * a - s1) ** 2 > lim for a in iv])
 
     def rfi_time_domain(data, k, niter=3):
         x = np.array(data, dtype=np.int64)
@@ -439,6 +449,7 @@ MUTANTS = {
     "offline windows per beam": dict(cluster_offline=_offline_variant("windows per beam")),
     "offline ties to the last": dict(cluster_offline=_offline_variant("ties to the last")),
     "rfi round half up": _rfi_variant("round half up"),
+    "rfi FP64 cut": _rfi_variant("fp64 cut"),
     "rfi sample sigma": _rfi_variant("sample sigma"),
     "rfi two-sided cut": _rfi_variant("two-sided cut"),
     "rfi one iteration": _rfi_variant("one iteration"),

@@ -785,6 +785,16 @@ def check_rfi_golden(o):
     assert np.array_equal(o.rfi_clean(f, 3.0, g["freq"]["k"]), np.array(g["freq"]["clean"]))
 
 
+def check_rfi_ties(o):
+    # a value exactly at mean + k sigma is not above the cut: the cut is decided exactly
+    g = _load("rfi_tiny.json")["ties"]
+    v = np.array(g["values"], np.uint8)
+    for k, want in ((g["k_tie"], g["clean_tie"]), (g["k_above"], g["clean_above"])):
+        assert np.array_equal(o.rfi_time_domain(v[None], k)[0], want), k
+        assert np.array_equal(o.rfi_freq_domain(v[:, None], k)[:, 0], want), k
+        assert np.array_equal(o.rfi_clean(v[:, None], 9.0, k)[:, 0], want), k
+
+
 def check_rfi_targets(o):
     nchan, nsamp = 96, 3000
     base = synth.noise((nchan, nsamp), seed=41)
@@ -838,6 +848,19 @@ def check_rfi_iterations(o):
 
 def test_rfi_golden():
     check_rfi_golden(O)
+
+
+def test_rfi_ties():
+    check_rfi_ties(O)
+
+
+def test_rfi_exact_cut_worked_values():
+    # the oracle's cut helper against hand-worked values (fixture "ties"): mean + 2 sigma is an
+    # exact integer in both cases
+    from oracle.arts_oracle import _cut
+    g = _load("rfi_tiny.json")["ties"]
+    assert _cut(np.array(g["cut_values"]), g["cut_k"]) == g["cut"]
+    assert _cut(np.array(g["values"]), g["k_tie"]) == 31
 
 
 def test_rfi_targets():
@@ -928,5 +951,5 @@ ALL_CHECKS = [check_delays_textbook, check_delay_invariants, check_delay_apertif
               check_subband_golden, check_subband_reductions, check_subband_smearing_bound,
               check_cluster_golden, check_cluster_brute_force, check_cluster_invariants,
               check_offline_golden, check_offline_brute_force, check_offline_invariants,
-              check_rfi_golden, check_rfi_targets, check_rfi_iterations,
+              check_rfi_golden, check_rfi_ties, check_rfi_targets, check_rfi_iterations,
               check_sb_beam_golden, check_sb_beam_nearest, check_sb_beam_invariants]
