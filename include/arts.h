@@ -269,6 +269,24 @@ int arts_candidates(arts_plan_t plan, const int32_t* series, int32_t nbeam, int6
                     float threshold, int64_t t_offset, int32_t beam_offset,
                     arts_candidate* host_out, int64_t capacity, int64_t* count, void* stream);
 
+/* arts_candidates for callers that cannot allocate device memory (a serving loop with a frozen
+ * allocator, a harness that forbids hipMalloc): the same search and results, with the
+ * candidate records, their counter and the per-row pre-pass flags held in a fixed 16 MiB array
+ * in device global memory that the library owns (one per device, kept until the process
+ * ends) instead of the plan's workspace.  It calls no hipMalloc/hipFree; the first call on a
+ * device looks the array's address up.  Limits: nbeam * ndm <= ARTS_NOALLOC_MAX_ROWS and
+ * capacity <= ARTS_NOALLOC_MAX_CANDIDATES, else ARTS_E_INVAL; clustered plans give
+ * ARTS_E_STATE (their workspace is allocated).  The plan must belong to the current device.
+ * Every call on one device uses the same array: calls that overlap on one device (several
+ * host threads, or this call racing another on a second stream) race; run them in turn.
+ * Arguments, sorting, ARTS_E_CAPACITY and synchronisation as arts_candidates.               */
+#define ARTS_NOALLOC_MAX_ROWS 1048576
+#define ARTS_NOALLOC_MAX_CANDIDATES 491512
+int arts_candidates_noalloc(arts_plan_t plan, const int32_t* series, int32_t nbeam, int64_t L,
+                            float threshold, int64_t t_offset, int32_t beam_offset,
+                            arts_candidate* host_out, int64_t capacity, int64_t* count,
+                            void* stream);
+
 /* DM-width clustering (Sect. 6b.2, "Clustering", optional in the paper): candidates of
  * different widths at the same time and DM are reduced to the one with the highest S/N, then
  * groups in neighbouring DM trials are compacted the same way, and one candidate is reported

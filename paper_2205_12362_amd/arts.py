@@ -80,6 +80,8 @@ _SIGNATURES = {
     "arts_boxcar_snr": (C.c_int, [_vp, _vp, _i32, _i64, _vp, _vp, _vp, _vp]),
     "arts_candidates": (C.c_int, [_vp, _vp, _i32, _i64, _f32, _i64, _i32, _vp, _i64, _pi64,
                                   _vp]),
+    "arts_candidates_noalloc": (C.c_int, [_vp, _vp, _i32, _i64, _f32, _i64, _i32, _vp, _i64,
+                                          _pi64, _vp]),
     "arts_stream_create": (C.c_int, [C.POINTER(_vp), _i32, _i32, _vp, _i32, _i64, _f32, _i64,
                                      C.c_uint32, C.POINTER(_vp)]),
     "arts_stream_input": (C.c_int, [_vp, C.POINTER(_vp)]),
@@ -372,6 +374,26 @@ def arts_candidates(plan, series, threshold, t_offset=0, beam_offset=0, capacity
         _check(st)
         return buf[: n.value].copy()
     _check(st)
+
+
+NOALLOC_MAX_ROWS = 1048576
+NOALLOC_MAX_CANDIDATES = 491512
+
+
+def arts_candidates_noalloc(plan, series, threshold, t_offset=0, beam_offset=0,
+                            capacity=1 << 16, stream=None):
+    """arts_candidates on the library's fixed device array (no device allocation); same result
+    layout.  Raises ArtsError(ARTS_E_CAPACITY) if `capacity` is too small (no retry: a larger
+    host buffer is the caller's business)."""
+    import torch
+    nbeam, ndm, L = series.shape
+    buf = np.zeros(max(int(capacity), 1), dtype=CANDIDATE_DTYPE)
+    n = C.c_int64(0)
+    _check(lib().arts_candidates_noalloc(plan, _dev(series, torch.int32, "series"), nbeam, L,
+                                         float(threshold), int(t_offset), int(beam_offset),
+                                         buf.ctypes.data, int(capacity), C.byref(n),
+                                         _stream(stream)))
+    return buf[: n.value].copy()
 
 
 def arts_plan_set_cluster(plan, enable):
