@@ -9,7 +9,10 @@ threshold-8 candidates.  The overlap (halo) stays on the device between steps.  
 resident in HBM before the timed region; each step copies its chunk from a device pool.
 
 Prints ONE JSON line.  Metric: DM-trial samples per second (reported samples, all SBs, both
-trial sets); also the real-time factor and chunk latency percentiles.
+trial sets); also the real-time factor and chunk latency percentiles.  The chunk latency is
+timed as the metric defines it, from a chunk's release in pinned host memory to the receipt of
+its candidates on the host (the host-to-device copy included), in a second loop after the timed
+region; the device-pool step time is reported beside it.
 """
 from __future__ import annotations
 
@@ -43,14 +46,33 @@ def log(*a):
 
 
 def cpu_model():
+    """Host CPU description: model name, logical CPUs, sockets, and the cores this process may
+    use (its affinity set)."""
+    name, sockets = None, set()
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if line.startswith("model name") and name is None:
+                    name = line.split(":", 1)[1].strip()
+                elif line.startswith("physical id"):
+                    sockets.add(line.split(":", 1)[1].strip())
     except OSError:
         pass
-    return platform.processor() or "unknown"
+    name = name or platform.processor() or "unknown"
+    return (f"{name}; {os.cpu_count()} logical CPUs in {max(1, len(sockets))} socket(s); "
+            f"{len(os.sched_getaffinity(0))} in this process's affinity set")
+
+
+def oracle_cores():
+    """Worker processes for the oracle: every core of the process's CPU share -- its affinity
+    set, bounded by OMP_NUM_THREADS where the host sets it (a GPU machine grants one GPU's share of
+    its cores that way)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
 
 
 def _oracle_rows(args):
@@ -63,18 +85,15 @@ def _oracle_rows(args):
     return x.shape[0]
 
 
-def cpu_baseline(beam, w_native):
-    """Time the CPU oracle on a bounded sample of the same workload: one beam of the chunk
-    (1536 channels, 12500 new samples plus the overlap), every 8th native DM trial, all widths,
-    parallelised over DM blocks on the host cores."""
+def oracle_rate(beam, w, nrep, cores):
+    """Time the CPU oracle (dedispersion + boxcars/S/N/candidates) on one beam over every DM
+    trial of workload w, parallelised over DM blocks; returns (DM-trial samples/s, seconds)."""
     import multiprocessing as mp
 
     import oracle as O
-    delays = O.delay_table(w_native.nchan, w_native.f_lo, w_native.df, w_native.tsamp,
-                           w_native.dms)
+    delays = O.delay_table(w.nchan, w.f_lo, w.df, w.tsamp, w.dms, w.downsample)
     dmax = int(delays.max())
-    rows = np.arange(0, delays.shape[0], 8)
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    rows = np.arange(delays.shape[0])
     jobs = []
     for b in np.array_split(rows, cores):
         if len(b):
@@ -82,17 +101,77 @@ def cpu_baseline(beam, w_native):
             # the reported window) equal to the full plan's
             pad = np.zeros((1, delays.shape[1]), dtype=delays.dtype)
             pad[0, 0] = dmax
-            jobs.append((beam, np.concatenate([delays[b], pad]), w_native.widths, CHUNK,
-                         THRESHOLD))
+            jobs.append((beam, np.concatenate([delays[b], pad]), w.widths, nrep, w.threshold))
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
         done = sum(pool.map(_oracle_rows, jobs))
     dt = time.perf_counter() - t0
-    return {"value": done * CHUNK / dt, "unit": "DM-trial samples/s", "cores": cores,
-            "kind": "oracle", "cpu": cpu_model(),
-            "sample": f"one beam of one chunk (1536 ch, 12500 reported samples), {done} of the "
-                      f"2048 native DM trials (every 8th), widths 1-256, threshold 8: "
-                      f"{dt:.1f} s wall on {cores} processes"}
+    assert done == len(rows)
+    return done * nrep / dt, dt
+
+
+def cpu_baseline(beams, w_native):
+    """The CPU oracle on a bounded sample of the serving workload: a few SBs of one chunk (1536
+    channels, 12500 new samples plus the overlap each), all 2048 native DM trials, all widths,
+    one SB after the other, each over every core of the process's share."""
+    cores = oracle_cores()
+    done, secs = 0.0, 0.0
+    for beam in beams:
+        rate, dt = oracle_rate(beam, w_native, CHUNK, cores)
+        done += rate * dt
+        secs += dt
+    return {"value": done / secs, "unit": "DM-trial samples/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"{len(beams)} SBs of one serving chunk (1536 ch, 12500 reported samples "
+                      f"each), all {w_native.dms.size} native DM trials, widths 1-256, "
+                      f"threshold 8: {secs:.1f} s wall on {cores} processes"}
+
+
+def small_configs(arts, synth, torch, with_oracle):
+    """The two single-beam configurations timed in full, on the GPU (plan calls: dedispersion
+    + candidates, one call after a warm-up call; HIP events) and, unless with_oracle is False,
+    by the oracle: the 128-channel beam (16384 samples, 256 DMs, widths 1-16) and one Apertif
+    beam-chunk (1536 channels, 12500 new samples plus the overlap, 2048 DMs, widths 1-256).
+    Rates in DM-trial samples/s over the reported window; the dedispersion launch's fraction
+    of the packed 16-bit add peak beside them."""
+    res = {}
+    for w, nsamp, reps in ((synth.cfg_small(), 16384, 20), (synth.cfg_apertif(), None, 3)):
+        p = arts.Plan.from_workload(w)
+        nin = nsamp if nsamp else CHUNK + p.halo
+        beam = synth.noise((w.nchan, nin), seed=w.seed)
+        dev = torch.from_numpy(beam[None]).cuda()
+        series = p.dedisperse(dev)
+        nrep = series.shape[2] - max(w.widths) + 1
+        p.candidates(series, w.threshold)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ms_d = ms_all = 0.0
+        for _ in range(reps):
+            e[0].record()
+            p.dedisperse(dev, out=series)
+            e[1].record()
+            p.candidates(series, w.threshold)
+            e[2].record()
+            torch.cuda.synchronize()
+            ms_d += e[0].elapsed_time(e[1]) / reps
+            ms_all += e[0].elapsed_time(e[2]) / reps
+        units = w.dms.size * nrep
+        adds = w.dms.size * nrep * w.nchan
+        entry = {"workload": w.name, "nchan": w.nchan, "ndm": int(w.dms.size),
+                 "reported_samples": int(nrep),
+                 "gpu": {"value": units / (ms_all * 1e-3), "unit": "DM-trial samples/s",
+                         "ms_per_call": ms_all, "dedisperse_ms": ms_d,
+                         "dedisperse_frac_pk16_peak": adds / (ms_d * 1e-3) / PEAK_PK16_ADDS,
+                         "note": "one beam per call: small grids do not fill 256 CUs"}}
+        if with_oracle:
+            cores = oracle_cores()
+            rate, dt = oracle_rate(beam, w, nrep, cores)
+            entry["oracle"] = {"value": rate, "unit": "DM-trial samples/s", "cores": cores,
+                               "seconds": dt, "sample": "the whole configuration, once"}
+        res[w.name] = entry
+        del series, dev, p
+    torch.cuda.empty_cache()
+    return res
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2205_12362_amd", "csrc", "arts_kernels.hip")
@@ -550,6 +629,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--graph", action="store_true", help="replay each step as a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the single-beam configurations (128-channel beam, one Apertif "
+                         "beam-chunk) timed after the serving steps")
     ap.add_argument("--variant", type=int, default=None, help="native dedispersion tiling")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 1 GiB twice (counter calibration)")
@@ -667,8 +749,9 @@ def main():
             ms, n = stream.timing(ph)
             ms0, n0 = base_ms[ph]
             phases[name] = (ms - ms0) / max(1, n - n0)
-        L_nat = CHUNK + max(w_nat.widths) - 1
-        adds = NSB * w_nat.dms.size * L_nat * NCHAN        # algorithmic adds per launch
+        # algorithmic adds per launch: the chunk's new outputs only (the launch also recomputes
+        # the wmax - 1 outputs the boxcars of the previous chunk's last starts read)
+        adds = NSB * w_nat.dms.size * CHUNK * NCHAN
         dur = phases["dedisperse_native"] * 1e-3
         achieved = adds / dur
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_PK16_ADDS / 1e12,
@@ -677,7 +760,21 @@ def main():
                     "kernel": kernel_name(arts.arts_tiling_describe(p_nat.tiling())),
                     "kernel_ms": phases["dedisperse_native"],
                     "adds_per_launch": adds}
-    lat_ms = np.array(lat) * 1e3
+    # chunk latency as the metric defines it: release of the chunk in pinned host memory ->
+    # its host-to-device copy into the stream's staging buffer -> search -> candidates on the
+    # host; a second loop after the timed region, same chunks
+    host_pool = [t.cpu().pin_memory() for t in pool]
+    staging = stream.input_buffer()
+    lat_h2d = []
+    for k in range(args.steps):
+        t1 = time.perf_counter()
+        staging.copy_(host_pool[(nwarm + args.steps + k) % 2], non_blocking=True)
+        stream.push(None, stream=cur)
+        stream.wait()
+        lat_h2d.append(time.perf_counter() - t1)
+    del host_pool, staging
+    lat_ms = np.array(lat_h2d) * 1e3
+    pool_ms = np.array(lat) * 1e3
     out = {
         "metric": "DM-trial samples/s",
         "value": value,
@@ -703,7 +800,12 @@ def main():
         "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
         "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                              "p99": float(np.percentile(lat_ms, 99)),
-                             "max": float(lat_ms.max())},
+                             "max": float(lat_ms.max()),
+                             "from": "release in pinned host memory, H2D copy included",
+                             "to": "candidates on the host", "steps": args.steps},
+        "step_latency_device_pool_ms": {"p50": float(np.percentile(pool_ms, 50)),
+                                        "p99": float(np.percentile(pool_ms, 99)),
+                                        "max": float(pool_ms.max())},
         "candidates_per_step": ncand / args.steps,
         "phases_ms": phases,
         "roofline": roofline,
@@ -718,10 +820,14 @@ def main():
         torch.cuda.synchronize()
         del a, b
     torch.cuda.empty_cache()
+    if not args.no_configs:
+        log("single-beam configurations ...")
+        out["single_beam_configs"] = small_configs(arts, synth, torch,
+                                                   with_oracle=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        beam = synth.noise((NCHAN, CHUNK + p_nat.halo), seed=777)
-        out["cpu_baseline"] = cpu_baseline(beam, w_nat)
+        beams = [synth.noise((NCHAN, CHUNK + p_nat.halo), seed=777 + k) for k in range(4)]
+        out["cpu_baseline"] = cpu_baseline(beams, w_nat)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
