@@ -180,9 +180,11 @@ PROFILE_JSON = os.path.join(ROOT, "profiles", "dedisperse_serving_chunk.json")
 
 def kernel_name(describe):
     """Template name of the dedispersion kernel of a tiling variant, from its description
-    ("J=5 ACC=3 WAVES=8 SPD=4 packed" -> "dedisperse_kernel<4, 5, 3, 8, 1>"; "framed" -> 2)."""
+    ("J=5 ACC=3 WAVES=8 SPD=4 packed" -> "dedisperse_kernel<4, 5, 3, 8, 1>"; "framed" -> 2,
+    "pairs" -> 5)."""
     f = dict(kv.split("=") for kv in describe.split() if "=" in kv)
-    pack = 2 if "framed" in describe else 1 if "packed" in describe else 0
+    pack = (5 if "pairs" in describe else 2 if "framed" in describe
+            else 1 if "packed" in describe else 0)
     return f"dedisperse_kernel<{f['SPD']}, {f['J']}, {f['ACC']}, {f['WAVES']}, {pack}>"
 
 
@@ -586,24 +588,29 @@ def tilings_bench(args):
             d = arts.arts_tiling_describe(v)
             if spd not in d or "group" in d:
                 continue
-            try:
-                p.set_tiling(v)
-            except arts.ArtsError:
-                res[v] = {"tiling": d, "plan": w.name, "ms": None, "tadd_s": None}
-                continue
-            log(f"tiling {v}: {d}")
-            out = p.dedisperse_sb(tab, table, out=out)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(args.steps):
-                p.dedisperse_sb(tab, table, out=out)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / args.steps
-            adds = NSB * w.dms.size * out.shape[2] * NCHAN
-            res[v] = {"tiling": d, "plan": w.name, "default": v == default, "ms": ms,
-                      "tadd_s": adds / ms / 1e9}
+            for nbuf in (2, 1):
+                key = f"{v}" if nbuf == 2 else f"{v}/1buf"
+                try:
+                    p.set_tiling_shape(v, nbuf, 0)
+                except arts.ArtsError:
+                    res[key] = {"tiling": d, "plan": w.name, "ms": None, "tadd_s": None}
+                    continue
+                cc = p.tiling_shape()[2]
+                log(f"tiling {v}: {d}, {nbuf} buffer(s), {cc} channels per chunk")
+                out = p.dedisperse_sb(tab, table, out=out)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(args.steps):
+                    p.dedisperse_sb(tab, table, out=out)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                adds = NSB * w.dms.size * out.shape[2] * NCHAN
+                res[key] = {"tiling": d, "plan": w.name, "buffers": nbuf, "channels": cc,
+                            "default": v == default and nbuf == 2, "ms": ms,
+                            "tadd_s": adds / ms / 1e9}
         del tab, out, p
         torch.cuda.empty_cache()
     print(json.dumps({"workload": "dedispersion tilings on the serving launches (71 SBs fused "

@@ -188,16 +188,32 @@ int arts_plan_delays(arts_plan_t plan, int32_t* host_out);
 
 /* Dedispersion tiling.  variant indexes the compiled kernel shapes listed by
  * arts_tiling_count / arts_tiling_describe; dm_per_block is implied by the variant.  Changing
- * it rebuilds the plan's tiling tables (device allocation).  The autotuner calls this.        */
+ * it rebuilds the plan's tiling tables (device allocation); streams capture their graphs
+ * again afterwards.  arts_plan_set_tiling(p, v) is arts_plan_set_tiling_shape(p, v, 1, 0),
+ * the shape plans are created with.                                                          */
 int arts_plan_set_tiling(arts_plan_t plan, int32_t variant);
 int arts_plan_get_tiling(arts_plan_t plan, int32_t* variant);
+/* Tile shape: the variant, the LDS chunk buffers (2: the next chunk of channels is fetched
+ * while this one is summed; 1: fetched in turn, twice the channels per chunk) and the channels
+ * per chunk (0: as many as the LDS allows; else at most that many).  For subband plans the
+ * shape applies to the first step.  On error (ARTS_E_INVAL: buffers not 1 or 2, channels
+ * outside 0..255, or the variant does not fit the plan) the plan keeps its tiling.  get
+ * reports the variant, buffers and channels per chunk in use (pointers nullable).             */
+int arts_plan_set_tiling_shape(arts_plan_t plan, int32_t variant, int32_t buffers,
+                               int32_t channels);
+int arts_plan_get_tiling_shape(arts_plan_t plan, int32_t* variant, int32_t* buffers,
+                               int32_t* channels);
 int32_t arts_tiling_count(void);
-/* Autotuner: time every compiled tiling variant that suits the plan on a synthetic input of
- * nbeam x nchan x nin (device memory allocated and freed by the call), keep the fastest
- * (`reps` timed launches each) and set it on the plan.  With cache_path (nullable) the result
- * is looked up in / appended to that text file, keyed by (nchan, ndm, D, max_delay, nbeam,
- * nin).  *variant_out and *ms_out (nullable) receive the choice and its time per launch.
- * Errors: ARTS_E_SHAPE (nin too short), ARTS_E_NOMEM, ARTS_E_DEVICE.  Synchronous.          */
+/* Autotuner (the paper's GPU search is auto-tuned per platform and setup, Sect. 6b.2): times
+ * tile shapes on pseudo-random input of nbeam x nchan x nin (device memory allocated and freed
+ * by the call): every suitable variant (DMs per block, samples per lane) with one buffer and
+ * the most channels per chunk, then the three fastest with two buffers and with half the
+ * channels per chunk; `reps` timed launches each.  The fastest shape is set on the plan.  With
+ * cache_path (nullable) the result is looked up in / appended to that text file, keyed by the
+ * device's architecture and CU count, nchan, ndm, D, max_delay, a hash of the delay tables,
+ * nbeam and nin.  *variant_out and *ms_out (nullable) receive the variant and its time per
+ * launch (arts_plan_get_tiling_shape gives the rest of the shape).  Errors: ARTS_E_SHAPE (nin
+ * too short), ARTS_E_NOMEM, ARTS_E_DEVICE.  Synchronous.                                     */
 int arts_plan_autotune(arts_plan_t plan, int32_t nbeam, int64_t nin, int32_t reps,
                        const char* cache_path, int32_t* variant_out, float* ms_out);
 /* Writes "J=<dwords per lane> ACC=<DMs per wave> WAVES=<waves per block> SPD=<samples per
@@ -390,6 +406,15 @@ int arts_batch_dedisperse(arts_batch_t b, const arts_request* reqs, int32_t n, i
 int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, float threshold,
                           arts_candidate* host_out, int64_t capacity, int64_t* count,
                           void* stream);
+
+/* Batch autotuner: one tile shape for all native requests (and one for all 16-bit ones), so
+ * that each kind goes into a single persistent launch; searched as arts_plan_autotune does,
+ * but timing arts_batch_dedisperse on the caller's own requests (their outputs are written).
+ * Every plan of a kind takes the fastest shape that fits all of them.  *variant_out / *ms_out
+ * (nullable): the native kind's choice (else the 16-bit one's) and its time per launch.
+ * Errors: ARTS_E_INVAL (no valid request), ARTS_E_DEVICE.  Synchronous.                      */
+int arts_batch_autotune(arts_batch_t b, const arts_request* reqs, int32_t n, int32_t reps,
+                        int32_t* variant_out, float* ms_out);
 
 /* ------------------------------------------------------------------------ streaming ---- */
 

@@ -58,6 +58,9 @@ _SIGNATURES = {
     "arts_plan_delays": (C.c_int, [_vp, _pi32]),
     "arts_plan_set_tiling": (C.c_int, [_vp, _i32]),
     "arts_plan_get_tiling": (C.c_int, [_vp, _pi32]),
+    "arts_plan_set_tiling_shape": (C.c_int, [_vp, _i32, _i32, _i32]),
+    "arts_plan_get_tiling_shape": (C.c_int, [_vp, _pi32, _pi32, _pi32]),
+    "arts_batch_autotune": (C.c_int, [_vp, _vp, _i32, _i32, _pi32, C.POINTER(C.c_float)]),
     "arts_plan_set_cluster": (C.c_int, [_vp, _i32]),
     "arts_plan_get_cluster": (C.c_int, [_vp, _pi32]),
     "arts_plan_set_integration": (C.c_int, [_vp, _i32]),
@@ -284,6 +287,17 @@ def arts_plan_get_tiling(plan):
     v = C.c_int32()
     _check(lib().arts_plan_get_tiling(plan, C.byref(v)))
     return v.value
+
+
+def arts_plan_set_tiling_shape(plan, variant, buffers=1, channels=0):
+    _check(lib().arts_plan_set_tiling_shape(plan, int(variant), int(buffers), int(channels)))
+
+
+def arts_plan_get_tiling_shape(plan):
+    """(variant, buffers, channels per chunk) in use."""
+    v, nb, cc = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().arts_plan_get_tiling_shape(plan, C.byref(v), C.byref(nb), C.byref(cc)))
+    return v.value, nb.value, cc.value
 
 
 # ---------------------------------------------------------------------------- hot path
@@ -560,6 +574,12 @@ class Plan:
     def tiling(self):
         return arts_plan_get_tiling(self.handle)
 
+    def set_tiling_shape(self, variant, buffers=1, channels=0):
+        arts_plan_set_tiling_shape(self.handle, variant, buffers, channels)
+
+    def tiling_shape(self):
+        return arts_plan_get_tiling_shape(self.handle)
+
     def dedisperse(self, data, out=None, stream=None):
         return arts_dedisperse(self.handle, data, out, stream)
 
@@ -821,12 +841,24 @@ def arts_batch_candidates(batch_h, items, threshold, capacity=1 << 18, stream=No
     _check(st)
 
 
+def arts_batch_autotune(batch_h, items, reps=2):
+    """One tile shape per sample kind for all requests (timed on them); returns (variant, ms)."""
+    arr = _requests(items)
+    v, ms = C.c_int32(), C.c_float()
+    _check(lib().arts_batch_autotune(batch_h, arr, len(items), int(reps), C.byref(v),
+                                     C.byref(ms)))
+    return v.value, ms.value
+
+
 class Batch:
     def __init__(self):
         self.handle = arts_batch_create()
 
     def dedisperse(self, items, stream=None):
         return arts_batch_dedisperse(self.handle, items, stream)
+
+    def autotune(self, items, reps=2):
+        return arts_batch_autotune(self.handle, items, reps)
 
     def candidates(self, items, threshold, **kw):
         return arts_batch_candidates(self.handle, items, threshold, **kw)

@@ -197,11 +197,16 @@ int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, f
 }  // extern "C"
 
 // ------------------------------------------------------------------------------ autotuner ----
-// Times every compiled tiling variant that suits the plan on a synthetic input of the caller's
-// shape and keeps the fastest (the paper's search is auto-tuned per platform and
-// observation setup, Sect. 6b.2).  Results are cached in a text file, one line per shape:
-//   <nchan> <ndm> <downsample> <max_delay> <nbeam> <nin> <variant> <ms>
-// (for subband plans <downsample> is followed by 's' and the subband count)
+// The paper's search is auto-tuned per platform and observation setup (Sect. 6b.2, AMBER's
+// run-time tuning).  Here the compiled kernel shapes are searched instead: every tiling variant
+// that suits the plan (DMs per block x samples per lane), each with one LDS buffer and the
+// most channels per chunk that fit, is timed; the three fastest are then timed again with two
+// buffers (half the channels per chunk, the next chunk fetched while one is summed) and with
+// half the channels per chunk, and the fastest shape of all is kept.  Plan calls are timed on pseudo-random bytes of the caller's
+// shape; batches on the caller's own requests.  Results are cached in a text file, one line
+// per key:
+//   <arch> <CUs> <nchan> <ndm> <D>[s<nsub>] <max_delay> <delay-table hash> <nbeam> <nin>
+//   <variant> <buffers> <channels> <ms>
 #include <cstdio>
 #include <fstream>
 #include <sstream>
@@ -209,15 +214,47 @@ int arts_batch_candidates(arts_batch_t b, const arts_request* reqs, int32_t n, f
 
 namespace {
 
+struct Shape {
+  int variant = -1, nbuf = kDefaultBuffers, cc = 0;
+  float ms = 0;
+};
+
+std::string device_tag() {
+  int dev = 0, ncu = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown 0";
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  std::string arch(prop.gcnArchName);
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  return arch + ' ' + std::to_string(ncu);
+}
+
+uint64_t delay_hash(const arts_plan_s* p) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the delay table (and subband step tables)
+  auto mix = [&h](const std::vector<int32_t>& v) {
+    for (int32_t x : v) {
+      h ^= static_cast<uint32_t>(x);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(p->delays);
+  if (p->sb1) mix(p->sb1->delays);
+  if (p->sb2) mix(p->sb2->delays);
+  return h;
+}
+
 std::string tune_key(const arts_plan_s* p, int32_t nbeam, int64_t nin) {
   std::ostringstream k;
-  k << p->nchan << ' ' << p->ndm << ' ' << p->ds;
-  if (p->nsub > 0) k << 's' << p->nsub;  // subband plans: D then 's' and the subband count
-  k << ' ' << p->max_delay << ' ' << nbeam << ' ' << nin;
+  k << device_tag() << ' ' << p->nchan << ' ' << p->ndm << ' ' << p->ds;
+  if (p->nsub > 0) k << 's' << p->nsub;
+  k << ' ' << p->max_delay << ' ' << std::hex << delay_hash(p) << std::dec << ' ' << nbeam << ' '
+    << nin;
   return k.str();
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* variant, float* ms) {
+bool cache_lookup(const char* path, const std::string& key, Shape* out) {
   if (!path) return false;
   std::ifstream f(path);
   std::string line;
@@ -227,15 +264,66 @@ bool cache_lookup(const char* path, const std::string& key, int* variant, float*
         line[key.size()] != ' ')
       continue;
     std::istringstream rest(line.substr(key.size()));
-    int v = -1;
-    float t = 0;
-    if (rest >> v >> t && v >= 0 && v < kNumVariants) {
-      *variant = v;
-      *ms = t;
+    Shape sh;
+    if (rest >> sh.variant >> sh.nbuf >> sh.cc >> sh.ms && sh.variant >= 0 &&
+        sh.variant < kNumVariants && (sh.nbuf == 1 || sh.nbuf == 2) && sh.cc >= 0 &&
+        sh.cc <= 255) {
+      *out = sh;
       found = true;  // the last entry for a key wins
     }
   }
   return found;
+}
+
+void cache_store(const char* path, const std::string& key, const Shape& sh) {
+  if (!path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s %d %d %d %.4f\n", key.c_str(), sh.variant, sh.nbuf, sh.cc, sh.ms);
+    std::fclose(f);
+  }
+}
+
+// The shapes to time: phase 1 every suitable variant at (1 buffer, max channels); phase 2 the
+// three fastest with two buffers and with half their channels per chunk.  apply(shape) sets a
+// shape on every plan involved (false if it does not fit); time(&ms) times the work.
+// Variants a search considers: byte or 16-bit samples as the plan reads them; group sums only
+// for subband plans (their first step), whose other tilings are the byte ones.
+bool suits(const arts_plan_s* p, int v) {
+  if (p->nsub > 0) return kVariants[v].spd == 4 && kVariants[v].pack != 2;
+  return (p->ds == 1) == (kVariants[v].spd == 4) && kVariants[v].pack != 4;
+}
+
+template <typename Suits, typename Apply, typename Time>
+int search_shapes(Suits suit, Apply apply, Time time, Shape* best_out) {
+  std::vector<Shape> first;
+  for (int v = 0; v < kNumVariants; ++v) {
+    if (!suit(v)) continue;
+    Shape sh;
+    sh.variant = v;
+    if (!apply(sh)) continue;
+    if (int st = time(&sh.ms)) return st;
+    first.push_back(sh);
+  }
+  if (first.empty()) return fail(ARTS_E_INVAL, "no tiling variant fits");
+  std::sort(first.begin(), first.end(), [](const Shape& a, const Shape& b) { return a.ms < b.ms; });
+  Shape best = first[0];
+  for (size_t i = 0; i < first.size() && i < 3; ++i) {
+    int cc_max = 0;
+    if (!apply(first[i])) continue;
+    if (int st = time(&first[i].ms)) return st;  // re-timed next to its variations
+    if (first[i].ms < best.ms) best = first[i];
+    cc_max = first[i].cc;  // apply() reports the channels per chunk it got
+    const Shape vars[2] = {{first[i].variant, 3 - kDefaultBuffers, 0, 0},
+                           {first[i].variant, kDefaultBuffers, cc_max / 2, 0}};
+    for (Shape sh : vars) {
+      if (sh.nbuf == kDefaultBuffers && sh.cc < 8) continue;
+      if (!apply(sh)) continue;
+      if (int st = time(&sh.ms)) return st;
+      if (sh.ms < best.ms) best = sh;
+    }
+  }
+  *best_out = best;
+  return ARTS_OK;
 }
 
 }  // namespace
@@ -245,12 +333,11 @@ extern "C" int arts_plan_autotune(arts_plan_t p, int32_t nbeam, int64_t nin, int
   if (!p || nbeam < 1 || reps < 1) return fail(ARTS_E_INVAL, "bad autotune arguments");
   if (nin / p->ds - p->max_delay < 1) return fail(ARTS_E_SHAPE, "nin shorter than the halo");
   const std::string key = tune_key(p, nbeam, nin);
-  int best = -1;
-  float best_ms = 0;
-  if (cache_lookup(cache_path, key, &best, &best_ms)) {
-    if (int st = arts_plan_set_tiling(p, best)) return st;
-    if (variant_out) *variant_out = best;
-    if (ms_out) *ms_out = best_ms;
+  Shape best;
+  if (cache_lookup(cache_path, key, &best)) {
+    if (int st = arts_plan_set_tiling_shape(p, best.variant, best.nbuf, best.cc)) return st;
+    if (variant_out) *variant_out = best.variant;
+    if (ms_out) *ms_out = best.ms;
     return ARTS_OK;
   }
   const int64_t L = nin / p->ds - p->max_delay;
@@ -260,7 +347,6 @@ extern "C" int arts_plan_autotune(arts_plan_t p, int32_t nbeam, int64_t nin, int
   int32_t* out = nullptr;
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  int st = ARTS_OK;
   auto cleanup = [&]() {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -270,44 +356,122 @@ extern "C" int arts_plan_autotune(arts_plan_t p, int32_t nbeam, int64_t nin, int
   };
   if (hipMalloc(&in, in_bytes) != hipSuccess || hipMalloc(&out, out_bytes) != hipSuccess ||
       hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
-      hipMemsetAsync(in, 0x5a, in_bytes, s) != hipSuccess) {
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     cleanup();
     return fail(ARTS_E_NOMEM, "autotune buffers (%lld + %lld bytes)", (long long)in_bytes,
                 (long long)out_bytes);
   }
-  const int original = p->tiling.variant;
-  for (int v = 0; v < kNumVariants && st == ARTS_OK; ++v) {
-    if ((p->ds == 1) != (kVariants[v].spd == 4)) continue;
-    if (arts_plan_set_tiling(p, v) != ARTS_OK) continue;  // e.g. windows too long for LDS
-    st = arts_dedisperse(p, in, nbeam, nin, out, s);      // warm-up (and table set-up)
-    if (st != ARTS_OK) break;
-    if (hipEventRecord(e0, s) != hipSuccess) st = fail(ARTS_E_DEVICE, "event record");
-    for (int r = 0; r < reps && st == ARTS_OK; ++r) st = arts_dedisperse(p, in, nbeam, nin, out, s);
-    float ms = 0;
-    if (st == ARTS_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-      st = fail(ARTS_E_DEVICE, "event timing");
-    ms /= reps;
-    if (st == ARTS_OK && (best < 0 || ms < best_ms)) {
-      best = v;
-      best_ms = ms;
+  if (int st = launch_fill_random(in, in_bytes, 0x5eedu, s)) {
+    cleanup();
+    return st;
+  }
+  const int v0 = p->tiling.variant;
+  const arts_plan_s* q = p->nsub > 0 ? p->sb1 : p;
+  const int32_t req_nb0 = q->tile_nbuf, req_cc0 = q->tile_cc;
+  auto apply = [&](Shape& sh) {
+    if (arts_plan_set_tiling_shape(p, sh.variant, sh.nbuf, sh.cc) != ARTS_OK) return false;
+    // the channels per chunk the shape got (for the half-channel variation)
+    if (sh.cc == 0) (void)arts_plan_get_tiling_shape(p, nullptr, nullptr, &sh.cc);
+    return true;
+  };
+  auto time = [&](float* ms) -> int {
+    if (int st = arts_dedisperse(p, in, nbeam, nin, out, s)) return st;  // warm-up, tables
+    if (hipEventRecord(e0, s) != hipSuccess) return fail(ARTS_E_DEVICE, "event record");
+    for (int r = 0; r < reps; ++r)
+      if (int st = arts_dedisperse(p, in, nbeam, nin, out, s)) return st;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return fail(ARTS_E_DEVICE, "event timing");
+    *ms /= reps;
+    return ARTS_OK;
+  };
+  int st = search_shapes([&](int v) { return suits(p, v); }, apply, time, &best);
+  cleanup();
+  if (st != ARTS_OK) {
+    (void)arts_plan_set_tiling_shape(p, v0, req_nb0, req_cc0);
+    return st;
+  }
+  if (int e = arts_plan_set_tiling_shape(p, best.variant, best.nbuf, best.cc)) return e;
+  cache_store(cache_path, key, best);
+  if (variant_out) *variant_out = best.variant;
+  if (ms_out) *ms_out = best.ms;
+  return ARTS_OK;
+}
+
+// Batch autotuner: the shape is searched for all requests of one sample kind together, timing
+// the persistent launch over the caller's own requests, so that they share one tiling and
+// go into one launch.  Native requests are tuned first, then 16-bit ones.
+extern "C" int arts_batch_autotune(arts_batch_t b, const arts_request* reqs, int32_t n,
+                                   int32_t reps, int32_t* variant_out, float* ms_out) {
+  if (!b || !reqs || n < 1 || reps < 1) return fail(ARTS_E_INVAL, "bad autotune arguments");
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+  };
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(ARTS_E_DEVICE, "autotune stream / events");
+  }
+  int first_variant = -1;
+  float first_ms = 0;
+  for (int kind = 0; kind < 2; ++kind) {  // 0: native byte requests, 1: 16-bit ones
+    std::vector<arts_request> grp;
+    std::vector<arts_plan_s*> plans;
+    for (int32_t i = 0; i < n; ++i) {
+      arts_plan_s* p = reqs[i].plan;
+      if (!p || p->nsub > 0 || reqs[i].nbeam < 1 || series_len(p, reqs[i].nin) < 1) continue;
+      if ((p->ds > 1) != (kind == 1)) continue;
+      grp.push_back(reqs[i]);
+      if (std::find(plans.begin(), plans.end(), p) == plans.end()) plans.push_back(p);
+    }
+    if (grp.empty()) continue;
+    std::vector<int32_t> v0(plans.size());
+    for (size_t i = 0; i < plans.size(); ++i) v0[i] = plans[i]->tiling.variant;
+    auto apply = [&](Shape& sh) {
+      int cc_got = 0;
+      for (arts_plan_s* p : plans) {
+        if (arts_plan_set_tiling_shape(p, sh.variant, sh.nbuf, sh.cc) != ARTS_OK) return false;
+        cc_got = std::max(cc_got, p->tiling.cc);
+      }
+      if (sh.cc == 0) sh.cc = cc_got;
+      return true;
+    };
+    auto time = [&](float* ms) -> int {
+      const int32_t m = static_cast<int32_t>(grp.size());
+      if (int st = arts_batch_dedisperse(b, grp.data(), m, nullptr, s)) return st;
+      if (hipEventRecord(e0, s) != hipSuccess) return fail(ARTS_E_DEVICE, "event record");
+      for (int r = 0; r < reps; ++r)
+        if (int st = arts_batch_dedisperse(b, grp.data(), m, nullptr, s)) return st;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+        return fail(ARTS_E_DEVICE, "event timing");
+      *ms /= reps;
+      return ARTS_OK;
+    };
+    Shape best;
+    int st = search_shapes([&](int v) { return suits(plans[0], v); }, apply, time, &best);
+    if (st == ARTS_OK) {
+      // every plan of the group takes the shape (a plan that the variant does not fit keeps
+      // its own and goes into a launch of its own)
+      for (arts_plan_s* p : plans) (void)arts_plan_set_tiling_shape(p, best.variant, best.nbuf,
+                                                                     best.cc);
+    } else {
+      for (size_t i = 0; i < plans.size(); ++i) (void)arts_plan_set_tiling(plans[i], v0[i]);
+      cleanup();
+      return st;
+    }
+    if (first_variant < 0) {
+      first_variant = best.variant;
+      first_ms = best.ms;
     }
   }
   cleanup();
-  if (st != ARTS_OK) {
-    (void)arts_plan_set_tiling(p, original);
-    return st;
-  }
-  if (best < 0) return fail(ARTS_E_INVAL, "no tiling variant fits this plan");
-  if (int e = arts_plan_set_tiling(p, best)) return e;
-  if (cache_path) {
-    if (FILE* f = std::fopen(cache_path, "a")) {
-      std::fprintf(f, "%s %d %.4f\n", key.c_str(), best, best_ms);
-      std::fclose(f);
-    }
-  }
-  if (variant_out) *variant_out = best;
-  if (ms_out) *ms_out = best_ms;
+  if (first_variant < 0) return fail(ARTS_E_INVAL, "no request to tune");
+  if (variant_out) *variant_out = first_variant;
+  if (ms_out) *ms_out = first_ms;
   return ARTS_OK;
 }

@@ -96,6 +96,7 @@ int build_tiling(arts_plan_s* p, int variant) {
       return fail(ARTS_E_INVAL, "variant %d cannot run the first subband step", variant);
     if (int st = build_tiling(p->sb1, variant)) return st;
     p->tiling.variant = variant;
+    ++p->generation;
     return ARTS_OK;
   }
   if (p->is16() != (v.spd == 2))
@@ -130,6 +131,22 @@ int build_tiling(arts_plan_s* p, int variant) {
     }
   }
   t.rmax = rmax;
+  if (v.pack == 5) {
+    // DM pairs read one window per pair: the second trial may start at most kPairMaxDeltaHost
+    // samples after the first, never before it
+    if (t.m_blk % 2 != 0) return fail(ARTS_E_INVAL, "variant %d: odd DMs per block", variant);
+    for (int b = 0; b < t.nblk; ++b)
+      for (int x = 0; x + 1 < t.m_blk && b * t.m_blk + x + 1 < p->ndm; x += 2)
+        for (int64_t c = 0; c < nchan; ++c) {
+          const int64_t r0 = (static_cast<int64_t>(b) * t.m_blk + x) * nchan + c;
+          const int32_t dlt = t.rel[r0 + nchan] - t.rel[r0];
+          if (dlt < 0 || dlt > kPairMaxDeltaHost)
+            return fail(ARTS_E_INVAL,
+                        "variant %d: trials %d and %d differ by %d samples in channel %lld "
+                        "(DM pairs need 0..%d)", variant, b * t.m_blk + x,
+                        b * t.m_blk + x + 1, dlt, (long long)c, kPairMaxDeltaHost);
+        }
+  }
   // lane 63 reads dwords 63 j + ((r + g) >> shift) .. + j, with g < spd the window's alignment
   t.win_dwords = (64 * v.j + ((rmax + v.spd - 1) >> shift) + 1 + 3) & ~3;
   // LDS per workgroup: a CU's 160 KiB shared by the workgroups that its registers and waves
@@ -139,9 +156,10 @@ int build_tiling(arts_plan_s* p, int variant) {
     const int nwg = std::max(variant_blocks_per_cu(variant, p->split > 0), 16 / v.waves);
     budget = std::max<int64_t>(16 * 1024, 160 * 1024 / nwg - 1024);
   }
-  // two buffers (each with 4 pad words) and an SB-table row; per channel its window plus one
+  // nbuf buffers (each with 4 pad words) and an SB-table row; per channel its window plus one
   // offset-list entry per DM of the block
-  const int64_t per_buf = (budget - ((nchan + 3) & ~int64_t(3))) / 2 - 16;
+  t.nbuf = p->tile_nbuf;
+  const int64_t per_buf = (budget - ((nchan + 3) & ~int64_t(3))) / t.nbuf - 16;
   // a chunk's channels must fit the kernels' narrow partial sums: 8-bit counts of each run, and
   // for packed 16-bit samples (sums of D bytes) a 16-bit half per output
   const int64_t cc_max = (v.pack && v.spd == 2) ? std::min<int64_t>(255, 65535 / p->smax) : 255;
@@ -150,6 +168,7 @@ int build_tiling(arts_plan_s* p, int variant) {
                 variant, p->smax);
   int cc = static_cast<int>(
       std::min<int64_t>({nchan, cc_max, per_buf / (4LL * (t.win_dwords + t.m_blk))}));
+  if (p->tile_cc > 0) cc = std::min(cc, p->tile_cc);
   // split plans: chunks must not straddle channel groups, so cc divides the group size
   if (p->split > 0)
     while (cc > 1 && p->split % cc != 0) --cc;
@@ -170,6 +189,7 @@ int build_tiling(arts_plan_s* p, int variant) {
   }
   free_tiling(p->tiling);
   p->tiling = std::move(t);
+  ++p->generation;
   return ARTS_OK;
 }
 
@@ -184,7 +204,42 @@ int ensure_tables(arts_plan_s* p, int g0) {
   const int shift = t.spd == 4 ? 2 : 1;
   std::vector<int32_t> list(t.rel.size(), 0);
   std::vector<uint32_t> cnt(static_cast<size_t>(t.nblk) * t.nchunk * t.m_blk, 0);
-  for (int b = 0; b < t.nblk; ++b) {
+  const bool pairs = kVariants[t.variant].pack == 5;
+  if (pairs) {
+    // per DM pair (trials 2P, 2P + 1 of the block) and chunk: channels ordered by class
+    // m0 * (max delta + 1) + delta, m0 = first trial's offset parity, delta = the second
+    // trial's offset minus the first's (its window is read from the first trial's word)
+    const int npair = t.m_blk / 2, ncls = 2 * (kPairMaxDeltaHost + 1);
+    list.assign(static_cast<size_t>(t.nblk) * npair * nchan, 0);
+    cnt.assign(static_cast<size_t>(t.nblk) * t.nchunk * npair * 4, 0);
+    for (int b = 0; b < t.nblk; ++b) {
+      const int32_t* base = &t.base[static_cast<int64_t>(b) * nchan];
+      for (int pr = 0; pr < npair; ++pr) {
+        const int32_t* r0 = &t.rel[(static_cast<int64_t>(b) * t.m_blk + 2 * pr) * nchan];
+        const int32_t* r1 = r0 + nchan;
+        const bool second = b * t.m_blk + 2 * pr + 1 < p->ndm;  // else a copy of the first
+        int32_t* l = &list[(static_cast<int64_t>(b) * npair + pr) * nchan];
+        for (int ch = 0; ch < t.nchunk; ++ch) {
+          const int c0 = ch * t.cc, c1 = static_cast<int>(std::min<int64_t>(nchan, c0 + t.cc));
+          int k = c0;
+          uint32_t* cw = &cnt[((static_cast<int64_t>(b) * t.nchunk + ch) * npair + pr) * 4];
+          for (int cls = 0; cls < ncls; ++cls) {
+            int n = 0;
+            for (int c = c0; c < c1; ++c) {
+              const int32_t g = (g0 + base[c]) & 1;
+              const int32_t a0 = r0[c] + g;
+              const int32_t dlt = second ? r1[c] - r0[c] : 0;
+              if ((a0 & 1) * (kPairMaxDeltaHost + 1) + dlt != cls) continue;
+              l[k++] = 4 * ((c - c0) * t.win_dwords + (a0 >> 1));  // LDS byte offset
+              ++n;
+            }
+            cw[cls / 4] |= static_cast<uint32_t>(n) << (8 * (cls % 4));
+          }
+        }
+      }
+    }
+  }
+  for (int b = 0; b < t.nblk && !pairs; ++b) {
     const int32_t* base = &t.base[static_cast<int64_t>(b) * nchan];
     for (int x = 0; x < t.m_blk; ++x) {
       const int32_t* r = &t.rel[(static_cast<int64_t>(b) * t.m_blk + x) * nchan];
@@ -410,6 +465,8 @@ static int plan_create(int32_t nchan, double f_lo, double df, double tsamp, cons
     return st;
   }
   st = build_tiling(p, variant >= 0 ? variant : default_variant(ds, ndm));
+  if (st != ARTS_OK && variant < 0 && fallback_variant(default_variant(ds, ndm)) >= 0)
+    st = build_tiling(p, fallback_variant(default_variant(ds, ndm)));
   if (st != ARTS_OK && variant < 0) {
     // wide DM spacing: fall back to the variant with the fewest DMs per block
     int best = -1;
@@ -644,10 +701,37 @@ int arts_plan_delays(arts_plan_t p, int32_t* host_out) {
   return ARTS_OK;
 }
 
-int arts_plan_set_tiling(arts_plan_t p, int32_t variant) {
+int arts_plan_set_tiling_shape(arts_plan_t p, int32_t variant, int32_t buffers,
+                               int32_t channels) {
   if (int st = check_plan(p)) return st;
-  if (p->tiling.variant == variant) return ARTS_OK;
-  return build_tiling(p, variant);
+  if (buffers != 1 && buffers != 2) return fail(ARTS_E_INVAL, "buffers must be 1 or 2");
+  if (channels < 0 || channels > 255) return fail(ARTS_E_INVAL, "channels must be 0..255");
+  arts_plan_s* q = p->nsub > 0 ? p->sb1 : p;  // subband plans: the first step's tiles
+  if (p->tiling.variant == variant && q->tile_nbuf == buffers && q->tile_cc == channels)
+    return ARTS_OK;
+  const int32_t nb0 = q->tile_nbuf, cc0 = q->tile_cc;
+  q->tile_nbuf = buffers;
+  q->tile_cc = channels;
+  const int st = build_tiling(p, variant);
+  if (st != ARTS_OK) {  // the plan keeps its tiling
+    q->tile_nbuf = nb0;
+    q->tile_cc = cc0;
+  }
+  return st;
+}
+
+int arts_plan_get_tiling_shape(arts_plan_t p, int32_t* variant, int32_t* buffers,
+                               int32_t* channels) {
+  if (int st = check_plan(p)) return st;
+  const arts_plan_s* q = p->nsub > 0 ? p->sb1 : p;
+  if (variant) *variant = p->tiling.variant;
+  if (buffers) *buffers = q->tiling.nbuf;
+  if (channels) *channels = q->tiling.cc;
+  return ARTS_OK;
+}
+
+int arts_plan_set_tiling(arts_plan_t p, int32_t variant) {
+  return arts_plan_set_tiling_shape(p, variant, kDefaultBuffers, 0);
 }
 
 int arts_plan_get_tiling(arts_plan_t p, int32_t* variant) {
@@ -659,6 +743,7 @@ int arts_plan_get_tiling(arts_plan_t p, int32_t* variant) {
 int arts_plan_set_cluster(arts_plan_t p, int32_t enable) {
   if (int st = check_plan(p)) return st;
   if (enable != 0 && enable != 1) return fail(ARTS_E_INVAL, "enable must be 0 or 1");
+  if (p->cluster != (enable != 0)) ++p->generation;
   p->cluster = enable != 0;
   return ARTS_OK;
 }
@@ -672,6 +757,7 @@ int arts_plan_get_cluster(arts_plan_t p, int32_t* enable) {
 int arts_plan_set_integration(arts_plan_t p, int32_t mode) {
   if (int st = check_plan(p)) return st;
   if (mode != 0 && mode != 1) return fail(ARTS_E_INVAL, "mode must be 0 or 1");
+  if (p->integration != mode) ++p->generation;
   p->integration = mode;
   return ARTS_OK;
 }
@@ -853,7 +939,8 @@ int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
     return fail(ARTS_E_INVAL, "bad variant or buffer");
   const TileVariant& v = kVariants[variant];
   snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d%s", v.j, v.acc, v.waves, v.spd,
-           v.pack == 4   ? " group sums"
+           v.pack == 5   ? " pairs"
+           : v.pack == 4 ? " group sums"
            : v.pack == 3 ? " packed held"
            : v.pack == 2 ? " framed"
            : v.pack      ? " packed"

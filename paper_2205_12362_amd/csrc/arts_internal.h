@@ -23,8 +23,14 @@ struct TileVariant {
 extern const TileVariant kVariants[];
 extern const int kNumVariants;
 int default_variant(int downsample, int64_t ndm);
+int fallback_variant(int variant);
+constexpr int kPairMaxDeltaHost = 7;  // DM-pair tilings: largest delay step inside a pair
 int packed_variant(int64_t ndm);
 int split_variant(int64_t ncoarse);
+
+// LDS chunk buffers of a tiling unless set otherwise: one buffer fetched in turn (the CU's
+// other workgroups sum meanwhile), which doubles the channels per chunk against two.
+constexpr int kDefaultBuffers = 1;
 
 // Widest supported boxcar (the candidate kernels stage a segment plus wmax samples in LDS).
 constexpr int kMaxWidth = 16384;
@@ -38,6 +44,7 @@ struct Tiling {
   int rmax = 0;         // largest delay spread inside a block (samples)
   int win_dwords = 0;   // LDS dwords staged per channel (a multiple of 4)
   int cc = 0;           // channels per LDS chunk (<= 255)
+  int nbuf = kDefaultBuffers;  // LDS chunk buffers (2: the next chunk's fetch overlaps the sums)
   int nchunk = 0;
   int spd = 4;
   std::vector<int32_t> rel;    // host [nblk][m_blk][nchan] delay - block base
@@ -70,6 +77,12 @@ struct arts_plan_s {
   double* d_dms = nullptr;
   arts::Tiling tiling;
   int lds_budget = 0;  // bytes of LDS per dedispersion workgroup; 0 = by wave count
+  // requested tile shape (arts_plan_set_tiling_shape): LDS buffers and channels per chunk
+  // (0: as many as the LDS budget allows)
+  int32_t tile_nbuf = arts::kDefaultBuffers, tile_cc = 0;
+  // bumped by every change that work captured earlier does not see (tiling tables freed and
+  // rebuilt, clustering, integration mode): streams drop their graphs when it moves
+  uint64_t generation = 0;
   // workspace, grown on demand outside any timed loop
   int64_t* d_s1 = nullptr;
   double* d_musig = nullptr;
@@ -210,6 +223,7 @@ int launch_boxcar_snr(const arts_plan_s* p, const int32_t* series, int32_t nbeam
 int launch_sb_gather(const uint8_t* tab, int32_t ntab, const uint8_t* sb_table, int32_t nsb,
                      int32_t nchan, int64_t nsamp, uint8_t* out, hipStream_t s);
 int launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+int launch_fill_random(uint8_t* p, int64_t n, uint64_t seed, hipStream_t s);
 // DM-width clustering.  launch_cluster replaces the candidates cand[beg, *count) by one per
 // cluster (cand[beg, beg + clusters), *count updated on the device), where beg is 0 or, with
 // from_mark, the value of *count that launch_cluster_mark saved before the plan's candidates
@@ -284,6 +298,8 @@ struct arts_stream_s {
   hipEvent_t ev_in = nullptr, ev_done = nullptr;
   // captured pushes, keyed by the ring parity and each subband plan's window origin
   std::map<std::vector<int>, hipGraphExec_t> graphs;
+  std::vector<uint64_t> plan_gen;  // the plans' generations the graphs were captured at
+  bool eager_next = false;         // the next push runs eagerly (after the plans changed)
   int64_t pushed = 0, waited = 0;
   int64_t device_bytes = 0;
   // profiling: events bracketing each phase of the last push

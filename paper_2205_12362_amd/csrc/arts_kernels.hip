@@ -12,34 +12,55 @@
 namespace arts {
 
 // ------------------------------------------------------------------ tiling variants ----
-// spd, j, acc, waves, pack.  j is odd so the lane stride of j dwords hits distinct LDS banks;
-// pack selects the packed 16-bit partial sums (native data only).
+// id, spd, j, acc, waves, pack.  j is odd so the lane stride of j dwords hits distinct LDS
+// banks; pack: 0 plain, 1 packed 16-bit partial sums, 2 framed, 3 packed halves held across
+// chunks, 4 group sums (split plans), 5 DM pairs read as one window (16-bit samples).
+#define ARTS_TILINGS(X)                                                                    \
+  X(0, 4, 5, 4, 8, 0)   /* 32 DMs x 1280 samples per block, 80 accumulators per lane */    \
+  X(1, 4, 7, 3, 8, 0)   /* 24 DMs x 1792 */                                                \
+  X(2, 4, 5, 4, 16, 0)  /* 64 DMs x 1280, one block per CU */                              \
+  X(3, 4, 3, 6, 8, 0)   /* 48 DMs x 768 */                                                 \
+  X(4, 4, 5, 2, 4, 0)   /*  8 DMs x 1280, small problems */                                \
+  X(5, 4, 7, 4, 8, 0)   /* 32 DMs x 1792, 112 accumulators */                              \
+  X(6, 2, 5, 4, 8, 0)   /* downsampled: 32 DMs x 640 */                                    \
+  X(7, 2, 9, 2, 8, 0)   /* downsampled: 16 DMs x 1152 */                                   \
+  X(8, 2, 7, 3, 8, 0)   /* downsampled: 24 DMs x 896 */                                    \
+  X(9, 4, 5, 4, 8, 1)   /* as 0, packed */                                                 \
+  X(10, 4, 5, 3, 8, 1)  /* 24 DMs x 1280, packed */                                        \
+  X(11, 4, 3, 6, 8, 1)  /* as 3, packed */                                                 \
+  X(12, 4, 5, 4, 16, 1) /* as 2, packed */                                                 \
+  X(13, 2, 5, 4, 8, 1)  /* as 6, packed */                                                 \
+  X(14, 2, 9, 2, 8, 1)  /* as 7, packed */                                                 \
+  X(15, 2, 7, 3, 8, 1)  /* as 8, packed */                                                 \
+  X(16, 2, 5, 6, 8, 1)  /* downsampled, packed: 48 DMs x 640 */                            \
+  X(17, 4, 5, 2, 4, 1)  /* as 4, packed */                                                 \
+  X(18, 4, 5, 1, 8, 2)  /* framed:  8 DMs x 1280 */                                        \
+  X(19, 4, 5, 1, 16, 2) /* framed: 16 DMs x 1280, one block per CU */                      \
+  X(20, 4, 3, 2, 8, 2)  /* framed: 16 DMs x 768 */                                         \
+  X(21, 4, 7, 1, 8, 2)  /* framed:  8 DMs x 1792 */                                        \
+  X(22, 4, 5, 2, 8, 3)  /* 16 DMs x 1280, packed halves held across chunks */              \
+  X(23, 4, 5, 4, 8, 4)  /* 32 DMs x 1280, group sums in packed halves (split plans) */     \
+  X(24, 2, 5, 4, 8, 5)  /* downsampled, DM pairs: 32 DMs x 640 */                          \
+  X(25, 2, 7, 2, 8, 5)  /* downsampled, DM pairs: 16 DMs x 896 */                          \
+  X(26, 2, 9, 2, 8, 5)  /* downsampled, DM pairs: 16 DMs x 1152 */
+
 const TileVariant kVariants[] = {
-    {4, 5, 4, 8, 0},   // 0: 32 DMs x 1280 samples per block, 80 accumulators per lane
-    {4, 7, 3, 8, 0},   // 1: 24 DMs x 1792
-    {4, 5, 4, 16, 0},  // 2: 64 DMs x 1280, one block per CU
-    {4, 3, 6, 8, 0},   // 3: 48 DMs x 768
-    {4, 5, 2, 4, 0},   // 4:  8 DMs x 1280, small problems
-    {4, 7, 4, 8, 0},   // 5: 32 DMs x 1792, 112 accumulators
-    {2, 5, 4, 8, 0},   // 6: downsampled: 32 DMs x 640
-    {2, 9, 2, 8, 0},   // 7: downsampled: 16 DMs x 1152
-    {2, 7, 3, 8, 0},   // 8: downsampled: 24 DMs x 896
-    {4, 5, 4, 8, 1},   // 9: as 0, packed
-    {4, 5, 3, 8, 1},   // 10: 24 DMs x 1280, packed
-    {4, 3, 6, 8, 1},   // 11: as 3, packed
-    {4, 5, 4, 16, 1},  // 12: as 2, packed
-    {2, 5, 4, 8, 1},   // 13: as 6, packed
-    {2, 9, 2, 8, 1},   // 14: as 7, packed
-    {2, 7, 3, 8, 1},   // 15: as 8, packed
-    {2, 5, 6, 8, 1},   // 16: downsampled, packed: 48 DMs x 640
-    {4, 5, 2, 4, 1},   // 17: as 4, packed
-    {4, 5, 1, 8, 2},   // 18: framed:  8 DMs x 1280
-    {4, 5, 1, 16, 2},  // 19: framed: 16 DMs x 1280, one block per CU
-    {4, 3, 2, 8, 2},   // 20: framed: 16 DMs x 768
-    {4, 7, 1, 8, 2},   // 21: framed:  8 DMs x 1792
-    {4, 5, 2, 8, 3},   // 22: 16 DMs x 1280, packed halves held across chunks
-    {4, 5, 4, 8, 4},   // 23: 32 DMs x 1280, group sums in packed halves (split plans only)
+#define ARTS_X(id, spd, j, acc, waves, pack) {spd, j, acc, waves, pack},
+    ARTS_TILINGS(ARTS_X)
+#undef ARTS_X
 };
+// the ids of the table are its indices
+constexpr int kTilingIds[] = {
+#define ARTS_X(id, spd, j, acc, waves, pack) id,
+    ARTS_TILINGS(ARTS_X)
+#undef ARTS_X
+};
+constexpr bool tiling_ids_ok() {
+  for (int i = 0; i < static_cast<int>(sizeof(kTilingIds) / sizeof(int)); ++i)
+    if (kTilingIds[i] != i) return false;
+  return true;
+}
+static_assert(tiling_ids_ok(), "tiling ids must run 0, 1, 2, ...");
 const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // Byte samples: the packed tiling with 32 DMs per block (9) unless 24 per block (10) leaves
@@ -59,9 +80,13 @@ int split_variant(int64_t ncoarse) {
 }
 
 int default_variant(int downsample, int64_t ndm) {
-  if (downsample > 1) return 6;
+  if (downsample > 1) return 24;
   return ndm <= 64 ? 17 : packed_variant(ndm);
 }
+
+// The tiling to try when the default does not fit a plan (DM-pair tilings need neighbouring
+// trials at most kPairMaxDelta samples apart in every channel), or -1.
+int fallback_variant(int variant) { return kVariants[variant].pack == 5 ? 6 : -1; }
 
 // ------------------------------------------------------------------ dedispersion ----
 //
@@ -100,7 +125,9 @@ struct DedispArgs {
   const uint8_t* sb_table;  // nullable: row (b, c) reads source beam sb_table[b*tbl_stride + c]
   const int32_t* base;      // [nblk][nchan]
   const int32_t* list;      // [nblk][m_blk][nchan] LDS byte offsets, by chunk then m
+                            // (DM-pair tilings: [nblk][m_blk / 2][nchan], by chunk then class)
   const uint32_t* cnt;      // [nblk][nchunk][m_blk] packed per-m channel counts
+                            // (DM-pair tilings: [nblk][nchunk][m_blk / 2][4], per class)
   int32_t* out;             // out[b*out_bstride + d*out_pitch + t], int32 (or uint16: out16)
   int64_t nout;
   int64_t out_pitch, out_bstride;
@@ -108,6 +135,8 @@ struct DedispArgs {
   int64_t nwg;
   int32_t nchan, ndm, nsrc, ds, nbeam;
   int32_t m_blk, nblk, win, cc, nchunk, ntt;
+  int32_t nlist;            // offset lists per block: m_blk, or m_blk / 2 for DM pairs
+  int32_t nbuf;             // LDS chunk buffers: 2 (fetch overlaps the sums) or 1
   int32_t src_stride;       // rows between source beams (nchan unless the job says otherwise)
   int32_t tbl_stride;       // SB table entries between beams
   int32_t out16;
@@ -371,6 +400,83 @@ __device__ __forceinline__ void flush_pk16(uint32_t* acc, uint32_t* pk) {
   }
 }
 
+// ---- DM pairs on 16-bit samples (spd = 2).  The lane sums two neighbouring DM trials of the
+// block together.  In channel c their windows start S = M0 + DELTA halves apart, DELTA =
+// r1 - r0 >= 0 (the delay grows with DM; the plan refuses pairs that are further apart), and
+// one read of J + ceil(S / 2) dwords from the first trial's word covers both: the first trial
+// adds half pairs at parity M0, the second those S halves further on.  The plan sorts each
+// pair's channels by (M0, DELTA), kPairClasses straight-line classes, so that the word offsets
+// are compile-time constants.  Against one read per trial this halves the LDS traffic at equal
+// delays and saves a third at DELTA = 6, which is what bounds the 16-bit kernels.
+constexpr int kPairMaxDelta = kPairMaxDeltaHost;
+constexpr int kPairClasses = 2 * (kPairMaxDelta + 1);  // 16: four 8-bit counts per word
+
+template <int J, int M0, int DELTA, bool PF>
+__device__ __forceinline__ void accum_run_pair(uint32_t* pk0, uint32_t* pk1, const int32_t* ent,
+                                               int n, const uint8_t* lane_base) {
+  constexpr int S = M0 + DELTA;
+  constexpr int NW = J + (S + 1) / 2;  // union of [M0, M0 + 2J) and [S, S + 2J) halves
+  constexpr int W1 = S / 2, P1 = S % 2;
+  int i = 0;
+  if (PF && n >= 4) {
+    int32_t q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = ent[u];
+    for (; i + 4 <= n; i += 4) {
+      uint32_t w[4][NW];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + q[u]);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) w[u][k] = p[k];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = ent[i + 4 + u];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        add_pk16<J, M0>(pk0, w[2 * h], w[2 * h + 1]);
+        add_pk16<J, P1>(pk1, w[2 * h] + W1, w[2 * h + 1] + W1);
+      }
+    }
+  }
+  for (; i + 2 <= n; i += 2) {
+    uint32_t w[2][NW];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i + u]);
+#pragma unroll
+      for (int k = 0; k < NW; ++k) w[u][k] = p[k];
+    }
+    add_pk16<J, M0>(pk0, w[0], w[1]);
+    add_pk16<J, P1>(pk1, w[0] + W1, w[1] + W1);
+  }
+  if (i < n) {
+    uint32_t w[NW];
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + ent[i]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = p[k];
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+      pk0[k] += half_pair<M0>(w, k);
+      pk1[k] += half_pair<P1>(w + W1, k);
+    }
+  }
+}
+
+// Every class of one pair, in the plan's order: class = M0 * (kPairMaxDelta + 1) + DELTA, its
+// channel count in byte (class % 4) of cnt[class / 4].
+template <int J, int CLS, bool PF>
+__device__ __forceinline__ void accum_pair_classes(uint32_t* pk0, uint32_t* pk1,
+                                                   const int32_t* ent, const uint32_t* cnt,
+                                                   const uint8_t* lane_base) {
+  if constexpr (CLS < kPairClasses) {
+    const int n = (cnt[CLS / 4] >> (8 * (CLS % 4))) & 0xff;
+    accum_run_pair<J, CLS / (kPairMaxDelta + 1), CLS % (kPairMaxDelta + 1), PF>(pk0, pk1, ent, n,
+                                                                                 lane_base);
+    accum_pair_classes<J, CLS + 1, PF>(pk0, pk1, ent + n, cnt, lane_base);
+  }
+}
+
 // Widen the packed halves into the int32 totals (one SDWA add each) and clear them.
 template <int J>
 __device__ __forceinline__ void flush_pk(uint32_t* acc, uint32_t* e, uint32_t* o) {
@@ -531,7 +637,7 @@ __device__ __forceinline__ void stage_windows(const DedispArgs& a, const uint8_t
 template <int WAVES>
 __device__ __forceinline__ void stage_lists(const DedispArgs& a, const int32_t* list_blk, int c0,
                                             int ncc, int32_t* ent, int lane, int wave) {
-  for (int x = wave; x < a.m_blk; x += WAVES) {
+  for (int x = wave; x < a.nlist; x += WAVES) {
     const int32_t* src = list_blk + static_cast<int64_t>(x) * a.nchan + c0;
     for (int j0 = 0; j0 < ncc; j0 += 64)
       if (j0 + lane < ncc)
@@ -674,7 +780,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   // LDS: two buffers, each cc windows of win dwords followed by the chunk's offset lists and
   // 4 pad words; then (for SB formation) the beam's SB-table row
   const int buf_words = a.cc * a.win + a.m_blk * a.cc + 4;
-  uint8_t* sbrow = reinterpret_cast<uint8_t*>(lds + 2 * buf_words);
+  uint8_t* sbrow = reinterpret_cast<uint8_t*>(lds + a.nbuf * buf_words);
   const int64_t t0 = static_cast<int64_t>(tt) * TT;
   const int dwave0 = blk * a.m_blk + wave * ACC;
   const bool wave_active = dwave0 < a.ndm;
@@ -712,11 +818,11 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   int since = 0;  // channels in the frames or held halves since they were last widened
 
   const int32_t* base_blk = a.base + static_cast<int64_t>(blk) * a.nchan;
-  const int32_t* list_blk = a.list + static_cast<int64_t>(blk) * a.m_blk * a.nchan;
+  const int32_t* list_blk = a.list + static_cast<int64_t>(blk) * a.nlist * a.nchan;
   const uint32_t* cnt_blk = a.cnt + static_cast<int64_t>(blk) * a.nchunk * a.m_blk + wave * ACC;
 
   // prologue: pad words, the SB-table row, then chunk 0 into buffer 0
-  if (threadIdx.x < 8) lds[(threadIdx.x >> 2) * buf_words + a.cc * a.win + a.m_blk * a.cc +
+  if (threadIdx.x < 4 * a.nbuf) lds[(threadIdx.x >> 2) * buf_words + a.cc * a.win + a.m_blk * a.cc +
                            (threadIdx.x & 3)] = 0;
   if (a.sb_table)
     for (int c = threadIdx.x; c < a.nchan; c += WAVES * 64)
@@ -730,7 +836,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   __syncthreads();
 
   for (int ch = 0; ch < a.nchunk; ++ch) {
-    uint32_t* cur = lds + (ch & 1) * buf_words;
+    uint32_t* cur = lds + (a.nbuf == 2 ? (ch & 1) * buf_words : 0);
     const int c0 = ch * a.cc;
     // ---- split plans: the previous chunk ended a channel group: store its sums now, so that
     // the stores have this chunk's work to complete before the wait at its end
@@ -753,8 +859,18 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
         }
       }
     }
-    // ---- start fetching the next chunk into the other buffer
-    if (ch + 1 < a.nchunk) {
+    // ---- one buffer: fetch this chunk now (the previous one's readers are done, see the
+    // barrier at the end of the loop); the CU's other workgroups compute meanwhile
+    if (a.nbuf == 1 && ch > 0) {
+      stage_windows<SPD, WAVES>(a, sbrow, b, blk, t0, base_blk, c0, min(a.cc, a.nchan - c0),
+                                cur, lane, wave);
+      stage_lists<WAVES>(a, list_blk, c0, min(a.cc, a.nchan - c0),
+                         reinterpret_cast<int32_t*>(cur + a.cc * a.win), lane, wave);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    // ---- two buffers: start fetching the next chunk into the other one
+    if (a.nbuf == 2 && ch + 1 < a.nchunk) {
       uint32_t* nxt = lds + ((ch + 1) & 1) * buf_words;
       const int c1 = c0 + a.cc;
       const int ncc1 = min(a.cc, a.nchan - c1);
@@ -801,7 +917,8 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
       const uint8_t* lane_base = reinterpret_cast<const uint8_t*>(cur) + 4 * J * lane;
 #pragma unroll
       for (int x = 0; x < ACC; ++x) {
-        const uint32_t packed = __builtin_amdgcn_readfirstlane(cnt_blk[ch * a.m_blk + x]);
+        const uint32_t packed =
+            PK == 5 ? 0u : __builtin_amdgcn_readfirstlane(cnt_blk[ch * a.m_blk + x]);
         const int32_t* ent = ent_cur + (wave * ACC + x) * a.cc;
         const int n0 = packed & 0xff, n1 = (packed >> 8) & 0xff;
         if constexpr (PK == 2) {
@@ -821,6 +938,24 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
           accum_run_pk<J, 1, PF>(he[x], ho[x], ent + n0, n1, lane_base);
           accum_run_pk<J, 2, PF>(he[x], ho[x], ent + n0 + n1, n2, lane_base);
           accum_run_pk<J, 3, PF>(he[x], ho[x], ent + n0 + n1 + n2, n3, lane_base);
+        } else if constexpr (PK == 5) {
+          // DM pairs: trials (x, x + 1) of the wave at even x; odd x have been summed
+          static_assert(SPD == 2 && ACC % 2 == 0, "DM pairs are for 16-bit samples");
+          if (x % 2 == 0) {
+            const int pr = (wave * ACC + x) / 2;
+            const uint32_t* cp = a.cnt + ((static_cast<int64_t>(blk) * a.nchunk + ch) *
+                                              (a.m_blk / 2) + pr) * 4;
+            uint32_t cnt4[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cnt4[k] = __builtin_amdgcn_readfirstlane(cp[k]);
+            uint32_t pk0[J], pk1[J];
+#pragma unroll
+            for (int k = 0; k < J; ++k) pk0[k] = pk1[k] = 0;
+            constexpr bool PF = ACC * T <= 60;
+            accum_pair_classes<J, 0, PF>(pk0, pk1, ent_cur + pr * a.cc, cnt4, lane_base);
+            flush_pk16<J>(acc[x], pk0);
+            flush_pk16<J>(acc[x + 1], pk1);
+          }
         } else if constexpr (PK && SPD == 2) {
           uint32_t pk[J];
 #pragma unroll
@@ -998,7 +1133,7 @@ void dedisperse_batch_kernel(BatchArgs q) {
 }
 
 static size_t lds_bytes(const DedispArgs& a) {
-  return 2 * (static_cast<size_t>(a.win) * a.cc + static_cast<size_t>(a.m_blk) * a.cc + 4) * 4 +
+  return a.nbuf * (static_cast<size_t>(a.win) * a.cc + static_cast<size_t>(a.m_blk) * a.cc + 4) * 4 +
          (a.sb_table ? ((static_cast<size_t>(a.nchan) + 3) & ~static_cast<size_t>(3)) : 0);
 }
 
@@ -1130,6 +1265,8 @@ static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
   a.ds = p->ds;
   a.nbeam = job.nbeam;
   a.m_blk = t.m_blk;
+  a.nlist = v.pack == 5 ? t.m_blk / 2 : t.m_blk;
+  a.nbuf = t.nbuf;
   a.nblk = t.nblk;
   a.win = t.win_dwords;
   a.cc = t.cc;
@@ -1234,30 +1371,10 @@ static int occupancy_variant(int kind) {
 
 int variant_occupancy(int variant, int kind) {
   switch (variant) {
-    case 0: return occupancy_variant<4, 5, 4, 8, 0>(kind);
-    case 1: return occupancy_variant<4, 7, 3, 8, 0>(kind);
-    case 2: return occupancy_variant<4, 5, 4, 16, 0>(kind);
-    case 3: return occupancy_variant<4, 3, 6, 8, 0>(kind);
-    case 4: return occupancy_variant<4, 5, 2, 4, 0>(kind);
-    case 5: return occupancy_variant<4, 7, 4, 8, 0>(kind);
-    case 6: return occupancy_variant<2, 5, 4, 8, 0>(kind);
-    case 7: return occupancy_variant<2, 9, 2, 8, 0>(kind);
-    case 8: return occupancy_variant<2, 7, 3, 8, 0>(kind);
-    case 9: return occupancy_variant<4, 5, 4, 8, 1>(kind);
-    case 10: return occupancy_variant<4, 5, 3, 8, 1>(kind);
-    case 11: return occupancy_variant<4, 3, 6, 8, 1>(kind);
-    case 12: return occupancy_variant<4, 5, 4, 16, 1>(kind);
-    case 13: return occupancy_variant<2, 5, 4, 8, 1>(kind);
-    case 14: return occupancy_variant<2, 9, 2, 8, 1>(kind);
-    case 15: return occupancy_variant<2, 7, 3, 8, 1>(kind);
-    case 16: return occupancy_variant<2, 5, 6, 8, 1>(kind);
-    case 17: return occupancy_variant<4, 5, 2, 4, 1>(kind);
-    case 18: return occupancy_variant<4, 5, 1, 8, 2>(kind);
-    case 19: return occupancy_variant<4, 5, 1, 16, 2>(kind);
-    case 20: return occupancy_variant<4, 3, 2, 8, 2>(kind);
-    case 21: return occupancy_variant<4, 7, 1, 8, 2>(kind);
-    case 22: return occupancy_variant<4, 5, 2, 8, 3>(kind);
-    case 23: return occupancy_variant<4, 5, 4, 8, 4>(kind);
+#define ARTS_X(id, spd, j, acc, waves, pack) \
+    case id: return occupancy_variant<spd, j, acc, waves, pack>(kind);
+    ARTS_TILINGS(ARTS_X)
+#undef ARTS_X
     default: return 0;
   }
 }
@@ -1271,30 +1388,10 @@ int launch_dedisperse(arts_plan_s* p, const DedispJob& job, hipStream_t s) {
   DedispArgs a;
   if (int st = make_args(p, job, &a)) return st;
   switch (p->tiling.variant) {
-    case 0: return launch_variant<4, 5, 4, 8, 0>(a, s);
-    case 1: return launch_variant<4, 7, 3, 8, 0>(a, s);
-    case 2: return launch_variant<4, 5, 4, 16, 0>(a, s);
-    case 3: return launch_variant<4, 3, 6, 8, 0>(a, s);
-    case 4: return launch_variant<4, 5, 2, 4, 0>(a, s);
-    case 5: return launch_variant<4, 7, 4, 8, 0>(a, s);
-    case 6: return launch_variant<2, 5, 4, 8, 0>(a, s);
-    case 7: return launch_variant<2, 9, 2, 8, 0>(a, s);
-    case 8: return launch_variant<2, 7, 3, 8, 0>(a, s);
-    case 9: return launch_variant<4, 5, 4, 8, 1>(a, s);
-    case 10: return launch_variant<4, 5, 3, 8, 1>(a, s);
-    case 11: return launch_variant<4, 3, 6, 8, 1>(a, s);
-    case 12: return launch_variant<4, 5, 4, 16, 1>(a, s);
-    case 13: return launch_variant<2, 5, 4, 8, 1>(a, s);
-    case 14: return launch_variant<2, 9, 2, 8, 1>(a, s);
-    case 15: return launch_variant<2, 7, 3, 8, 1>(a, s);
-    case 16: return launch_variant<2, 5, 6, 8, 1>(a, s);
-    case 17: return launch_variant<4, 5, 2, 4, 1>(a, s);
-    case 18: return launch_variant<4, 5, 1, 8, 2>(a, s);
-    case 19: return launch_variant<4, 5, 1, 16, 2>(a, s);
-    case 20: return launch_variant<4, 3, 2, 8, 2>(a, s);
-    case 21: return launch_variant<4, 7, 1, 8, 2>(a, s);
-    case 22: return launch_variant<4, 5, 2, 8, 3>(a, s);
-    case 23: return launch_variant<4, 5, 4, 8, 4>(a, s);
+#define ARTS_X(id, spd, j, acc, waves, pack) \
+    case id: return launch_variant<spd, j, acc, waves, pack>(a, s);
+    ARTS_TILINGS(ARTS_X)
+#undef ARTS_X
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
@@ -1369,30 +1466,10 @@ int launch_dedisperse_batch(arts_plan_s* const* plans, const DedispJob* jobs, in
   q.njobs = n;
   for (int x = 0; x <= 8; ++x) q.part[x] = hs[n] * x / 8;
   switch (variant) {
-    case 0: return launch_batch_variant<4, 5, 4, 8, 0>(q, lds, s);
-    case 1: return launch_batch_variant<4, 7, 3, 8, 0>(q, lds, s);
-    case 2: return launch_batch_variant<4, 5, 4, 16, 0>(q, lds, s);
-    case 3: return launch_batch_variant<4, 3, 6, 8, 0>(q, lds, s);
-    case 4: return launch_batch_variant<4, 5, 2, 4, 0>(q, lds, s);
-    case 5: return launch_batch_variant<4, 7, 4, 8, 0>(q, lds, s);
-    case 6: return launch_batch_variant<2, 5, 4, 8, 0>(q, lds, s);
-    case 7: return launch_batch_variant<2, 9, 2, 8, 0>(q, lds, s);
-    case 8: return launch_batch_variant<2, 7, 3, 8, 0>(q, lds, s);
-    case 9: return launch_batch_variant<4, 5, 4, 8, 1>(q, lds, s);
-    case 10: return launch_batch_variant<4, 5, 3, 8, 1>(q, lds, s);
-    case 11: return launch_batch_variant<4, 3, 6, 8, 1>(q, lds, s);
-    case 12: return launch_batch_variant<4, 5, 4, 16, 1>(q, lds, s);
-    case 13: return launch_batch_variant<2, 5, 4, 8, 1>(q, lds, s);
-    case 14: return launch_batch_variant<2, 9, 2, 8, 1>(q, lds, s);
-    case 15: return launch_batch_variant<2, 7, 3, 8, 1>(q, lds, s);
-    case 16: return launch_batch_variant<2, 5, 6, 8, 1>(q, lds, s);
-    case 17: return launch_batch_variant<4, 5, 2, 4, 1>(q, lds, s);
-    case 18: return launch_batch_variant<4, 5, 1, 8, 2>(q, lds, s);
-    case 19: return launch_batch_variant<4, 5, 1, 16, 2>(q, lds, s);
-    case 20: return launch_batch_variant<4, 3, 2, 8, 2>(q, lds, s);
-    case 21: return launch_batch_variant<4, 7, 1, 8, 2>(q, lds, s);
-    case 22: return launch_batch_variant<4, 5, 2, 8, 3>(q, lds, s);
-    case 23: return launch_batch_variant<4, 5, 4, 8, 4>(q, lds, s);
+#define ARTS_X(id, spd, j, acc, waves, pack) \
+    case id: return launch_batch_variant<spd, j, acc, waves, pack>(q, lds, s);
+    ARTS_TILINGS(ARTS_X)
+#undef ARTS_X
     default: return fail(ARTS_E_INVAL, "plan has no tiling");
   }
 }
@@ -2207,6 +2284,27 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
                      p->nwidth, p->wmax, p->d_dms, static_cast<double>(thr),
                      t_offset + t_begin, beam_offset, p->ds, cand, count, cap,
                      pre ? flags : nullptr, p->integration);
+  ARTS_HIP(hipGetLastError());
+  return ARTS_OK;
+}
+
+// Pseudo-random bytes (a counter hash, SplitMix64's finaliser) for the autotuner's inputs.
+__global__ __launch_bounds__(256) void fill_random_kernel(uint8_t* p, int64_t n, uint64_t seed) {
+  const int64_t i0 = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 8;
+  if (i0 >= n) return;
+  uint64_t z = seed + static_cast<uint64_t>(i0) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  for (int k = 0; k < 8 && i0 + k < n; ++k) p[i0 + k] = static_cast<uint8_t>(z >> (8 * k));
+}
+
+int launch_fill_random(uint8_t* p, int64_t n, uint64_t seed, hipStream_t s) {
+  if (n <= 0) return ARTS_OK;
+  const int64_t blocks = (n + 2047) / 2048;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(fill_random_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p,
+                     n, seed);
   ARTS_HIP(hipGetLastError());
   return ARTS_OK;
 }

@@ -470,6 +470,17 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
   if (!s) return fail(ARTS_E_INVAL, "stream is NULL");
   if (s->pushed != s->waited)
     return fail(ARTS_E_STATE, "the previous chunk has not been collected with arts_stream_wait");
+  // captured pushes read the plans' tables and modes as they were at capture: after any
+  // change (a new tiling frees the old tables; clustering or integration mode) capture again
+  std::vector<uint64_t> gen;
+  for (const arts_plan_s* p : s->plans) gen.push_back(p->generation);
+  if (gen != s->plan_gen) {
+    for (auto& kv : s->graphs)
+      if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    s->graphs.clear();
+    s->plan_gen = gen;
+    s->eager_next = true;  // lazily built tables must exist before a capture
+  }
   hipStream_t caller = static_cast<hipStream_t>(stream);
   ARTS_HIP(hipEventRecord(s->ev_in, caller));
   ARTS_HIP(hipStreamWaitEvent(s->hs, s->ev_in, 0));
@@ -481,7 +492,7 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
   // warm-up chunks search a chunk-dependent part of each series: they run eagerly, and the
   // graphs are captured once every plan searches its whole chunk, one per ring parity and
   // step-1 window position
-  if ((s->flags & kGraph) && stream_warm(s, s->pushed) && !s->y_stale) {
+  if ((s->flags & kGraph) && stream_warm(s, s->pushed) && !s->y_stale && !s->eager_next) {
     std::vector<int> key{parity};
     for (size_t p = 0; p < s->plans.size(); ++p) key.push_back(s->ybuf[p] ? s->y_at[p] : 0);
     hipGraphExec_t& ge = s->graphs[key];
@@ -510,6 +521,7 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
   ARTS_HIP(hipEventRecord(s->ev_done, s->hs));
   ++s->pushed;
   s->y_stale = false;
+  s->eager_next = false;
   return ARTS_OK;
 }
 

@@ -209,6 +209,13 @@ def test_dedisperse_sb_fused_apertif_sampled():
 
 
 # ------------------------------------------------------------------------ downsampling
+def _pair_step(delays):
+    """Largest and smallest delay step between the trials of a DM pair (trials 2k, 2k + 1)."""
+    n = delays.shape[0] // 2 * 2
+    d = delays[1:n:2].astype(np.int64) - delays[0:n:2]
+    return int(d.max()), int(d.min())
+
+
 @pytest.mark.parametrize("variant", _ds_variants())
 @pytest.mark.parametrize("D", [2, 4, 5])
 def test_dedisperse_downsampled(variant, D):
@@ -218,11 +225,52 @@ def test_dedisperse_downsampled(variant, D):
     nin = (int(delays.max()) + 1500) * D + (D - 1)       # trailing partial group dropped
     data = synth.noise((2, 96, nin), seed=66 + D)
     w = synth.Workload("ds", 96, f_lo, df, synth.TSAMP, dms, [1, 2, 4], downsample=D)
+    if "pairs" in arts.arts_tiling_describe(variant) and _pair_step(delays)[0] > 7:
+        # DM-pair tilings read one window per pair: trials more than 7 samples apart in some
+        # channel are refused (plans then take another tiling)
+        with pytest.raises(arts.ArtsError) as e:
+            _plan(w, variant)
+        assert e.value.status == arts.ARTS_E_INVAL
+        with _plan(w) as p:
+            assert "pairs" not in arts.arts_tiling_describe(p.tiling())
+        return
     with _plan(w, variant) as p:
         got = p.dedisperse(to_dev(data)).cpu().numpy()
     for b in range(2):
         ref = O.dedisperse(O.downsample(data[b], D), delays)
         assert np.array_equal(got[b], ref)
+
+
+def _pair_variants():
+    return [v for v in _ds_variants() if "pairs" in arts.arts_tiling_describe(v)]
+
+
+@pytest.mark.parametrize("variant", _pair_variants())
+@pytest.mark.parametrize("case", ["classes", "saturated", "odd"])
+def test_dedisperse_ds_pairs(variant, case):
+    # DM pairs: every class (both parities of the first trial's offset, steps 0..7 inside a
+    # pair) occurs; an odd trial count leaves the last pair with one trial; all-255 input fills
+    # the 16-bit partial sums of a 64-channel chunk (64 x 1020 < 2^16)
+    D, nchan = 4, 160
+    f_lo, df = synth.band(nchan)
+    ndm = 77 if case == "odd" else 64
+    dms = 2048.0 + 2.3 * np.arange(ndm)
+    delays = O.delay_table(nchan, f_lo, df, synth.TSAMP, dms, downsample=D)
+    hi, lo = _pair_step(delays)
+    assert hi <= 7 and lo == 0
+    steps = set((delays[1::2][: ndm // 2] - delays[0::2][: ndm // 2]).ravel().tolist())
+    assert steps == set(range(hi + 1)), steps
+    nin = (int(delays.max()) + 1300) * D + 2
+    if case == "saturated":
+        data = np.full((3, nchan, nin), 255, np.uint8)
+    else:
+        data = synth.noise((3, nchan, nin), seed=91 + ndm)
+    w = synth.Workload("pairs", nchan, f_lo, df, synth.TSAMP, dms, [1, 2, 4], downsample=D)
+    _say("DM pairs", variant, arts.arts_tiling_describe(variant), case)
+    with _plan(w, variant) as p:
+        got = p.dedisperse(to_dev(data)).cpu().numpy()
+    for b in range(3):
+        assert np.array_equal(got[b], O.dedisperse(O.downsample(data[b], D), delays)), b
 
 
 # ------------------------------------------------------------------------ boxcar / S/N

@@ -142,6 +142,41 @@ def test_stream_graph_replay_matches_eager():
         assert np.array_equal(ce, cg)
 
 
+def test_stream_graphs_follow_plan_changes():
+    # a captured push reads the plans' tables and modes as they were: after set_tiling_shape
+    # (old tables freed), the integration mode or clustering change, the replayed stream must
+    # still equal an eager stream that sees the same changes
+    import torch
+    nsrc = 2
+    chunks = _chunks(nsrc, 11, seed=150)
+    out = {}
+    for graph in (False, True):
+        ws, plans = _plans()
+        res = []
+        with arts.Stream(plans, nsrc, CHUNK, 6.0, graph=graph) as st:
+            for k, c in enumerate(chunks):
+                if k == 7:
+                    v, nb, cc = plans[0].tiling_shape()
+                    plans[0].set_tiling_shape(v, 1 if nb == 2 else 2, 0)
+                if k == 8:
+                    plans[0].integration = "decimated"
+                    plans[1].integration = "decimated"
+                if k == 9:
+                    plans[0].integration = "sliding"
+                    plans[1].cluster = True
+                st.push(to_dev(c))
+                cands, _ = st.wait()
+                torch.cuda.synchronize()
+                res.append(([st.series(p).cpu().numpy().copy() for p in range(2)], cands))
+        out[graph] = res
+        for p in plans:
+            p.close()
+    for k, ((se, ce), (sg, cg)) in enumerate(zip(out[False], out[True])):
+        for p in range(2):
+            assert np.array_equal(se[p], sg[p]), (k, p)
+        assert np.array_equal(ce, cg), k
+
+
 def test_stream_rejects_bad_arguments():
     ws, plans = _plans()
     with pytest.raises(arts.ArtsError):
