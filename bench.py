@@ -245,55 +245,84 @@ def summarize_profile(stats_dir, fetch_dir, write_dir, sq_dir=None):
     # the calibration copies are the largest dispatches of the copy kernel (1 GiB each)
     copy_name = "copyBuffer" if pick(fetch, "copyBuffer") else "elementwise"
     cf, cw = pick(fetch, copy_name, True), pick(write, copy_name, True)
-    # the dominant kernel: the native (byte-sample) dedispersion kernel with the most time
-    nat = [r for r in stats if "dedisperse_kernel<4," in r["Name"]]
-    dom = max(nat, key=lambda r: float(r["TotalDurationNs"])) if nat else None
-    name = dom["Name"] if dom else "dedisperse_kernel<4,"
-    short = name[name.index("dedisperse_kernel"):name.index(">") + 1] if dom else name
-    df, dw = pick(fetch, short), pick(write, short)
     f_scale = copy_bytes / (cf * 1024) if cf else None   # bytes per KiB reported
     w_scale = copy_bytes / (cw * 1024) if cw else None
-    traffic = (df * 1024 * f_scale + dw * 1024 * w_scale) if (df and dw and f_scale and w_scale) else None
-    lines = ["rocprofv3 summary: 71-SB serving chunk (bench.py), dominant kernel " + short, ""]
+    sq_rows = rows(sq_dir, "*counter_collection.csv") if sq_dir else []
+    # algorithmic adds per launch of each dedispersion kernel (every output it computes): 71 SBs
+    # x 2048 trials x 12755 outputs (native) and x 1476 trials x 3188 outputs (D = 4), x 1536
+    work = {"dedisperse_kernel<4,": NSB * 2048 * (CHUNK + 255) * NCHAN,
+            "dedisperse_kernel<2,": NSB * 1476 * (CHUNK // 4 + 63) * NCHAN}
+    summary = {}
+    lines = ["rocprofv3 summary: 71-SB serving chunk (bench.py)", ""]
     lines.append("kernel stats (rocprofv3 --kernel-trace --stats):")
     for r in stats:
         lines.append(f"  {r['Name'][:70]:70s} calls {r['Calls']:>4s}  avg {float(r['AverageNs'])/1e6:9.3f} ms")
     lines.append("")
-    lines.append(f"FETCH_SIZE per dispatch (KiB): dedisperse {df}, 1 GiB copy {cf} -> scale {f_scale}")
-    lines.append(f"WRITE_SIZE per dispatch (KiB): dedisperse {dw}, 1 GiB copy {cw} -> scale {w_scale}")
-    lines.append(f"HBM bytes per dedisperse launch (scaled): {traffic}")
-    sq = {}
-    if sq_dir:
-        for r in rows(sq_dir, "*counter_collection.csv"):
+    lines.append(f"1 GiB copy: FETCH_SIZE {cf} KiB -> scale {f_scale} B/KiB; WRITE_SIZE {cw} KiB -> "
+                 f"scale {w_scale} B/KiB")
+    for prefix, label in (("dedisperse_kernel<4,", "native dedispersion (dominant)"),
+                          ("dedisperse_kernel<2,", "D=4 dedispersion")):
+        ks = [r for r in stats if prefix in r["Name"]]
+        if not ks:
+            continue
+        dom = max(ks, key=lambda r: float(r["TotalDurationNs"]))
+        name = dom["Name"]
+        short = name[name.index("dedisperse_kernel"):name.index(">") + 1]
+        ms = float(dom["AverageNs"]) / 1e6
+        df, dw = pick(fetch, short), pick(write, short)
+        traffic = (df * 1024 * f_scale + dw * 1024 * w_scale) if (df and dw and f_scale and w_scale) else None
+        sq = {}
+        for r in sq_rows:
             if short in r["Kernel_Name"]:
                 sq.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
         sq = {k: sum(v) / len(v) for k, v in sq.items()}
+        adds = work[prefix]
         lines.append("")
-        lines.append("SQ counters per dispatch of the dominant kernel (rocprofv3 --pmc):")
-        for k in sorted(sq):
-            lines.append(f"  {k:24s} {sq[k]:.4e}")
-        if sq.get("SQ_LDS_IDX_ACTIVE"):
-            lines.append(f"  LDS bank-conflict cycles / LDS active cycles: "
-                         f"{sq.get('SQ_LDS_BANK_CONFLICT', 0) / sq['SQ_LDS_IDX_ACTIVE']:.4f}")
+        lines.append(f"{label}: {short}, {ms:.3f} ms per launch, {adds:.4e} adds, "
+                     f"{adds / ms / 1e9:.2f} Tadd/s = {adds / ms * 1e3 / PEAK_PK16_ADDS:.3f} of the "
+                     f"packed 16-bit peak")
+        if traffic:
+            lines.append(f"  HBM bytes per launch: FETCH {df:.4e} KiB x {f_scale:.4f} + WRITE "
+                         f"{dw:.4e} KiB x {w_scale:.4f} = {traffic:.4e} B ({traffic / ms / 1e9:.3f} TB/s)")
+        derived = {}
+        if sq:
+            cycles = sq.get("SQ_BUSY_CYCLES", 0) / 32.0   # summed over the 32 shader engines
+            derived = {"cycles": cycles}
+            for k in sorted(sq):
+                lines.append(f"  {k:24s} {sq[k]:.4e}")
+            if cycles > 0:
+                derived["valu_lane_instr_per_add"] = sq.get("SQ_INSTS_VALU", 0) * 64 / adds
+                derived["valu_issue_per_cu_cycle"] = sq.get("SQ_INSTS_VALU", 0) / (256 * cycles)
+                derived["lds_busy_per_cu_cycle"] = sq.get("SQ_LDS_IDX_ACTIVE", 0) / (256 * cycles)
+                derived["lds_instr_per_add"] = sq.get("SQ_INSTS_LDS", 0) * 64 / adds
+                derived["clock_ghz"] = cycles / (ms * 1e6)
+                lines.append(f"  derived: {derived['valu_lane_instr_per_add']:.3f} VALU lane-instructions "
+                             f"per add, VALU issue {derived['valu_issue_per_cu_cycle']:.3f} per CU-cycle, "
+                             f"LDS busy {derived['lds_busy_per_cu_cycle']:.3f} per CU-cycle, "
+                             f"{derived['lds_instr_per_add']:.3f} LDS lane-instructions per add, "
+                             f"clock {derived['clock_ghz']:.2f} GHz (busy cycles / 32 SEs / duration)")
+        summary[short] = {"avg_ms": ms, "adds_per_launch": adds, "fetch_kib": df, "write_kib": dw,
+                          "hbm_bytes_per_launch": traffic, "sq_counters": sq, "derived": derived}
     lines.append("")
     lines.append("commands (from the repository root, TMPDIR=/tmp):")
     lines.append("  rocprofv3 --kernel-trace --stats --output-format csv -d <stats_dir> -o bench -- "
-                 "python3 bench.py --steps 4 --warmup 3 --no-cpu-baseline --copy-probe")
+                 "python3 bench.py --steps 4 --warmup 3 --no-cpu-baseline --no-configs --copy-probe")
     lines.append("  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o pmc -- "
-                 "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-probe")
+                 "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-configs --copy-probe")
     lines.append("  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write_dir> -o pmc -- "
-                 "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-probe")
+                 "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-configs --copy-probe")
     lines.append(f"  rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d <sq_dir> -o pmc -- "
-                 "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline")
+                 "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-configs")
     lines.append("  python3 bench.py --summarize-profile <stats_dir> <fetch_dir> <write_dir> <sq_dir>")
+    dom_name = next((k for k in summary if k.startswith("dedisperse_kernel<4,")), None)
+    dom = summary.get(dom_name, {})
     os.makedirs(os.path.dirname(PROFILE_JSON), exist_ok=True)
     with open(PROFILE_JSON[:-5] + ".txt", "w") as f:
         f.write("\n".join(lines) + "\n")
     with open(PROFILE_JSON, "w") as f:
-        json.dump({"kernel": short, "kernel_sha": kernel_hash(),
-                   "avg_ms": float(dom["AverageNs"]) / 1e6 if dom else None,
-                   "fetch_kib": df, "write_kib": dw, "copy_fetch_kib": cf, "copy_write_kib": cw,
-                   "hbm_bytes_per_launch": traffic, "sq_counters": sq}, f, indent=1)
+        json.dump({"kernel": dom_name, "kernel_sha": kernel_hash(), "avg_ms": dom.get("avg_ms"),
+                   "hbm_bytes_per_launch": dom.get("hbm_bytes_per_launch"),
+                   "copy_fetch_kib": cf, "copy_write_kib": cw, "kernels": summary}, f, indent=1)
     print("\n".join(lines))
 
 
