@@ -514,8 +514,9 @@ void arts_stream_destroy(arts_stream_t s);
  * ticks.  Each tick runs one search step for every stream with a submitted chunk: the
  * dedispersion of all of them goes into one persistent launch per tiling variant, so their
  * work shares the device.  A stream's results are identical to a standalone arts_stream fed
- * the same chunks.  All engine work runs on one HIP stream of default priority owned by the
- * server; the calls below are not thread-safe.                                               */
+ * the same chunks.  Ticks go to the server's compute lanes (HIP streams of default priority)
+ * in turn, so a tick enqueued while an earlier one still runs executes beside it on the
+ * device; chunk copies use a further stream.  The calls below are not thread-safe.           */
 typedef struct arts_server_s* arts_server_t;
 int arts_server_create(int64_t hbm_budget_bytes, arts_server_t* out);
 void arts_server_destroy(arts_server_t server);  /* closes every stream */
@@ -533,6 +534,12 @@ int arts_server_submit(arts_server_t server, int32_t stream_id, const uint8_t* c
  * ARTS_E_INVAL (a plan switched to decimated integration that no longer fits the stream's
  * chunk); the streams of that tick are then left part-way through their step: close them.    */
 int arts_server_tick(arts_server_t server, int32_t* nrun);
+/* Compute lanes used for ticks (1 or 2, default 2); waits for queued work first.           */
+int arts_server_set_lanes(arts_server_t server, int32_t nlanes);
+/* *done = 1 if the stream's last step has finished (or it has none in flight), 0 while it is
+ * submitted or running; does not block, so a serving loop can keep admitting and submitting
+ * while ticks run and collect each stream as soon as it is done.                             */
+int arts_server_poll(arts_server_t server, int32_t stream_id, int32_t* done);
 /* Wait for a stream's last step and return its candidates (as arts_stream_wait).             */
 int arts_server_collect(arts_server_t server, int32_t stream_id, arts_candidate* host_out,
                         int64_t capacity, int64_t* count, int64_t* chunk_index);

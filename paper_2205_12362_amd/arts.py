@@ -110,6 +110,8 @@ _SIGNATURES = {
     "arts_server_submit": (C.c_int, [_vp, _i32, _vp, _i32]),
     "arts_server_tick": (C.c_int, [_vp, _pi32]),
     "arts_server_collect": (C.c_int, [_vp, _i32, _vp, _i64, _pi64, _pi64]),
+    "arts_server_poll": (C.c_int, [_vp, _i32, _pi32]),
+    "arts_server_set_lanes": (C.c_int, [_vp, _i32]),
     "arts_server_stream": (C.c_int, [_vp, _i32, C.POINTER(_vp)]),
     "arts_server_info": (C.c_int, [_vp, _pi64, _pi64, _pi32]),
     "arts_strerror": (C.c_char_p, [C.c_int]),
@@ -927,6 +929,15 @@ class Server:
         n = C.c_int32()
         _check(lib().arts_server_tick(self.handle, C.byref(n)))
         return n.value
+
+    def poll(self, sid):
+        """True once the stream's last step has finished (collect will not block)."""
+        d = C.c_int32()
+        _check(lib().arts_server_poll(self.handle, int(sid), C.byref(d)))
+        return bool(d.value)
+
+    def set_lanes(self, nlanes):
+        _check(lib().arts_server_set_lanes(self.handle, int(nlanes)))
 
     def collect(self, sid):
         cap = self._keep[sid][2]

@@ -68,8 +68,10 @@ def build(verbose: bool = False) -> str:
                 print(o)
     objs = [j[-1] for j in jobs]
     tmp = LIB + ".tmp"
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     _run([hipcc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp,
-          "-Wl,-soname,libarts.so"])
+          "-Wl,-soname,libarts.so", f"-L{rocm}/lib", "-lrocprofiler-sdk-roctx",
+          f"-Wl,-rpath,{rocm}/lib"])
     os.replace(tmp, LIB)
     return LIB
 

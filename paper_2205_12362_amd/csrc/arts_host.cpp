@@ -959,6 +959,7 @@ int arts_sb_synthesize(const uint8_t* tab, int32_t ntab, const uint8_t* sb_table
 
 int arts_dedisperse(arts_plan_t p, const uint8_t* in, int32_t nbeam, int64_t nin, int32_t* out,
                     void* stream) {
+  TraceRange range("arts_dedisperse");
   if (int st = check_plan(p)) return st;
   if (!in || !out || nbeam < 1) return fail(ARTS_E_INVAL, "NULL pointer or nbeam < 1");
   const int64_t L = nin / p->ds - p->max_delay;
@@ -1019,6 +1020,7 @@ int arts_boxcar_snr(arts_plan_t p, const int32_t* series, int32_t nbeam, int64_t
 int arts_candidates(arts_plan_t p, const int32_t* series, int32_t nbeam, int64_t L,
                     float threshold, int64_t t_offset, int32_t beam_offset,
                     arts_candidate* host_out, int64_t capacity, int64_t* count, void* stream) {
+  TraceRange range("arts_candidates");
   if (int st = check_plan(p)) return st;
   if (!series || nbeam < 1 || !count || capacity < 0 || (capacity > 0 && !host_out))
     return fail(ARTS_E_INVAL, "bad pointer or size");

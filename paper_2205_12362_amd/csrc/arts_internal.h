@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
 #include <map>
@@ -12,6 +13,15 @@
 #include "../../include/arts.h"
 
 namespace arts {
+
+// A named range on the ROCTx marker timeline (seen by rocprofv3 --marker-trace) for the span
+// of a host call: each chunk step of streams and servers is bracketed by one.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Dedispersion kernel shapes compiled into the library.  A workgroup of `waves` wave64s owns
 // `waves * acc` consecutive DM trials and one time tile of 64 * j * spd output samples; each

@@ -1410,6 +1410,10 @@ BatchBuffers::~BatchBuffers() {
 int launch_dedisperse_batch(arts_plan_s* const* plans, const DedispJob* jobs, int n,
                             BatchBuffers& bb, hipStream_t s) {
   if (n <= 0) return ARTS_OK;
+  // a single job: the one-launch kernel, whose workgroups retire tile by tile, so that work
+  // queued on another HIP stream (a concurrent serving tick) gets compute units as they free up
+  // instead of waiting for a persistent grid to drain its queue
+  if (n == 1) return launch_dedisperse(plans[0], jobs[0], s);
   const int variant = plans[0]->tiling.variant;
   for (int i = 1; i < n; ++i)
     if (plans[i]->tiling.variant != variant)

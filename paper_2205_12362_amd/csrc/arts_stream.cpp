@@ -467,6 +467,7 @@ int arts_stream_input(arts_stream_t s, uint8_t** chunk_buffer) {
 }
 
 int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
+  TraceRange range("arts_stream_push");
   if (!s) return fail(ARTS_E_INVAL, "stream is NULL");
   if (s->pushed != s->waited)
     return fail(ARTS_E_STATE, "the previous chunk has not been collected with arts_stream_wait");
@@ -527,6 +528,7 @@ int arts_stream_push(arts_stream_t s, const uint8_t* chunk, void* stream) {
 
 int arts_stream_wait(arts_stream_t s, arts_candidate* host_out, int64_t capacity, int64_t* count,
                      int64_t* chunk_index) {
+  TraceRange range("arts_stream_wait");
   if (!s || !count) return fail(ARTS_E_INVAL, "NULL argument");
   if (s->pushed == s->waited) return fail(ARTS_E_STATE, "nothing pushed");
   ARTS_HIP(hipEventSynchronize(s->ev_done));

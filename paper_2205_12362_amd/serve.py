@@ -1,10 +1,15 @@
 """Real-time serving driver: streams whose chunks are released at the real-time rate (one
 chunk of `chunk` samples every chunk * tsamp seconds per stream) are admitted into the
-continuous-batching engine (libarts' arts_server) as the HBM budget allows; every engine turn
-submits whatever chunks have been released, runs one batched step and collects the results.
-Chunk latency = time the candidates are back on the host minus the chunk's release time.
+continuous-batching engine (libarts' arts_server) as the HBM budget allows.  The loop never
+blocks on the GPU: every turn it admits streams, submits each chunk as soon as it is released
+and steps it at once (arts_server_tick returns after enqueueing; ticks alternate between the
+engine's two compute lanes, so a chunk released while another tick runs is stepped beside it),
+and collects each stream as soon as arts_server_poll reports its step done.
+Chunk latency = time the candidates are back on the host minus the chunk's release time; a
+chunk is late when that exceeds its deadline (by default one chunk duration: the next chunk
+of the stream is then already due).
 
-    python -m paper_2205_12362_amd.serve --seconds 20
+    python -m paper_2205_12362_amd.serve --seconds 20 [--contention] [--lanes 1]
 """
 from __future__ import annotations
 
@@ -19,6 +24,34 @@ import numpy as np
 from . import arts, synth
 
 
+class LatencyBook:
+    """Per-stream chunk latencies against a deadline (seconds after release)."""
+
+    def __init__(self, deadline: float):
+        if not deadline > 0:
+            raise ValueError("deadline must be positive")
+        self.deadline = deadline
+        self.latencies = []
+        self.late = 0
+
+    def record(self, release: float, receipt: float) -> float:
+        if receipt < release:
+            raise ValueError("receipt before release")
+        lat = receipt - release
+        self.latencies.append(lat)
+        if lat > self.deadline:
+            self.late += 1
+        return lat
+
+    def summary(self) -> dict:
+        lat = np.array(self.latencies) * 1e3
+        return {"chunks": int(lat.size),
+                "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+                "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+                "max_ms": float(lat.max()) if lat.size else None,
+                "late": self.late, "deadline_ms": self.deadline * 1e3}
+
+
 @dataclass
 class StreamSpec:
     """A stream to serve: its plans (Workloads), source rows, optional SB table, chunk length,
@@ -31,33 +64,40 @@ class StreamSpec:
     sb_table: np.ndarray | None = None
     start: float = 0.0
     threshold: float = 8.0
-    latencies: list = field(default_factory=list)
+    book: LatencyBook | None = None
     ncand: int = 0
+    results: list = field(default_factory=list)
 
 
-def serve(specs, seconds: float, budget_bytes: int, log=None):
-    """Serve the streams for `seconds` of wall-clock time; returns per-stream latency stats."""
+def serve(specs, seconds: float, budget_bytes: int, log=None, lanes: int = 2,
+          keep_results: bool = False):
+    """Serve the streams for `seconds` of wall-clock time; returns per-stream latency stats
+    (and, with keep_results, each stream's candidate arrays in spec.results)."""
     import torch
     tsamp = synth.TSAMP
     plans = {s.name: [arts.Plan.from_workload(w) for w in s.workloads] for s in specs}
     pinned = {s.name: [torch.from_numpy(c).pin_memory() for c in s.pool] for s in specs}
     tables = {s.name: (torch.from_numpy(s.sb_table).cuda() if s.sb_table is not None else None)
               for s in specs}
+    for s in specs:
+        s.book = LatencyBook(s.chunk * tsamp)
     srv = arts.Server(budget_bytes)
+    srv.set_lanes(lanes)
     sid, nsub, pending = {}, {}, {}
     waiting = list(specs)
-    rejected = 0
+    rejected = ticks = 0
     t0 = time.perf_counter()
     next_log = 10.0
     try:
         while True:
             now = time.perf_counter() - t0
             if log is not None and now >= next_log:
-                log(f"{now:.0f} s: " + ", ".join(f"{s.name} {len(s.latencies)} chunks"
+                log(f"{now:.0f} s: " + ", ".join(f"{s.name} {len(s.book.latencies)} chunks"
                                                  for s in specs))
                 next_log += 10.0
             if now >= seconds and not pending:
                 break
+            busy = False
             # admission: streams whose start time has come, while the budget allows
             for s in list(waiting):
                 if now < s.start:
@@ -71,7 +111,8 @@ def serve(specs, seconds: float, budget_bytes: int, log=None):
                     if e.status != arts.ARTS_E_BUDGET:
                         raise
                     rejected += 1
-            # submit every released chunk (one in flight per stream)
+            # submit every released chunk (one in flight per stream) and step them at once
+            submitted = 0
             for s in specs:
                 if s.name not in sid or s.name in pending:
                     continue
@@ -81,27 +122,33 @@ def serve(specs, seconds: float, budget_bytes: int, log=None):
                     srv.submit(sid[s.name], pinned[s.name][k % len(s.pool)])
                     pending[s.name] = release
                     nsub[s.name] = k + 1
-            if not pending:
-                time.sleep(0.0005)
-                continue
-            srv.tick()
+                    submitted += 1
+            if submitted:
+                srv.tick()
+                ticks += 1
+                busy = True
+            # collect whatever has finished, without blocking
             for name in list(pending):
+                if not srv.poll(sid[name]):
+                    continue
                 cands, _ = srv.collect(sid[name])
                 t = time.perf_counter() - t0
                 spec = next(s for s in specs if s.name == name)
-                spec.latencies.append(t - pending.pop(name))
+                spec.book.record(pending.pop(name), t)
                 spec.ncand += len(cands)
+                if keep_results:
+                    spec.results.append(cands)
+                busy = True
+            if not busy:
+                time.sleep(0.0002)
     finally:
         srv.close()
     out = {}
     for s in specs:
-        lat = np.array(s.latencies) * 1e3
-        out[s.name] = {"chunks": int(lat.size),
-                       "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
-                       "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
-                       "max_ms": float(lat.max()) if lat.size else None,
-                       "candidates": s.ncand}
+        out[s.name] = dict(s.book.summary(), candidates=s.ncand)
     out["_admission_retries"] = rejected
+    out["_ticks"] = ticks
+    out["_lanes"] = lanes
     return out
 
 
@@ -120,6 +167,16 @@ def default_specs(seed=7):
                            [1 << k for k in range(9)])
         spool = [synth.noise((1, nchan, 6250), seed=seed + 10 + i) for i in range(2)]
         specs.append(StreamSpec(name, [w], 1, 6250, spool, start=start))
+    return specs
+
+
+def contention_specs(seed=7):
+    """The default streams, with the two small streams' chunks released inside the 71-SB
+    stream's steps: the 0.512 s chunks of b384 are released 30 ms and those of b768 60 ms after
+    a 1.024 s boundary every second chunk, while the 71-SB step (about 0.1 s) is on the GPU."""
+    specs = default_specs(seed)
+    for s, off in zip(specs[1:], (0.030, 0.060)):
+        s.start = 1.024 + off
     return specs
 
 
@@ -166,14 +223,20 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--compare-batching", action="store_true",
                     help="time one-stream-per-tick against one batched tick (71 SB streams)")
+    ap.add_argument("--contention", action="store_true",
+                    help="release the small streams' chunks while the 71-SB step runs")
+    ap.add_argument("--lanes", type=int, default=2, choices=[1, 2],
+                    help="engine compute lanes (1: every tick waits behind the previous one)")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     if args.compare_batching:
         print(json.dumps(compare_batching(budget_bytes=int(args.budget_gb * 2**30))))
         return
-    res = serve(default_specs(), args.seconds, int(args.budget_gb * 2**30),
-                log=lambda m: print(m, file=sys.stderr, flush=True))
+    specs = contention_specs() if args.contention else default_specs()
+    res = serve(specs, args.seconds, int(args.budget_gb * 2**30),
+                log=lambda m: print(m, file=sys.stderr, flush=True), lanes=args.lanes)
+    res["_scenario"] = "contention" if args.contention else "default"
     print(json.dumps(res))
 
 

@@ -112,3 +112,68 @@ def test_server_admission_budget():
         assert e.value.status == arts.ARTS_E_STATE
         srv.tick()
         srv.collect(b)
+
+
+def test_server_overlapping_ticks_same_results():
+    # a chunk submitted while another stream's tick is still in flight is stepped at once (on
+    # the other compute lane) and both streams' results equal standalone streams; with one lane
+    # the same calls give the same results.  The big stream's chunks come from pinned host
+    # memory (the asynchronous copy path).
+    import torch
+    ws, nsrc, chunk = _stream_a()
+    wb = _spec(128, np.arange(0, 100, 0.5), [1, 2, 4], 1, 2000)
+    chunks_a = _chunks(nsrc, 64, chunk, 6, seed=310)
+    chunks_b = [synth.noise((2, 128, 2000), seed=950 + k) for k in range(6)]
+    out = {}
+    for lanes in (2, 1):
+        res_a, res_b = [], []
+        with arts.Server(8 << 30) as srv:
+            srv.set_lanes(lanes)
+            pa = [arts.Plan.from_workload(w) for w in ws]
+            pb = [arts.Plan.from_workload(wb)]
+            a = srv.open(pa, nsrc, chunk, 6.0)
+            b = srv.open(pb, 2, 2000, 7.0)
+            assert srv.poll(a) and srv.poll(b)       # nothing in flight
+            for k in range(6):
+                host = torch.from_numpy(chunks_a[k]).pin_memory()
+                srv.submit(a, host)
+                assert not srv.poll(a)               # submitted, not yet stepped
+                assert srv.tick() == 1
+                srv.submit(b, to_dev(chunks_b[k]))   # while a's step may still run
+                assert srv.tick() == 1
+                # collect in the order they finish, polling
+                left = {a, b}
+                while left:
+                    for sid in list(left):
+                        if srv.poll(sid):
+                            cands, idx = srv.collect(sid)
+                            assert idx == k
+                            ser = [srv.series(sid, p).cpu().numpy().copy()
+                                   for p in range(2 if sid == a else 1)]
+                            (res_a if sid == a else res_b).append((ser, cands))
+                            left.discard(sid)
+                del host
+        out[lanes] = (res_a, res_b)
+    # standalone streams fed the same chunks
+    for which, (wl, ns, ch, thr, chunks) in enumerate(((ws, nsrc, chunk, 6.0, chunks_a),
+                                                       ([wb], 2, 2000, 7.0, chunks_b))):
+        plans = [arts.Plan.from_workload(w) for w in wl]
+        with arts.Stream(plans, ns, ch, thr) as st:
+            for k, c in enumerate(chunks):
+                st.push(to_dev(c))
+                cands, _ = st.wait()
+                for lanes in (2, 1):
+                    ser, cs = out[lanes][which][k]
+                    for p in range(len(plans)):
+                        assert np.array_equal(st.series(p).cpu().numpy(), ser[p]), (lanes, k, p)
+                    assert np.array_equal(cands, cs), (lanes, k)
+
+
+def test_server_poll_and_lane_arguments():
+    with arts.Server(1 << 30) as srv:
+        with pytest.raises(arts.ArtsError) as e:
+            srv.set_lanes(3)
+        assert e.value.status == arts.ARTS_E_INVAL
+        with pytest.raises(arts.ArtsError) as e:
+            srv.poll(12345)
+        assert e.value.status == arts.ARTS_E_INVAL
