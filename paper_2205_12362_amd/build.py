@@ -76,5 +76,39 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized_host(driver_src: str, out_exe: str) -> str:
+    """A CPU executable of `driver_src` linked with the library's host code built under
+    AddressSanitizer and UndefinedBehaviorSanitizer (the .cpp host sources recompiled with the
+    sanitizers; the .hip objects of the normal build, whose device code is never run on the
+    CPU, linked as they are).  Used by the CPU test suite."""
+    hipcc = _hipcc()
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    hip_srcs, cpp_srcs = sources()
+    hip_objs = [os.path.join(BUILD, os.path.basename(x) + ".o") for x in hip_srcs]
+    if not all(os.path.exists(o) for o in hip_objs):
+        build()
+    work = os.path.dirname(os.path.abspath(out_exe))
+    san = ["-g", "-O1", "-fno-omit-frame-pointer"]
+    jobs = []
+    for src in cpp_srcs:
+        obj = os.path.join(work, os.path.basename(src) + ".asan.o")
+        # host-only compilation (-x c++): the sanitizers instrument host code only
+        jobs.append([hipcc, "-c", "-x", "c++", *COMMON, *san, "-Xarch_host", "-fsanitize=address",
+                     "-Xarch_host", "-fsanitize=undefined", "-D__HIP_PLATFORM_AMD__",
+                     f"-I{rocm}/include", src, "-o", obj])
+    # the driver and the link use ROCm's host clang (the sanitizer runtimes must match the
+    # compiler that instrumented the objects)
+    clang = os.path.join(rocm, "llvm", "bin", "clang++")
+    drv_obj = os.path.join(work, "driver.asan.o")
+    jobs.append([clang, "-c", "-std=c++17", *san, "-fsanitize=address,undefined",
+                 f"-I{os.path.join(PKG, '..', 'include')}", driver_src, "-o", drv_obj])
+    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        list(ex.map(_run, jobs))
+    objs = [j[-1] for j in jobs]
+    _run([clang, "-fsanitize=address,undefined", *objs, *hip_objs, f"-L{rocm}/lib",
+          "-lamdhip64", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{rocm}/lib", "-o", out_exe])
+    return out_exe
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
