@@ -14,7 +14,9 @@ namespace arts {
 // ------------------------------------------------------------------ tiling variants ----
 // id, spd, j, acc, waves, pack.  j is odd so the lane stride of j dwords hits distinct LDS
 // banks; pack: 0 plain, 1 packed 16-bit partial sums, 2 framed, 3 packed halves held across
-// chunks, 4 group sums (split plans), 5 DM pairs read as one window (16-bit samples).
+// chunks, 4 group sums (split plans), 5 DM pairs read as one window (16-bit samples), 7 framed
+// runs (raw-dword frames per sub-dword class, added into the totals at the end of each run),
+// 8 framed runs with four channels per step and the offsets prefetched.
 #define ARTS_TILINGS(X)                                                                    \
   X(0, 4, 5, 4, 8, 0)   /* 32 DMs x 1280 samples per block, 80 accumulators per lane */    \
   X(1, 4, 7, 3, 8, 0)   /* 24 DMs x 1792 */                                                \
@@ -42,7 +44,10 @@ namespace arts {
   X(23, 4, 5, 4, 8, 4)  /* 32 DMs x 1280, group sums in packed halves (split plans) */     \
   X(24, 2, 5, 4, 8, 5)  /* downsampled, DM pairs: 32 DMs x 640 */                          \
   X(25, 2, 7, 2, 8, 5)  /* downsampled, DM pairs: 16 DMs x 896 */                          \
-  X(26, 2, 9, 2, 8, 5)  /* downsampled, DM pairs: 16 DMs x 1152 */
+  X(26, 2, 9, 2, 8, 5)  /* downsampled, DM pairs: 16 DMs x 1152 */                         \
+  X(27, 4, 5, 4, 8, 7)  /* framed runs: 32 DMs x 1280 */                                   \
+  X(28, 4, 5, 3, 8, 7)  /* framed runs: 24 DMs x 1280 */                                   \
+  X(29, 4, 5, 3, 8, 8)  /* as 28, four channels per step with the offsets prefetched */
 
 const TileVariant kVariants[] = {
 #define ARTS_X(id, spd, j, acc, waves, pack) {spd, j, acc, waves, pack},
@@ -79,9 +84,17 @@ int split_variant(int64_t ncoarse) {
   return ncoarse % 16 == 0 ? 22 : packed_variant(ncoarse);
 }
 
+// Byte samples, plain plans: framed runs with 32 DMs per block (27) unless 24 per block (29)
+// leaves fewer idle DM slots; a slot of 29 costs about 0.5% more than one of 27 (serving plan:
+// 77.2 ms for 2064 slots against 76.3 ms for 2048).
+int runs_variant(int64_t ndm) {
+  const int64_t s24 = (ndm + 23) / 24 * 24, s32 = (ndm + 31) / 32 * 32;
+  return s24 * 1005 < s32 * 1000 ? 29 : 27;
+}
+
 int default_variant(int downsample, int64_t ndm) {
   if (downsample > 1) return 24;
-  return ndm <= 64 ? 17 : packed_variant(ndm);
+  return ndm <= 64 ? 17 : runs_variant(ndm);
 }
 
 // The tiling to try when the default does not fit a plan (DM-pair tilings need neighbouring
@@ -578,6 +591,110 @@ __device__ __forceinline__ void flush_fr(uint32_t* acc, uint32_t* A, uint32_t* O
   }
 }
 
+// ---- framed runs (spd = 4).  The channels of one sub-dword class MS form a run (the plan sorts
+// them so); within a run the raw dwords are summed into a frame A (byte lanes overlap in the
+// 32-bit sum) and their odd bytes, moved into 16-bit halves by one v_perm_b32, into O, two
+// channels per v_add3_u32: 2 instructions per 4 samples instead of the packed sums' 3.  The
+// first channels of the run initialise the frame, so nothing is cleared.  At the end of the
+// run the frame is exact (a run has at most 255 channels, so every half stays below 2^16):
+// E = A - (O << 8) holds the even bytes' sums, and E and O are added into the int32 totals
+// directly (one SDWA add per output), so no packed halves persist between runs or chunks.
+__device__ __forceinline__ uint32_t even_sums(uint32_t a, uint32_t o) {
+  // a - 256 o (mod 2^32) in one instruction: the 24-bit product only needs o's low 24 bits
+  uint32_t r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(o), "v"(-256), "v"(a));
+  return r;
+}
+
+// Add frame MS (NW = J or J + 1 words) into the lane's int32 totals: byte j of word k is output
+// 4k + j - MS; outputs outside the lane's T = 4J samples belong to no total of this lane.
+template <int J, int MS>
+__device__ __forceinline__ void frame_to_totals(uint32_t* acc, const uint32_t* A,
+                                                const uint32_t* O) {
+  constexpr int NW = (MS == 0) ? J : J + 1;
+  constexpr int T = 4 * J;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int i0 = 4 * k - MS;
+    const bool even_used = (i0 >= 0 && i0 < T) || (i0 + 2 >= 0 && i0 + 2 < T);
+    if (even_used) {
+      const uint32_t e = even_sums(A[k], O[k]);
+      if (i0 >= 0 && i0 < T) add_half<0>(acc[i0], e);
+      if (i0 + 2 >= 0 && i0 + 2 < T) add_half<1>(acc[i0 + 2], e);
+    }
+    if (i0 + 1 >= 0 && i0 + 1 < T) add_half<0>(acc[i0 + 1], O[k]);
+    if (i0 + 3 >= 0 && i0 + 3 < T) add_half<1>(acc[i0 + 3], O[k]);
+  }
+}
+
+template <int NW>
+__device__ __forceinline__ void load_words(uint32_t* w, const uint8_t* lane_base, int32_t off) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + off);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) w[k] = p[k];
+}
+
+template <int J, int MS, bool PF = false>
+__device__ __forceinline__ void accum_frame_run(uint32_t* acc, const int32_t* ent, int n,
+                                                const uint8_t* lane_base) {
+  if (n == 0) return;
+  constexpr int NW = (MS == 0) ? J : J + 1;
+  uint32_t A[NW], O[NW];
+  int i;
+  if (n >= 2) {
+    uint32_t w[2][NW];
+    load_words<NW>(w[0], lane_base, ent[0]);
+    load_words<NW>(w[1], lane_base, ent[1]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      A[k] = w[0][k] + w[1][k];
+      O[k] = odd_bytes(w[0][k]) + odd_bytes(w[1][k]);
+    }
+    i = 2;
+  } else {
+    uint32_t w[NW];
+    load_words<NW>(w, lane_base, ent[0]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      A[k] = w[k];
+      O[k] = odd_bytes(w[k]);
+    }
+    i = 1;
+  }
+  if (PF && i + 4 <= n) {
+    // four channels per step, the next step's offsets read while this step's words are summed
+    // (the lists' pad words keep that read in bounds at the end of the last run)
+    int32_t q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = ent[i + u];
+    for (; i + 4 <= n; i += 4) {
+      uint32_t w[4][NW];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) load_words<NW>(w[u], lane_base, q[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = ent[i + 4 + u];
+      add_fr<NW>(A, O, w[0], w[1]);
+      add_fr<NW>(A, O, w[2], w[3]);
+    }
+  }
+  for (; i + 2 <= n; i += 2) {
+    uint32_t w[2][NW];
+    load_words<NW>(w[0], lane_base, ent[i]);
+    load_words<NW>(w[1], lane_base, ent[i + 1]);
+    add_fr<NW>(A, O, w[0], w[1]);
+  }
+  if (i < n) {
+    uint32_t w[NW];
+    load_words<NW>(w, lane_base, ent[i]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      A[k] += w[k];
+      O[k] += odd_bytes(w[k]);
+    }
+  }
+  frame_to_totals<J, MS>(acc, A, O);
+}
+
 typedef __attribute__((address_space(1))) const void* global_ptr_t;
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
@@ -938,6 +1055,14 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
           accum_run_pk<J, 1, PF>(he[x], ho[x], ent + n0, n1, lane_base);
           accum_run_pk<J, 2, PF>(he[x], ho[x], ent + n0 + n1, n2, lane_base);
           accum_run_pk<J, 3, PF>(he[x], ho[x], ent + n0 + n1 + n2, n3, lane_base);
+        } else if constexpr (PK == 7 || PK == 8) {
+          static_assert(SPD == 4, "framed runs are for byte samples");
+          const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
+          constexpr bool PF = PK == 8;
+          accum_frame_run<J, 0, PF>(acc[x], ent, n0, lane_base);
+          accum_frame_run<J, 1, PF>(acc[x], ent + n0, n1, lane_base);
+          accum_frame_run<J, 2, PF>(acc[x], ent + n0 + n1, n2, lane_base);
+          accum_frame_run<J, 3, PF>(acc[x], ent + n0 + n1 + n2, n3, lane_base);
         } else if constexpr (PK == 5) {
           // DM pairs: trials (x, x + 1) of the wave at even x; odd x have been summed
           static_assert(SPD == 2 && ACC % 2 == 0, "DM pairs are for 16-bit samples");
