@@ -939,7 +939,7 @@ int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
     return fail(ARTS_E_INVAL, "bad variant or buffer");
   const TileVariant& v = kVariants[variant];
   snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d%s", v.j, v.acc, v.waves, v.spd,
-           v.pack == 8   ? " framed runs prefetch"
+           v.pack == 9   ? " framed runs shared"
            : v.pack == 7 ? " framed runs"
            : v.pack == 5 ? " pairs"
            : v.pack == 4 ? " group sums"

@@ -30,6 +30,11 @@ struct TraceRange {
 struct TileVariant {
   int spd, j, acc, waves, pack;
 };
+// Outputs of one time tile: 64 lanes of t, less the 4 that a tiling whose lanes share their last
+// dword (pack 9) leaves to the next tile.
+constexpr __host__ __device__ int tile_outputs(int t, int pack) {
+  return 64 * t - (pack == 9 ? 4 : 0);
+}
 extern const TileVariant kVariants[];
 extern const int kNumVariants;
 int default_variant(int downsample, int64_t ndm);

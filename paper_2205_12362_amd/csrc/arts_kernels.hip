@@ -16,7 +16,8 @@ namespace arts {
 // banks; pack: 0 plain, 1 packed 16-bit partial sums, 2 framed, 3 packed halves held across
 // chunks, 4 group sums (split plans), 5 DM pairs read as one window (16-bit samples), 7 framed
 // runs (raw-dword frames per sub-dword class, added into the totals at the end of each run),
-// 8 framed runs with four channels per step and the offsets prefetched.
+// 9 framed runs whose lanes read J dwords per channel and take the sums of their last dword
+// from the next lane (a tile then covers 64 T - 4 outputs).
 #define ARTS_TILINGS(X)                                                                    \
   X(0, 4, 5, 4, 8, 0)   /* 32 DMs x 1280 samples per block, 80 accumulators per lane */    \
   X(1, 4, 7, 3, 8, 0)   /* 24 DMs x 1792 */                                                \
@@ -46,8 +47,8 @@ namespace arts {
   X(25, 2, 7, 2, 8, 5)  /* downsampled, DM pairs: 16 DMs x 896 */                          \
   X(26, 2, 9, 2, 8, 5)  /* downsampled, DM pairs: 16 DMs x 1152 */                         \
   X(27, 4, 5, 4, 8, 7)  /* framed runs: 32 DMs x 1280 */                                   \
-  X(28, 4, 5, 3, 8, 7)  /* framed runs: 24 DMs x 1280 */                                   \
-  X(29, 4, 5, 3, 8, 8)  /* as 28, four channels per step with the offsets prefetched */
+  X(28, 4, 5, 4, 8, 9)  /* framed runs, last word shared: 32 DMs x 1276 */                 \
+  X(29, 4, 5, 3, 8, 9)  /* framed runs, last word shared: 24 DMs x 1276 */
 
 const TileVariant kVariants[] = {
 #define ARTS_X(id, spd, j, acc, waves, pack) {spd, j, acc, waves, pack},
@@ -84,12 +85,12 @@ int split_variant(int64_t ncoarse) {
   return ncoarse % 16 == 0 ? 22 : packed_variant(ncoarse);
 }
 
-// Byte samples, plain plans: framed runs with 32 DMs per block (27) unless 24 per block (29)
-// leaves fewer idle DM slots; a slot of 29 costs about 0.5% more than one of 27 (serving plan:
-// 77.2 ms for 2064 slots against 76.3 ms for 2048).
+// Byte samples, plain plans: framed runs with a shared last word, 32 DMs per block (28) unless
+// 24 per block (29) leaves fewer idle DM slots; a slot of 29 costs about 3% more than one of 28
+// (serving plan: 74.5 ms for 2064 slots against 71.6 ms for 2048).
 int runs_variant(int64_t ndm) {
   const int64_t s24 = (ndm + 23) / 24 * 24, s32 = (ndm + 31) / 32 * 32;
-  return s24 * 1005 < s32 * 1000 ? 29 : 27;
+  return s24 * 103 < s32 * 100 ? 29 : 28;
 }
 
 int default_variant(int downsample, int64_t ndm) {
@@ -608,22 +609,35 @@ __device__ __forceinline__ uint32_t even_sums(uint32_t a, uint32_t o) {
 
 // Add frame MS (NW = J or J + 1 words) into the lane's int32 totals: byte j of word k is output
 // 4k + j - MS; outputs outside the lane's T = 4J samples belong to no total of this lane.
-template <int J, int MS>
+//
+// SH (shared last word): dword J of a lane's window is dword 0 of the next lane's, so for
+// MS > 0 the lane sums only J dwords and takes the finished sums of dword J from lane + 1 (two
+// ds_bpermute per run).  Lane 63 gets lane 0's instead: its last MS outputs are wrong, and the
+// tile leaves its last 4 outputs to the next tile.
+template <int J, int MS, bool SH = false>
 __device__ __forceinline__ void frame_to_totals(uint32_t* acc, const uint32_t* A,
                                                 const uint32_t* O) {
   constexpr int NW = (MS == 0) ? J : J + 1;
+  constexpr int NR = (MS == 0 || SH) ? J : J + 1;  // words summed by this lane
   constexpr int T = 4 * J;
+  uint32_t e[NW], o[NW];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    e[k] = even_sums(A[k], O[k]);
+    o[k] = O[k];
+  }
+  if constexpr (NR < NW) {
+    const int next = ((__lane_id() + 1) & 63) << 2;
+    e[J] = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(next, static_cast<int>(e[0])));
+    o[J] = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(next, static_cast<int>(o[0])));
+  }
 #pragma unroll
   for (int k = 0; k < NW; ++k) {
     const int i0 = 4 * k - MS;
-    const bool even_used = (i0 >= 0 && i0 < T) || (i0 + 2 >= 0 && i0 + 2 < T);
-    if (even_used) {
-      const uint32_t e = even_sums(A[k], O[k]);
-      if (i0 >= 0 && i0 < T) add_half<0>(acc[i0], e);
-      if (i0 + 2 >= 0 && i0 + 2 < T) add_half<1>(acc[i0 + 2], e);
-    }
-    if (i0 + 1 >= 0 && i0 + 1 < T) add_half<0>(acc[i0 + 1], O[k]);
-    if (i0 + 3 >= 0 && i0 + 3 < T) add_half<1>(acc[i0 + 3], O[k]);
+    if (i0 >= 0 && i0 < T) add_half<0>(acc[i0], e[k]);
+    if (i0 + 2 >= 0 && i0 + 2 < T) add_half<1>(acc[i0 + 2], e[k]);
+    if (i0 + 1 >= 0 && i0 + 1 < T) add_half<0>(acc[i0 + 1], o[k]);
+    if (i0 + 3 >= 0 && i0 + 3 < T) add_half<1>(acc[i0 + 3], o[k]);
   }
 }
 
@@ -634,11 +648,11 @@ __device__ __forceinline__ void load_words(uint32_t* w, const uint8_t* lane_base
   for (int k = 0; k < NW; ++k) w[k] = p[k];
 }
 
-template <int J, int MS, bool PF = false>
+template <int J, int MS, bool SH>
 __device__ __forceinline__ void accum_frame_run(uint32_t* acc, const int32_t* ent, int n,
                                                 const uint8_t* lane_base) {
   if (n == 0) return;
-  constexpr int NW = (MS == 0) ? J : J + 1;
+  constexpr int NW = (MS == 0 || SH) ? J : J + 1;
   uint32_t A[NW], O[NW];
   int i;
   if (n >= 2) {
@@ -661,22 +675,6 @@ __device__ __forceinline__ void accum_frame_run(uint32_t* acc, const int32_t* en
     }
     i = 1;
   }
-  if (PF && i + 4 <= n) {
-    // four channels per step, the next step's offsets read while this step's words are summed
-    // (the lists' pad words keep that read in bounds at the end of the last run)
-    int32_t q[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) q[u] = ent[i + u];
-    for (; i + 4 <= n; i += 4) {
-      uint32_t w[4][NW];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) load_words<NW>(w[u], lane_base, q[u]);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) q[u] = ent[i + 4 + u];
-      add_fr<NW>(A, O, w[0], w[1]);
-      add_fr<NW>(A, O, w[2], w[3]);
-    }
-  }
   for (; i + 2 <= n; i += 2) {
     uint32_t w[2][NW];
     load_words<NW>(w[0], lane_base, ent[i]);
@@ -692,7 +690,7 @@ __device__ __forceinline__ void accum_frame_run(uint32_t* acc, const int32_t* en
       O[k] += odd_bytes(w[k]);
     }
   }
-  frame_to_totals<J, MS>(acc, A, O);
+  frame_to_totals<J, MS, SH>(acc, A, O);
 }
 
 typedef __attribute__((address_space(1))) const void* global_ptr_t;
@@ -763,8 +761,9 @@ __device__ __forceinline__ void stage_lists(const DedispArgs& a, const int32_t* 
   }
 }
 
-// Store a lane's sums of ACC DM trials (rows dwave0 + x) for outputs t0 + lane*T + i < nout;
-// off: output elements added (the channel group of split plans).
+// Store a lane's sums of ACC DM trials (rows dwave0 + x) for outputs t0 + lane*T + i < tend
+// (the end of the tile or of the row); off: output elements added (the channel group of split
+// plans).
 // A lane's N consecutive int32 sums to p, where p is M dwords past a 16-byte boundary (VW = 4)
 // or M dwords past an 8-byte boundary (VW = 2): scalar stores up to the boundary, then vector
 // stores, then the remainder.
@@ -790,7 +789,7 @@ __device__ __forceinline__ void store_run(int32_t* p, const uint32_t* v) {
 template <int T, int ACC, bool OUT16>
 __device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (*acc)[T],
                                            int64_t off, int b, int dwave0, int64_t t0,
-                                           int lane) {
+                                           int64_t tend, int lane) {
 #pragma unroll
   for (int x = 0; x < ACC; ++x) {
     const int d = dwave0 + x;
@@ -803,7 +802,7 @@ __device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (
         static_assert(T % 4 == 0, "16-bit group stores need T % 4 == 0");
         uint16_t* o = reinterpret_cast<uint16_t*>(a.out) + row;
         const int64_t tl = t0 + static_cast<int64_t>(lane) * T;
-        if (tl + T <= a.nout && (reinterpret_cast<uintptr_t>(o + tl) & 7u) == 0) {
+        if (tl + T <= tend && (reinterpret_cast<uintptr_t>(o + tl) & 7u) == 0) {
           uint2* q = reinterpret_cast<uint2*>(o + tl);
 #pragma unroll
           for (int k = 0; k < T / 4; ++k)
@@ -812,7 +811,7 @@ __device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (
         } else {
 #pragma unroll
           for (int i = 0; i < T; ++i)
-            if (tl + i < a.nout) o[tl + i] = static_cast<uint16_t>(acc[x][i]);
+            if (tl + i < tend) o[tl + i] = static_cast<uint16_t>(acc[x][i]);
         }
       } else {
         // lanes are T dwords apart, a multiple of 16 bytes for T % 4 == 0 (8 bytes for even
@@ -821,7 +820,7 @@ __device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (
         const int64_t tl = t0 + static_cast<int64_t>(lane) * T;
         int32_t* p = o + tl;
         const int mis = static_cast<int>((reinterpret_cast<uintptr_t>(p) >> 2) & 3);
-        if (tl + T <= a.nout) {
+        if (tl + T <= tend) {
           if constexpr (T % 4 == 0) {
             switch (mis) {
               case 0: store_run<T, 4, 0>(p, acc[x]); break;
@@ -841,7 +840,7 @@ __device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (
         } else {
 #pragma unroll
           for (int i = 0; i < T; ++i)
-            if (tl + i < a.nout) p[i] = static_cast<int32_t>(acc[x][i]);
+            if (tl + i < tend) p[i] = static_cast<int32_t>(acc[x][i]);
         }
       }
     }
@@ -891,7 +890,7 @@ template <int SPD, int J, int ACC, int WAVES, int PK, bool SPLIT = false>
 __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, int tt, int b,
                                                 uint32_t* lds) {
   constexpr int T = SPD * J;
-  constexpr int TT = 64 * T;
+  constexpr int TT = tile_outputs(T, PK);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // LDS: two buffers, each cc windows of win dwords followed by the chunk's offset lists and
@@ -899,6 +898,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   const int buf_words = a.cc * a.win + a.m_blk * a.cc + 4;
   uint8_t* sbrow = reinterpret_cast<uint8_t*>(lds + a.nbuf * buf_words);
   const int64_t t0 = static_cast<int64_t>(tt) * TT;
+  const int64_t tend = min(a.nout, t0 + TT);  // outputs this tile stores
   const int dwave0 = blk * a.m_blk + wave * ACC;
   const bool wave_active = dwave0 < a.ndm;
 
@@ -968,7 +968,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
             for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
           }
           store_tile<T, ACC, true>(a, acc, (c0 / a.split - 1) * a.out_sstride, b, dwave0, t0,
-                                   lane);
+                                   tend, lane);
 #pragma unroll
           for (int x = 0; x < ACC; ++x)
 #pragma unroll
@@ -1055,14 +1055,14 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
           accum_run_pk<J, 1, PF>(he[x], ho[x], ent + n0, n1, lane_base);
           accum_run_pk<J, 2, PF>(he[x], ho[x], ent + n0 + n1, n2, lane_base);
           accum_run_pk<J, 3, PF>(he[x], ho[x], ent + n0 + n1 + n2, n3, lane_base);
-        } else if constexpr (PK == 7 || PK == 8) {
+        } else if constexpr (PK == 7 || PK == 9) {
           static_assert(SPD == 4, "framed runs are for byte samples");
           const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
-          constexpr bool PF = PK == 8;
-          accum_frame_run<J, 0, PF>(acc[x], ent, n0, lane_base);
-          accum_frame_run<J, 1, PF>(acc[x], ent + n0, n1, lane_base);
-          accum_frame_run<J, 2, PF>(acc[x], ent + n0 + n1, n2, lane_base);
-          accum_frame_run<J, 3, PF>(acc[x], ent + n0 + n1 + n2, n3, lane_base);
+          constexpr bool SH = PK == 9;
+          accum_frame_run<J, 0, SH>(acc[x], ent, n0, lane_base);
+          accum_frame_run<J, 1, SH>(acc[x], ent + n0, n1, lane_base);
+          accum_frame_run<J, 2, SH>(acc[x], ent + n0 + n1, n2, lane_base);
+          accum_frame_run<J, 3, SH>(acc[x], ent + n0 + n1 + n2, n3, lane_base);
         } else if constexpr (PK == 5) {
           // DM pairs: trials (x, x + 1) of the wave at even x; odd x have been summed
           static_assert(SPD == 2 && ACC % 2 == 0, "DM pairs are for 16-bit samples");
@@ -1126,7 +1126,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
           for (int x = 0; x < ACC; ++x) flush_pk<J>(acc[x], he[x], ho[x]);
         }
         store_tile<T, ACC, true>(a, acc, (a.nchan / a.split - 1) * a.out_sstride, b, dwave0,
-                                 t0, lane);
+                                 t0, tend, lane);
       }
     }
   }
@@ -1145,7 +1145,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
       }
     }
     if constexpr (PK != 4)  // group-sum variants run split plans only
-      store_tile<T, ACC, false>(a, acc, 0, b, dwave0, t0, lane);
+      store_tile<T, ACC, false>(a, acc, 0, b, dwave0, t0, tend, lane);
   }
 }
 
@@ -1396,8 +1396,8 @@ static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
   a.win = t.win_dwords;
   a.cc = t.cc;
   a.nchunk = t.nchunk;
-  const int T = v.spd * v.j;
-  a.ntt = static_cast<int>((a.nout + 64 * T - 1) / (64 * T));
+  const int TT = tile_outputs(v.spd * v.j, v.pack);
+  a.ntt = static_cast<int>((a.nout + TT - 1) / TT);
   *out = a;
   return ARTS_OK;
 }
