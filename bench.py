@@ -195,15 +195,18 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(kernel):
     """HBM bytes per launch of the dominant kernel from the committed counter summary, if the
-    kernel source has not changed since the counters were taken (else None)."""
+    counters were taken on this kernel (template name as kernel_name gives it) and its source
+    has not changed since (else None)."""
     try:
         with open(PROFILE_JSON) as f:
             prof = json.load(f)
     except (OSError, ValueError):
         return None
     if prof.get("kernel_sha") != kernel_hash():
+        return None
+    if (prof.get("kernel") or "").replace(", false>", ">") != kernel:
         return None
     return prof.get("hbm_bytes_per_launch")
 
@@ -681,6 +684,9 @@ def main():
                     help="skip the single-beam configurations (128-channel beam, one Apertif "
                          "beam-chunk) timed after the serving steps")
     ap.add_argument("--variant", type=int, default=None, help="native dedispersion tiling")
+    ap.add_argument("--autotune", type=int, default=0, metavar="REPS",
+                    help="serving: autotune both plans' tile shapes before timing")
+    ap.add_argument("--tune-cache", default=None, help="tune cache file (with --autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 1 GiB twice (counter calibration)")
     ap.add_argument("--workload", choices=["serving", "uneven", "alert", "cluster", "tilings"],
@@ -728,6 +734,16 @@ def main():
     p_ds = arts.Plan.from_workload(w_ds)
     if args.variant is not None:
         p_nat.set_tiling(args.variant)
+    tuned = None
+    if args.autotune:
+        # tile shapes timed on this device for this step (all SBs, one chunk plus the halo)
+        tuned = {}
+        for name, p in (("native", p_nat), ("ds4", p_ds)):
+            nin = p.info["downsample"] * p.info["halo"] + CHUNK
+            v, ms = p.autotune(NSB, nin, args.autotune, args.tune_cache)
+            tuned[name] = {"shape": list(p.tiling_shape()), "tiling": arts.arts_tiling_describe(v),
+                           "ms": ms}
+        log(f"autotuned: {tuned}")
     if args.cluster:
         p_nat.cluster = p_ds.cluster = True
     if args.sb_table == "model":
@@ -802,10 +818,11 @@ def main():
         adds = NSB * w_nat.dms.size * CHUNK * NCHAN
         dur = phases["dedisperse_native"] * 1e-3
         achieved = adds / dur
+        kname = kernel_name(arts.arts_tiling_describe(p_nat.tiling()))
         roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_PK16_ADDS / 1e12,
                     "unit": "Tadd/s", "frac": achieved / PEAK_PK16_ADDS,
-                    "frac_int32_peak": achieved / PEAK_INT32_ADDS, "traffic": measured_traffic(),
-                    "kernel": kernel_name(arts.arts_tiling_describe(p_nat.tiling())),
+                    "frac_int32_peak": achieved / PEAK_INT32_ADDS,
+                    "traffic": measured_traffic(kname), "kernel": kname,
                     "kernel_ms": phases["dedisperse_native"],
                     "adds_per_launch": adds}
     # chunk latency as the metric defines it: release of the chunk in pinned host memory ->
@@ -843,7 +860,9 @@ def main():
                    "ndm_native": int(w_nat.dms.size), "ndm_ds4": int(w_ds.dms.size),
                    "graph": bool(args.graph), "threshold": THRESHOLD,
                    "cluster": bool(args.cluster), "rfi": bool(args.rfi),
-                   "sb_table": args.sb_table, "device_bytes": info["device_bytes"]},
+                   "sb_table": args.sb_table, "device_bytes": info["device_bytes"],
+                   "tiles": {"native": list(p_nat.tiling_shape()), "ds4": list(p_ds.tiling_shape()),
+                             "autotuned": tuned}},
         "adds_per_s": (units_nat + units_ds) * NCHAN * args.steps / elapsed,
         "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
         "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),

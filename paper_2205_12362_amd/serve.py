@@ -7,9 +7,10 @@ engine's two compute lanes, so a chunk released while another tick runs is stepp
 and collects each stream as soon as arts_server_poll reports its step done.
 Chunk latency = time the candidates are back on the host minus the chunk's release time; a
 chunk is late when that exceeds its deadline (by default one chunk duration: the next chunk
-of the stream is then already due).
+of the stream is then already due).  A producer that hands chunks over after their release
+(producer_delay) makes them late by construction: the late-chunk count is the deadline watchdog.
 
-    python -m paper_2205_12362_amd.serve --seconds 20 [--contention] [--lanes 1]
+    python -m paper_2205_12362_amd.serve --seconds 20 [--contention] [--lanes 1] [--autotune]
 """
 from __future__ import annotations
 
@@ -69,19 +70,58 @@ class StreamSpec:
     results: list = field(default_factory=list)
 
 
+class DeviceBackend:
+    """The serving loop's device side: libarts plans (optionally autotuned for the stream's step:
+    its beams and one chunk plus the plan's halo, with the tune cache at `tune_cache`), chunk
+    pools in pinned host memory, SB tables in HBM and the arts_server engine."""
+
+    def __init__(self, tune_reps: int = 0, tune_cache: str | None = None):
+        import torch
+        self.torch = torch
+        self.tune_reps = tune_reps
+        self.tune_cache = tune_cache
+        self.tuned = {}
+
+    def plans(self, spec):
+        plans = [arts.Plan.from_workload(w) for w in spec.workloads]
+        if self.tune_reps > 0:
+            nbeam = spec.sb_table.shape[0] if spec.sb_table is not None else spec.nsrc
+            for w, p in zip(spec.workloads, plans):
+                info = p.info
+                nin = info["downsample"] * info["halo"] + spec.chunk
+                v, ms = p.autotune(nbeam, nin, self.tune_reps, self.tune_cache)
+                self.tuned[f"{spec.name}/{w.name}"] = {"shape": list(p.tiling_shape()),
+                                                       "tiling": arts.arts_tiling_describe(v),
+                                                       "ms": ms}
+        return plans
+
+    def host_chunk(self, a):
+        return self.torch.from_numpy(a).pin_memory()
+
+    def table(self, t):
+        return self.torch.from_numpy(t).cuda() if t is not None else None
+
+    def server(self, budget_bytes):
+        return arts.Server(budget_bytes)
+
+
 def serve(specs, seconds: float, budget_bytes: int, log=None, lanes: int = 2,
-          keep_results: bool = False):
+          keep_results: bool = False, backend=None, producer_delay=None):
     """Serve the streams for `seconds` of wall-clock time; returns per-stream latency stats
-    (and, with keep_results, each stream's candidate arrays in spec.results)."""
-    import torch
+    (and, with keep_results, each stream's candidate arrays in spec.results).
+
+    backend: plans, chunk buffers and the engine (DeviceBackend by default).  producer_delay:
+    optional callable (stream name, chunk index) -> seconds after its release at which the
+    producer hands the chunk over (a slow producer); its latency still counts from the release."""
     tsamp = synth.TSAMP
-    plans = {s.name: [arts.Plan.from_workload(w) for w in s.workloads] for s in specs}
-    pinned = {s.name: [torch.from_numpy(c).pin_memory() for c in s.pool] for s in specs}
-    tables = {s.name: (torch.from_numpy(s.sb_table).cuda() if s.sb_table is not None else None)
-              for s in specs}
+    if backend is None:
+        backend = DeviceBackend()
+    plans = {s.name: backend.plans(s) for s in specs}
+    pinned = {s.name: [backend.host_chunk(c) for c in s.pool] for s in specs}
+    tables = {s.name: backend.table(s.sb_table) for s in specs}
     for s in specs:
         s.book = LatencyBook(s.chunk * tsamp)
-    srv = arts.Server(budget_bytes)
+    srv = backend.server(budget_bytes)
     srv.set_lanes(lanes)
     sid, nsub, pending = {}, {}, {}
     waiting = list(specs)
@@ -118,7 +158,8 @@ def serve(specs, seconds: float, budget_bytes: int, log=None, lanes: int = 2,
                     continue
                 k = nsub[s.name]
                 release = s.start + (k + 1) * s.chunk * tsamp   # chunk k complete at this time
-                if release <= now and release <= seconds:
+                handed = release + (producer_delay(s.name, k) if producer_delay else 0.0)
+                if handed <= now and release <= seconds:
                     srv.submit(sid[s.name], pinned[s.name][k % len(s.pool)])
                     pending[s.name] = release
                     nsub[s.name] = k + 1
@@ -149,6 +190,8 @@ def serve(specs, seconds: float, budget_bytes: int, log=None, lanes: int = 2,
     out["_admission_retries"] = rejected
     out["_ticks"] = ticks
     out["_lanes"] = lanes
+    if getattr(backend, "tuned", None):
+        out["_autotuned"] = backend.tuned
     return out
 
 
@@ -227,6 +270,9 @@ def main():
                     help="release the small streams' chunks while the 71-SB step runs")
     ap.add_argument("--lanes", type=int, default=2, choices=[1, 2],
                     help="engine compute lanes (1: every tick waits behind the previous one)")
+    ap.add_argument("--autotune", type=int, default=0, metavar="REPS",
+                    help="autotune every plan for its stream's step before serving")
+    ap.add_argument("--tune-cache", default=None, help="tune cache file (with --autotune)")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -235,7 +281,8 @@ def main():
         return
     specs = contention_specs() if args.contention else default_specs()
     res = serve(specs, args.seconds, int(args.budget_gb * 2**30),
-                log=lambda m: print(m, file=sys.stderr, flush=True), lanes=args.lanes)
+                log=lambda m: print(m, file=sys.stderr, flush=True), lanes=args.lanes,
+                backend=DeviceBackend(args.autotune, args.tune_cache))
     res["_scenario"] = "contention" if args.contention else "default"
     print(json.dumps(res))
 
