@@ -837,6 +837,16 @@ __device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (
 #pragma unroll
             for (int i = 0; i < T; ++i) p[i] = static_cast<int32_t>(acc[x][i]);
           }
+        } else if (T % 4 == 0 && T > 4 && tl + T - 4 == tend) {
+          // the last lane of a tile whose lanes share their last dword: T - 4 outputs
+          if constexpr (T % 4 == 0 && T > 4) {
+            switch (mis) {
+              case 0: store_run<T - 4, 4, 0>(p, acc[x]); break;
+              case 1: store_run<T - 4, 4, 1>(p, acc[x]); break;
+              case 2: store_run<T - 4, 4, 2>(p, acc[x]); break;
+              default: store_run<T - 4, 4, 3>(p, acc[x]); break;
+            }
+          }
         } else {
 #pragma unroll
           for (int i = 0; i < T; ++i)

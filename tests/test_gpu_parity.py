@@ -79,11 +79,13 @@ def test_dedisperse_variants_ragged(variant):
 
 
 @pytest.mark.parametrize("variant", [v for v in _native_variants()
-                                     if "packed" in arts.arts_tiling_describe(v)])
+                                     if "packed" in arts.arts_tiling_describe(v)
+                                     or "runs" in arts.arts_tiling_describe(v)])
 def test_packed_variants_many_channels(variant):
     # 600 channels: the 16-bit partial sums are widened more than once per tile (every staged
-    # chunk, or every 257 channels when they are held across chunks); saturated input puts
-    # every half at its largest value, random input is checked against the oracle
+    # chunk, every run of a sub-dword class, or every 257 channels when they are held across
+    # chunks); saturated input puts every half at its largest value, random input is checked
+    # against the oracle
     _say("packed variant, 600 channels", variant, arts.arts_tiling_describe(variant))
     nchan = 600
     f_lo, df = synth.band(nchan)
@@ -98,6 +100,27 @@ def test_packed_variants_many_channels(variant):
         full = p.dedisperse(to_dev(np.full((nchan, nin), 255, np.uint8))).cpu().numpy()[0]
     assert np.array_equal(got, O.dedisperse(data, delays))
     assert np.all(full == 255 * nchan)
+
+
+@pytest.mark.parametrize("variant", [v for v in _native_variants()
+                                     if "runs shared" in arts.arts_tiling_describe(v)])
+def test_shared_word_tile_edges(variant):
+    # lanes that take their last dword's sums from the next lane leave a tile's last 4 outputs
+    # to the next tile (the last lane's are wrong): output counts just below, at and above
+    # multiples of the 1276-output tile, with all four sub-dword classes in every chunk
+    _say("shared-word tile edges", variant, arts.arts_tiling_describe(variant))
+    f_lo, df = synth.band(96)
+    dms = np.arange(70) * 1.3
+    delays = O.delay_table(96, f_lo, df, synth.TSAMP, dms)
+    w = synth.Workload("edges", 96, f_lo, df, synth.TSAMP, dms, [1])
+    rng = np.random.default_rng(variant)
+    with _plan(w, variant) as p:
+        for nout in (1, 4, 1272, 1275, 1276, 1277, 1280, 2551, 2552, 2556, 3830):
+            nin = int(delays.max()) + nout
+            data = rng.integers(0, 256, size=(96, nin), dtype=np.uint8)
+            got = p.dedisperse(to_dev(data)).cpu().numpy()[0]
+            assert got.shape[1] == nout
+            assert np.array_equal(got, O.dedisperse(data, delays)), nout
 
 
 @pytest.mark.parametrize("nchan,ndm,extra", [(1, 1, 1), (3, 5, 2), (37, 33, 1000), (7, 70, 5),
