@@ -625,7 +625,7 @@ def tilings_bench(args):
         g.manual_seed(1)
         tab = torch.randint(0, 256, (NTAB, NCHAN, nin), dtype=torch.uint8, device="cuda",
                             generator=g)
-        default = p.tiling()
+        default = p.tiling_shape()
         spd = "SPD=4" if w.downsample == 1 else "SPD=2"
         out = None
         for v in range(arts.arts_tiling_count()):
@@ -653,13 +653,50 @@ def tilings_bench(args):
                 ms = e0.elapsed_time(e1) / args.steps
                 adds = NSB * w.dms.size * out.shape[2] * NCHAN
                 res[key] = {"tiling": d, "plan": w.name, "buffers": nbuf, "channels": cc,
-                            "default": v == default and nbuf == 2, "ms": ms,
+                            "default": v == default[0] and nbuf == default[1], "ms": ms,
                             "tadd_s": adds / ms / 1e9}
         del tab, out, p
         torch.cuda.empty_cache()
     print(json.dumps({"workload": "dedispersion tilings on the serving launches (71 SBs fused "
                                   "from 12 TABs x 1536 ch; 2048 native / 1476 D=4 trials)",
                       "steps": args.steps, "tilings": res}), flush=True)
+
+
+TILINGS_TXT = os.path.join(ROOT, "profiles", "dedisperse_tilings_serving.txt")
+
+
+def summarize_tilings(json_path):
+    """Write the table of a `--workload tilings` JSON line to profiles/ (one row per tiling and
+    buffer count, the plans' default shapes marked)."""
+    with open(json_path) as f:
+        d = json.loads(f.read().strip().splitlines()[-1])
+    lines = ["Dedispersion tile shapes on the serving launches (MI355X, one GPU)",
+             "(fused SB formation of 71 SBs from 12 TABs x 1536 channels; 2048 native trials over",
+             " 12 755 outputs per row, and 1476 D=4 trials over 3188 outputs; "
+             f"{d['steps']} timed launches each",
+             " after one warm-up launch, HIP events.  A D=4 plan call on byte input first "
+             "downsamples",
+             " the whole input (12 x 1536 rows) into its 16-bit workspace, about 1.3 ms of these "
+             "times;",
+             " in the serving stream only the new chunk is downsampled, in the ring advance.)",
+             "Each tiling twice: two LDS buffers (the next chunk of channels fetched while one is",
+             "summed) and one buffer (fetched in turn, twice the channels per chunk).  * marks the",
+             "plans' default shape.",
+             f"command: python3 bench.py --workload tilings --steps {d['steps']} > t.json; "
+             "python3 bench.py --summarize-tilings t.json", "",
+             f"{'tiling':>9s}  {'plan':26s}  {'shape':44s} {'ch/chunk':>8s}  {'ms/launch':>9s}  "
+             f"{'Tadd/s':>6s}"]
+    for key, r in d["tilings"].items():
+        if r.get("ms") is None:
+            lines.append(f"{key:>9s}  {r['plan']:26s}  {r['tiling']:44s} {'-':>8s}  "
+                         f"{'does not fit':>9s}")
+            continue
+        mark = "*" if r.get("default") else " "
+        lines.append(f"{key:>8s}{mark}  {r['plan']:26s}  {r['tiling']:44s} {r['channels']:8d}  "
+                     f"{r['ms']:9.2f}  {r['tadd_s']:6.2f}")
+    with open(TILINGS_TXT, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def ctypes_cluster(arts, plan, work, n):
@@ -673,6 +710,9 @@ def ctypes_cluster(arts, plan, work, n):
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profile":
         summarize_profile(*sys.argv[2:6])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-tilings":
+        summarize_tilings(sys.argv[2])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
