@@ -181,9 +181,10 @@ PROFILE_JSON = os.path.join(ROOT, "profiles", "dedisperse_serving_chunk.json")
 def kernel_name(describe):
     """Template name of the dedispersion kernel of a tiling variant, from its description
     ("J=5 ACC=3 WAVES=8 SPD=4 packed" -> "dedisperse_kernel<4, 5, 3, 8, 1>"; "framed" -> 2,
-    "pairs" -> 5, "framed runs" -> 7, "framed runs shared" -> 9)."""
+    "pairs" -> 5, "framed runs" -> 7, "framed runs shared" -> 9, "pairs framed" -> 10)."""
     f = dict(kv.split("=") for kv in describe.split() if "=" in kv)
-    pack = (9 if "runs shared" in describe else 7 if "framed runs" in describe
+    pack = (10 if "pairs framed" in describe else 9 if "runs shared" in describe
+            else 7 if "framed runs" in describe
             else 5 if "pairs" in describe
             else 2 if "framed" in describe else 1 if "packed" in describe else 0)
     return f"dedisperse_kernel<{f['SPD']}, {f['J']}, {f['ACC']}, {f['WAVES']}, {pack}>"

@@ -131,7 +131,7 @@ int build_tiling(arts_plan_s* p, int variant) {
     }
   }
   t.rmax = rmax;
-  if (v.pack == 5) {
+  if (is_pairs(v.pack)) {
     // DM pairs read one window per pair: the second trial may start at most kPairMaxDeltaHost
     // samples after the first, never before it
     if (t.m_blk % 2 != 0) return fail(ARTS_E_INVAL, "variant %d: odd DMs per block", variant);
@@ -204,7 +204,7 @@ int ensure_tables(arts_plan_s* p, int g0) {
   const int shift = t.spd == 4 ? 2 : 1;
   std::vector<int32_t> list(t.rel.size(), 0);
   std::vector<uint32_t> cnt(static_cast<size_t>(t.nblk) * t.nchunk * t.m_blk, 0);
-  const bool pairs = kVariants[t.variant].pack == 5;
+  const bool pairs = is_pairs(kVariants[t.variant].pack);
   if (pairs) {
     // per DM pair (trials 2P, 2P + 1 of the block) and chunk: channels ordered by class
     // m0 * (max delta + 1) + delta, m0 = first trial's offset parity, delta = the second
@@ -939,7 +939,8 @@ int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
     return fail(ARTS_E_INVAL, "bad variant or buffer");
   const TileVariant& v = kVariants[variant];
   snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d%s", v.j, v.acc, v.waves, v.spd,
-           v.pack == 9   ? " framed runs shared"
+           v.pack == 10  ? " pairs framed"
+           : v.pack == 9 ? " framed runs shared"
            : v.pack == 7 ? " framed runs"
            : v.pack == 5 ? " pairs"
            : v.pack == 4 ? " group sums"

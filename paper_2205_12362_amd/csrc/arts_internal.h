@@ -35,6 +35,9 @@ struct TileVariant {
 constexpr __host__ __device__ int tile_outputs(int t, int pack) {
   return 64 * t - (pack == 9 ? 4 : 0);
 }
+// DM-pair tilings (16-bit samples): per pair and chunk, channels in 16 classes of (first
+// trial's sample parity, delay step)
+constexpr __host__ __device__ bool is_pairs(int pack) { return pack == 5 || pack == 10; }
 extern const TileVariant kVariants[];
 extern const int kNumVariants;
 int default_variant(int downsample, int64_t ndm);

@@ -17,7 +17,8 @@ namespace arts {
 // chunks, 4 group sums (split plans), 5 DM pairs read as one window (16-bit samples), 7 framed
 // runs (raw-dword frames per sub-dword class, added into the totals at the end of each run),
 // 9 framed runs whose lanes read J dwords per channel and take the sums of their last dword
-// from the next lane (a tile then covers 64 T - 4 outputs).
+// from the next lane (a tile then covers 64 T - 4 outputs), 10 DM pairs summed in raw frames
+// per sample parity (16-bit samples), aligned once per chunk.
 #define ARTS_TILINGS(X)                                                                    \
   X(0, 4, 5, 4, 8, 0)   /* 32 DMs x 1280 samples per block, 80 accumulators per lane */    \
   X(1, 4, 7, 3, 8, 0)   /* 24 DMs x 1792 */                                                \
@@ -48,7 +49,8 @@ namespace arts {
   X(26, 2, 9, 2, 8, 5)  /* downsampled, DM pairs: 16 DMs x 1152 */                         \
   X(27, 4, 5, 4, 8, 7)  /* framed runs: 32 DMs x 1280 */                                   \
   X(28, 4, 5, 4, 8, 9)  /* framed runs, last word shared: 32 DMs x 1276 */                 \
-  X(29, 4, 5, 3, 8, 9)  /* framed runs, last word shared: 24 DMs x 1276 */
+  X(29, 4, 5, 3, 8, 9)  /* framed runs, last word shared: 24 DMs x 1276 */ \
+  X(30, 2, 5, 4, 8, 10) /* downsampled, DM pairs in raw frames: 32 DMs x 640 */
 
 const TileVariant kVariants[] = {
 #define ARTS_X(id, spd, j, acc, waves, pack) {spd, j, acc, waves, pack},
@@ -94,13 +96,13 @@ int runs_variant(int64_t ndm) {
 }
 
 int default_variant(int downsample, int64_t ndm) {
-  if (downsample > 1) return 24;
+  if (downsample > 1) return 30;
   return ndm <= 64 ? 17 : runs_variant(ndm);
 }
 
 // The tiling to try when the default does not fit a plan (DM-pair tilings need neighbouring
 // trials at most kPairMaxDelta samples apart in every channel), or -1.
-int fallback_variant(int variant) { return kVariants[variant].pack == 5 ? 6 : -1; }
+int fallback_variant(int variant) { return is_pairs(kVariants[variant].pack) ? 6 : -1; }
 
 // ------------------------------------------------------------------ dedispersion ----
 //
@@ -491,6 +493,74 @@ __device__ __forceinline__ void accum_pair_classes(uint32_t* pk0, uint32_t* pk1,
   }
 }
 
+// NW consecutive LDS dwords of a channel's window, from the lane's word at byte offset off.
+template <int NW>
+__device__ __forceinline__ void load_words(uint32_t* w, const uint8_t* lane_base, int32_t off) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + off);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) w[k] = p[k];
+}
+
+// ---- DM pairs in raw frames (spd = 2).  As the DM pairs above, but each trial adds the raw
+// dwords of a channel into one of two frames chosen by the parity of its first sample: word k
+// of frame 0 holds outputs 2k and 2k + 1 as they are, frame 1 (J + 1 words) holds them one
+// sample later, which one v_alignbyte_b32 per word undoes when the frames are widened at the
+// end of the pair's chunk.  A half never carries into its neighbour (a chunk holds at most
+// floor(65535 / (255 D)) channels), so the frames are exact: a channel costs one add per word
+// and trial, shared by two channels in v_add3_u32, and no per-channel alignment.
+template <int J, int M0, int DELTA>
+__device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
+                                                      uint32_t (*f1)[J + 1], const int32_t* ent,
+                                                      int n, const uint8_t* lane_base) {
+  constexpr int S = M0 + DELTA;
+  constexpr int NW = J + (S + 1) / 2;    // union of both trials' words
+  constexpr int W1 = S / 2, P1 = S % 2;  // the second trial's first word and parity
+  constexpr int N0 = J + M0, N1 = J + P1;
+  int i = 0;
+  for (; i + 2 <= n; i += 2) {
+    uint32_t w[2][NW];
+    load_words<NW>(w[0], lane_base, ent[i]);
+    load_words<NW>(w[1], lane_base, ent[i + 1]);
+#pragma unroll
+    for (int k = 0; k < N0; ++k) f0[M0][k] += w[0][k] + w[1][k];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) f1[P1][k] += w[0][W1 + k] + w[1][W1 + k];
+  }
+  if (i < n) {
+    uint32_t w[NW];
+    load_words<NW>(w, lane_base, ent[i]);
+#pragma unroll
+    for (int k = 0; k < N0; ++k) f0[M0][k] += w[k];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) f1[P1][k] += w[W1 + k];
+  }
+}
+
+template <int J, int CLS>
+__device__ __forceinline__ void accum_pair_frames(uint32_t (*f0)[J + 1], uint32_t (*f1)[J + 1],
+                                                  const int32_t* ent, const uint32_t* cnt,
+                                                  const uint8_t* lane_base) {
+  if constexpr (CLS < kPairClasses) {
+    const int n = (cnt[CLS / 4] >> (8 * (CLS % 4))) & 0xff;
+    accum_run_pair_frames<J, CLS / (kPairMaxDelta + 1), CLS % (kPairMaxDelta + 1)>(
+        f0, f1, ent, n, lane_base);
+    accum_pair_frames<J, CLS + 1>(f0, f1, ent + n, cnt, lane_base);
+  }
+}
+
+// Widen a trial's two parity frames into its int32 totals (outputs 2k, 2k + 1 per word).
+template <int J>
+__device__ __forceinline__ void flush_pair_frames(uint32_t* acc, const uint32_t (*f)[J + 1]) {
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    const uint32_t odd = __builtin_amdgcn_alignbyte(f[1][k + 1], f[1][k], 2);
+    add_half<0>(acc[2 * k], f[0][k]);
+    add_half<1>(acc[2 * k + 1], f[0][k]);
+    add_half<0>(acc[2 * k], odd);
+    add_half<1>(acc[2 * k + 1], odd);
+  }
+}
+
 // Widen the packed halves into the int32 totals (one SDWA add each) and clear them.
 template <int J>
 __device__ __forceinline__ void flush_pk(uint32_t* acc, uint32_t* e, uint32_t* o) {
@@ -639,13 +709,6 @@ __device__ __forceinline__ void frame_to_totals(uint32_t* acc, const uint32_t* A
     if (i0 + 1 >= 0 && i0 + 1 < T) add_half<0>(acc[i0 + 1], o[k]);
     if (i0 + 3 >= 0 && i0 + 3 < T) add_half<1>(acc[i0 + 3], o[k]);
   }
-}
-
-template <int NW>
-__device__ __forceinline__ void load_words(uint32_t* w, const uint8_t* lane_base, int32_t off) {
-  const uint32_t* p = reinterpret_cast<const uint32_t*>(lane_base + off);
-#pragma unroll
-  for (int k = 0; k < NW; ++k) w[k] = p[k];
 }
 
 template <int J, int MS, bool SH>
@@ -1045,7 +1108,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
 #pragma unroll
       for (int x = 0; x < ACC; ++x) {
         const uint32_t packed =
-            PK == 5 ? 0u : __builtin_amdgcn_readfirstlane(cnt_blk[ch * a.m_blk + x]);
+            is_pairs(PK) ? 0u : __builtin_amdgcn_readfirstlane(cnt_blk[ch * a.m_blk + x]);
         const int32_t* ent = ent_cur + (wave * ACC + x) * a.cc;
         const int n0 = packed & 0xff, n1 = (packed >> 8) & 0xff;
         if constexpr (PK == 2) {
@@ -1090,6 +1153,25 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
             accum_pair_classes<J, 0, PF>(pk0, pk1, ent_cur + pr * a.cc, cnt4, lane_base);
             flush_pk16<J>(acc[x], pk0);
             flush_pk16<J>(acc[x + 1], pk1);
+          }
+        } else if constexpr (PK == 10) {
+          // DM pairs in raw frames: trials (x, x + 1) at even x
+          static_assert(SPD == 2 && ACC % 2 == 0, "DM pairs are for 16-bit samples");
+          if (x % 2 == 0) {
+            const int pr = (wave * ACC + x) / 2;
+            const uint32_t* cp = a.cnt + ((static_cast<int64_t>(blk) * a.nchunk + ch) *
+                                              (a.m_blk / 2) + pr) * 4;
+            uint32_t cnt4[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cnt4[k] = __builtin_amdgcn_readfirstlane(cp[k]);
+            uint32_t f0[2][J + 1], f1[2][J + 1];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+              for (int k = 0; k <= J; ++k) f0[m][k] = f1[m][k] = 0;
+            accum_pair_frames<J, 0>(f0, f1, ent_cur + pr * a.cc, cnt4, lane_base);
+            flush_pair_frames<J>(acc[x], f0);
+            flush_pair_frames<J>(acc[x + 1], f1);
           }
         } else if constexpr (PK && SPD == 2) {
           uint32_t pk[J];
@@ -1400,7 +1482,7 @@ static int make_args(arts_plan_s* p, const DedispJob& job, DedispArgs* out) {
   a.ds = p->ds;
   a.nbeam = job.nbeam;
   a.m_blk = t.m_blk;
-  a.nlist = v.pack == 5 ? t.m_blk / 2 : t.m_blk;
+  a.nlist = is_pairs(v.pack) ? t.m_blk / 2 : t.m_blk;
   a.nbuf = t.nbuf;
   a.nblk = t.nblk;
   a.win = t.win_dwords;
