@@ -262,6 +262,34 @@ def summarize_profile(stats_dir, fetch_dir, write_dir, sq_dir=None):
     lines.append("kernel stats (rocprofv3 --kernel-trace --stats):")
     for r in stats:
         lines.append(f"  {r['Name'][:70]:70s} calls {r['Calls']:>4s}  avg {float(r['AverageNs'])/1e6:9.3f} ms")
+    # the HBM-bound steps against the stream rate measured in the same run (the probe's 1 GiB
+    # elementwise stream, read once and written once: its fastest dispatch)
+    trace = rows(stats_dir, "*kernel_trace.csv")
+    copies = sorted(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
+                    if "bitwise_not" in r["Kernel_Name"])
+    copy_tbs = 2 * copy_bytes / (copies[0] * 1e-9) / 1e12 if copies else None
+    hbm_steps = (
+        ("cand_pre_kernel<10,", "candidate pre-pass, native rows (71 x 2048 x 12 755 int32 read)",
+         NSB * 2048 * (CHUNK + 255) * 4),
+        ("cand_pre_kernel<8,", "candidate pre-pass, D=4 rows (71 x 1476 x 3188 int32 read)",
+         NSB * 1476 * (CHUNK // 4 + 63) * 4),
+        ("downsample_rows_kernel", "D=4 downsampling of the new chunk (12 x 1536 x 12 500 B read, "
+         "x 3125 x 2 B written)", NTAB * NCHAN * CHUNK + NTAB * NCHAN * (CHUNK // 4) * 2))
+    if copy_tbs:
+        lines.append("")
+        lines.append(f"HBM-bound steps (algorithmic bytes / average duration) against the measured "
+                     f"stream rate, {copy_tbs:.2f} TB/s (an elementwise kernel reading 1 GiB and "
+                     f"writing 1 GiB in {copies[0] / 1e6:.3f} ms; HBM peak 8 TB/s):")
+        for key, label, nbytes in hbm_steps:
+            ks = [r for r in stats if key in r["Name"].replace(" ", "")]
+            if not ks:
+                continue
+            ms = float(ks[0]["AverageNs"]) / 1e6
+            tbs = nbytes / (ms * 1e-3) / 1e12
+            lines.append(f"  {label}: {ms:.3f} ms, {tbs:.2f} TB/s = {tbs / copy_tbs:.2f} of the "
+                         f"stream rate")
+            summary.setdefault("hbm_steps", {})[key] = {"ms": ms, "bytes": nbytes, "tb_s": tbs,
+                                                        "frac_stream": tbs / copy_tbs}
     lines.append("")
     lines.append(f"1 GiB copy: FETCH_SIZE {cf} KiB -> scale {f_scale} B/KiB; WRITE_SIZE {cw} KiB -> "
                  f"scale {w_scale} B/KiB")
@@ -921,10 +949,14 @@ def main():
     stream.close()
     del pool
     if args.copy_probe:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        # 1 GiB copies (the counters' calibration) and a 1 GiB elementwise stream (read once,
+        # written once: the achievable HBM rate the HBM-bound steps are compared with)
+        a = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         for _ in range(2):
             b.copy_(a)
+        for _ in range(3):
+            torch.bitwise_not(a, out=b)
         torch.cuda.synchronize()
         del a, b
     torch.cuda.empty_cache()

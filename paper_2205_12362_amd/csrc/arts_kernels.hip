@@ -2728,7 +2728,9 @@ int launch_copy_rows(uint8_t* dst, int64_t dpitch, const uint8_t* src, int64_t s
 
 // ------------------------------------------------------------------ downsampling ----
 // dst[r][s] = sum_{i<D} src[r][D s + i] for s < nout (16-bit: D <= 257).  Each thread makes
-// 4 consecutive outputs; rows whose start is 4-byte aligned are read with dword loads.
+// 4 consecutive outputs; rows whose start is 4-byte aligned are read with dword loads.  For
+// D = 4 an output is the byte sum of one dword (v_sad_u8 against zero), read 16 bytes at a time
+// where the row allows, and the four outputs are stored as one 8-byte word where aligned.
 __global__ __launch_bounds__(256) void downsample_rows_kernel(
     uint16_t* __restrict__ dst, int64_t dpitch, const uint8_t* __restrict__ src, int64_t spitch,
     int64_t nout, int32_t D, int64_t nblk_row) {
@@ -2740,7 +2742,24 @@ __global__ __launch_bounds__(256) void downsample_rows_kernel(
   const int nv = static_cast<int>(min<int64_t>(4, nout - s0));
   uint32_t acc[4] = {0, 0, 0, 0};
   const uint8_t* q = sr + s0 * D;
-  if ((reinterpret_cast<uintptr_t>(q) & 3u) == 0 && nv == 4) {
+  if (D == 4 && nv == 4 && (reinterpret_cast<uintptr_t>(q) & 3u) == 0) {
+    uint4 w;
+    if ((reinterpret_cast<uintptr_t>(q) & 15u) == 0) {
+      w = *reinterpret_cast<const uint4*>(q);
+    } else {
+      const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
+      w = make_uint4(qw[0], qw[1], qw[2], qw[3]);
+    }
+    acc[0] = __builtin_amdgcn_sad_u8(w.x, 0u, 0u);
+    acc[1] = __builtin_amdgcn_sad_u8(w.y, 0u, 0u);
+    acc[2] = __builtin_amdgcn_sad_u8(w.z, 0u, 0u);
+    acc[3] = __builtin_amdgcn_sad_u8(w.w, 0u, 0u);
+    if ((reinterpret_cast<uintptr_t>(dr + s0) & 7u) == 0) {
+      *reinterpret_cast<uint2*>(dr + s0) =
+          make_uint2(acc[0] | (acc[1] << 16), acc[2] | (acc[3] << 16));
+      return;
+    }
+  } else if ((reinterpret_cast<uintptr_t>(q) & 3u) == 0 && nv == 4) {
     const uint32_t* qw = reinterpret_cast<const uint32_t*>(q);
     for (int j = 0; j < D; ++j) {  // 4 D bytes = D dwords
       const uint32_t w = qw[j];
