@@ -217,11 +217,15 @@ int32_t arts_tiling_count(void);
 int arts_plan_autotune(arts_plan_t plan, int32_t nbeam, int64_t nin, int32_t reps,
                        const char* cache_path, int32_t* variant_out, float* ms_out);
 /* Writes "J=<dwords per lane> ACC=<DMs per wave> WAVES=<waves per block> SPD=<samples per
- * dword>" and the partial-sum form (" packed": 16-bit halves widened once per staged chunk;
- * " packed held": widened every 257 channels; " group sums": the halves are the channel
- * group sums of the first subband step, the only plans these variants run; " framed":
- * raw-dword frames per sub-dword offset; none: single-sample adds) for a variant into buf
- * (NUL-terminated, at most len bytes).                                                       */
+ * dword>" and the partial-sum form for a variant into buf (NUL-terminated, at most len bytes):
+ * " packed": 16-bit halves widened once per staged chunk; " packed held": widened every 257
+ * channels; " group sums": the halves are the channel group sums of the first subband step,
+ * the only plans these variants run; " framed": raw-dword frames per sub-dword offset held
+ * across chunks; " framed runs": raw-dword frames per run of channels with one sub-dword
+ * offset, added into the totals at the end of each run; " framed runs shared": the same with
+ * each lane taking the sums of its last dword from the next lane (a time tile then covers
+ * 64 x 4J - 4 outputs); " pairs": two DM trials of 16-bit samples summed from one window
+ * read; " pairs framed": the same in raw frames per sample parity; none: single-sample adds. */
 int arts_tiling_describe(int32_t variant, char* buf, int32_t len);
 /* Workgroups per CU that registers and waves allow (LDS aside) on the current device for a
  * variant's one-launch kernel (*per_job; for group-sum variants the split-plan kernel) and its
