@@ -718,7 +718,16 @@ __device__ __forceinline__ void accum_frame_run(uint32_t* acc, const int32_t* en
   constexpr int NW = (MS == 0 || SH) ? J : J + 1;
   uint32_t A[NW], O[NW];
   int i;
-  if (n >= 2) {
+  if (n & 1) {  // an odd run starts with its lone channel: the frame is that channel's words
+    uint32_t w[NW];
+    load_words<NW>(w, lane_base, ent[0]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      A[k] = w[k];
+      O[k] = odd_bytes(w[k]);
+    }
+    i = 1;
+  } else {
     uint32_t w[2][NW];
     load_words<NW>(w[0], lane_base, ent[0]);
     load_words<NW>(w[1], lane_base, ent[1]);
@@ -728,30 +737,12 @@ __device__ __forceinline__ void accum_frame_run(uint32_t* acc, const int32_t* en
       O[k] = odd_bytes(w[0][k]) + odd_bytes(w[1][k]);
     }
     i = 2;
-  } else {
-    uint32_t w[NW];
-    load_words<NW>(w, lane_base, ent[0]);
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      A[k] = w[k];
-      O[k] = odd_bytes(w[k]);
-    }
-    i = 1;
   }
-  for (; i + 2 <= n; i += 2) {
+  for (; i < n; i += 2) {  // the rest in pairs
     uint32_t w[2][NW];
     load_words<NW>(w[0], lane_base, ent[i]);
     load_words<NW>(w[1], lane_base, ent[i + 1]);
     add_fr<NW>(A, O, w[0], w[1]);
-  }
-  if (i < n) {
-    uint32_t w[NW];
-    load_words<NW>(w, lane_base, ent[i]);
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      A[k] += w[k];
-      O[k] += odd_bytes(w[k]);
-    }
   }
   frame_to_totals<J, MS, SH>(acc, A, O);
 }
