@@ -197,11 +197,23 @@ def serve(specs, seconds: float, budget_bytes: int, log=None, lanes: int = 2,
 
 def default_specs(seed=7):
     """The 71-SB Apertif stream (12 TABs, native + D=4 trials) plus two smaller streams of other
-    shapes that join later: a 384-channel beam to DM 500 and a 768-channel beam to DM 2000."""
+    shapes that join later: a 384-channel beam to DM 500 and a 768-channel beam to DM 2000.
+    Each chunk of the 71-SB stream carries four dispersed top-hat bursts (16 samples, 6 counts
+    per channel) in TAB 11, which SB 35 takes across the whole band."""
     specs = []
     chunk = synth.CHUNK
-    pool = [synth.noise((12, 1536, chunk), seed=seed + i) for i in range(2)]
-    specs.append(StreamSpec("apertif71", [synth.cfg_apertif(), synth.cfg_apertif_ds()], 12, chunk,
+    w_nat = synth.cfg_apertif()
+    delays, _ = arts.arts_delay_table(w_nat.nchan, w_nat.f_lo, w_nat.df, w_nat.tsamp, w_nat.dms)
+    pool = []
+    for i in range(2):
+        c = synth.noise((12, 1536, chunk), seed=seed + i)
+        rng = np.random.default_rng(seed + 100 + i)
+        for _ in range(4):
+            d = int(rng.integers(100, 2000))
+            t = int(rng.integers(0, chunk - 300))
+            synth.add_tophat(c[11], t + delays[d] - int(delays[d].max()), 16, 6)
+        pool.append(c)
+    specs.append(StreamSpec("apertif71", [w_nat, synth.cfg_apertif_ds()], 12, chunk,
                             pool, sb_table=synth.sb_table_synthetic()))
     for name, nchan, dm_hi, ntr, start in (("b384", 384, 500.0, 1024, 2.0),
                                            ("b768", 768, 2000.0, 2048, 4.0)):
