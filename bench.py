@@ -497,6 +497,16 @@ def alert_bench(args):
     for p in plans:
         p.cluster = bool(args.cluster)
         p.integration = args.integration
+    tuned = None
+    if args.autotune:
+        # first-step tile shapes timed on this device: one-shot plan calls over all SBs and one
+        # chunk plus the plan's halo (both steps timed, the first step's shape varied)
+        tuned = {}
+        for p, (a, st, n, nf) in zip(plans, ALERT_PLANS):
+            v, ms = p.autotune(NSB, CHUNK + p.halo, args.autotune, args.tune_cache)
+            tuned[f"dm{a:g}"] = {"shape": list(p.tiling_shape()),
+                                 "tiling": arts.arts_tiling_describe(v), "ms": ms}
+        log(f"autotuned: {tuned}")
     table = torch.from_numpy(synth.sb_table_synthetic(NSB, NTAB, NCHAN)).cuda()
     pool = [torch.from_numpy(synth.noise((NTAB, NCHAN, CHUNK), seed=900 + k)).cuda()
             for k in range(2)]
@@ -553,7 +563,10 @@ def alert_bench(args):
                                "250; 12500 new samples per step",
                    "ntrial": ntrial, "nsb": NSB, "chunk": CHUNK, "threshold": THRESHOLD,
                    "cluster": bool(args.cluster), "rfi": bool(args.rfi),
-                   "integration": args.integration, "device_bytes": info["device_bytes"]},
+                   "integration": args.integration, "device_bytes": info["device_bytes"],
+                   "step1_tiles": {f"dm{a:g}": list(p.tiling_shape())
+                                   for p, (a, st, n, nf) in zip(plans, ALERT_PLANS)},
+                   "autotuned": tuned},
         "real_time_factor": (CHUNK * synth.TSAMP) / (ms_step * 1e-3),
         "chunk_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                              "p99": float(np.percentile(lat_ms, 99)),
@@ -754,7 +767,7 @@ def main():
                          "beam-chunk) timed after the serving steps")
     ap.add_argument("--variant", type=int, default=None, help="native dedispersion tiling")
     ap.add_argument("--autotune", type=int, default=0, metavar="REPS",
-                    help="serving: autotune both plans' tile shapes before timing")
+                    help="serving and alert: autotune the plans' tile shapes before timing")
     ap.add_argument("--tune-cache", default=None, help="tune cache file (with --autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 1 GiB twice (counter calibration)")
