@@ -268,13 +268,20 @@ def summarize_profile(stats_dir, fetch_dir, write_dir, sq_dir=None):
     copies = sorted(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
                     if "bitwise_not" in r["Kernel_Name"])
     copy_tbs = 2 * copy_bytes / (copies[0] * 1e-9) / 1e12 if copies else None
-    hbm_steps = (
-        ("cand_pre_kernel<10,", "candidate pre-pass, native rows (71 x 2048 x 12 755 int32 read)",
-         NSB * 2048 * (CHUNK + 255) * 4),
-        ("cand_pre_kernel<8,", "candidate pre-pass, D=4 rows (71 x 1476 x 3188 int32 read)",
-         NSB * 1476 * (CHUNK // 4 + 63) * 4),
-        ("downsample_rows_kernel", "D=4 downsampling of the new chunk (12 x 1536 x 12 500 B read, "
-         "x 3125 x 2 B written)", NTAB * NCHAN * CHUNK + NTAB * NCHAN * (CHUNK // 4) * 2))
+    # the pre-pass instances (one per evaluated-width count): the longer one reads the native
+    # rows, the shorter one the D=4 rows
+    pre = sorted((r for r in stats if "cand_pre_kernel" in r["Name"]),
+                 key=lambda r: -float(r["AverageNs"]))
+    pre_names = [r["Name"][r["Name"].index("cand_pre_kernel"):r["Name"].index(">") + 1]
+                 .replace(" ", "") for r in pre]
+    hbm_steps = tuple(
+        (key, label, nbytes) for key, label, nbytes in (
+            (pre_names[0] if pre_names else "-", "candidate pre-pass, native rows (71 x 2048 x "
+             "12 755 int32 read)", NSB * 2048 * (CHUNK + 255) * 4),
+            (pre_names[1] if len(pre_names) > 1 else "-", "candidate pre-pass, D=4 rows (71 x "
+             "1476 x 3188 int32 read)", NSB * 1476 * (CHUNK // 4 + 63) * 4),
+            ("downsample_rows_kernel", "D=4 downsampling of the new chunk (12 x 1536 x 12 500 B "
+             "read, x 3125 x 2 B written)", NTAB * NCHAN * CHUNK + NTAB * NCHAN * (CHUNK // 4) * 2)))
     if copy_tbs:
         lines.append("")
         lines.append(f"HBM-bound steps (algorithmic bytes / average duration) against the measured "

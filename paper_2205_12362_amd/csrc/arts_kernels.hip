@@ -2277,13 +2277,23 @@ __global__ __launch_bounds__(NT) void candidates_kernel(
 // continues into a guard of kPreC entries that mirrors the ring's first chunk slot (written
 // together with it), so no read address is wrapped.  A row is flagged if some width's maximum
 // exceeds its threshold (the same moments and width_params as the main kernel, so the main
-// kernel finds no candidate in a row left unflagged).  NW is the width count rounded up to an
-// even number, the extra widths repeating the last; the ring holds D + 2 chunks.
+// kernel finds no candidate in a row left unflagged).
+//
+// Widths w = 2v whose half v is also a width are not evaluated: the series is non-negative, so
+// B_2v(t) = B_v(t) + B_v(t + v) <= 2 max B_v over starts up to nrep + v, and the row is
+// flagged when that bound exceeds w's threshold.  v's maximum is then taken over those starts
+// too.  Both only ever flag more rows (the main kernel decides exactly); on noise the bound
+// stays below threshold unless B_v reaches thr / sqrt(2) sigma above its mean.  NW is the count
+// of evaluated widths; the ring holds D + 2 chunks.
 constexpr int kPreC = 256;
 constexpr int kPreMaxW = 6 * kPreC;
 
 struct PreWidths {
-  int32_t w[kCandRegW];
+  int32_t w[kCandRegW];    // evaluated widths
+  int32_t ext[kCandRegW];  // starts evaluated beyond the searched ones: v where v bounds 2v
+  int32_t nb;              // widths checked through the bound
+  int32_t bw[kCandRegW];   // those widths
+  int32_t bs[kCandRegW];   // the slot in w of their half
 };
 
 // Inclusive prefix sum across a wave64 with DPP moves (no LDS round trip): shifts by 1, 2, 4
@@ -2396,9 +2406,10 @@ __global__ __launch_bounds__(256) void cand_pre_kernel(
 #pragma unroll
         for (int wi = 0; wi < NW; ++wi) {
           const uint32_t* pw = rg + ((t0 + wd.w[wi] - 1) & (RB - 1)) + lane;
+          const int64_t lim = nrep + wd.ext[wi];
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (t0 + lane + 64 * u < nrep)
+            if (t0 + lane + 64 * u < lim)
               bm[wi] = max(bm[wi], static_cast<int32_t>(pw[64 * u] - av[u]));
         }
       }
@@ -2417,9 +2428,13 @@ __global__ __launch_bounds__(256) void cand_pre_kernel(
     int hit = 0;
     if (sigma > 0.0)
 #pragma unroll
-      for (int wi = 0; wi < NW; ++wi)
-        if (static_cast<long long>(bm[wi]) > width_params(wd.w[wi], nrep, mu, sigma, thr).thr_int)
-          hit = 1;
+      for (int wi = 0; wi < NW; ++wi) {
+        const long long m = bm[wi];
+        if (m > width_params(wd.w[wi], nrep, mu, sigma, thr).thr_int) hit = 1;
+        for (int b = 0; b < wd.nb; ++b)
+          if (wd.bs[b] == wi && 2 * m > width_params(wd.bw[b], nrep, mu, sigma, thr).thr_int)
+            hit = 1;
+      }
     flags[row] = static_cast<uint8_t>(hit);
   }
 }
@@ -2427,18 +2442,11 @@ __global__ __launch_bounds__(256) void cand_pre_kernel(
 typedef void (*PreKernel)(const int32_t*, int64_t, int64_t, int64_t, PreWidths, int32_t, double,
                           uint8_t*);
 
-template <int RB>
-PreKernel pre_kernel_nw(int nwp) {
-  switch (nwp) {
-    case 2: return cand_pre_kernel<2, RB>;
-    case 4: return cand_pre_kernel<4, RB>;
-    case 6: return cand_pre_kernel<6, RB>;
-    case 8: return cand_pre_kernel<8, RB>;
-    case 10: return cand_pre_kernel<10, RB>;
-    case 12: return cand_pre_kernel<12, RB>;
-    case 14: return cand_pre_kernel<14, RB>;
-    default: return cand_pre_kernel<16, RB>;
-  }
+template <int RB, int N = 1>
+PreKernel pre_kernel_nw(int nw) {
+  if constexpr (N < kCandRegW)
+    if (nw > N) return pre_kernel_nw<RB, N + 1>(nw);
+  return cand_pre_kernel<N, RB>;
 }
 
 int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam, int64_t L,
@@ -2481,12 +2489,28 @@ int launch_candidates(const arts_plan_s* p, const int32_t* series, int32_t nbeam
   const bool pre = flags != nullptr && p->nwidth <= kCandRegW && p->wmax <= kPreMaxW &&
                    nrows >= 1024;
   if (pre) {
-    PreWidths wd;
-    const int nwp = (p->nwidth + 1) & ~1;
-    for (int wi = 0; wi < kCandRegW; ++wi) wd.w[wi] = p->widths[min(wi, p->nwidth - 1)];
+    // evaluated widths in ascending order; 2v is bounded through v when v is evaluated
+    PreWidths wd{};
+    std::vector<int32_t> ws(p->widths.begin(), p->widths.end());
+    std::sort(ws.begin(), ws.end());
+    ws.erase(std::unique(ws.begin(), ws.end()), ws.end());
+    int nw = 0;
+    for (const int32_t w : ws) {
+      int half = -1;
+      for (int j = 0; j < nw && w % 2 == 0; ++j)
+        if (wd.w[j] == w / 2 && wd.ext[j] == 0) half = j;
+      if (half >= 0) {
+        wd.ext[half] = w / 2;
+        wd.bw[wd.nb] = w;
+        wd.bs[wd.nb] = half;
+        ++wd.nb;
+      } else {
+        wd.w[nw++] = w;
+      }
+    }
     // the ring holds D + 2 chunks: 4 of them up to wmax = 2 kPreC, else 8
-    const PreKernel kp = p->wmax <= 2 * kPreC ? pre_kernel_nw<4 * kPreC>(nwp)
-                                              : pre_kernel_nw<8 * kPreC>(nwp);
+    const PreKernel kp = p->wmax <= 2 * kPreC ? pre_kernel_nw<4 * kPreC>(nw)
+                                              : pre_kernel_nw<8 * kPreC>(nw);
     hipLaunchKernelGGL(kp, dim3(static_cast<unsigned>((nrows + 3) / 4)), dim3(256), 0, s,
                        series + t_begin, L, nrep - t_begin, nrows, wd, p->wmax,
                        static_cast<double>(thr), flags);

@@ -441,6 +441,36 @@ def test_candidates_many_rows_match_oracle(widths, nrep):
     assert compare_candidates(got, ora, near) > 0
 
 
+@pytest.mark.parametrize("widths", [[1, 2, 4, 8, 16, 32, 64, 128, 256],
+                                    [1, 5, 10, 25, 50, 100, 250]])
+def test_candidates_bounded_widths(widths):
+    # the pre-pass checks a width 2v through twice the largest sum of v over starts up to
+    # nrep + v: top-hats whose width is such a 2v, just above threshold at that width, some of
+    # them ending in the last searched starts (where the bound needs the extended starts);
+    # 1030 rows (the pre-pass runs), all against the oracle
+    ndm, thr, nrep = 1030, 8.0, 3001
+    wmax = max(widths)
+    L = nrep + wmax - 1
+    bounded = [w for w in widths if w % 2 == 0 and w // 2 in widths]
+    rng = np.random.default_rng(900 + wmax)
+    x = np.rint(rng.normal(1.5e6, 600.0, (ndm, L))).astype(np.int64)
+    rows = rng.choice(ndm, 48, replace=False)
+    for i, r in enumerate(rows):
+        w = bounded[i % len(bounded)]
+        t = nrep - 1 - int(rng.integers(0, 3)) if i % 3 == 0 else int(rng.integers(0, nrep - 1))
+        x[r, t:t + w] += int(round(600.0 * (8.3 + 0.5 * (i % 5)) / math.sqrt(w)))
+    x = x.astype(np.int32)
+    f_lo, df = synth.band(64)
+    _say("candidates, bounded widths", widths)
+    with arts.Plan(64, f_lo, df, synth.TSAMP, np.arange(ndm) * 0.01, widths) as p:
+        got = p.candidates(to_dev(x[None]), thr)
+    ora = O.candidates(x, widths, nrep, thr)
+    near = near_threshold_runs(x, widths, nrep, thr, np.arange(ndm))
+    assert len(ora) >= 20
+    assert any(int(c[2]) in bounded for c in ora)
+    assert compare_candidates(got, ora, near) > 0
+
+
 def test_candidates_apertif_rows():
     # full-size Apertif chunk with 20 bursts: candidates of 48 DM rows (around the bursts and
     # random) against the oracle on those rows; the moments use the reported window only
