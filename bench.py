@@ -183,7 +183,8 @@ def kernel_name(describe):
     ("J=5 ACC=3 WAVES=8 SPD=4 packed" -> "dedisperse_kernel<4, 5, 3, 8, 1>"; "framed" -> 2,
     "pairs" -> 5, "framed runs" -> 7, "framed runs shared" -> 9, "pairs framed" -> 10)."""
     f = dict(kv.split("=") for kv in describe.split() if "=" in kv)
-    pack = (10 if "pairs framed" in describe else 9 if "runs shared" in describe
+    pack = (11 if "runs group sums" in describe else 10 if "pairs framed" in describe
+            else 9 if "runs shared" in describe
             else 7 if "framed runs" in describe
             else 5 if "pairs" in describe
             else 2 if "framed" in describe else 1 if "packed" in describe else 0)

@@ -290,7 +290,7 @@ void cache_store(const char* path, const std::string& key, const Shape& sh) {
 // for subband plans (their first step), whose other tilings are the byte ones.
 bool suits(const arts_plan_s* p, int v) {
   if (p->nsub > 0) return kVariants[v].spd == 4 && kVariants[v].pack != 2;
-  return (p->ds == 1) == (kVariants[v].spd == 4) && kVariants[v].pack != 4;
+  return (p->ds == 1) == (kVariants[v].spd == 4) && !is_group(kVariants[v].pack);
 }
 
 template <typename Suits, typename Apply, typename Time>

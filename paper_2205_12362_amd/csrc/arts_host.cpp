@@ -104,7 +104,7 @@ int build_tiling(arts_plan_s* p, int variant) {
                 v.spd == 4 ? "byte (native)" : "16-bit (downsampled)");
   // group-sum tilings keep a channel group's sums in 16-bit halves: split plans with groups of
   // at most 257 byte channels
-  if (v.pack == 4 && (p->split <= 0 || p->split > 257))
+  if (is_group(v.pack) && (p->split <= 0 || p->split > 257))
     return fail(ARTS_E_INVAL, "variant %d runs the first subband step only (groups of at most "
                 "257 channels)", variant);
   Tiling t;
@@ -926,7 +926,7 @@ int32_t arts_tiling_count(void) { return kNumVariants; }
 int arts_tiling_occupancy(int32_t variant, int32_t* per_job, int32_t* persistent) {
   if (variant < 0 || variant >= kNumVariants || !per_job || !persistent)
     return fail(ARTS_E_INVAL, "bad variant or NULL output");
-  const bool group = kVariants[variant].pack == 4;
+  const bool group = is_group(kVariants[variant].pack);
   *per_job = variant_occupancy(variant, group ? kOccSplit : kOccPlain);
   *persistent = variant_occupancy(variant, kOccBatch);
   if (*per_job < 1 || (!group && *persistent < 1))
@@ -939,7 +939,8 @@ int arts_tiling_describe(int32_t variant, char* buf, int32_t len) {
     return fail(ARTS_E_INVAL, "bad variant or buffer");
   const TileVariant& v = kVariants[variant];
   snprintf(buf, len, "J=%d ACC=%d WAVES=%d SPD=%d%s", v.j, v.acc, v.waves, v.spd,
-           v.pack == 10  ? " pairs framed"
+           v.pack == 11  ? " framed runs group sums"
+           : v.pack == 10 ? " pairs framed"
            : v.pack == 9 ? " framed runs shared"
            : v.pack == 7 ? " framed runs"
            : v.pack == 5 ? " pairs"

@@ -31,10 +31,12 @@ struct TileVariant {
   int spd, j, acc, waves, pack;
 };
 // Outputs of one time tile: 64 lanes of t, less the 4 that a tiling whose lanes share their last
-// dword (pack 9) leaves to the next tile.
+// dword (pack 9 and 11) leaves to the next tile.
 constexpr __host__ __device__ int tile_outputs(int t, int pack) {
-  return 64 * t - (pack == 9 ? 4 : 0);
+  return 64 * t - (pack == 9 || pack == 11 ? 4 : 0);
 }
+// Group-sum tilings (the first subband step only): the packed halves are the group sums
+constexpr __host__ __device__ bool is_group(int pack) { return pack == 4 || pack == 11; }
 // DM-pair tilings (16-bit samples): per pair and chunk, channels in 16 classes of (first
 // trial's sample parity, delay step)
 constexpr __host__ __device__ bool is_pairs(int pack) { return pack == 5 || pack == 10; }

@@ -18,7 +18,8 @@ namespace arts {
 // runs (raw-dword frames per sub-dword class, added into the totals at the end of each run),
 // 9 framed runs whose lanes read J dwords per channel and take the sums of their last dword
 // from the next lane (a tile then covers 64 T - 4 outputs), 10 DM pairs summed in raw frames
-// per sample parity (16-bit samples), aligned once per chunk.
+// per sample parity (16-bit samples), aligned once per chunk, 11 framed runs (last word shared)
+// added into packed group sums at the end of each run (split plans).
 #define ARTS_TILINGS(X)                                                                    \
   X(0, 4, 5, 4, 8, 0)   /* 32 DMs x 1280 samples per block, 80 accumulators per lane */    \
   X(1, 4, 7, 3, 8, 0)   /* 24 DMs x 1792 */                                                \
@@ -50,7 +51,8 @@ namespace arts {
   X(27, 4, 5, 4, 8, 7)  /* framed runs: 32 DMs x 1280 */                                   \
   X(28, 4, 5, 4, 8, 9)  /* framed runs, last word shared: 32 DMs x 1276 */                 \
   X(29, 4, 5, 3, 8, 9)  /* framed runs, last word shared: 24 DMs x 1276 */ \
-  X(30, 2, 5, 4, 8, 10) /* downsampled, DM pairs in raw frames: 32 DMs x 640 */
+  X(30, 2, 5, 4, 8, 10) /* downsampled, DM pairs in raw frames: 32 DMs x 640 */            \
+  X(31, 4, 5, 4, 8, 11) /* 32 DMs x 1276, framed runs into group sums (split plans) */
 
 const TileVariant kVariants[] = {
 #define ARTS_X(id, spd, j, acc, waves, pack) {spd, j, acc, waves, pack},
@@ -78,12 +80,12 @@ int packed_variant(int64_t ndm) {
   return s24 * 102 < s32 * 100 ? 10 : 9;
 }
 
-// The first step of subband plans: the group-sum tiling (32 DMs per block) when the coarse
-// trials fill its blocks, else the held one (16 per block), else as above.  Plan creation
+// The first step of subband plans: framed runs into group sums (32 DMs per block) when the
+// coarse trials fill its blocks, else the held packed halves (16 per block), else as above.  Plan creation
 // falls back to the default if the choice does not fit (for instance groups of more than 257
 // channels).
 int split_variant(int64_t ncoarse) {
-  if (ncoarse % 32 == 0) return 23;
+  if (ncoarse % 32 == 0) return 31;
   return ncoarse % 16 == 0 ? 22 : packed_variant(ncoarse);
 }
 
@@ -747,6 +749,81 @@ __device__ __forceinline__ void accum_frame_run(uint32_t* acc, const int32_t* en
   frame_to_totals<J, MS, SH>(acc, A, O);
 }
 
+// Framed runs into group sums: at the end of a run of sub-dword class MS its frame, now exact
+// (E = A - 256 O even bytes, O odd bytes, the sums of the lane's last dword taken from the next
+// lane), is added into the lane's packed group sums he / ho, where word k holds outputs
+// (4k, 4k + 2) and (4k + 1, 4k + 3).  Byte j of frame word k is output 4k + j - MS, so E and O
+// land there directly (MS = 0), through one v_alignbyte_b32 per word (half-word shifts), or
+// one word later (MS = 3, E).  A group has at most 257 channels, so no half carries into its
+// neighbour and the 32-bit adds are exact.
+template <int J, int MS>
+__device__ __forceinline__ void frame_to_group(uint32_t* he, uint32_t* ho, const uint32_t* A,
+                                               const uint32_t* O) {
+  uint32_t e[J + 1], o[J + 1];
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    e[k] = even_sums(A[k], O[k]);
+    o[k] = O[k];
+  }
+  if constexpr (MS > 0) {
+    const int next = ((__lane_id() + 1) & 63) << 2;
+    e[J] = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(next, static_cast<int>(e[0])));
+    o[J] = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(next, static_cast<int>(o[0])));
+  }
+#pragma unroll
+  for (int k = 0; k < J; ++k) {
+    if constexpr (MS == 0) {
+      he[k] += e[k];
+      ho[k] += o[k];
+    } else if constexpr (MS == 1) {
+      he[k] += o[k];
+      ho[k] += __builtin_amdgcn_alignbyte(e[k + 1], e[k], 2);
+    } else if constexpr (MS == 2) {
+      he[k] += __builtin_amdgcn_alignbyte(e[k + 1], e[k], 2);
+      ho[k] += __builtin_amdgcn_alignbyte(o[k + 1], o[k], 2);
+    } else {
+      he[k] += __builtin_amdgcn_alignbyte(o[k + 1], o[k], 2);
+      ho[k] += e[k + 1];
+    }
+  }
+}
+
+template <int J, int MS>
+__device__ __forceinline__ void accum_frame_run_group(uint32_t* he, uint32_t* ho,
+                                                      const int32_t* ent, int n,
+                                                      const uint8_t* lane_base) {
+  if (n == 0) return;
+  uint32_t A[J], O[J];
+  int i;
+  if (n & 1) {
+    uint32_t w[J];
+    load_words<J>(w, lane_base, ent[0]);
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+      A[k] = w[k];
+      O[k] = odd_bytes(w[k]);
+    }
+    i = 1;
+  } else {
+    uint32_t w[2][J];
+    load_words<J>(w[0], lane_base, ent[0]);
+    load_words<J>(w[1], lane_base, ent[1]);
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+      A[k] = w[0][k] + w[1][k];
+      O[k] = odd_bytes(w[0][k]) + odd_bytes(w[1][k]);
+    }
+    i = 2;
+  }
+  for (; i < n; i += 2) {
+    uint32_t w[2][J];
+    load_words<J>(w[0], lane_base, ent[i]);
+    load_words<J>(w[1], lane_base, ent[i + 1]);
+    add_fr<J>(A, O, w[0], w[1]);
+  }
+  frame_to_group<J, MS>(he, ho, A, O);
+}
+
 typedef __attribute__((address_space(1))) const void* global_ptr_t;
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
@@ -917,7 +994,7 @@ __device__ __forceinline__ void store_tile(const DedispArgs& a, const uint32_t (
 template <int J, int ACC>
 __device__ __forceinline__ void store_group_pk(const DedispArgs& a, uint32_t (*e)[J],
                                                uint32_t (*o)[J], int64_t off, int b,
-                                               int dwave0, int64_t t0, int lane) {
+                                               int dwave0, int64_t t0, int64_t tend, int lane) {
   constexpr int T = 4 * J;
 #pragma unroll
   for (int x = 0; x < ACC; ++x) {
@@ -926,7 +1003,7 @@ __device__ __forceinline__ void store_group_pk(const DedispArgs& a, uint32_t (*e
       const int64_t row = off + static_cast<int64_t>(b) * a.out_bstride + d * a.out_pitch;
       uint16_t* op = reinterpret_cast<uint16_t*>(a.out) + row;
       const int64_t tl = t0 + static_cast<int64_t>(lane) * T;
-      if (tl + T <= a.nout && (reinterpret_cast<uintptr_t>(op + tl) & 7u) == 0) {
+      if (tl + T <= tend && (reinterpret_cast<uintptr_t>(op + tl) & 7u) == 0) {
         uint2* q = reinterpret_cast<uint2*>(op + tl);
 #pragma unroll
         for (int k = 0; k < J; ++k)
@@ -939,7 +1016,7 @@ __device__ __forceinline__ void store_group_pk(const DedispArgs& a, uint32_t (*e
                                  o[x][k] >> 16};
 #pragma unroll
           for (int m = 0; m < 4; ++m)
-            if (tl + 4 * k + m < a.nout) op[tl + 4 * k + m] = static_cast<uint16_t>(v[m]);
+            if (tl + 4 * k + m < tend) op[tl + 4 * k + m] = static_cast<uint16_t>(v[m]);
         }
       }
     }
@@ -967,7 +1044,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   const bool wave_active = dwave0 < a.ndm;
 
   // int32 totals (unused by the group-sum variants, whose groups fit the packed halves)
-  constexpr int TA = (PK == 4) ? 1 : T;
+  constexpr int TA = is_group(PK) ? 1 : T;
   uint32_t acc[ACC][TA];
 #pragma unroll
   for (int x = 0; x < ACC; ++x)
@@ -987,10 +1064,10 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   }
   // held and group-sum variants: per DM, packed halves that persist across chunks (unused
   // otherwise)
-  constexpr int NH = (PK == 3 || PK == 4) ? ACC : 1;
-  constexpr int NHW = (PK == 3 || PK == 4) ? J : 1;
+  constexpr int NH = (PK == 3 || is_group(PK)) ? ACC : 1;
+  constexpr int NHW = (PK == 3 || is_group(PK)) ? J : 1;
   uint32_t he[NH][NHW], ho[NH][NHW];
-  if constexpr (PK == 3 || PK == 4) {
+  if constexpr (PK == 3 || is_group(PK)) {
 #pragma unroll
     for (int x = 0; x < NH; ++x)
 #pragma unroll
@@ -1023,9 +1100,9 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
     // the stores have this chunk's work to complete before the wait at its end
     if constexpr (SPLIT) {
       if (ch > 0 && (c0 % a.split) == 0 && wave_active) {
-        if constexpr (PK == 4) {
+        if constexpr (is_group(PK)) {
           store_group_pk<J, ACC>(a, he, ho, (c0 / a.split - 1) * a.out_sstride, b, dwave0, t0,
-                                 lane);
+                                 tend, lane);
         } else {
           if constexpr (PK == 3) {
 #pragma unroll
@@ -1119,6 +1196,13 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
           accum_run_pk<J, 1, PF>(he[x], ho[x], ent + n0, n1, lane_base);
           accum_run_pk<J, 2, PF>(he[x], ho[x], ent + n0 + n1, n2, lane_base);
           accum_run_pk<J, 3, PF>(he[x], ho[x], ent + n0 + n1 + n2, n3, lane_base);
+        } else if constexpr (PK == 11) {
+          static_assert(SPD == 4, "framed runs are for byte samples");
+          const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
+          accum_frame_run_group<J, 0>(he[x], ho[x], ent, n0, lane_base);
+          accum_frame_run_group<J, 1>(he[x], ho[x], ent + n0, n1, lane_base);
+          accum_frame_run_group<J, 2>(he[x], ho[x], ent + n0 + n1, n2, lane_base);
+          accum_frame_run_group<J, 3>(he[x], ho[x], ent + n0 + n1 + n2, n3, lane_base);
         } else if constexpr (PK == 7 || PK == 9) {
           static_assert(SPD == 4, "framed runs are for byte samples");
           const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
@@ -1200,9 +1284,9 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
   }
   if constexpr (SPLIT) {  // the last channel group
     if (wave_active) {
-      if constexpr (PK == 4) {
+      if constexpr (is_group(PK)) {
         store_group_pk<J, ACC>(a, he, ho, (a.nchan / a.split - 1) * a.out_sstride, b, dwave0,
-                               t0, lane);
+                               t0, tend, lane);
       } else {
         if constexpr (PK == 3) {
 #pragma unroll
@@ -1227,7 +1311,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
         flush_fr<J, 3>(acc[x], fa[x][3], fo[x][3]);
       }
     }
-    if constexpr (PK != 4)  // group-sum variants run split plans only
+    if constexpr (!is_group(PK))  // group-sum variants run split plans only
       store_tile<T, ACC, false>(a, acc, 0, b, dwave0, t0, tend, lane);
   }
 }
@@ -1379,7 +1463,7 @@ static int launch_variant(DedispArgs a, hipStream_t s) {
   if (a.nwg > INT_MAX) return fail(ARTS_E_INVAL, "grid too large (%lld blocks)", (long long)a.nwg);
   static bool attr_plain = false, attr_split = false;  // one pair per template instance
   if (a.split > 0) {
-    if constexpr (PK == 4)
+    if constexpr (is_group(PK))
       return launch_kernel(&dedisperse_group_kernel<SPD, J, ACC, WAVES, PK>, WAVES, a, lds, s,
                            attr_split);
     else if constexpr (SPD == 4 && PK != 2)
@@ -1388,7 +1472,7 @@ static int launch_variant(DedispArgs a, hipStream_t s) {
     else
       return fail(ARTS_E_INVAL, "this tiling variant cannot split channel groups");
   }
-  if constexpr (PK == 4)
+  if constexpr (is_group(PK))
     return fail(ARTS_E_INVAL, "group-sum tilings run the first subband step only");
   else
     return launch_kernel(&dedisperse_kernel<SPD, J, ACC, WAVES, PK, false>, WAVES, a, lds, s,
@@ -1397,7 +1481,7 @@ static int launch_variant(DedispArgs a, hipStream_t s) {
 
 template <int SPD, int J, int ACC, int WAVES, int PK>
 static int launch_batch_variant(BatchArgs q, size_t lds, hipStream_t s) {
-  if constexpr (PK == 4) {
+  if constexpr (is_group(PK)) {
     return fail(ARTS_E_INVAL, "group-sum tilings run the first subband step only");
   } else {
     if (lds + kBatchStaticLds > 160 * 1024)
@@ -1554,7 +1638,7 @@ template <int SPD, int J, int ACC, int WAVES, int PK>
 static int occupancy_variant(int kind) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
-  if constexpr (PK == 4) {  // group sums: split plans only, no persistent instance
+  if constexpr (is_group(PK)) {  // group sums: split plans only, no persistent instance
     if (kind == kOccBatch) return 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &n, dedisperse_group_kernel<SPD, J, ACC, WAVES, PK>, WAVES * 64, 0);
