@@ -224,8 +224,10 @@ int arts_plan_autotune(arts_plan_t plan, int32_t nbeam, int64_t nin, int32_t rep
  * across chunks; " framed runs": raw-dword frames per run of channels with one sub-dword
  * offset, added into the totals at the end of each run; " framed runs shared": the same with
  * each lane taking the sums of its last dword from the next lane (a time tile then covers
- * 64 x 4J - 4 outputs); " pairs": two DM trials of 16-bit samples summed from one window
- * read; " pairs framed": the same in raw frames per sample parity; none: single-sample adds. */
+ * 64 x 4J - 4 outputs); " framed runs group sums": shared-word framed runs added into the
+ * packed channel-group sums of the first subband step (split plans only); " pairs": two DM
+ * trials of 16-bit samples summed from one window read; " pairs framed": the same in raw
+ * frames per sample parity; none: single-sample adds.                                        */
 int arts_tiling_describe(int32_t variant, char* buf, int32_t len);
 /* Workgroups per CU that registers and waves allow (LDS aside) on the current device for a
  * variant's one-launch kernel (*per_job; for group-sum variants the split-plan kernel) and its
