@@ -169,6 +169,8 @@ int build_tiling(arts_plan_s* p, int variant) {
   int cc = static_cast<int>(
       std::min<int64_t>({nchan, cc_max, per_buf / (4LL * (t.win_dwords + t.m_blk))}));
   if (p->tile_cc > 0) cc = std::min(cc, p->tile_cc);
+  // DM pairs in raw frames hold a pair's offset list one entry per lane
+  if (v.pack == 10) cc = std::min(cc, 64);
   // split plans: chunks must not straddle channel groups, so cc divides the group size
   if (p->split > 0)
     while (cc > 1 && p->split % cc != 0) --cc;

@@ -512,7 +512,7 @@ __device__ __forceinline__ void load_words(uint32_t* w, const uint8_t* lane_base
 // and trial, shared by two channels in v_add3_u32, and no per-channel alignment.
 template <int J, int M0, int DELTA>
 __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
-                                                      uint32_t (*f1)[J + 1], const int32_t* ent,
+                                                      uint32_t (*f1)[J + 1], int32_t lv, int pos,
                                                       int n, const uint8_t* lane_base) {
   constexpr int S = M0 + DELTA;
   constexpr int NW = J + (S + 1) / 2;    // union of both trials' words
@@ -521,8 +521,8 @@ __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
   int i = 0;
   for (; i + 2 <= n; i += 2) {
     uint32_t w[2][NW];
-    load_words<NW>(w[0], lane_base, ent[i]);
-    load_words<NW>(w[1], lane_base, ent[i + 1]);
+    load_words<NW>(w[0], lane_base, __builtin_amdgcn_readlane(lv, pos + i));
+    load_words<NW>(w[1], lane_base, __builtin_amdgcn_readlane(lv, pos + i + 1));
 #pragma unroll
     for (int k = 0; k < N0; ++k) f0[M0][k] += w[0][k] + w[1][k];
 #pragma unroll
@@ -530,7 +530,7 @@ __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
   }
   if (i < n) {
     uint32_t w[NW];
-    load_words<NW>(w, lane_base, ent[i]);
+    load_words<NW>(w, lane_base, __builtin_amdgcn_readlane(lv, pos + i));
 #pragma unroll
     for (int k = 0; k < N0; ++k) f0[M0][k] += w[k];
 #pragma unroll
@@ -538,15 +538,18 @@ __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
   }
 }
 
+// Every class of one pair.  The pair's offset list for the chunk (at most 64 entries: the plan
+// caps these chunks) is held one entry per lane in lv, so a channel's offset comes from one
+// v_readlane_b32 instead of an LDS round trip before each class's reads.
 template <int J, int CLS>
 __device__ __forceinline__ void accum_pair_frames(uint32_t (*f0)[J + 1], uint32_t (*f1)[J + 1],
-                                                  const int32_t* ent, const uint32_t* cnt,
+                                                  int32_t lv, int pos, const uint32_t* cnt,
                                                   const uint8_t* lane_base) {
   if constexpr (CLS < kPairClasses) {
     const int n = (cnt[CLS / 4] >> (8 * (CLS % 4))) & 0xff;
     accum_run_pair_frames<J, CLS / (kPairMaxDelta + 1), CLS % (kPairMaxDelta + 1)>(
-        f0, f1, ent, n, lane_base);
-    accum_pair_frames<J, CLS + 1>(f0, f1, ent + n, cnt, lane_base);
+        f0, f1, lv, pos, n, lane_base);
+    accum_pair_frames<J, CLS + 1>(f0, f1, lv, pos + n, cnt, lane_base);
   }
 }
 
@@ -1244,7 +1247,9 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
             for (int m = 0; m < 2; ++m)
 #pragma unroll
               for (int k = 0; k <= J; ++k) f0[m][k] = f1[m][k] = 0;
-            accum_pair_frames<J, 0>(f0, f1, ent_cur + pr * a.cc, cnt4, lane_base);
+            const int32_t* lst = ent_cur + pr * a.cc;
+            const int32_t lv = lane < min(a.cc, a.nchan - c0) ? lst[lane] : 0;
+            accum_pair_frames<J, 0>(f0, f1, lv, 0, cnt4, lane_base);
             flush_pair_frames<J>(acc[x], f0);
             flush_pair_frames<J>(acc[x + 1], f1);
           }
