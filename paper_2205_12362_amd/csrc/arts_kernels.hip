@@ -519,22 +519,41 @@ __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
   constexpr int W1 = S / 2, P1 = S % 2;  // the second trial's first word and parity
   constexpr int N0 = J + M0, N1 = J + P1;
   int i = 0;
-  for (; i + 2 <= n; i += 2) {
-    uint32_t w[2][NW];
-    load_words<NW>(w[0], lane_base, __builtin_amdgcn_readlane(lv, pos + i));
-    load_words<NW>(w[1], lane_base, __builtin_amdgcn_readlane(lv, pos + i + 1));
+  for (; i + 4 <= n; i += 4) {
+    uint32_t w[4][NW];
 #pragma unroll
-    for (int k = 0; k < N0; ++k) f0[M0][k] += w[0][k] + w[1][k];
+    for (int u = 0; u < 4; ++u)
+      load_words<NW>(w[u], lane_base, __builtin_amdgcn_readlane(lv, pos + i + u));
 #pragma unroll
-    for (int k = 0; k < N1; ++k) f1[P1][k] += w[0][W1 + k] + w[1][W1 + k];
+    for (int k = 0; k < N0; ++k) f0[M0][k] += (w[0][k] + w[1][k]) + (w[2][k] + w[3][k]);
+#pragma unroll
+    for (int k = 0; k < N1; ++k)
+      f1[P1][k] += (w[0][W1 + k] + w[1][W1 + k]) + (w[2][W1 + k] + w[3][W1 + k]);
   }
-  if (i < n) {
-    uint32_t w[NW];
-    load_words<NW>(w, lane_base, __builtin_amdgcn_readlane(lv, pos + i));
+  // the last 1-3 channels: read together (the unused reads repeat the run's last channel),
+  // so that a short class waits for LDS once
+  const int r = n - i;
+  if (r > 0) {
+    uint32_t w[3][NW];
 #pragma unroll
-    for (int k = 0; k < N0; ++k) f0[M0][k] += w[k];
+    for (int u = 0; u < 3; ++u)
+      load_words<NW>(w[u], lane_base, __builtin_amdgcn_readlane(lv, pos + i + min(u, r - 1)));
+    if (r == 1) {
 #pragma unroll
-    for (int k = 0; k < N1; ++k) f1[P1][k] += w[W1 + k];
+      for (int k = 0; k < N0; ++k) f0[M0][k] += w[0][k];
+#pragma unroll
+      for (int k = 0; k < N1; ++k) f1[P1][k] += w[0][W1 + k];
+    } else if (r == 2) {
+#pragma unroll
+      for (int k = 0; k < N0; ++k) f0[M0][k] += w[0][k] + w[1][k];
+#pragma unroll
+      for (int k = 0; k < N1; ++k) f1[P1][k] += w[0][W1 + k] + w[1][W1 + k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < N0; ++k) f0[M0][k] += (w[0][k] + w[1][k]) + w[2][k];
+#pragma unroll
+      for (int k = 0; k < N1; ++k) f1[P1][k] += (w[0][W1 + k] + w[1][W1 + k]) + w[2][W1 + k];
+    }
   }
 }
 
