@@ -762,7 +762,19 @@ __device__ __forceinline__ void accum_frame_run(uint32_t* acc, const int32_t* en
     }
     i = 2;
   }
-  for (; i < n; i += 2) {  // the rest in pairs
+  for (; i + 4 <= n; i += 4) {  // the rest in pairs, four offsets read at a time
+    int32_t q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = ent[i + u];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint32_t w[2][NW];
+      load_words<NW>(w[0], lane_base, q[2 * h]);
+      load_words<NW>(w[1], lane_base, q[2 * h + 1]);
+      add_fr<NW>(A, O, w[0], w[1]);
+    }
+  }
+  if (i < n) {
     uint32_t w[2][NW];
     load_words<NW>(w[0], lane_base, ent[i]);
     load_words<NW>(w[1], lane_base, ent[i + 1]);
@@ -837,7 +849,19 @@ __device__ __forceinline__ void accum_frame_run_group(uint32_t* he, uint32_t* ho
     }
     i = 2;
   }
-  for (; i < n; i += 2) {
+  for (; i + 4 <= n; i += 4) {  // the rest in pairs, four offsets read at a time
+    int32_t q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = ent[i + u];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint32_t w[2][J];
+      load_words<J>(w[0], lane_base, q[2 * h]);
+      load_words<J>(w[1], lane_base, q[2 * h + 1]);
+      add_fr<J>(A, O, w[0], w[1]);
+    }
+  }
+  if (i < n) {
     uint32_t w[2][J];
     load_words<J>(w[0], lane_base, ent[i]);
     load_words<J>(w[1], lane_base, ent[i + 1]);
