@@ -572,16 +572,19 @@ __device__ __forceinline__ void accum_pair_frames(uint32_t (*f0)[J + 1], uint32_
   }
 }
 
-// Widen a trial's two parity frames into its int32 totals (outputs 2k, 2k + 1 per word).
+// Widen a trial's two parity frames into its int32 totals (outputs 2k, 2k + 1 per word).  Every
+// channel of the chunk sits in exactly one of the two frames, so the halves of the two frames
+// added together still hold at most one chunk of channels and one packed 16-bit add is exact.
 template <int J>
 __device__ __forceinline__ void flush_pair_frames(uint32_t* acc, const uint32_t (*f)[J + 1]) {
+  typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int k = 0; k < J; ++k) {
     const uint32_t odd = __builtin_amdgcn_alignbyte(f[1][k + 1], f[1][k], 2);
-    add_half<0>(acc[2 * k], f[0][k]);
-    add_half<1>(acc[2 * k + 1], f[0][k]);
-    add_half<0>(acc[2 * k], odd);
-    add_half<1>(acc[2 * k + 1], odd);
+    const uint32_t both = __builtin_bit_cast(
+        uint32_t, __builtin_bit_cast(u16x2, f[0][k]) + __builtin_bit_cast(u16x2, odd));
+    add_half<0>(acc[2 * k], both);
+    add_half<1>(acc[2 * k + 1], both);
   }
 }
 
