@@ -123,6 +123,54 @@ def test_shared_word_tile_edges(variant):
             assert np.array_equal(got, O.dedisperse(data, delays)), nout
 
 
+def _framed_sweep_variants():
+    return [v for v in range(arts.arts_tiling_count())
+            if ("framed runs" in arts.arts_tiling_describe(v)
+                and "group" not in arts.arts_tiling_describe(v))
+            or "pairs framed" in arts.arts_tiling_describe(v)]
+
+
+@pytest.mark.parametrize("variant", _framed_sweep_variants())
+def test_framed_channels_per_chunk(variant):
+    # channels per chunk 1..13, 17, 44 and as many as the plan allows: a class's run takes every
+    # length from 0 up (byte runs: an odd run's lone first channel, then four offsets per step,
+    # then a last pair; DM pairs: four channels per step, then the last one to three together),
+    # one and two LDS buffers; the largest chunk also with all-255 input, which fills the 16-bit
+    # halves of a chunk's frames (for the DM pairs, both parity frames merged at the flush)
+    desc = arts.arts_tiling_describe(variant)
+    pairs = "pairs" in desc
+    if pairs:
+        D, nchan = 4, 160
+        dms = 2048.0 + 2.3 * np.arange(64)
+    else:
+        D, nchan = 1, 96
+        dms = np.arange(70) * 1.3
+    f_lo, df = synth.band(nchan)
+    delays = O.delay_table(nchan, f_lo, df, synth.TSAMP, dms, downsample=D)
+    nin = (int(delays.max()) + 1500) * D + (D - 1)
+    w = synth.Workload("sweep", nchan, f_lo, df, synth.TSAMP, dms, [1], downsample=D)
+    rng = np.random.default_rng(variant + 4000)
+    data = rng.integers(0, 256, size=(nchan, nin), dtype=np.uint8)
+    ref = O.dedisperse(O.downsample(data, D) if D > 1 else data, delays)
+    full = np.full((nchan, nin), 255, np.uint8)
+    with _plan(w) as p:
+        shapes = [(cc, 1 + cc % 2) for cc in list(range(1, 14)) + [17]] + [(44, 2), (0, 1)]
+        for cc, buffers in shapes:
+            p.set_tiling_shape(variant, buffers, cc)
+            v, nb, used = p.tiling_shape()
+            _say("framed chunk sweep", variant, desc, "buffers", nb, "channels", used)
+            # a requested count is an upper bound: the LDS may hold fewer
+            assert (v, nb) == (variant, buffers) and 1 <= used <= (cc or 255)
+            assert cc == 0 or cc > 17 or used == cc
+            got = p.dedisperse(to_dev(data)).cpu().numpy()[0]
+            assert np.array_equal(got, ref), (cc, buffers)
+        assert used > 17
+        if pairs:
+            assert used <= 64  # the plan's cap for these chunks: 64 x 1020 < 2^16
+        got = p.dedisperse(to_dev(full)).cpu().numpy()[0]
+        assert np.all(got == 255 * D * nchan)
+
+
 @pytest.mark.parametrize("nchan,ndm,extra", [(1, 1, 1), (3, 5, 2), (37, 33, 1000), (7, 70, 5),
                                              (255, 9, 300), (256, 40, 64), (300, 3, 33)])
 def test_dedisperse_edge_shapes(nchan, ndm, extra):
