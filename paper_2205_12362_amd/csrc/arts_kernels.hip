@@ -495,6 +495,10 @@ __device__ __forceinline__ void accum_pair_classes(uint32_t* pk0, uint32_t* pk1,
   }
 }
 
+// A block's offset list read from global memory through the scalar cache: base and index are
+// uniform, so four offsets are one s_load_dwordx4, which costs the LDS and the VALU nothing.
+typedef const __attribute__((address_space(4))) int32_t* const_list_t;
+
 // NW consecutive LDS dwords of a channel's window, from the lane's word at byte offset off.
 template <int NW>
 __device__ __forceinline__ void load_words(uint32_t* w, const uint8_t* lane_base, int32_t off) {
@@ -739,7 +743,7 @@ __device__ __forceinline__ void frame_to_totals(uint32_t* acc, const uint32_t* A
 }
 
 template <int J, int MS, bool SH>
-__device__ __forceinline__ void accum_frame_run(uint32_t* acc, const int32_t* ent, int n,
+__device__ __forceinline__ void accum_frame_run(uint32_t* acc, const_list_t ent, int n,
                                                 const uint8_t* lane_base) {
   if (n == 0) return;
   constexpr int NW = (MS == 0 || SH) ? J : J + 1;
@@ -1256,10 +1260,15 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
           static_assert(SPD == 4, "framed runs are for byte samples");
           const int n2 = (packed >> 16) & 0xff, n3 = packed >> 24;
           constexpr bool SH = PK == 9;
-          accum_frame_run<J, 0, SH>(acc[x], ent, n0, lane_base);
-          accum_frame_run<J, 1, SH>(acc[x], ent + n0, n1, lane_base);
-          accum_frame_run<J, 2, SH>(acc[x], ent + n0 + n1, n2, lane_base);
-          accum_frame_run<J, 3, SH>(acc[x], ent + n0 + n1 + n2, n3, lane_base);
+          // the runs read their offsets from the global list through the scalar cache; the
+          // chunk's copy in LDS goes unread, but fetching it has just brought those lines into
+          // L2 (the whole list table does not stay there), so the scalar loads hit
+          const const_list_t gl = (const_list_t)(list_blk +
+                                                 static_cast<int64_t>(wave * ACC + x) * a.nchan + c0);
+          accum_frame_run<J, 0, SH>(acc[x], gl, n0, lane_base);
+          accum_frame_run<J, 1, SH>(acc[x], gl + n0, n1, lane_base);
+          accum_frame_run<J, 2, SH>(acc[x], gl + n0 + n1, n2, lane_base);
+          accum_frame_run<J, 3, SH>(acc[x], gl + n0 + n1 + n2, n3, lane_base);
         } else if constexpr (PK == 5) {
           // DM pairs: trials (x, x + 1) of the wave at even x; odd x have been summed
           static_assert(SPD == 2 && ACC % 2 == 0, "DM pairs are for 16-bit samples");
