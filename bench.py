@@ -192,9 +192,16 @@ def kernel_name(describe):
 
 
 def kernel_hash():
+    """Hash of the kernel source's code: comments, trailing blanks and empty lines removed, so
+    that a comment edit does not void counters taken on the same code."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    import re
+    with open(KERNEL_SRC, encoding="utf-8") as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", l).rstrip() for l in text.splitlines())
+    code = "\n".join(l for l in lines if l)
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def measured_traffic(kernel):

@@ -742,6 +742,8 @@ __device__ __forceinline__ void frame_to_totals(uint32_t* acc, const uint32_t* A
   }
 }
 
+// One run: n channels of class MS, whose window offsets in the chunk's LDS (bytes from the
+// lane's word) ent lists in the plan's global table, read four at a time by scalar loads.
 template <int J, int MS, bool SH>
 __device__ __forceinline__ void accum_frame_run(uint32_t* acc, const_list_t ent, int n,
                                                 const uint8_t* lane_base) {
