@@ -52,7 +52,9 @@ namespace arts {
   X(28, 4, 5, 4, 8, 9)  /* framed runs, last word shared: 32 DMs x 1276 */                 \
   X(29, 4, 5, 3, 8, 9)  /* framed runs, last word shared: 24 DMs x 1276 */ \
   X(30, 2, 5, 4, 8, 10) /* downsampled, DM pairs in raw frames: 32 DMs x 640 */            \
-  X(31, 4, 5, 4, 8, 11) /* 32 DMs x 1276, framed runs into group sums (split plans) */
+  X(31, 4, 5, 4, 8, 11) /* 32 DMs x 1276, framed runs into group sums (split plans) */     \
+  X(32, 4, 5, 2, 12, 9) /* framed runs, last word shared, 12-wave blocks, six waves per SIMD:
+                           24 DMs x 1276 */
 
 const TileVariant kVariants[] = {
 #define ARTS_X(id, spd, j, acc, waves, pack) {spd, j, acc, waves, pack},
@@ -89,12 +91,13 @@ int split_variant(int64_t ncoarse) {
   return ncoarse % 16 == 0 ? 22 : packed_variant(ncoarse);
 }
 
-// Byte samples, plain plans: framed runs with a shared last word, 32 DMs per block (28) unless
-// 24 per block (29) leaves fewer idle DM slots; a slot of 29 costs about 3% more than one of 28
-// (serving plan: 74.5 ms for 2064 slots against 71.6 ms for 2048).
+// Byte samples, plain plans: framed runs with a shared last word in 12-wave blocks of 24 DMs
+// (32: six waves per SIMD) unless 32 DMs per block (28: four waves per SIMD) leave enough fewer
+// idle DM slots; a slot of 28 costs about 7% more than one of 32 (serving plan: 68.8 ms for
+// 2048 slots against 63.9 ms for 2064).
 int runs_variant(int64_t ndm) {
   const int64_t s24 = (ndm + 23) / 24 * 24, s32 = (ndm + 31) / 32 * 32;
-  return s24 * 103 < s32 * 100 ? 29 : 28;
+  return s24 * 100 <= s32 * 107 ? 32 : 28;
 }
 
 int default_variant(int downsample, int64_t ndm) {
@@ -1398,6 +1401,16 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
   dedisperse_grid<SPD, J, ACC, WAVES, PK, SPLIT>(a, lds);
 }
 
+// Framed runs in 12-wave blocks of 2 DMs per wave: compiled for six waves per SIMD (at most 80
+// VGPRs), so that two blocks share a CU and every SIMD holds six waves to hide the LDS
+// latency of the others (the 8-wave tilings hold four).
+template <>
+__global__ __launch_bounds__(12 * 64) __attribute__((amdgpu_waves_per_eu(6)))
+void dedisperse_kernel<4, 5, 2, 12, 9, false>(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  dedisperse_grid<4, 5, 2, 12, 9, false>(a, lds);
+}
+
 // Group-sum split plans (the first subband step): four waves per SIMD, two 8-wave workgroups.
 template <int SPD, int J, int ACC, int WAVES, int PK>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
@@ -1432,13 +1445,14 @@ struct BatchArgs {
 // same tiling reaches, since the plan sizes its LDS chunks for that many workgroups per CU.
 // Four (<= 128 VGPRs: two 8-wave workgroups per CU), except six (<= 80 VGPRs) for the two
 // plain tilings whose one-launch kernels need 76 registers: 16-bit samples with 32 DMs per
-// block (three 8-wave workgroups per CU) and byte samples with 8 DMs per 4-wave block (six).
+// block (three 8-wave workgroups per CU) and byte samples with 8 DMs per 4-wave block (six),
+// and for the 12-wave framed runs (two blocks per CU).
 template <int SPD, int J, int ACC, int WAVES, int PK>
 constexpr int batch_waves_per_eu() {
   return (PK == 0 && J == 5 && ((SPD == 2 && ACC == 4 && WAVES == 8) ||
                                 (SPD == 4 && ACC == 2 && WAVES == 4)))
              ? 6
-             : 4;
+             : (WAVES == 12 ? 6 : 4);
 }
 
 template <int SPD, int J, int ACC, int WAVES, int PK>
