@@ -54,7 +54,8 @@ namespace arts {
   X(30, 2, 5, 4, 8, 10) /* downsampled, DM pairs in raw frames: 32 DMs x 640 */            \
   X(31, 4, 5, 4, 8, 11) /* 32 DMs x 1276, framed runs into group sums (split plans) */     \
   X(32, 4, 5, 2, 12, 9) /* framed runs, last word shared, 12-wave blocks, six waves per SIMD:
-                           24 DMs x 1276 */
+                           24 DMs x 1276 */ \
+  X(33, 2, 5, 2, 12, 10) /* DM pairs in raw frames, 12-wave blocks, six waves per SIMD */
 
 const TileVariant kVariants[] = {
 #define ARTS_X(id, spd, j, acc, waves, pack) {spd, j, acc, waves, pack},
@@ -100,8 +101,10 @@ int runs_variant(int64_t ndm) {
   return s24 * 100 <= s32 * 107 ? 32 : 28;
 }
 
+// Downsampled samples: DM pairs in raw frames in 12-wave blocks at six waves per SIMD (33);
+// on the serving plan 14.6 ms per plan call against 15.0 ms in 8-wave blocks (30).
 int default_variant(int downsample, int64_t ndm) {
-  if (downsample > 1) return 30;
+  if (downsample > 1) return 33;
   return ndm <= 64 ? 17 : runs_variant(ndm);
 }
 
@@ -516,8 +519,10 @@ __device__ __forceinline__ void load_words(uint32_t* w, const uint8_t* lane_base
 // sample later, which one v_alignbyte_b32 per word undoes when the frames are widened at the
 // end of the pair's chunk.  A half never carries into its neighbour (a chunk holds at most
 // floor(65535 / (255 D)) channels), so the frames are exact: a channel costs one add per word
-// and trial, shared by two channels in v_add3_u32, and no per-channel alignment.
-template <int J, int M0, int DELTA>
+// and trial, shared by two channels in v_add3_u32, and no per-channel alignment.  A class's
+// channels are read STEP at a time: four (then the last one to three together), or two where
+// the registers must leave room for six waves per SIMD.
+template <int J, int M0, int DELTA, int STEP>
 __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
                                                       uint32_t (*f1)[J + 1], int32_t lv, int pos,
                                                       int n, const uint8_t* lane_base) {
@@ -526,6 +531,27 @@ __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
   constexpr int W1 = S / 2, P1 = S % 2;  // the second trial's first word and parity
   constexpr int N0 = J + M0, N1 = J + P1;
   int i = 0;
+  if constexpr (STEP == 2) {  // two channels per step: fewer words live, for more waves
+    for (; i + 2 <= n; i += 2) {
+      uint32_t w[2][NW];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        load_words<NW>(w[u], lane_base, __builtin_amdgcn_readlane(lv, pos + i + u));
+#pragma unroll
+      for (int k = 0; k < N0; ++k) f0[M0][k] += w[0][k] + w[1][k];
+#pragma unroll
+      for (int k = 0; k < N1; ++k) f1[P1][k] += w[0][W1 + k] + w[1][W1 + k];
+    }
+    if (i < n) {
+      uint32_t w[NW];
+      load_words<NW>(w, lane_base, __builtin_amdgcn_readlane(lv, pos + i));
+#pragma unroll
+      for (int k = 0; k < N0; ++k) f0[M0][k] += w[k];
+#pragma unroll
+      for (int k = 0; k < N1; ++k) f1[P1][k] += w[W1 + k];
+    }
+    return;
+  }
   for (; i + 4 <= n; i += 4) {
     uint32_t w[4][NW];
 #pragma unroll
@@ -567,15 +593,15 @@ __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
 // Every class of one pair.  The pair's offset list for the chunk (at most 64 entries: the plan
 // caps these chunks) is held one entry per lane in lv, so a channel's offset comes from one
 // v_readlane_b32 instead of an LDS round trip before each class's reads.
-template <int J, int CLS>
+template <int J, int CLS, int STEP>
 __device__ __forceinline__ void accum_pair_frames(uint32_t (*f0)[J + 1], uint32_t (*f1)[J + 1],
                                                   int32_t lv, int pos, const uint32_t* cnt,
                                                   const uint8_t* lane_base) {
   if constexpr (CLS < kPairClasses) {
     const int n = (cnt[CLS / 4] >> (8 * (CLS % 4))) & 0xff;
-    accum_run_pair_frames<J, CLS / (kPairMaxDelta + 1), CLS % (kPairMaxDelta + 1)>(
+    accum_run_pair_frames<J, CLS / (kPairMaxDelta + 1), CLS % (kPairMaxDelta + 1), STEP>(
         f0, f1, lv, pos, n, lane_base);
-    accum_pair_frames<J, CLS + 1>(f0, f1, lv, pos + n, cnt, lane_base);
+    accum_pair_frames<J, CLS + 1, STEP>(f0, f1, lv, pos + n, cnt, lane_base);
   }
 }
 
@@ -1309,7 +1335,7 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
               for (int k = 0; k <= J; ++k) f0[m][k] = f1[m][k] = 0;
             const int32_t* lst = ent_cur + pr * a.cc;
             const int32_t lv = lane < min(a.cc, a.nchan - c0) ? lst[lane] : 0;
-            accum_pair_frames<J, 0>(f0, f1, lv, 0, cnt4, lane_base);
+            accum_pair_frames<J, 0, WAVES == 12 ? 2 : 4>(f0, f1, lv, 0, cnt4, lane_base);
             flush_pair_frames<J>(acc[x], f0);
             flush_pair_frames<J>(acc[x + 1], f1);
           }
@@ -1401,14 +1427,21 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
   dedisperse_grid<SPD, J, ACC, WAVES, PK, SPLIT>(a, lds);
 }
 
-// Framed runs in 12-wave blocks of 2 DMs per wave: compiled for six waves per SIMD (at most 80
-// VGPRs), so that two blocks share a CU and every SIMD holds six waves to hide the LDS
-// latency of the others (the 8-wave tilings hold four).
+// 12-wave blocks of 2 DMs per wave (framed runs; DM pairs in raw frames, which read two
+// channels per step to fit): compiled for six waves per SIMD (at most 80 VGPRs), so that two
+// blocks share a CU and every SIMD holds six waves to hide the LDS latency of the others (the
+// 8-wave tilings hold four).
 template <>
 __global__ __launch_bounds__(12 * 64) __attribute__((amdgpu_waves_per_eu(6)))
 void dedisperse_kernel<4, 5, 2, 12, 9, false>(DedispArgs a) {
   extern __shared__ uint32_t lds[];
   dedisperse_grid<4, 5, 2, 12, 9, false>(a, lds);
+}
+template <>
+__global__ __launch_bounds__(12 * 64) __attribute__((amdgpu_waves_per_eu(6)))
+void dedisperse_kernel<2, 5, 2, 12, 10, false>(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  dedisperse_grid<2, 5, 2, 12, 10, false>(a, lds);
 }
 
 // Group-sum split plans (the first subband step): four waves per SIMD, two 8-wave workgroups.
