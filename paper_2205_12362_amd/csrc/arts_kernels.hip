@@ -55,7 +55,9 @@ namespace arts {
   X(31, 4, 5, 4, 8, 11) /* 32 DMs x 1276, framed runs into group sums (split plans) */     \
   X(32, 4, 5, 2, 12, 9) /* framed runs, last word shared, 12-wave blocks, six waves per SIMD:
                            24 DMs x 1276 */ \
-  X(33, 2, 5, 2, 12, 10) /* DM pairs in raw frames, 12-wave blocks, six waves per SIMD */
+  X(33, 2, 5, 2, 12, 10) /* DM pairs in raw frames, 12-wave blocks, six waves per SIMD */ \
+  X(34, 2, 5, 2, 16, 10) /* DM pairs in raw frames, 16-wave blocks, eight waves per SIMD:
+                            32 DMs x 640 */
 
 const TileVariant kVariants[] = {
 #define ARTS_X(id, spd, j, acc, waves, pack) {spd, j, acc, waves, pack},
@@ -101,10 +103,11 @@ int runs_variant(int64_t ndm) {
   return s24 * 100 <= s32 * 107 ? 32 : 28;
 }
 
-// Downsampled samples: DM pairs in raw frames in 12-wave blocks at six waves per SIMD (33);
-// on the serving plan 14.6 ms per plan call against 15.0 ms in 8-wave blocks (30).
+// Downsampled samples: DM pairs in raw frames in 16-wave blocks at eight waves per SIMD (34);
+// on the serving plan 13.4 ms per plan call, against 14.7 ms in 12-wave blocks at six (33)
+// and 15.0 ms in 8-wave blocks at four (30).
 int default_variant(int downsample, int64_t ndm) {
-  if (downsample > 1) return 33;
+  if (downsample > 1) return 34;
   return ndm <= 64 ? 17 : runs_variant(ndm);
 }
 
@@ -520,8 +523,8 @@ __device__ __forceinline__ void load_words(uint32_t* w, const uint8_t* lane_base
 // end of the pair's chunk.  A half never carries into its neighbour (a chunk holds at most
 // floor(65535 / (255 D)) channels), so the frames are exact: a channel costs one add per word
 // and trial, shared by two channels in v_add3_u32, and no per-channel alignment.  A class's
-// channels are read STEP at a time: four (then the last one to three together), or two where
-// the registers must leave room for six waves per SIMD.
+// channels are read STEP at a time: four (then the last one to three together), or two or one
+// where the registers must leave room for six or eight waves per SIMD.
 template <int J, int M0, int DELTA, int STEP>
 __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
                                                       uint32_t (*f1)[J + 1], int32_t lv, int pos,
@@ -531,6 +534,17 @@ __device__ __forceinline__ void accum_run_pair_frames(uint32_t (*f0)[J + 1],
   constexpr int W1 = S / 2, P1 = S % 2;  // the second trial's first word and parity
   constexpr int N0 = J + M0, N1 = J + P1;
   int i = 0;
+  if constexpr (STEP == 1) {  // one channel per step: fewest words live
+    for (; i < n; ++i) {
+      uint32_t w[NW];
+      load_words<NW>(w, lane_base, __builtin_amdgcn_readlane(lv, pos + i));
+#pragma unroll
+      for (int k = 0; k < N0; ++k) f0[M0][k] += w[k];
+#pragma unroll
+      for (int k = 0; k < N1; ++k) f1[P1][k] += w[W1 + k];
+    }
+    return;
+  }
   if constexpr (STEP == 2) {  // two channels per step: fewer words live, for more waves
     for (; i + 2 <= n; i += 2) {
       uint32_t w[2][NW];
@@ -1335,7 +1349,8 @@ __device__ __forceinline__ void dedisperse_tile(const DedispArgs& a, int blk, in
               for (int k = 0; k <= J; ++k) f0[m][k] = f1[m][k] = 0;
             const int32_t* lst = ent_cur + pr * a.cc;
             const int32_t lv = lane < min(a.cc, a.nchan - c0) ? lst[lane] : 0;
-            accum_pair_frames<J, 0, WAVES == 12 ? 2 : 4>(f0, f1, lv, 0, cnt4, lane_base);
+            accum_pair_frames<J, 0, WAVES == 16 ? 1 : WAVES == 12 ? 2 : 4>(f0, f1, lv, 0, cnt4,
+                                                                           lane_base);
             flush_pair_frames<J>(acc[x], f0);
             flush_pair_frames<J>(acc[x + 1], f1);
           }
@@ -1430,7 +1445,8 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
 // 12-wave blocks of 2 DMs per wave (framed runs; DM pairs in raw frames, which read two
 // channels per step to fit): compiled for six waves per SIMD (at most 80 VGPRs), so that two
 // blocks share a CU and every SIMD holds six waves to hide the LDS latency of the others (the
-// 8-wave tilings hold four).
+// 8-wave tilings hold four).  16-wave blocks of one DM pair per wave, reading one channel per
+// step: eight waves per SIMD (at most 64 VGPRs).
 template <>
 __global__ __launch_bounds__(12 * 64) __attribute__((amdgpu_waves_per_eu(6)))
 void dedisperse_kernel<4, 5, 2, 12, 9, false>(DedispArgs a) {
@@ -1442,6 +1458,12 @@ __global__ __launch_bounds__(12 * 64) __attribute__((amdgpu_waves_per_eu(6)))
 void dedisperse_kernel<2, 5, 2, 12, 10, false>(DedispArgs a) {
   extern __shared__ uint32_t lds[];
   dedisperse_grid<2, 5, 2, 12, 10, false>(a, lds);
+}
+template <>
+__global__ __launch_bounds__(16 * 64) __attribute__((amdgpu_waves_per_eu(8)))
+void dedisperse_kernel<2, 5, 2, 16, 10, false>(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  dedisperse_grid<2, 5, 2, 16, 10, false>(a, lds);
 }
 
 // Group-sum split plans (the first subband step): four waves per SIMD, two 8-wave workgroups.
@@ -1479,13 +1501,13 @@ struct BatchArgs {
 // Four (<= 128 VGPRs: two 8-wave workgroups per CU), except six (<= 80 VGPRs) for the two
 // plain tilings whose one-launch kernels need 76 registers: 16-bit samples with 32 DMs per
 // block (three 8-wave workgroups per CU) and byte samples with 8 DMs per 4-wave block (six),
-// and for the 12-wave framed runs (two blocks per CU).
+// and for the 12-wave tilings (two blocks per CU); eight for the 16-wave DM pairs.
 template <int SPD, int J, int ACC, int WAVES, int PK>
 constexpr int batch_waves_per_eu() {
   return (PK == 0 && J == 5 && ((SPD == 2 && ACC == 4 && WAVES == 8) ||
                                 (SPD == 4 && ACC == 2 && WAVES == 4)))
              ? 6
-             : (WAVES == 12 ? 6 : 4);
+             : (WAVES == 12 ? 6 : (WAVES == 16 && PK == 10) ? 8 : 4);
 }
 
 template <int SPD, int J, int ACC, int WAVES, int PK>
