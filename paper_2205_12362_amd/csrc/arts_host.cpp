@@ -550,8 +550,10 @@ static int plan_create_subband(int32_t nchan, double f_lo, double df, double tsa
   if (st == ARTS_OK) {
     p->max_d1 = p->sb1->max_delay;
     const double top = df > 0 ? csub - 1 : 0;
+    // step 2: one block per coarse group (32 trials: 8-wave blocks of 4 per wave at six waves
+    // per SIMD; 16: 16-wave blocks of 1 per wave at eight)
     st = plan_create(nsub, f_lo + top * df, csub * df, tsamp, fine.data(), ndm, kOne, 1, 1,
-                     &p->sb2, true, 255 * csub, nfine == 32 ? 6 : 7);
+                     &p->sb2, true, 255 * csub, nfine == 32 ? 6 : 36);
   }
   if (st != ARTS_OK) {
     plan_free(p);

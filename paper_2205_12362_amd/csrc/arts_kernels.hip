@@ -58,7 +58,8 @@ namespace arts {
   X(33, 2, 5, 2, 12, 10) /* DM pairs in raw frames, 12-wave blocks, six waves per SIMD */ \
   X(34, 2, 5, 2, 16, 10) /* DM pairs in raw frames, 16-wave blocks, eight waves per SIMD:
                             32 DMs x 640 */ \
-  X(35, 4, 5, 2, 16, 11) /* as 31 in 16-wave blocks, eight waves per SIMD (split plans) */
+  X(35, 4, 5, 2, 16, 11) /* as 31 in 16-wave blocks, eight waves per SIMD (split plans) */ \
+  X(36, 2, 5, 1, 16, 0) /* 16-bit, 16-wave blocks, eight waves per SIMD: 16 DMs x 640 */
 
 const TileVariant kVariants[] = {
 #define ARTS_X(id, spd, j, acc, waves, pack) {spd, j, acc, waves, pack},
@@ -1448,7 +1449,8 @@ __global__ __launch_bounds__(WAVES * 64) void dedisperse_kernel(DedispArgs a) {
 // channels per step to fit): compiled for six waves per SIMD (at most 80 VGPRs), so that two
 // blocks share a CU and every SIMD holds six waves to hide the LDS latency of the others (the
 // 8-wave tilings hold four).  16-wave blocks of one DM pair per wave, reading one channel per
-// step: eight waves per SIMD (at most 64 VGPRs).
+// step, and of one 16-bit trial per wave (the second subband step with 16 fine trials): eight
+// waves per SIMD (at most 64 VGPRs).
 template <>
 __global__ __launch_bounds__(12 * 64) __attribute__((amdgpu_waves_per_eu(6)))
 void dedisperse_kernel<4, 5, 2, 12, 9, false>(DedispArgs a) {
@@ -1460,6 +1462,12 @@ __global__ __launch_bounds__(12 * 64) __attribute__((amdgpu_waves_per_eu(6)))
 void dedisperse_kernel<2, 5, 2, 12, 10, false>(DedispArgs a) {
   extern __shared__ uint32_t lds[];
   dedisperse_grid<2, 5, 2, 12, 10, false>(a, lds);
+}
+template <>
+__global__ __launch_bounds__(16 * 64) __attribute__((amdgpu_waves_per_eu(8)))
+void dedisperse_kernel<2, 5, 1, 16, 0, false>(DedispArgs a) {
+  extern __shared__ uint32_t lds[];
+  dedisperse_grid<2, 5, 1, 16, 0, false>(a, lds);
 }
 template <>
 __global__ __launch_bounds__(16 * 64) __attribute__((amdgpu_waves_per_eu(8)))
@@ -1510,13 +1518,15 @@ struct BatchArgs {
 // Four (<= 128 VGPRs: two 8-wave workgroups per CU), except six (<= 80 VGPRs) for the two
 // plain tilings whose one-launch kernels need 76 registers: 16-bit samples with 32 DMs per
 // block (three 8-wave workgroups per CU) and byte samples with 8 DMs per 4-wave block (six),
-// and for the 12-wave tilings (two blocks per CU); eight for the 16-wave DM pairs.
+// and for the 12-wave tilings (two blocks per CU); eight for the 16-wave 16-bit tilings.
 template <int SPD, int J, int ACC, int WAVES, int PK>
 constexpr int batch_waves_per_eu() {
   return (PK == 0 && J == 5 && ((SPD == 2 && ACC == 4 && WAVES == 8) ||
                                 (SPD == 4 && ACC == 2 && WAVES == 4)))
              ? 6
-             : (WAVES == 12 ? 6 : (WAVES == 16 && PK == 10) ? 8 : 4);
+             : (WAVES == 12                                                   ? 6
+                : (WAVES == 16 && SPD == 2 && (PK == 10 || (PK == 0 && ACC == 1))) ? 8
+                                                                                 : 4);
 }
 
 template <int SPD, int J, int ACC, int WAVES, int PK>
