@@ -144,3 +144,24 @@ def test_batch_autotune_one_launch_same_results():
             assert np.array_equal(o.cpu().numpy()[0][rows], x)
     for p in plans:
         p.close()
+
+
+def test_default_tilings_of_the_measured_plans():
+    # the shapes the plans take by default are the fastest measured on these plans: framed runs
+    # in 12-wave blocks (six waves per SIMD) for the 2048 native serving trials, DM pairs in raw
+    # frames in 16-wave blocks (eight) for the 1476 D=4 trials, and framed group sums in 16-wave
+    # blocks for the first step of the ALERT subband plans; each stays exact (the parity suites
+    # run every tiling)
+    for w, want in ((synth.cfg_apertif(), "WAVES=12 SPD=4 framed runs shared"),
+                    (synth.cfg_apertif_ds(), "WAVES=16 SPD=2 pairs framed")):
+        with arts.Plan.from_workload(w) as p:
+            d = arts.arts_tiling_describe(p.tiling())
+            _say(w.name, p.tiling_shape(), d)
+            assert d.endswith(want), d
+    f_lo, df = synth.band(1536)
+    for dm0, step, ndm, nfine in ((0.0, 0.2, 2048, 32), (819.2, 2.5, 1024, 16)):
+        with arts.Plan.subband(1536, f_lo, df, synth.TSAMP, dm0, step, ndm, nfine, 32,
+                               [1, 5, 10]) as p:
+            d = arts.arts_tiling_describe(p.tiling())
+            _say("subband", dm0, p.tiling_shape(), d)
+            assert d.endswith("WAVES=16 SPD=4 framed runs group sums"), d
